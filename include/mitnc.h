@@ -1,0 +1,217 @@
+/*
+ * mitnc: sliced tensor-network contraction of random quantum circuits on
+ * AMD MI355X (gfx950).  C ABI of libmitnc.so.
+ *
+ * The calls follow the problem as the paper states it (SW-TNC, arXiv
+ * 2504.09186): a circuit becomes a tensor network (Sec. II-A), a contraction
+ * path orders the pairwise contractions (Sec. II-A; Evaluation), a set of
+ * sliced indices splits the work into 2^s independent subtasks whose results
+ * are summed (Sec. II-A, Sec. III-A), and the requested amplitudes are the
+ * remaining open indices.
+ *
+ * General conventions
+ *  - Every call returns an int32_t status: MITNC_OK (0) or a negative error
+ *    code; mitnc_last_error() returns a thread-local message for the last
+ *    failing call on the calling thread.  No C++ exception crosses the ABI.
+ *  - Host objects (mitnc_network, mitnc_plan) are owned by the library and
+ *    freed by the matching destroy call.
+ *  - The library never allocates device memory.  The caller allocates the
+ *    device workspace (size from mitnc_plan_query) and all device outputs;
+ *    "device" pointers below must point to memory of the current HIP device.
+ *  - "stream" is a hipStream_t passed as void* (NULL = default stream).  GPU
+ *    calls are asynchronous on that stream.
+ *  - Index (edge) labels are canonical: the wire segment of qubit q after its
+ *    t-th gate (t = 0: after the initial |0>) has label q*65536 + t.
+ *  - Leaf (tensor) ids are canonical: gate instances in circuit order, then
+ *    the initial-state leaf of each qubit 0..n-1, then one output projector
+ *    leaf for each fixed or batched qubit in increasing qubit order.
+ *  - Result order: batch index (if any) most significant, then the open
+ *    qubits in increasing qubit order (lower qubit = more significant bit).
+ */
+#ifndef MITNC_H
+#define MITNC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MITNC_OK = 0,
+  MITNC_INVALID_ARG = -1,
+  MITNC_PATH_INVALID = -2,
+  MITNC_WORKSPACE_TOO_SMALL = -3,
+  MITNC_HIP_ERROR = -4,
+  MITNC_UNSUPPORTED = -5,
+  MITNC_NUMERIC = -6
+};
+
+enum { MITNC_C64 = 0, MITNC_CF16 = 1, MITNC_CBF16 = 2 };
+
+typedef struct mitnc_network mitnc_network;
+typedef struct mitnc_plan mitnc_plan;
+
+/* One gate instance.  arity 1 or 2; q1 ignored for arity 1.  mat points to
+ * the complex128 matrix U[out][in], interleaved (re, im), row-major, 2x2 or
+ * 4x4; for two qubits the row/column index is (bit of q0)*2 + (bit of q1).
+ * The matrix is copied. */
+typedef struct mitnc_gate {
+  int32_t arity;
+  int32_t q0, q1;
+  const double* mat;
+} mitnc_gate;
+
+/* Circuit -> tensor network (Sec. II-A: gates are the nodes, wire segments
+ * the edges; initial state |0...0>).  Every gate instance becomes its own
+ * leaf.  Errors: INVALID_ARG for bad qubits, arity or null pointers. */
+int32_t mitnc_network_from_circuit(int32_t n_qubits, int32_t n_gates, const mitnc_gate* gates,
+                                   mitnc_network** out);
+
+/* Requested amplitudes.  per_qubit[q]: 0 or 1 = fixed output bit, -1 = open,
+ * -2 = batched.  batch_bits: n_batch x (number of batched qubits) bytes
+ * (0/1), row-major, batched qubits in increasing order; n_batch must be a
+ * power of two (the batch index is a set of log2(n_batch) binary hyper-
+ * indices) and may be 0 if no qubit is batched.  Must be called exactly once
+ * before any path call. */
+int32_t mitnc_network_set_output(mitnc_network* net, const int8_t* per_qubit, int32_t n_batch,
+                                 const uint8_t* batch_bits);
+
+/* Number of leaves (tensors) and of contraction steps (n_leaves - 1). */
+int32_t mitnc_network_info(const mitnc_network* net, int32_t* n_leaves, int32_t* n_labels);
+
+/* Contraction order and slicing search.  Runs `trials` randomised greedy
+ * paths (the first one unperturbed; pair cost size(out) - alpha *
+ * (size(a) + size(b)), perturbed by Gumbel noise), slices each greedily
+ * until the largest intermediate is <= 2^max_log2_elems and at least
+ * min_sliced indices are sliced (at most max_sliced), and keeps the path and
+ * slicing with the lowest total flops.  Sliced indices are ordered
+ * outer -> inner by decreasing recomputation cost, which is the slice-id
+ * bit order (the last one is the least significant bit).  The paper's index
+ * overhead O(a) = 2 C_a / C_ori (Eq. 1) is reported by
+ * mitnc_index_overhead.  Errors: UNSUPPORTED if the cap cannot be met within
+ * max_sliced. */
+typedef struct mitnc_search_opts {
+  uint64_t seed;
+  int32_t trials;
+  int32_t max_log2_elems;
+  int32_t min_sliced;
+  int32_t max_sliced;
+} mitnc_search_opts;
+int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* opts);
+
+/* Path as SSA pairs: step t contracts ids pairs[2t], pairs[2t+1] into id
+ * n_leaves + t.  get: pairs_out has room for 2*(n_leaves-1) int32.
+ * set: validates (every id used once, ids exist when used).  Setting a path
+ * keeps the slicing. */
+int32_t mitnc_get_path(const mitnc_network* net, int32_t* pairs_out);
+int32_t mitnc_set_path(mitnc_network* net, int32_t n_steps, const int32_t* pairs);
+
+/* Sliced indices, outer -> inner (the last is the least significant bit of
+ * the slice id).  get: n_out receives the count; ids_out (may be NULL) has
+ * room for 64 labels.  set: every label must be a closed binary edge (shared
+ * by exactly two leaves, not an output). */
+int32_t mitnc_get_slicing(const mitnc_network* net, int32_t* n_out, int64_t* ids_out);
+int32_t mitnc_set_slicing(mitnc_network* net, int32_t n, const int64_t* ids);
+
+/* Greedy slicing for the current path (see mitnc_path_search). */
+int32_t mitnc_slice_greedy(mitnc_network* net, int32_t max_log2_elems, int32_t min_sliced,
+                           int32_t max_sliced);
+
+/* Eq. (1) of the paper for label `a` on the current path and slicing:
+ * O(a) = 2 C_a / C_ori, C = real flops of one subtask (8 per complex
+ * multiply-add).  Host only. */
+int32_t mitnc_index_overhead(const mitnc_network* net, int64_t label, double* overhead);
+
+/* Plan options.  precision: MITNC_C64 (complex64 storage, FP32 arithmetic on
+ * MFMA); reuse: 1 = recompute a tree node only when the sliced indices below
+ * it change between consecutive slices (Sec. III-B, pre-lifetime reuse), 0 =
+ * recompute every node for every slice; cache_budget_bytes: maximum device
+ * bytes of tensors kept across slices (0 = unlimited); force_kernel: -1 =
+ * automatic kernel choice, otherwise a kernel class id (testing aid). */
+typedef struct mitnc_plan_opts {
+  int32_t precision;
+  int32_t reuse;
+  uint64_t cache_budget_bytes;
+  int32_t force_kernel;
+} mitnc_plan_opts;
+
+int32_t mitnc_plan_create(const mitnc_network* net, const mitnc_plan_opts* opts, mitnc_plan** out);
+
+typedef struct mitnc_plan_stats {
+  uint64_t workspace_bytes;   /* device bytes the caller must provide */
+  uint64_t result_elems;      /* complex entries of the result */
+  int32_t n_sliced;           /* S: slice ids are 0 .. 2^S - 1 */
+  int32_t n_steps;            /* contraction steps per full slice */
+  int32_t max_log2_elems;     /* largest intermediate */
+  int32_t n_kernel_classes;
+  double flops_full_slice;    /* real flops of one slice without reuse */
+  double flops_reused_slice;  /* average real flops per slice with reuse over 2^S slices */
+  double bytes_full_slice;    /* algorithmic HBM bytes of one slice without reuse */
+  double bytes_reused_slice;
+  int32_t steps_by_class[8];  /* step count per kernel class */
+  double flops_by_class[8];   /* full-slice flops per kernel class */
+} mitnc_plan_stats;
+int32_t mitnc_plan_query(const mitnc_plan* plan, mitnc_plan_stats* stats);
+
+/* Per-step description for reports (host only).  info has 12 doubles per
+ * step: kernel class, m bits, n bits, k bits, batch bits, recompute level
+ * (-1 = slice invariant), flops, algorithmic bytes, k-split count, swapped,
+ * output log2 size, is-root. */
+int32_t mitnc_plan_steps(const mitnc_plan* plan, double* info);
+
+/* Copies leaves into the caller-owned device workspace (ws, ws_bytes) and
+ * resets the cross-slice cache.  Errors: WORKSPACE_TOO_SMALL, HIP_ERROR. */
+int32_t mitnc_plan_upload(mitnc_plan* plan, void* ws, size_t ws_bytes, void* stream);
+
+/* Contracts slices slice_begin .. slice_end-1 in order and ADDS their sum to
+ * result_accum (device, complex128 interleaved, result_elems entries; FP64
+ * cross-slice sum, Sec. VI: the single reduction of the method).  Must
+ * follow mitnc_plan_upload on the same workspace.  Errors: INVALID_ARG for
+ * an empty or out-of-range slice range, WORKSPACE_TOO_SMALL, HIP_ERROR. */
+int32_t mitnc_execute(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t slice_begin,
+                      uint64_t slice_end, double* result_accum, void* stream);
+
+/* Single pairwise contraction on the GPU (the TTGT step of Sec. II-A /
+ * Sec. V with the permutation fused into the loads).  A, B, C: device
+ * complex64 (interleaved float) tensors of 2^ra, 2^rb, 2^rc entries whose
+ * address bit i carries label la[i] / lb[i] / lc[i].  Labels shared by A and
+ * B and absent from C are summed; labels in all three are batch labels;
+ * every other label must appear in exactly one operand and in C.  C is
+ * overwritten.  work/work_bytes: device scratch for split-K partials (may be
+ * NULL/0 when kernel != split-K; query with work == NULL to get the size in
+ * *work_bytes_needed).  kernel: -1 automatic, else a class id.  Errors:
+ * INVALID_ARG for inconsistent labels. */
+int32_t mitnc_contract(const float* A, int32_t ra, const int64_t* la, const float* B, int32_t rb,
+                       const int64_t* lb, float* C, int32_t rc, const int64_t* lc, int32_t kernel,
+                       void* work, size_t work_bytes, size_t* work_bytes_needed, void* stream);
+
+/* Launch timing for measurement.  mitnc_plan_timing(plan, 1) starts
+ * recording a hipEvent pair around the main kernel of every step launched by
+ * mitnc_execute (events are created on first use and reused after a reset);
+ * calling it again (enable 0 or 1) discards the recorded pairs.
+ * mitnc_plan_timing_read waits for the recorded events and fills, per kernel
+ * class (8 entries each): summed kernel milliseconds, launch count, and the
+ * algorithmic real flops and HBM bytes of those launches. */
+int32_t mitnc_plan_timing(mitnc_plan* plan, int32_t enable);
+int32_t mitnc_plan_timing_read(mitnc_plan* plan, double* ms, double* launches, double* flops,
+                               double* bytes);
+
+void mitnc_plan_destroy(mitnc_plan* plan);
+void mitnc_network_destroy(mitnc_network* net);
+const char* mitnc_last_error(void);
+
+/* Kernel class ids (mitnc_plan_stats.steps_by_class index, force_kernel). */
+enum {
+  MITNC_K_SMALL = 0,  /* tiny step: one thread per output entry */
+  MITNC_K_STEM = 1,   /* big tensor times small matrix: vector FMA, one thread per row */
+  MITNC_K_TILE = 2,   /* LDS-staged, bit-permuted tiles, complex GEMM on FP32 MFMA */
+  MITNC_K_TALL = 3,   /* as TILE with a 128 x 16 tile for narrow N */
+  MITNC_K_SPLITK = 4  /* small M, N, long K: K split over workgroups, FP64 reduction */
+};
+
+#ifdef __cplusplus
+}
+#endif
+#endif

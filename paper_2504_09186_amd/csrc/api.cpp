@@ -1,0 +1,492 @@
+// extern "C" entry points of libmitnc (declared in include/mitnc.h) and the
+// slice executor.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <random>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace mitnc;
+
+static thread_local std::string g_err;
+
+template <class F>
+static int32_t guarded(F&& f) {
+  try {
+    f();
+    return MITNC_OK;
+  } catch (const Error& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host out of memory";
+    return MITNC_INVALID_ARG;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return MITNC_INVALID_ARG;
+  }
+}
+
+static void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(MITNC_HIP_ERROR, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+extern "C" {
+
+const char* mitnc_last_error(void) { return g_err.c_str(); }
+
+int32_t mitnc_network_from_circuit(int32_t n_qubits, int32_t n_gates, const mitnc_gate* gates,
+                                   mitnc_network** out) {
+  return guarded([&] {
+    if (!out || n_qubits <= 0 || n_qubits > 65535 || n_gates < 0 || (n_gates > 0 && !gates))
+      fail(MITNC_INVALID_ARG, "bad arguments");
+    auto net = std::make_unique<mitnc_network>();
+    net->n_qubits = n_qubits;
+    std::vector<int32_t> seg(n_qubits, 0);
+    for (int g = 0; g < n_gates; ++g) {
+      const mitnc_gate& G = gates[g];
+      if (!G.mat) fail(MITNC_INVALID_ARG, "gate matrix is null");
+      Leaf L;
+      L.gate = g;
+      L.arity = G.arity;
+      if (G.arity == 1) {
+        if (G.q0 < 0 || G.q0 >= n_qubits) fail(MITNC_INVALID_ARG, "gate qubit out of range");
+        int q = G.q0;
+        int64_t lin = wire_label(q, seg[q]);
+        int64_t lout = wire_label(q, ++seg[q]);
+        // U[out][in] row-major: address bit 0 = in, bit 1 = out.
+        L.labels = {lin, lout};
+        L.data.resize(4);
+        for (int e = 0; e < 4; ++e) L.data[e] = cd(G.mat[2 * e], G.mat[2 * e + 1]);
+      } else if (G.arity == 2) {
+        int q0 = G.q0, q1 = G.q1;
+        if (q0 < 0 || q1 < 0 || q0 >= n_qubits || q1 >= n_qubits || q0 == q1)
+          fail(MITNC_INVALID_ARG, "two-qubit gate qubits invalid");
+        int64_t i0 = wire_label(q0, seg[q0]), i1 = wire_label(q1, seg[q1]);
+        int64_t o0 = wire_label(q0, ++seg[q0]), o1 = wire_label(q1, ++seg[q1]);
+        // U[o0 o1][i0 i1] row-major: bits (LSB first) i1, i0, o1, o0.
+        L.labels = {i1, i0, o1, o0};
+        L.data.resize(16);
+        for (int e = 0; e < 16; ++e) L.data[e] = cd(G.mat[2 * e], G.mat[2 * e + 1]);
+      } else {
+        fail(MITNC_INVALID_ARG, "gate arity must be 1 or 2");
+      }
+      net->leaves.push_back(std::move(L));
+    }
+    for (int q = 0; q < n_qubits; ++q) {
+      Leaf L;
+      L.labels = {wire_label(q, 0)};
+      L.data = {cd(1, 0), cd(0, 0)};
+      net->leaves.push_back(std::move(L));
+    }
+    net->segs = seg;
+    *out = net.release();
+  });
+}
+
+int32_t mitnc_network_set_output(mitnc_network* net, const int8_t* per_qubit, int32_t n_batch,
+                                 const uint8_t* batch_bits) {
+  return guarded([&] {
+    if (!net || !per_qubit) fail(MITNC_INVALID_ARG, "null argument");
+    if (net->output_set) fail(MITNC_INVALID_ARG, "output already set");
+    int n = net->n_qubits;
+    std::vector<int> batched;
+    for (int q = 0; q < n; ++q) {
+      int v = per_qubit[q];
+      if (v < -2 || v > 1) fail(MITNC_INVALID_ARG, "output spec must be 0, 1, -1 or -2");
+      if (v == -2) batched.push_back(q);
+    }
+    int nbb = 0;
+    if (!batched.empty()) {
+      if (n_batch < 1 || (n_batch & (n_batch - 1)) || !batch_bits)
+        fail(MITNC_INVALID_ARG, "n_batch must be a power of two and batch_bits given");
+      while ((1 << nbb) < n_batch) ++nbb;
+    }
+    net->n_batch_bits = nbb;
+    for (int q = 0; q < n; ++q) {
+      int v = per_qubit[q];
+      int64_t last = wire_label(q, net->segs[q]);
+      if (v == 0 || v == 1) {
+        Leaf L;
+        L.labels = {last};
+        L.data = {cd(v == 0 ? 1 : 0, 0), cd(v == 1 ? 1 : 0, 0)};
+        net->leaves.push_back(std::move(L));
+      } else if (v == -2) {
+        int col = (int)(std::find(batched.begin(), batched.end(), q) - batched.begin());
+        Leaf L;
+        L.labels = {last};
+        for (int j = 0; j < nbb; ++j) L.labels.push_back(batch_label(j));
+        L.data.assign((size_t)2 << nbb, cd(0, 0));
+        for (int b = 0; b < n_batch; ++b) {
+          int x = batch_bits[(size_t)b * batched.size() + col] ? 1 : 0;
+          L.data[(size_t)b * 2 + x] = cd(1, 0);
+        }
+        net->leaves.push_back(std::move(L));
+      }
+    }
+    // Result layout (LSB first): open qubits from the highest to the lowest
+    // qubit, then the batch bits.
+    for (int q = n - 1; q >= 0; --q)
+      if (per_qubit[q] == -1) net->output_lsb.push_back(wire_label(q, net->segs[q]));
+    for (int j = 0; j < nbb; ++j) net->output_lsb.push_back(batch_label(j));
+    net->output_set = true;
+  });
+}
+
+int32_t mitnc_network_info(const mitnc_network* net, int32_t* n_leaves, int32_t* n_labels) {
+  return guarded([&] {
+    if (!net) fail(MITNC_INVALID_ARG, "null network");
+    if (n_leaves) *n_leaves = (int32_t)net->leaves.size();
+    if (n_labels) *n_labels = make_symnet(net->leaves, net->output_lsb).n_labels;
+  });
+}
+
+static std::vector<int> dense_sliced(const SymNet& sn, const std::vector<int64_t>& ids) {
+  std::vector<int> v;
+  for (auto x : ids) v.push_back(sn.dense.at(x));
+  return v;
+}
+
+int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
+  return guarded([&] {
+    if (!net || !o) fail(MITNC_INVALID_ARG, "null argument");
+    if (!net->output_set) fail(MITNC_INVALID_ARG, "output not set");
+    SymNet sn = make_symnet(net->leaves, net->output_lsb);
+    int trials = std::max(1, o->trials);
+    std::mt19937_64 rng(o->seed);
+    const double alphas[] = {1.0, 0.5, 1.5, 2.0};
+    const double temps[] = {0.02, 0.05, 0.1, 0.2};
+    double best = -1;
+    Path best_path;
+    std::vector<int> best_sl;
+    for (int t = 0; t < trials; ++t) {
+      double a = t == 0 ? 1.0 : alphas[rng() % 4];
+      double tau = t == 0 ? 0.0 : temps[rng() % 4];
+      Path p = greedy_path(sn, a, tau, rng());
+      bool ok;
+      std::vector<int> sl = greedy_slices(sn, p, o->max_log2_elems, o->min_sliced, o->max_sliced, &ok);
+      if (!ok) continue;
+      std::vector<char> m(sn.n_labels, 0);
+      for (int x : sl) m[x] = 1;
+      double f = sym_total_flops(sym_run(sn, p, m)) * std::ldexp(1.0, (int)sl.size());
+      if (best < 0 || f < best) {
+        best = f;
+        best_path = p;
+        best_sl = sl;
+      }
+    }
+    if (best < 0) fail(MITNC_UNSUPPORTED, "no path met the size cap within max_sliced");
+    net->path = best_path;
+    net->sliced.clear();
+    for (int x : order_slices(sn, best_path, best_sl)) net->sliced.push_back(sn.label_id[x]);
+  });
+}
+
+int32_t mitnc_get_path(const mitnc_network* net, int32_t* pairs_out) {
+  return guarded([&] {
+    if (!net || !pairs_out) fail(MITNC_INVALID_ARG, "null argument");
+    if (net->path.empty()) fail(MITNC_PATH_INVALID, "no path");
+    for (size_t s = 0; s < net->path.size(); ++s) {
+      pairs_out[2 * s] = net->path[s].first;
+      pairs_out[2 * s + 1] = net->path[s].second;
+    }
+  });
+}
+
+int32_t mitnc_set_path(mitnc_network* net, int32_t n_steps, const int32_t* pairs) {
+  return guarded([&] {
+    if (!net || !pairs) fail(MITNC_INVALID_ARG, "null argument");
+    Path p;
+    for (int s = 0; s < n_steps; ++s) p.push_back({pairs[2 * s], pairs[2 * s + 1]});
+    validate_path((int)net->leaves.size(), p);
+    net->path = p;
+  });
+}
+
+int32_t mitnc_get_slicing(const mitnc_network* net, int32_t* n_out, int64_t* ids_out) {
+  return guarded([&] {
+    if (!net || !n_out) fail(MITNC_INVALID_ARG, "null argument");
+    *n_out = (int32_t)net->sliced.size();
+    if (ids_out)
+      for (size_t i = 0; i < net->sliced.size(); ++i) ids_out[i] = net->sliced[i];
+  });
+}
+
+int32_t mitnc_set_slicing(mitnc_network* net, int32_t n, const int64_t* ids) {
+  return guarded([&] {
+    if (!net || n < 0 || n > 62 || (n > 0 && !ids)) fail(MITNC_INVALID_ARG, "bad arguments");
+    if (!net->output_set) fail(MITNC_INVALID_ARG, "output not set");
+    SymNet sn = make_symnet(net->leaves, net->output_lsb);
+    std::vector<int64_t> v;
+    for (int i = 0; i < n; ++i) {
+      auto it = sn.dense.find(ids[i]);
+      if (it == sn.dense.end() || !sn.closed[it->second])
+        fail(MITNC_INVALID_ARG, "label " + std::to_string(ids[i]) + " is not a closed edge");
+      if (std::find(v.begin(), v.end(), ids[i]) != v.end()) fail(MITNC_INVALID_ARG, "duplicate sliced label");
+      v.push_back(ids[i]);
+    }
+    net->sliced = v;
+  });
+}
+
+int32_t mitnc_slice_greedy(mitnc_network* net, int32_t max_log2_elems, int32_t min_sliced, int32_t max_sliced) {
+  return guarded([&] {
+    if (!net) fail(MITNC_INVALID_ARG, "null network");
+    if (net->path.empty()) fail(MITNC_PATH_INVALID, "no path");
+    SymNet sn = make_symnet(net->leaves, net->output_lsb);
+    bool ok;
+    auto sl = greedy_slices(sn, net->path, max_log2_elems, min_sliced, max_sliced, &ok);
+    if (!ok) fail(MITNC_UNSUPPORTED, "cap not met within max_sliced");
+    net->sliced.clear();
+    for (int x : order_slices(sn, net->path, sl)) net->sliced.push_back(sn.label_id[x]);
+  });
+}
+
+int32_t mitnc_index_overhead(const mitnc_network* net, int64_t label, double* overhead) {
+  return guarded([&] {
+    if (!net || !overhead) fail(MITNC_INVALID_ARG, "null argument");
+    if (net->path.empty()) fail(MITNC_PATH_INVALID, "no path");
+    SymNet sn = make_symnet(net->leaves, net->output_lsb);
+    auto it = sn.dense.find(label);
+    if (it == sn.dense.end() || !sn.closed[it->second]) fail(MITNC_INVALID_ARG, "label is not a closed edge");
+    std::vector<char> m(sn.n_labels, 0);
+    for (int x : dense_sliced(sn, net->sliced)) m[x] = 1;
+    double c_ori = sym_total_flops(sym_run(sn, net->path, m));
+    m[it->second] = 1;
+    double c_a = sym_total_flops(sym_run(sn, net->path, m));
+    *overhead = 2.0 * c_a / c_ori;
+  });
+}
+
+int32_t mitnc_plan_create(const mitnc_network* net, const mitnc_plan_opts* opts, mitnc_plan** out) {
+  return guarded([&] {
+    if (!net || !opts || !out) fail(MITNC_INVALID_ARG, "null argument");
+    *out = build_plan(net, *opts);
+  });
+}
+
+int32_t mitnc_plan_query(const mitnc_plan* P, mitnc_plan_stats* st) {
+  return guarded([&] {
+    if (!P || !st) fail(MITNC_INVALID_ARG, "null argument");
+    std::memset(st, 0, sizeof(*st));
+    st->workspace_bytes = P->ws_bytes;
+    st->result_elems = P->result_elems;
+    st->n_sliced = P->S;
+    st->n_steps = (int32_t)P->steps.size();
+    st->max_log2_elems = P->max_log2;
+    st->n_kernel_classes = 5;
+    double nsl = std::ldexp(1.0, P->S);
+    for (auto& s : P->steps) {
+      st->flops_full_slice += s.flops;
+      st->bytes_full_slice += s.bytes;
+      st->steps_by_class[s.kclass] += 1;
+      st->flops_by_class[s.kclass] += s.flops;
+      // how many of the 2^S slices (run in order from 0) recompute this step
+      int lo = P->nodes[s.out].lo;
+      double runs;
+      if (lo >= kLevelNever) runs = 1;
+      else runs = std::ldexp(1.0, P->S - lo);  // slices whose ctz >= lo, plus slice 0
+      runs = std::min(runs, nsl);
+      st->flops_reused_slice += s.flops * runs / nsl;
+      st->bytes_reused_slice += s.bytes * runs / nsl;
+    }
+  });
+}
+
+int32_t mitnc_plan_steps(const mitnc_plan* P, double* info) {
+  return guarded([&] {
+    if (!P || !info) fail(MITNC_INVALID_ARG, "null argument");
+    for (size_t i = 0; i < P->steps.size(); ++i) {
+      const PlanStep& s = P->steps[i];
+      double* r = info + 12 * i;
+      int lo = P->nodes[s.out].lo;
+      r[0] = s.kclass;
+      r[1] = s.d.mb;
+      r[2] = s.d.nb;
+      r[3] = s.d.kb;
+      r[4] = s.d.bb;
+      r[5] = lo >= kLevelNever ? -1 : lo;
+      r[6] = s.flops;
+      r[7] = s.bytes;
+      r[8] = std::ldexp(1.0, s.d.ks_bits);
+      r[9] = s.swapped;
+      r[10] = P->nodes[s.out].rank;
+      r[11] = s.root;
+    }
+  });
+}
+
+int32_t mitnc_plan_upload(mitnc_plan* P, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    if (!P || !ws) fail(MITNC_INVALID_ARG, "null argument");
+    if (ws_bytes < P->ws_bytes) fail(MITNC_WORKSPACE_TOO_SMALL, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    for (int i = 0; i < P->n_leaves; ++i) {
+      const auto& h = P->leaf_data[i];
+      hip_check(hipMemcpyAsync(base + P->nodes[i].offset, h.data(), h.size() * sizeof(float),
+                               hipMemcpyHostToDevice, s),
+                "leaf upload");
+    }
+    hip_check(hipStreamSynchronize(s), "leaf upload sync");
+    P->uploaded = true;
+    P->uploaded_ws = ws;
+  });
+}
+
+mitnc_plan::~mitnc_plan() {
+  for (void* e : ev_pool) hipEventDestroy((hipEvent_t)e);
+}
+
+static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t slice, double* acc,
+                             hipStream_t s) {
+  StepDesc d = st.d;
+  auto ptr = [&](int node) -> char* {
+    const PlanNode& nd = P->nodes[node];
+    uint64_t off;
+    if (nd.region == 0) {
+      off = nd.offset;
+      uint64_t e = 0;
+      for (auto& [sb, pb] : nd.slice_bits) e += ((slice >> sb) & 1ull) << pb;
+      off += e * 8;
+    } else if (nd.region == 1) {
+      off = P->off_persist + nd.offset;
+    } else {
+      off = P->off_arena + nd.offset;
+    }
+    return base + off;
+  };
+  d.A = (const float*)ptr(st.a);
+  d.B = (const float*)ptr(st.b);
+  if (st.root) {
+    d.C = nullptr;
+    d.acc = acc;
+    d.mode = EPI_ACC64;
+  } else {
+    d.C = (float*)ptr(st.out);
+    d.acc = nullptr;
+    d.mode = EPI_STORE;
+  }
+  d.part = (float*)(base + P->off_part);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (P->timing) {
+    size_t need = 2 * (P->ev_used + 1);
+    while (P->ev_pool.size() < need) {
+      hipEvent_t e;
+      hip_check(hipEventCreate(&e), "event create");
+      P->ev_pool.push_back((void*)e);
+    }
+    e0 = (hipEvent_t)P->ev_pool[2 * P->ev_used];
+    e1 = (hipEvent_t)P->ev_pool[2 * P->ev_used + 1];
+    P->ev_step.push_back((int)(&st - P->steps.data()));
+    P->ev_used++;
+  }
+  hip_check(launch_step(st.kclass, d, s, e0, e1), "kernel launch");
+}
+
+int32_t mitnc_execute(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, uint64_t s1, double* acc,
+                      void* stream) {
+  return guarded([&] {
+    if (!P || !ws || !acc) fail(MITNC_INVALID_ARG, "null argument");
+    if (!P->uploaded || P->uploaded_ws != ws) fail(MITNC_INVALID_ARG, "plan not uploaded to this workspace");
+    if (ws_bytes < P->ws_bytes) fail(MITNC_WORKSPACE_TOO_SMALL, "workspace too small");
+    uint64_t n_slices = 1ull << P->S;
+    if (s0 >= s1 || s1 > n_slices) fail(MITNC_INVALID_ARG, "slice range out of bounds");
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    for (uint64_t sl = s0; sl < s1; ++sl) {
+      int level = (sl == s0) ? kLevelFirst : __builtin_ctzll(sl);
+      for (auto& st : P->steps) {
+        if (P->nodes[st.out].lo > level) continue;
+        launch_plan_step(P, st, base, sl, acc, s);
+      }
+    }
+  });
+}
+
+int32_t mitnc_contract(const float* A, int32_t ra, const int64_t* la, const float* B, int32_t rb,
+                       const int64_t* lb, float* C, int32_t rc, const int64_t* lc, int32_t kernel, void* work,
+                       size_t work_bytes, size_t* work_bytes_needed, void* stream) {
+  return guarded([&] {
+    if (ra < 0 || rb < 0 || rc < 0 || ra > 32 || rb > 32 || rc > 32) fail(MITNC_INVALID_ARG, "bad rank");
+    if ((ra && !la) || (rb && !lb) || (rc && !lc)) fail(MITNC_INVALID_ARG, "null labels");
+    // Reuse the plan step builder on a two-leaf pseudo-plan.
+    mitnc_plan P;
+    P.nodes.resize(3);
+    auto setn = [](PlanNode& nd, int r, const int64_t* l) {
+      for (int i = 0; i < r; ++i) {
+        nd.labels.push_back(l[i]);
+        nd.pos.push_back(i);
+      }
+      nd.rank = r;
+    };
+    setn(P.nodes[0], ra, la);
+    setn(P.nodes[1], rb, lb);
+    std::map<int64_t, int> cnt;
+    for (int i = 0; i < ra; ++i) cnt[la[i]] |= 1;
+    for (int i = 0; i < rb; ++i) cnt[lb[i]] |= 2;
+    std::vector<int64_t> cl(lc, lc + rc);
+    for (auto x : cl)
+      if (!cnt.count(x)) fail(MITNC_INVALID_ARG, "output label not in any operand");
+    for (size_t i = 0; i < cl.size(); ++i)
+      for (size_t j = i + 1; j < cl.size(); ++j)
+        if (cl[i] == cl[j]) fail(MITNC_INVALID_ARG, "duplicate output label");
+    PlanStep st;
+    st.a = 0;
+    st.b = 1;
+    st.out = 2;
+    st.root = false;
+    build_step_for(&P, st, cl, &cl, kernel);
+    if (work_bytes_needed) *work_bytes_needed = st.part_bytes;
+    if (!A && !B && !C) return;  // size query
+    if (!A || !B || !C) fail(MITNC_INVALID_ARG, "null tensor");
+    if (st.part_bytes > 0 && (!work || work_bytes < st.part_bytes))
+      fail(MITNC_WORKSPACE_TOO_SMALL, "split-K work buffer too small");
+    StepDesc d = st.d;
+    d.A = st.swapped ? B : A;
+    d.B = st.swapped ? A : B;
+    d.C = C;
+    d.acc = nullptr;
+    d.part = (float*)work;
+    d.mode = EPI_STORE;
+    hip_check(launch_step(st.kclass, d, (hipStream_t)stream), "kernel launch");
+  });
+}
+
+int32_t mitnc_plan_timing(mitnc_plan* P, int32_t enable) {
+  return guarded([&] {
+    if (!P) fail(MITNC_INVALID_ARG, "null plan");
+    P->timing = enable != 0;
+    P->ev_used = 0;
+    P->ev_step.clear();
+  });
+}
+
+int32_t mitnc_plan_timing_read(mitnc_plan* P, double* ms, double* launches, double* flops, double* bytes) {
+  return guarded([&] {
+    if (!P || !ms || !launches || !flops || !bytes) fail(MITNC_INVALID_ARG, "null argument");
+    for (int c = 0; c < 8; ++c) ms[c] = launches[c] = flops[c] = bytes[c] = 0;
+    for (size_t i = 0; i < P->ev_used; ++i) {
+      hipEvent_t e0 = (hipEvent_t)P->ev_pool[2 * i], e1 = (hipEvent_t)P->ev_pool[2 * i + 1];
+      hip_check(hipEventSynchronize(e1), "event sync");
+      float t = 0;
+      hip_check(hipEventElapsedTime(&t, e0, e1), "event time");
+      const PlanStep& st = P->steps[P->ev_step[i]];
+      ms[st.kclass] += t;
+      launches[st.kclass] += 1;
+      flops[st.kclass] += st.flops;
+      bytes[st.kclass] += st.bytes;
+    }
+  });
+}
+
+void mitnc_plan_destroy(mitnc_plan* plan) { delete plan; }
+void mitnc_network_destroy(mitnc_network* net) { delete net; }
+
+}  // extern "C"

@@ -1,0 +1,18 @@
+// Kernel launch interface (host side of kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/mitnc.h"
+#include "step.hpp"
+
+namespace mitnc {
+
+// Launches the kernel(s) of one contraction step of class `kclass` on stream
+// `s` (for split-K: the partial-tile kernel, then the FP64 reduction).
+// With ev0/ev1 given, ev0 is recorded before and ev1 right after the main
+// kernel (before a split-K reduction).
+hipError_t launch_step(int kclass, const StepDesc& d, hipStream_t s, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
+
+}  // namespace mitnc

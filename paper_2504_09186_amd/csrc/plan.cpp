@@ -1,0 +1,407 @@
+// Plan construction: layouts, kernel classes, reuse levels and memory.
+//
+//  * Layouts (Sec. V-A): a rank-r tensor is a flat array whose address bits
+//    are its binary indices.  The permutation that brings the common indices
+//    together is never materialised; each step carries, for every operand,
+//    the address bit of every logical m/n/k/batch bit, and the kernels stage
+//    tiles through LDS with that map.  The output layout is free: the new
+//    indices of the small operand take the address bits freed by the
+//    contracted indices of the large one, so a stem tensor keeps its layout
+//    from step to step.  The larger operand is always "A" (Sec. V-A: keep the
+//    large tensor as the multiplier).
+//  * Reuse (Sec. III-B, tree-like pre-lifetime reuse): slices are run in
+//    slice-id order, the last sliced index fastest.  A node depends on the
+//    slice-id bits of the sliced indices in its subtree; between slice s-1 and
+//    s the bits 0..ctz(s) change, so a node is recomputed iff its lowest
+//    dependency bit is <= ctz(s).  A node recomputed less often than its parent
+//    is kept across slices (one stored tensor per fork).
+//  * Kernel classes: tiny steps, stem steps (a big tensor times a small
+//    matrix, HBM bound), square-ish GEMM tiles on MFMA, narrow tiles, and
+//    split-K for K >> M, N (Sec. V-B, split-common TTGT).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <tuple>
+
+#include "plan.hpp"
+
+namespace mitnc {
+
+static uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+static void fill_positions(uint8_t* dst, const std::vector<int>& src) {
+  for (size_t i = 0; i < src.size(); ++i) dst[i] = (uint8_t)src[i];
+}
+
+// Tile bits of one operand sorted by address position.  Each entry is
+// (position, code).
+static void tile_order(uint8_t* dst, std::vector<std::pair<int, uint8_t>> v) {
+  std::sort(v.begin(), v.end());
+  for (size_t i = 0; i < v.size(); ++i) dst[i] = v[i].second;
+}
+
+static TileGeom geom_of(int kclass) {
+  switch (kclass) {
+    case MITNC_K_TILE: return geom_tile();
+    case MITNC_K_TALL: return geom_tall();
+    case MITNC_K_SPLITK: return geom_splitk();
+    default: return {0, 0, 0};
+  }
+}
+
+static int choose_class(int mb, int nb, int kb, int bb) {
+  int out_bits = mb + nb + bb;
+  if (out_bits <= 10 && kb <= 6) return MITNC_K_SMALL;
+  if (nb <= 2 && kb <= 4) return MITNC_K_STEM;
+  if (mb <= 4 && nb <= 4) return MITNC_K_SPLITK;
+  if (nb <= 4) return MITNC_K_TALL;
+  return MITNC_K_TILE;
+}
+
+// Builds the descriptor of a step given the operand layouts.
+static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& c_labels_set,
+                       const std::vector<int64_t>* root_layout, int force_kernel) {
+  PlanNode& A0 = P->nodes[st.a];
+  PlanNode& B0 = P->nodes[st.b];
+  std::map<int64_t, int> pa, pb, inC;
+  for (size_t i = 0; i < A0.labels.size(); ++i) pa[A0.labels[i]] = A0.pos[i];
+  for (size_t i = 0; i < B0.labels.size(); ++i) pb[B0.labels[i]] = B0.pos[i];
+  for (int64_t x : c_labels_set) inC[x] = 1;
+  if (B0.rank > A0.rank) {
+    std::swap(st.a, st.b);
+    std::swap(pa, pb);
+    st.swapped = true;
+  }
+  PlanNode& A = P->nodes[st.a];
+  PlanNode& B = P->nodes[st.b];
+  std::vector<int64_t> M, N, K, Bt;
+  for (auto& [x, p] : pa) {
+    bool b = pb.count(x), c = inC.count(x);
+    if (b && c) Bt.push_back(x);
+    else if (b) K.push_back(x);
+    else if (c) M.push_back(x);
+    else fail(MITNC_UNSUPPORTED, "index held by one operand only and not kept");
+  }
+  for (auto& [x, p] : pb) {
+    if (pa.count(x)) continue;
+    if (!inC.count(x)) fail(MITNC_UNSUPPORTED, "index held by one operand only and not kept");
+    N.push_back(x);
+  }
+  auto by = [](std::map<int64_t, int>& m) { return [&m](int64_t u, int64_t v) { return m[u] < m[v]; }; };
+  std::sort(M.begin(), M.end(), by(pa));
+  std::sort(N.begin(), N.end(), by(pb));
+  std::sort(Bt.begin(), Bt.end(), by(pa));
+  // K order: indices among the lowest 4 address bits of A or B first (they
+  // must be inside every tile for coalesced loads), then by A position.
+  std::sort(K.begin(), K.end(), [&](int64_t u, int64_t v) {
+    int lu = std::min(pa[u], pb[u]) < 4 ? 0 : 1, lv = std::min(pa[v], pb[v]) < 4 ? 0 : 1;
+    if (lu != lv) return lu < lv;
+    if (lu == 0) return std::min(pa[u], pb[u]) < std::min(pa[v], pb[v]);
+    return pa[u] < pa[v];
+  });
+  // Output layout.
+  std::vector<int64_t> C;
+  if (root_layout) {
+    C = *root_layout;
+  } else {
+    std::vector<std::pair<int, int64_t>> order;
+    for (auto& [x, p] : pa) order.push_back({p, x});
+    std::sort(order.begin(), order.end());
+    size_t ni = 0;
+    std::map<int64_t, char> isK;
+    for (auto x : K) isK[x] = 1;
+    for (auto& [p, x] : order) {
+      if (isK.count(x)) {
+        if (ni < N.size()) C.push_back(N[ni++]);
+      } else {
+        C.push_back(x);  // M or batch
+      }
+    }
+    while (ni < N.size()) C.push_back(N[ni++]);
+  }
+  std::map<int64_t, int> pc;
+  for (size_t i = 0; i < C.size(); ++i) pc[C[i]] = (int)i;
+  if (C.size() != M.size() + N.size() + Bt.size()) fail(MITNC_UNSUPPORTED, "output label mismatch");
+
+  PlanNode& O = P->nodes[st.out];
+  O.labels = C;
+  O.pos.resize(C.size());
+  std::iota(O.pos.begin(), O.pos.end(), 0);
+  O.rank = (int)C.size();
+
+  StepDesc& d = st.d;
+  std::memset(&d, 0, sizeof(d));
+  d.mb = (int)M.size();
+  d.nb = (int)N.size();
+  d.kb = (int)K.size();
+  d.bb = (int)Bt.size();
+  if (d.mb > 32 || d.nb > 32 || d.kb > 32 || d.bb > 32) fail(MITNC_UNSUPPORTED, "rank too large");
+  std::vector<int> v;
+  auto put = [&](uint8_t* dst, const std::vector<int64_t>& ls, std::map<int64_t, int>& m) {
+    v.clear();
+    for (auto x : ls) v.push_back(m[x]);
+    fill_positions(dst, v);
+  };
+  put(d.am, M, pa);
+  put(d.ak, K, pa);
+  put(d.ab, Bt, pa);
+  put(d.bk, K, pb);
+  put(d.bn, N, pb);
+  put(d.bbt, Bt, pb);
+  put(d.cm, M, pc);
+  put(d.cn, N, pc);
+  put(d.cb, Bt, pc);
+
+  st.kclass = force_kernel >= 0 ? force_kernel : choose_class(d.mb, d.nb, d.kb, d.bb);
+  if (st.kclass < MITNC_K_SMALL || st.kclass > MITNC_K_SPLITK) fail(MITNC_INVALID_ARG, "unknown kernel class");
+  if (st.kclass == MITNC_K_STEM && (d.kb > 4 || d.nb > 2))
+    fail(MITNC_UNSUPPORTED, "stem kernel needs at most 4 contracted and 2 new indices");
+  TileGeom g = geom_of(st.kclass);
+  d.tm = std::min(g.tm_bits, d.mb);
+  d.tn = std::min(g.tn_bits, d.nb);
+  d.tk = std::min(g.tk_bits, d.kb);
+  if (st.kclass == MITNC_K_TILE || st.kclass == MITNC_K_TALL || st.kclass == MITNC_K_SPLITK) {
+    std::vector<std::pair<int, uint8_t>> ta, tb, tc;
+    for (int i = 0; i < d.tm; ++i) ta.push_back({d.am[i], tile_code(TB_M, i)});
+    for (int i = 0; i < d.tk; ++i) ta.push_back({d.ak[i], tile_code(TB_K, i)});
+    for (int i = 0; i < d.tk; ++i) tb.push_back({d.bk[i], tile_code(TB_K, i)});
+    for (int i = 0; i < d.tn; ++i) tb.push_back({d.bn[i], tile_code(TB_N, i)});
+    for (int i = 0; i < d.tm; ++i) tc.push_back({d.cm[i], tile_code(TB_M, i)});
+    for (int i = 0; i < d.tn; ++i) tc.push_back({d.cn[i], tile_code(TB_N, i)});
+    tile_order(d.a_tile, ta);
+    tile_order(d.b_tile, tb);
+    tile_order(d.c_tile, tc);
+    // Split K over workgroups when there are too few output tiles to fill the
+    // chip; keep at least 4 k-tiles per workgroup.
+    int tiles_bits = (d.mb - d.tm) + (d.nb - d.tn) + d.bb;
+    int khigh = d.kb - d.tk;
+    int ks = 0;
+    while (tiles_bits + ks < 11 && ks + 2 < khigh) ++ks;
+    uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
+    while (ks > 0 && (c_elems << ks) * 8 > (256ull << 20)) --ks;
+    d.ks_bits = ks;
+    st.part_bytes = ks > 0 ? (c_elems << ks) * 8 : 0;
+  }
+  st.flops = 8.0 * std::ldexp(1.0, d.mb + d.nb + d.kb + d.bb);
+  st.bytes = 8.0 * (std::ldexp(1.0, A.rank) + std::ldexp(1.0, B.rank) + std::ldexp(1.0, O.rank));
+}
+
+// Replays the launch schedule of slices 0 .. n_slices-1 on the host with a
+// map of which node value every workspace byte range holds, and fails if a
+// step reads an operand whose bytes were overwritten since it was produced,
+// or writes its output over one of its own operands.
+static void verify_memory_plan(const mitnc_plan* P, uint64_t n_slices) {
+  struct Buf {
+    uint64_t lo, hi;
+    int node;
+  };
+  std::vector<Buf> held;
+  auto range = [&](int node, uint64_t& lo, uint64_t& hi) {
+    const PlanNode& nd = P->nodes[node];
+    uint64_t base = nd.region == 0 ? 0 : nd.region == 1 ? P->off_persist : P->off_arena;
+    lo = base + nd.offset;
+    hi = lo + (nd.region == 0 ? P->leaf_data[nd.leaf_id].size() * 4 : (8ull << nd.rank));
+  };
+  for (int i = 0; i < P->n_leaves; ++i) {
+    uint64_t lo, hi;
+    range(i, lo, hi);
+    held.push_back({lo, hi, i});
+  }
+  for (uint64_t s = 0; s < n_slices; ++s) {
+    int level = s == 0 ? kLevelFirst : __builtin_ctzll(s);
+    for (const PlanStep& st : P->steps) {
+      if (P->nodes[st.out].lo > level) continue;
+      uint64_t alo, ahi, blo, bhi;
+      range(st.a, alo, ahi);
+      range(st.b, blo, bhi);
+      for (auto [node, lo, hi] : {std::tuple<int, uint64_t, uint64_t>{st.a, alo, ahi}, {st.b, blo, bhi}}) {
+        bool ok = false;
+        for (auto& b : held)
+          if (b.node == node && b.lo == lo && b.hi == hi) ok = true;
+        if (!ok) fail(MITNC_INVALID_ARG, "internal: operand " + std::to_string(node) + " clobbered before use");
+      }
+      if (st.root) continue;
+      uint64_t olo, ohi;
+      range(st.out, olo, ohi);
+      if ((olo < ahi && alo < ohi) || (olo < bhi && blo < ohi))
+        fail(MITNC_INVALID_ARG, "internal: step output overlaps an operand");
+      std::vector<Buf> keep;
+      for (auto& b : held)
+        if (!(b.lo < ohi && olo < b.hi) && b.node != st.out) keep.push_back(b);
+      keep.push_back({olo, ohi, st.out});
+      held.swap(keep);
+    }
+  }
+}
+
+void build_step_for(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& c_labels,
+                    const std::vector<int64_t>* root_layout, int force_kernel) {
+  build_step(P, st, c_labels, root_layout, force_kernel);
+}
+
+mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
+  if (!net->output_set) fail(MITNC_INVALID_ARG, "output not set");
+  int n = (int)net->leaves.size();
+  if (n < 2) fail(MITNC_UNSUPPORTED, "network needs at least two tensors");
+  if (net->path.empty()) fail(MITNC_PATH_INVALID, "no path set");
+  validate_path(n, net->path);
+  if (opts.precision != MITNC_C64) fail(MITNC_UNSUPPORTED, "precision not supported by this plan builder");
+  auto P = std::make_unique<mitnc_plan>();
+  P->opts = opts;
+  P->n_leaves = n;
+  P->S = (int)net->sliced.size();
+  int S = P->S;
+  if (S > 62) fail(MITNC_UNSUPPORTED, "too many sliced indices");
+  std::map<int64_t, int> slice_bit;  // label -> slice-id bit (last listed = bit 0)
+  for (int j = 0; j < S; ++j) slice_bit[net->sliced[j]] = S - 1 - j;
+
+  SymNet sn = make_symnet(net->leaves, net->output_lsb);
+  std::vector<char> slm(sn.n_labels, 0);
+  for (auto x : net->sliced) {
+    auto it = sn.dense.find(x);
+    if (it == sn.dense.end() || !sn.closed[it->second]) fail(MITNC_INVALID_ARG, "sliced label is not a closed edge");
+    slm[it->second] = 1;
+  }
+  auto sym = sym_run(sn, net->path, slm);
+  P->max_log2 = sym_max_bits(sn, sym, slm);
+
+  // Leaves.
+  P->nodes.resize(n + net->path.size());
+  uint64_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    const Leaf& L = net->leaves[i];
+    PlanNode& nd = P->nodes[i];
+    nd.leaf = true;
+    nd.leaf_id = i;
+    nd.region = 0;
+    for (size_t b = 0; b < L.labels.size(); ++b) {
+      auto it = slice_bit.find(L.labels[b]);
+      if (it != slice_bit.end()) {
+        nd.slice_bits.push_back({it->second, (int)b});
+        nd.dmask |= 1ull << it->second;
+      } else {
+        nd.labels.push_back(L.labels[b]);
+        nd.pos.push_back((int)b);
+      }
+    }
+    nd.rank = (int)nd.labels.size();
+    std::vector<float> h(L.data.size() * 2);
+    for (size_t e = 0; e < L.data.size(); ++e) {
+      h[2 * e] = (float)L.data[e].real();
+      h[2 * e + 1] = (float)L.data[e].imag();
+    }
+    P->leaf_data.push_back(std::move(h));
+    nd.offset = off;
+    off = align_up(off + L.data.size() * 8, 256);
+  }
+  P->leaf_bytes = off;
+
+  // Steps: layouts and descriptors in path order.
+  P->steps.resize(net->path.size());
+  for (size_t s = 0; s < net->path.size(); ++s) {
+    PlanStep& st = P->steps[s];
+    st.a = net->path[s].first;
+    st.b = net->path[s].second;
+    st.out = n + (int)s;
+    st.root = (s + 1 == net->path.size());
+    P->nodes[st.a].parent = st.out;
+    P->nodes[st.b].parent = st.out;
+    std::vector<int64_t> cset;
+    for (int x : sym[s].c) cset.push_back(sn.label_id[x]);
+    build_step(P.get(), st, cset, st.root ? &net->output_lsb : nullptr, opts.force_kernel);
+    PlanNode& O = P->nodes[st.out];
+    O.dmask = P->nodes[st.a].dmask | P->nodes[st.b].dmask;
+  }
+  // Recompute levels.
+  for (auto& nd : P->nodes) {
+    if (nd.dmask == 0 || !opts.reuse) nd.lo = nd.dmask == 0 ? kLevelNever : 0;
+    else nd.lo = __builtin_ctzll(nd.dmask);
+  }
+  if (!opts.reuse)
+    for (auto& nd : P->nodes) nd.lo = 0;
+  // Region choice: a node recomputed less often than its parent is kept.
+  auto assign_regions = [&]() {
+    uint64_t pb = 0;
+    for (size_t s = 0; s < P->steps.size(); ++s) {
+      PlanNode& O = P->nodes[P->steps[s].out];
+      if (P->steps[s].root) {
+        O.region = 3;
+        continue;
+      }
+      int lp = P->nodes[O.parent].lo;
+      O.region = (O.lo > lp) ? 1 : 2;
+      if (O.region == 1) pb += std::ldexp(8.0, O.rank);
+    }
+    return pb;
+  };
+  uint64_t pbytes = assign_regions();
+  if (opts.cache_budget_bytes > 0) {
+    while (pbytes > opts.cache_budget_bytes) {
+      int best = -1;
+      for (size_t s = 0; s < P->steps.size(); ++s) {
+        PlanNode& O = P->nodes[P->steps[s].out];
+        if (O.region == 1 && (best < 0 || O.rank > P->nodes[best].rank)) best = P->steps[s].out;
+      }
+      if (best < 0) break;
+      P->nodes[best].lo = P->nodes[P->nodes[best].parent].lo;
+      pbytes = assign_regions();
+    }
+  }
+  // Memory: persistent slots, then a transient arena with first-fit reuse.
+  uint64_t poff = 0;
+  for (auto& st : P->steps) {
+    PlanNode& O = P->nodes[st.out];
+    if (O.region == 1) {
+      O.offset = poff;
+      poff = align_up(poff + (8ull << O.rank), 256);
+    }
+  }
+  P->persist_bytes = poff;
+  std::vector<std::pair<uint64_t, uint64_t>> live;  // (offset, size) of live transient buffers
+  std::vector<int> live_node;
+  uint64_t arena = 0;
+  for (size_t s = 0; s < P->steps.size(); ++s) {
+    PlanStep& st = P->steps[s];
+    // The output is placed while the operands are still live (a kernel must
+    // never write over its own inputs); the operands are released afterwards.
+    PlanNode& O = P->nodes[st.out];
+    if (O.region == 2) {
+      uint64_t sz = align_up(8ull << O.rank, 256);
+      std::vector<std::pair<uint64_t, uint64_t>> sorted = live;
+      std::sort(sorted.begin(), sorted.end());
+      uint64_t cand = 0;
+      for (auto& [o, z] : sorted) {
+        if (cand + sz <= o) break;
+        cand = std::max(cand, o + z);
+      }
+      O.offset = cand;
+      live.push_back({cand, sz});
+      live_node.push_back(st.out);
+      arena = std::max(arena, cand + sz);
+    }
+    for (int op : {st.a, st.b}) {
+      for (size_t i = 0; i < live_node.size(); ++i)
+        if (live_node[i] == op) {
+          live.erase(live.begin() + i);
+          live_node.erase(live_node.begin() + i);
+          break;
+        }
+    }
+  }
+  P->arena_bytes = arena;
+  uint64_t part = 0;
+  for (auto& st : P->steps) part = std::max(part, st.part_bytes);
+  P->part_bytes = align_up(part, 256);
+  P->off_persist = align_up(P->leaf_bytes, 256);
+  P->off_arena = align_up(P->off_persist + P->persist_bytes, 256);
+  P->off_part = align_up(P->off_arena + P->arena_bytes, 256);
+  P->ws_bytes = align_up(P->off_part + P->part_bytes, 256);
+  P->result_elems = 1ull << net->output_lsb.size();
+  verify_memory_plan(P.get(), std::min<uint64_t>(1ull << P->S, 64));
+  return P.release();
+}
+
+}  // namespace mitnc

@@ -1,0 +1,68 @@
+// Execution plan of a sliced contraction tree (host side).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "internal.hpp"
+#include "step.hpp"
+
+namespace mitnc {
+
+constexpr int kLevelNever = 1000;   // node does not depend on any sliced index
+constexpr int kLevelFirst = 1001;   // first slice of a range: everything runs
+
+struct PlanNode {
+  bool leaf = false;
+  int leaf_id = -1;
+  std::vector<int64_t> labels;  // labels present after slicing
+  std::vector<int> pos;         // physical address bit of each label
+  std::vector<std::pair<int, int>> slice_bits;  // (slice-id bit, physical bit) of sliced labels
+  int rank = 0;                 // labels.size()
+  uint64_t dmask = 0;           // slice-id bits this node depends on
+  int lo = kLevelNever;         // recompute when a slice-id bit <= lo changes
+  int parent = -1;
+  int region = 0;               // 0 leaf, 1 persistent, 2 transient, 3 result accumulator
+  uint64_t offset = 0;          // byte offset inside the workspace
+};
+
+struct PlanStep {
+  int a = -1, b = -1, out = -1;  // node ids; a is the larger operand
+  bool swapped = false;
+  bool root = false;
+  int kclass = MITNC_K_SMALL;
+  StepDesc d{};                  // pointer fields filled at launch
+  double flops = 0, bytes = 0;
+  uint64_t part_bytes = 0;
+};
+
+}  // namespace mitnc
+
+struct mitnc_plan {
+  mitnc_plan_opts opts{};
+  int n_leaves = 0;
+  int S = 0;                                 // number of sliced indices
+  std::vector<mitnc::PlanNode> nodes;        // leaves then step outputs
+  std::vector<mitnc::PlanStep> steps;
+  std::vector<std::vector<float>> leaf_data; // complex64 interleaved, full (unsliced) leaves
+  uint64_t leaf_bytes = 0, persist_bytes = 0, arena_bytes = 0, part_bytes = 0;
+  uint64_t off_persist = 0, off_arena = 0, off_part = 0, ws_bytes = 0;
+  uint64_t result_elems = 0;
+  int max_log2 = 0;
+  bool uploaded = false;
+  void* uploaded_ws = nullptr;
+  // Optional per-launch timing (hipEvent pairs around each step's main kernel).
+  bool timing = false;
+  std::vector<void*> ev_pool;          // hipEvent_t
+  size_t ev_used = 0;                  // pairs recorded since the last reset
+  std::vector<int> ev_step;            // step index of each recorded pair
+  ~mitnc_plan();
+};
+
+namespace mitnc {
+mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts);
+// Builds the descriptor and output layout of one step (operands P->nodes[st.a],
+// P->nodes[st.b]; output labels c_labels, in root_layout order if given).
+void build_step_for(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& c_labels,
+                    const std::vector<int64_t>* root_layout, int force_kernel);
+}

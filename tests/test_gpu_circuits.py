@@ -1,0 +1,114 @@
+"""Whole sliced contractions on the GPU against the FP64 oracle.
+
+Slicing labels are chosen by the test (canonical wire labels) and set in both
+the library and the oracle; each side plans its own contraction order, which
+does not change the value.  Tolerance: complex64 within 1e-5 relative L2.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _lib_net(circ, spec, bits=None):
+    from paper_2504_09186_amd import tnc
+    return tnc.Network(circ, spec, bits)
+
+
+def _run(net, s0=0, s1=None, reuse=True, force=-1):
+    import torch
+    from paper_2504_09186_amd import tnc
+    plan = tnc.Plan(net, reuse=reuse, force_kernel=force)
+    plan.upload()
+    acc = plan.new_result()
+    plan.execute(acc, s0, plan.n_slices if s1 is None else s1)
+    torch.cuda.synchronize()
+    return acc.cpu().numpy(), plan
+
+
+def test_config1_against_statevector():
+    """3x4 lattice, 8 cycles, greedy path, 2 sliced indices, one amplitude."""
+    require_gpu()
+    c = synth.lattice_circuit(3, 4, 8, seed=1000)
+    spec = synth.output_spec(12, [], seed=2000)
+    net = _lib_net(c, spec)
+    net.path_search(seed=3000, trials=8, max_log2=30, min_sliced=2, max_sliced=2)
+    assert len(net.slicing()) == 2
+    got, plan = _run(net)
+    assert plan.n_slices == 4
+    ref = oracle.sv_amplitudes(c, spec)
+    assert abs(got[0] - ref) / abs(ref) < TOL
+
+
+@pytest.mark.parametrize("rows,cols,cycles,nopen,nsl,seed", [
+    (2, 3, 5, 2, 2, 1), (3, 3, 6, 3, 3, 2), (3, 4, 8, 4, 3, 3), (2, 4, 10, 0, 4, 4), (4, 4, 8, 6, 4, 5)])
+def test_per_slice_partial_sums(rows, cols, cycles, nopen, nsl, seed):
+    require_gpu()
+    c = synth.lattice_circuit(rows, cols, cycles, seed=seed)
+    n = c.n_qubits
+    spec = synth.output_spec(n, list(range(n - nopen, n)), seed=seed + 50)
+    onet = oracle.build_network(c, spec)
+    rng = np.random.default_rng(seed + 99)
+    sliced = [int(x) for x in rng.choice(onet.closed_labels(), size=nsl, replace=False)]
+    opath = oracle.greedy_path(onet)
+    total, parts = oracle.contract_sliced(onet, opath, sliced, per_slice=True)
+    net = _lib_net(c, spec)
+    net.path_search(seed=seed, trials=4, max_log2=30)
+    net.set_slicing(sliced)
+    print(f"partial sums case {rows}x{cols}x{cycles} sliced {sliced}", flush=True)
+    for s in range(1 << nsl):
+        got, _ = _run(net, s, s + 1)
+        ref = np.asarray(parts[s]).reshape(-1)
+        assert np.linalg.norm(got - ref) <= TOL * max(np.linalg.norm(ref), 1e-12), f"slice {s}"
+    got, _ = _run(net)
+    ref = np.asarray(total).reshape(-1)
+    assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)
+    assert np.linalg.norm(got - oracle.sv_amplitudes(c, spec).reshape(-1)) <= TOL * np.linalg.norm(ref)
+
+
+def test_reuse_and_ranges_consistent():
+    """Cross-slice reuse and any split of the slice range give the same sum."""
+    require_gpu()
+    c = synth.lattice_circuit(4, 4, 10, seed=7)
+    spec = synth.output_spec(16, [13, 14, 15], seed=8)
+    net = _lib_net(c, spec)
+    net.path_search(seed=9, trials=8, max_log2=11, min_sliced=5)
+    full_reuse, plan = _run(net, reuse=True)
+    full_plain, _ = _run(net, reuse=False)
+    n = plan.n_slices
+    a, _ = _run(net, 0, 5)
+    b, _ = _run(net, 5, n)
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    for x in (full_reuse, full_plain, a + b):
+        assert np.linalg.norm(x - ref) <= TOL * np.linalg.norm(ref)
+
+
+def test_batched_bitstrings():
+    require_gpu()
+    c = synth.lattice_circuit(3, 3, 6, seed=21)
+    bits = synth.random_bitstrings(9, 16, seed=22)
+    spec = np.full(9, -2, dtype=np.int8)
+    net = _lib_net(c, spec, bits)
+    net.path_search(seed=23, trials=8, max_log2=30, min_sliced=2)
+    got, _ = _run(net)
+    ref = oracle.sv_amplitudes(c, spec, bits).reshape(-1)
+    assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("force", [0, 2, 3, 4])
+def test_forced_kernel_class(force):
+    """Every step on one kernel class (any shape must be handled correctly)."""
+    require_gpu()
+    c = synth.lattice_circuit(3, 4, 6, seed=31)
+    spec = synth.output_spec(12, [10, 11], seed=32)
+    net = _lib_net(c, spec)
+    net.path_search(seed=33, trials=4, max_log2=30, min_sliced=2)
+    got, _ = _run(net, force=force)
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)

@@ -1,0 +1,125 @@
+"""Host-side checks of libmitnc (no GPU): exported symbols, planner arithmetic
+against the oracle's counted flops, validation of paths and slicing."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2504_09186_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2504_09186_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_exports_every_header_symbol(lib):
+    from paper_2504_09186_amd import _lib
+    text = open(os.path.join(ROOT, "include", "mitnc.h")).read()
+    declared = set(re.findall(r"\b(mitnc_[a-z_0-9]+)\s*\(", text))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(_lib.EXPORTED)
+
+
+def _nets(rows=2, cols=3, cycles=5, seed=31, nopen=1):
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(rows, cols, cycles, seed=seed)
+    n = c.n_qubits
+    spec = synth.output_spec(n, list(range(n - nopen, n)), seed=seed + 1)
+    onet = oracle.build_network(c, spec)
+    return c, spec, onet, tnc.Network(c, spec)
+
+
+def test_leaf_count_and_canonical_order(lib):
+    c, spec, onet, net = _nets()
+    assert net.n_leaves == onet.n_leaves
+
+
+def test_planner_flops_match_counted_flops(lib):
+    """The oracle's path and a slicing chosen by the test are set in the
+    library; its per-slice flop count must equal the flops counted while the
+    oracle actually contracts one subtask (8 real flops per complex MAC)."""
+    from paper_2504_09186_amd import tnc
+    c, spec, onet, net = _nets(3, 3, 6, seed=41, nopen=2)
+    path = oracle.greedy_path(onet)
+    net.set_path(path)
+    for sliced in ([], onet.closed_labels()[5:7]):
+        net.set_slicing(sliced)
+        plan = tnc.Plan(net)
+        counted = oracle.count_contraction_flops(onet, path, sliced)
+        assert plan.stats.flops_full_slice == pytest.approx(counted, rel=1e-12)
+        assert plan.stats.n_sliced == len(sliced)
+
+
+def test_index_overhead_eq1(lib):
+    c, spec, onet, net = _nets(3, 3, 6, seed=51, nopen=2)
+    path = oracle.greedy_path(onet)
+    net.set_path(path)
+    for a in onet.closed_labels()[:8]:
+        want = 2.0 * oracle.count_contraction_flops(onet, path, [a], 1) / oracle.count_contraction_flops(onet, path)
+        assert net.index_overhead(a) == pytest.approx(want, rel=1e-12)
+
+
+def test_path_search_structure(lib):
+    c, spec, onet, net = _nets(4, 4, 8, seed=61, nopen=3)
+    net.path_search(seed=1, trials=8, max_log2=9, min_sliced=3)
+    p = net.path()
+    n = net.n_leaves
+    assert len(p) == n - 1
+    used = set()
+    for t, (i, j) in enumerate(p):
+        assert i != j and i < n + t and j < n + t and i not in used and j not in used
+        used |= {i, j}
+    sl = net.slicing()
+    assert len(sl) >= 3
+    assert set(sl) <= set(onet.closed_labels())
+    from paper_2504_09186_amd import tnc
+    plan = tnc.Plan(net)
+    assert plan.stats.max_log2_elems <= 9
+    assert plan.stats.flops_reused_slice <= plan.stats.flops_full_slice + 1e-9
+    info = plan.steps()
+    assert info.shape == (n - 1, 12)
+    assert info[-1, 11] == 1 and info[:-1, 11].sum() == 0
+
+
+def test_validation_errors(lib):
+    from paper_2504_09186_amd import _lib
+    c, spec, onet, net = _nets()
+    n = net.n_leaves
+    with pytest.raises(_lib.MitncError):
+        net.set_path([(0, 0)] * (n - 1))
+    with pytest.raises(_lib.MitncError):
+        net.set_path([(0, 1)])
+    open_label = onet.output[0]
+    with pytest.raises(_lib.MitncError):
+        net.set_slicing([open_label])
+    with pytest.raises(_lib.MitncError):
+        net.set_slicing([12345678])
+    good = onet.closed_labels()[0]
+    with pytest.raises(_lib.MitncError):
+        net.set_slicing([good, good])
+
+
+def test_plan_workspace_and_reuse_levels(lib):
+    from paper_2504_09186_amd import tnc
+    c, spec, onet, net = _nets(4, 4, 10, seed=71, nopen=2)
+    net.path_search(seed=3, trials=4, max_log2=10, min_sliced=4)
+    p1 = tnc.Plan(net, reuse=True)
+    p0 = tnc.Plan(net, reuse=False)
+    assert p1.stats.workspace_bytes >= p0.stats.workspace_bytes * 0  # both positive
+    assert p1.stats.workspace_bytes > 0 and p0.stats.workspace_bytes > 0
+    assert p0.stats.flops_reused_slice == pytest.approx(p0.stats.flops_full_slice)
+    assert p1.stats.flops_reused_slice < p1.stats.flops_full_slice
+    # budget 0 bytes of cache except unavoidable: still plans
+    p2 = tnc.Plan(net, reuse=True, cache_budget_bytes=256)
+    assert p2.stats.flops_reused_slice >= p1.stats.flops_reused_slice - 1e-9
