@@ -98,6 +98,8 @@ typedef struct mitnc_search_opts {
   int32_t max_log2_elems;
   int32_t min_sliced;
   int32_t max_sliced;
+  int32_t keep_slicing; /* 1: keep the current sliced indices (outermost, in
+                           their order) and only add more if the cap needs it */
 } mitnc_search_opts;
 int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* opts);
 
@@ -125,11 +127,16 @@ int32_t mitnc_slice_greedy(mitnc_network* net, int32_t max_log2_elems, int32_t m
 int32_t mitnc_index_overhead(const mitnc_network* net, int64_t label, double* overhead);
 
 /* Plan options.  precision: MITNC_C64 (complex64 storage, FP32 arithmetic on
- * MFMA); reuse: 1 = recompute a tree node only when the sliced indices below
- * it change between consecutive slices (Sec. III-B, pre-lifetime reuse), 0 =
- * recompute every node for every slice; cache_budget_bytes: maximum device
- * bytes of tensors kept across slices (0 = unlimited); force_kernel: -1 =
- * automatic kernel choice, otherwise a kernel class id (testing aid). */
+ * MFMA) or MITNC_CF16 / MITNC_CBF16 (each tensor stored as complex FP16 or
+ * BF16 mantissas with a power-of-two exponent per tensor, contractions on
+ * FP16/BF16 MFMA with FP32 accumulation, FP64 cross-slice sum; requires
+ * mitnc_calibrate after upload); reuse: 1 = recompute a tree node only when
+ * the sliced indices below it change between consecutive slices (Sec. III-B,
+ * pre-lifetime reuse), 0 = recompute every node for every slice;
+ * cache_budget_bytes: maximum device bytes of tensors kept across slices
+ * (0 = unlimited; Sec. III-B dynamic tuning demotes the largest cached
+ * tensors); force_kernel: -1 = automatic kernel choice, otherwise a kernel
+ * class id (testing aid). */
 typedef struct mitnc_plan_opts {
   int32_t precision;
   int32_t reuse;
@@ -168,24 +175,44 @@ int32_t mitnc_plan_upload(mitnc_plan* plan, void* ws, size_t ws_bytes, void* str
 /* Contracts slices slice_begin .. slice_end-1 in order and ADDS their sum to
  * result_accum (device, complex128 interleaved, result_elems entries; FP64
  * cross-slice sum, Sec. VI: the single reduction of the method).  Must
- * follow mitnc_plan_upload on the same workspace.  Errors: INVALID_ARG for
- * an empty or out-of-range slice range, WORKSPACE_TOO_SMALL, HIP_ERROR. */
+ * follow mitnc_plan_upload on the same workspace (and, for FP16/BF16 plans,
+ * mitnc_calibrate).  Errors: INVALID_ARG for an empty or out-of-range slice
+ * range or an uncalibrated FP16/BF16 plan, WORKSPACE_TOO_SMALL, HIP_ERROR. */
 int32_t mitnc_execute(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t slice_begin,
                       uint64_t slice_end, double* result_accum, void* stream);
 
+/* FP16/BF16 plans: chooses every tensor's power-of-two exponent.  Runs
+ * slices slice_begin .. slice_end-1 in complex64 inside the workspace,
+ * records each step's largest |Re|, |Im| and sets the exponent so that this
+ * maximum maps into [2^13, 2^14) (two bits of headroom below the FP16
+ * maximum); slices are statistically alike, so one or a few slices suffice.
+ * Synchronises the stream.  No effect on complex64 plans. */
+int32_t mitnc_calibrate(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t slice_begin,
+                        uint64_t slice_end, void* stream);
+
+/* FP16/BF16 plans record, per step, the largest stored |Re|, |Im| (after
+ * scaling; +inf for a non-finite value) over all executed slices.  Copies
+ * n_steps floats to host memory `out` (synchronises the stream) and clears
+ * them if reset != 0.  A value >= 65504 means FP16 overflow. */
+int32_t mitnc_step_maxima(mitnc_plan* plan, void* ws, size_t ws_bytes, float* out, int32_t reset,
+                          void* stream);
+
 /* Single pairwise contraction on the GPU (the TTGT step of Sec. II-A /
  * Sec. V with the permutation fused into the loads).  A, B, C: device
- * complex64 (interleaved float) tensors of 2^ra, 2^rb, 2^rc entries whose
- * address bit i carries label la[i] / lb[i] / lc[i].  Labels shared by A and
- * B and absent from C are summed; labels in all three are batch labels;
- * every other label must appear in exactly one operand and in C.  C is
- * overwritten.  work/work_bytes: device scratch for split-K partials (may be
- * NULL/0 when kernel != split-K; query with work == NULL to get the size in
+ * tensors of 2^ra, 2^rb, 2^rc complex entries (precision MITNC_C64:
+ * interleaved float; MITNC_CF16 / MITNC_CBF16: interleaved 16-bit halves)
+ * whose address bit i carries label la[i] / lb[i] / lc[i].  Labels shared by
+ * A and B and absent from C are summed; labels in all three are batch
+ * labels; every other label must appear in exactly one operand and in C.  C
+ * is overwritten with the result times out_scale (use 1 for complex64).
+ * work/work_bytes: device scratch for split-K partials (may be NULL/0 when no
+ * split is needed; call with A, B and C all NULL to get the size in
  * *work_bytes_needed).  kernel: -1 automatic, else a class id.  Errors:
  * INVALID_ARG for inconsistent labels. */
-int32_t mitnc_contract(const float* A, int32_t ra, const int64_t* la, const float* B, int32_t rb,
-                       const int64_t* lb, float* C, int32_t rc, const int64_t* lc, int32_t kernel,
-                       void* work, size_t work_bytes, size_t* work_bytes_needed, void* stream);
+int32_t mitnc_contract(const void* A, int32_t ra, const int64_t* la, const void* B, int32_t rb,
+                       const int64_t* lb, void* C, int32_t rc, const int64_t* lc, int32_t precision,
+                       float out_scale, int32_t kernel, void* work, size_t work_bytes,
+                       size_t* work_bytes_needed, void* stream);
 
 /* Launch timing for measurement.  mitnc_plan_timing(plan, 1) starts
  * recording a hipEvent pair around the main kernel of every step launched by

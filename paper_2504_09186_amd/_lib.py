@@ -32,7 +32,7 @@ class mitnc_gate(C.Structure):
 
 class mitnc_search_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("trials", C.c_int32), ("max_log2_elems", C.c_int32),
-                ("min_sliced", C.c_int32), ("max_sliced", C.c_int32)]
+                ("min_sliced", C.c_int32), ("max_sliced", C.c_int32), ("keep_slicing", C.c_int32)]
 
 
 class mitnc_plan_opts(C.Structure):
@@ -70,8 +70,11 @@ _SIGS = {
     "mitnc_plan_timing": [_VP, _I32],
     "mitnc_plan_timing_read": [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                C.POINTER(C.c_double)],
+    "mitnc_calibrate": [_VP, _VP, C.c_size_t, C.c_uint64, C.c_uint64, _VP],
+    "mitnc_step_maxima": [_VP, _VP, C.c_size_t, C.POINTER(C.c_float), _I32, _VP],
     "mitnc_contract": [_VP, _I32, C.POINTER(C.c_int64), _VP, _I32, C.POINTER(C.c_int64), _VP, _I32,
-                       C.POINTER(C.c_int64), _I32, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP],
+                       C.POINTER(C.c_int64), _I32, C.c_float, _I32, _VP, C.c_size_t, C.POINTER(C.c_size_t),
+                       _VP],
 }
 _VOID = {"mitnc_plan_destroy": [_VP], "mitnc_network_destroy": [_VP]}
 

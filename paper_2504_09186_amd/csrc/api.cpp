@@ -162,15 +162,42 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
     std::mt19937_64 rng(o->seed);
     const double alphas[] = {1.0, 0.5, 1.5, 2.0};
     const double temps[] = {0.02, 0.05, 0.1, 0.2};
+    // With keep_slicing the current sliced indices are fixed: paths are
+    // searched on the network without them, and further indices are sliced
+    // only if the size cap requires it.
+    std::vector<char> fixed(sn.n_labels, 0);
+    std::vector<int> fixed_list;
+    if (o->keep_slicing)
+      for (auto x : net->sliced) {
+        fixed[sn.dense.at(x)] = 1;
+        fixed_list.push_back(sn.dense.at(x));
+      }
     double best = -1;
     Path best_path;
     std::vector<int> best_sl;
     for (int t = 0; t < trials; ++t) {
       double a = t == 0 ? 1.0 : alphas[rng() % 4];
       double tau = t == 0 ? 0.0 : temps[rng() % 4];
-      Path p = greedy_path(sn, a, tau, rng());
+      Path p = greedy_path(sn, a, tau, rng(), o->keep_slicing ? &fixed : nullptr);
       bool ok;
-      std::vector<int> sl = greedy_slices(sn, p, o->max_log2_elems, o->min_sliced, o->max_sliced, &ok);
+      std::vector<int> sl;
+      if (o->keep_slicing) {
+        SymNet sub = sn;
+        for (auto& v : sub.leaf) {
+          std::vector<int> w;
+          for (int x : v)
+            if (!fixed[x]) w.push_back(x);
+          v.swap(w);
+        }
+        for (int x : fixed_list) sub.closed[x] = 0;
+        int extra_min = std::max(0, o->min_sliced - (int)fixed_list.size());
+        int extra_max = std::max(0, o->max_sliced - (int)fixed_list.size());
+        std::vector<int> extra = greedy_slices(sub, p, o->max_log2_elems, extra_min, extra_max, &ok);
+        sl = fixed_list;
+        sl.insert(sl.end(), extra.begin(), extra.end());
+      } else {
+        sl = greedy_slices(sn, p, o->max_log2_elems, o->min_sliced, o->max_sliced, &ok);
+      }
       if (!ok) continue;
       std::vector<char> m(sn.n_labels, 0);
       for (int x : sl) m[x] = 1;
@@ -184,7 +211,14 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
     if (best < 0) fail(MITNC_UNSUPPORTED, "no path met the size cap within max_sliced");
     net->path = best_path;
     net->sliced.clear();
-    for (int x : order_slices(sn, best_path, best_sl)) net->sliced.push_back(sn.label_id[x]);
+    if (o->keep_slicing) {
+      // the given indices keep their order (outer); added ones go inside
+      std::vector<int> extra(best_sl.begin() + fixed_list.size(), best_sl.end());
+      for (int x : fixed_list) net->sliced.push_back(sn.label_id[x]);
+      for (int x : order_slices(sn, best_path, extra)) net->sliced.push_back(sn.label_id[x]);
+    } else {
+      for (int x : order_slices(sn, best_path, best_sl)) net->sliced.push_back(sn.label_id[x]);
+    }
   });
 }
 
@@ -328,12 +362,20 @@ int32_t mitnc_plan_upload(mitnc_plan* P, void* ws, size_t ws_bytes, void* stream
     if (ws_bytes < P->ws_bytes) fail(MITNC_WORKSPACE_TOO_SMALL, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)ws;
+    if (P->opts.precision != MITNC_C64) P->calibrated = false;
     for (int i = 0; i < P->n_leaves; ++i) {
       const auto& h = P->leaf_data[i];
       hip_check(hipMemcpyAsync(base + P->nodes[i].offset, h.data(), h.size() * sizeof(float),
                                hipMemcpyHostToDevice, s),
                 "leaf upload");
+      if (!P->leaf_half.empty()) {
+        const auto& w = P->leaf_half[i];
+        hip_check(hipMemcpyAsync(base + P->off_leaf_half + P->nodes[i].offset / 2, w.data(),
+                                 w.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s),
+                  "leaf upload");
+      }
     }
+    hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * P->steps.size(), s), "stats reset");
     hip_check(hipStreamSynchronize(s), "leaf upload sync");
     P->uploaded = true;
     P->uploaded_ws = ws;
@@ -344,17 +386,19 @@ mitnc_plan::~mitnc_plan() {
   for (void* e : ev_pool) hipEventDestroy((hipEvent_t)e);
 }
 
+// Launches one step.  prec: storage precision of this run (the plan's own,
+// or complex64 for a calibration slice of an FP16/BF16 plan).
 static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t slice, double* acc,
-                             hipStream_t s) {
+                             hipStream_t s, int prec, bool stats) {
   StepDesc d = st.d;
+  const bool half = prec != MITNC_C64;
   auto ptr = [&](int node) -> char* {
     const PlanNode& nd = P->nodes[node];
     uint64_t off;
     if (nd.region == 0) {
-      off = nd.offset;
       uint64_t e = 0;
       for (auto& [sb, pb] : nd.slice_bits) e += ((slice >> sb) & 1ull) << pb;
-      off += e * 8;
+      off = half ? P->off_leaf_half + nd.offset / 2 + e * 4 : nd.offset + e * 8;
     } else if (nd.region == 1) {
       off = P->off_persist + nd.offset;
     } else {
@@ -362,18 +406,25 @@ static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t s
     }
     return base + off;
   };
-  d.A = (const float*)ptr(st.a);
-  d.B = (const float*)ptr(st.b);
+  d.A = ptr(st.a);
+  d.B = ptr(st.b);
+  d.prec = prec;
+  if (!half) {
+    d.out_scale = 1.f;
+    d.acc_scale = 1.0;
+  }
   if (st.root) {
     d.C = nullptr;
     d.acc = acc;
     d.mode = EPI_ACC64;
   } else {
-    d.C = (float*)ptr(st.out);
+    d.C = ptr(st.out);
     d.acc = nullptr;
     d.mode = EPI_STORE;
   }
   d.part = (float*)(base + P->off_part);
+  d.stats = stats ? (float*)(base + P->off_stats) : nullptr;
+  d.step_index = (int32_t)(&st - P->steps.data());
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (P->timing) {
     size_t need = 2 * (P->ev_used + 1);
@@ -390,32 +441,92 @@ static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t s
   hip_check(launch_step(st.kclass, d, s, e0, e1), "kernel launch");
 }
 
+static void run_slices(mitnc_plan* P, char* base, uint64_t s0, uint64_t s1, double* acc, hipStream_t s, int prec,
+                       bool stats) {
+  for (uint64_t sl = s0; sl < s1; ++sl) {
+    int level = (sl == s0) ? kLevelFirst : __builtin_ctzll(sl);
+    for (auto& st : P->steps) {
+      if (P->nodes[st.out].lo > level) continue;
+      launch_plan_step(P, st, base, sl, acc, s, prec, stats);
+    }
+  }
+}
+
+static void check_ws(mitnc_plan* P, void* ws, size_t ws_bytes) {
+  if (!P || !ws) fail(MITNC_INVALID_ARG, "null argument");
+  if (!P->uploaded || P->uploaded_ws != ws) fail(MITNC_INVALID_ARG, "plan not uploaded to this workspace");
+  if (ws_bytes < P->ws_bytes) fail(MITNC_WORKSPACE_TOO_SMALL, "workspace too small");
+}
+
 int32_t mitnc_execute(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, uint64_t s1, double* acc,
                       void* stream) {
   return guarded([&] {
-    if (!P || !ws || !acc) fail(MITNC_INVALID_ARG, "null argument");
-    if (!P->uploaded || P->uploaded_ws != ws) fail(MITNC_INVALID_ARG, "plan not uploaded to this workspace");
-    if (ws_bytes < P->ws_bytes) fail(MITNC_WORKSPACE_TOO_SMALL, "workspace too small");
+    check_ws(P, ws, ws_bytes);
+    if (!acc) fail(MITNC_INVALID_ARG, "null result");
+    if (!P->calibrated) fail(MITNC_INVALID_ARG, "FP16/BF16 plan: call mitnc_calibrate first");
+    uint64_t n_slices = 1ull << P->S;
+    if (s0 >= s1 || s1 > n_slices) fail(MITNC_INVALID_ARG, "slice range out of bounds");
+    const bool half = P->opts.precision != MITNC_C64;
+    run_slices(P, (char*)ws, s0, s1, acc, (hipStream_t)stream, P->opts.precision, half);
+  });
+}
+
+int32_t mitnc_calibrate(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, uint64_t s1, void* stream) {
+  return guarded([&] {
+    check_ws(P, ws, ws_bytes);
+    if (P->opts.precision == MITNC_C64) return;  // nothing to calibrate
     uint64_t n_slices = 1ull << P->S;
     if (s0 >= s1 || s1 > n_slices) fail(MITNC_INVALID_ARG, "slice range out of bounds");
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)ws;
-    for (uint64_t sl = s0; sl < s1; ++sl) {
-      int level = (sl == s0) ? kLevelFirst : __builtin_ctzll(sl);
-      for (auto& st : P->steps) {
-        if (P->nodes[st.out].lo > level) continue;
-        launch_plan_step(P, st, base, sl, acc, s);
+    const size_t nst = P->steps.size();
+    hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * nst, s), "stats reset");
+    hip_check(hipMemsetAsync(base + P->off_calib, 0, 16 * P->result_elems, s), "calibration result reset");
+    run_slices(P, base, s0, s1, (double*)(base + P->off_calib), s, MITNC_C64, true);
+    std::vector<float> mx(nst);
+    hip_check(hipMemcpyAsync(mx.data(), base + P->off_stats, 4 * nst, hipMemcpyDeviceToHost, s), "stats read");
+    hip_check(hipStreamSynchronize(s), "calibration sync");
+    // Exponents in path order: stored C = true C * 2^-eC, and the kernel
+    // result is (true A B) * 2^-(eA + eB).
+    for (size_t i = 0; i < nst; ++i) {
+      PlanStep& st = P->steps[i];
+      const int ea = P->nodes[st.a].exp, eb = P->nodes[st.b].exp;
+      if (st.root) {
+        st.d.acc_scale = std::ldexp(1.0, ea + eb);
+        st.d.out_scale = 1.f;
+        continue;
       }
+      const int ec = mx[i] > 0 ? mantissa_exponent((double)mx[i]) : ea + eb;
+      P->nodes[st.out].exp = ec;
+      st.d.out_scale = (float)std::ldexp(1.0, ea + eb - ec);
+      st.d.acc_scale = 1.0;
     }
+    hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * nst, s), "stats reset");
+    P->calibrated = true;
   });
 }
 
-int32_t mitnc_contract(const float* A, int32_t ra, const int64_t* la, const float* B, int32_t rb,
-                       const int64_t* lb, float* C, int32_t rc, const int64_t* lc, int32_t kernel, void* work,
-                       size_t work_bytes, size_t* work_bytes_needed, void* stream) {
+int32_t mitnc_step_maxima(mitnc_plan* P, void* ws, size_t ws_bytes, float* out, int32_t reset, void* stream) {
+  return guarded([&] {
+    check_ws(P, ws, ws_bytes);
+    if (!out) fail(MITNC_INVALID_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    const size_t nst = P->steps.size();
+    hip_check(hipMemcpyAsync(out, base + P->off_stats, 4 * nst, hipMemcpyDeviceToHost, s), "stats read");
+    hip_check(hipStreamSynchronize(s), "stats sync");
+    if (reset) hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * nst, s), "stats reset");
+  });
+}
+
+int32_t mitnc_contract(const void* A, int32_t ra, const int64_t* la, const void* B, int32_t rb, const int64_t* lb,
+                       void* C, int32_t rc, const int64_t* lc, int32_t precision, float out_scale, int32_t kernel,
+                       void* work, size_t work_bytes, size_t* work_bytes_needed, void* stream) {
   return guarded([&] {
     if (ra < 0 || rb < 0 || rc < 0 || ra > 32 || rb > 32 || rc > 32) fail(MITNC_INVALID_ARG, "bad rank");
     if ((ra && !la) || (rb && !lb) || (rc && !lc)) fail(MITNC_INVALID_ARG, "null labels");
+    if (precision != MITNC_C64 && precision != MITNC_CF16 && precision != MITNC_CBF16)
+      fail(MITNC_INVALID_ARG, "unknown precision");
     // Reuse the plan step builder on a two-leaf pseudo-plan.
     mitnc_plan P;
     P.nodes.resize(3);
@@ -442,7 +553,7 @@ int32_t mitnc_contract(const float* A, int32_t ra, const int64_t* la, const floa
     st.b = 1;
     st.out = 2;
     st.root = false;
-    build_step_for(&P, st, cl, &cl, kernel);
+    build_step_for(&P, st, cl, &cl, kernel, precision);
     if (work_bytes_needed) *work_bytes_needed = st.part_bytes;
     if (!A && !B && !C) return;  // size query
     if (!A || !B || !C) fail(MITNC_INVALID_ARG, "null tensor");
@@ -454,7 +565,11 @@ int32_t mitnc_contract(const float* A, int32_t ra, const int64_t* la, const floa
     d.C = C;
     d.acc = nullptr;
     d.part = (float*)work;
+    d.stats = nullptr;
     d.mode = EPI_STORE;
+    d.prec = precision;
+    d.out_scale = out_scale;
+    d.acc_scale = 1.0;
     hip_check(launch_step(st.kclass, d, (hipStream_t)stream), "kernel launch");
   });
 }

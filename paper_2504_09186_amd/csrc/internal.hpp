@@ -59,7 +59,8 @@ SymNet make_symnet(const std::vector<Leaf>& leaves, const std::vector<int64_t>& 
 std::vector<SymStep> sym_run(const SymNet& sn, const Path& path, const std::vector<char>& sliced);
 double sym_total_flops(const std::vector<SymStep>& st);
 int sym_max_bits(const SymNet& sn, const std::vector<SymStep>& st, const std::vector<char>& sliced);
-Path greedy_path(const SymNet& sn, double alpha, double temperature, uint64_t seed);
+Path greedy_path(const SymNet& sn, double alpha, double temperature, uint64_t seed,
+                 const std::vector<char>* removed = nullptr);
 std::vector<int> greedy_slices(const SymNet& sn, const Path& path, int cap, int min_sliced,
                                int max_sliced, bool* ok);
 std::vector<int> order_slices(const SymNet& sn, const Path& path, const std::vector<int>& sl);

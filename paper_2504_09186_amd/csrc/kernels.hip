@@ -5,71 +5,180 @@
 // with each logical bit scattered to an arbitrary address bit of each operand
 // (TTGT of Sec. II-A with the transposes fused into the loads, Sec. V-A).
 //
-// Complex GEMM on MFMA (4M form): with A viewed as a real M x 2K matrix
-// A'[m][2k + p] = (Re, Im)[p] of A[m][k] and B expanded into 2 x 2 real blocks
-// B'[2k .. 2k+1][2n .. 2n+1] = [[br, bi], [-bi, br]], the real product A' B'
-// holds Re C in even and Im C in odd columns (8 M K N real flops, the complex
-// flop count).  One v_mfma_f32_16x16x4_f32 covers 16 rows, 8 complex columns
-// and 2 complex k.
+// Storage precision P: 0 = complex64 (interleaved float), 1 = complex FP16,
+// 2 = complex BF16 (interleaved 16-bit halves, one 32-bit word per entry).
+// Arithmetic accumulates in FP32.  A stored FP16/BF16 tensor is a mantissa
+// tensor with a per-tensor power-of-two exponent kept by the host plan: the
+// epilogue multiplies by out_scale (2^(eA + eB - eC)) before rounding, and the
+// last step of a slice adds result * acc_scale (2^(eA + eB)) into the FP64
+// result.
+//
+// The bit-position tables of the descriptor are copied to LDS once per
+// workgroup; every address decode then reads LDS (a dynamically indexed
+// kernel argument would cost a global load per bit).
+//
+// Flop counts reported by the library use the 4M convention, 8 M K N real
+// flops per complex contraction, whichever split executes.
 #include <hip/hip_runtime.h>
+
+#include <cstddef>
 
 #include "kernels.hpp"
 
 namespace mitnc {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
+static_assert(offsetof(StepDesc, am) % 4 == 0, "tables must be dword aligned");
+static_assert(offsetof(StepDesc, c_tile) + 16 - offsetof(StepDesc, am) == TAB_BYTES, "table layout");
+
+__device__ __forceinline__ void load_tables(const StepDesc& d, uint8_t* tab) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(d.am);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(tab);
+  for (int i = threadIdx.x; i < TAB_BYTES / 4; i += blockDim.x) dst[i] = src[i];
+}
+
+// Deposits the low n bits of x at the address bits pos[0..n) (n <= 32).
 __device__ __forceinline__ uint64_t scatter_bits(uint64_t x, const uint8_t* pos, int n) {
   uint64_t r = 0;
-  for (int i = 0; i < n; ++i) r |= ((x >> i) & 1ull) << pos[i];
+#pragma unroll
+  for (int i = 0; i < 32; ++i)
+    if (i < n) r |= ((x >> i) & 1ull) << pos[i];
   return r;
 }
 
+// Extracts the address bits pos[0..n) of a into the low n bits (n <= 32).
 __device__ __forceinline__ uint64_t gather_bits(uint64_t a, const uint8_t* pos, int n) {
   uint64_t r = 0;
-  for (int i = 0; i < n; ++i) r |= ((a >> pos[i]) & 1ull) << i;
+#pragma unroll
+  for (int i = 0; i < 32; ++i)
+    if (i < n) r |= ((a >> pos[i]) & 1ull) << i;
   return r;
 }
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// ---------------------------------------------------------------- element I/O
+__device__ __forceinline__ float h_to_f(uint32_t bits16) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+}
+__device__ __forceinline__ uint32_t f_to_h(float f) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);
+}
+// float -> bfloat16, round to nearest even (NaN stays NaN)
+__device__ __forceinline__ uint32_t f_to_bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
 }
 
-__device__ __forceinline__ void epilogue_store(const StepDesc& d, uint64_t addr, float2 v, uint64_t split,
-                                               uint64_t c_elems) {
+template <int P>
+__device__ __forceinline__ float2 unpack(uint32_t w) {
+  if constexpr (P == 1) return make_float2(h_to_f(w & 0xffffu), h_to_f(w >> 16));
+  else return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+
+template <int P>
+__device__ __forceinline__ uint32_t pack(float2 v) {
+  if constexpr (P == 1) return f_to_h(v.x) | (f_to_h(v.y) << 16);
+  else return f_to_bf(v.x) | (f_to_bf(v.y) << 16);
+}
+
+template <int P>
+__device__ __forceinline__ float2 load_c(const void* p, uint64_t i) {
+  if constexpr (P == 0) return reinterpret_cast<const float2*>(p)[i];
+  else return unpack<P>(reinterpret_cast<const uint32_t*>(p)[i]);
+}
+
+__device__ __forceinline__ float absmax2(float2 v) {
+  float a = fmaxf(fabsf(v.x), fabsf(v.y));
+  return (isfinite(v.x) && isfinite(v.y)) ? a : __builtin_inff();
+}
+
+// Writes one output entry; returns the magnitude stored (for statistics).
+template <int P>
+__device__ __forceinline__ float epilogue_store(const StepDesc& d, uint64_t addr, float2 v, uint64_t split,
+                                                uint64_t c_elems) {
   if (d.mode == EPI_STORE) {
-    reinterpret_cast<float2*>(d.C)[addr] = v;
+    if constexpr (P == 0) {
+      reinterpret_cast<float2*>(d.C)[addr] = v;
+      return absmax2(v);
+    } else {
+      const float2 s = make_float2(v.x * d.out_scale, v.y * d.out_scale);
+      reinterpret_cast<uint32_t*>(d.C)[addr] = pack<P>(s);
+      return absmax2(s);
+    }
   } else if (d.mode == EPI_ACC64) {
     double2* acc = reinterpret_cast<double2*>(d.acc);
     double2 o = acc[addr];
-    o.x += (double)v.x;
-    o.y += (double)v.y;
+    o.x += (double)v.x * d.acc_scale;
+    o.y += (double)v.y * d.acc_scale;
     acc[addr] = o;
+    return 0.f;  // nothing stored in 16 bits
   } else {
     reinterpret_cast<float2*>(d.part)[split * c_elems + addr] = v;
+    return 0.f;
   }
+}
+
+// Per-step maximum of stored magnitudes: wave reduction, one atomic per wave.
+// Every lane of the wave must call it (no early returns before it).
+__device__ __forceinline__ void record_max(const StepDesc& d, float m) {
+  if (!d.stats) return;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0 && m > 0.f)
+    atomicMax(reinterpret_cast<unsigned int*>(d.stats) + d.step_index, __float_as_uint(m));
 }
 
 // ---------------------------------------------------------------- small steps
 // One thread per output entry, direct loads; correct for any shape.
+template <int P>
 __global__ __launch_bounds__(256) void k_small(StepDesc d) {
+  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  load_tables(d, tab);
+  __syncthreads();
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
   const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= c_elems) return;
-  const float2* A = reinterpret_cast<const float2*>(d.A);
-  const float2* B = reinterpret_cast<const float2*>(d.B);
-  uint64_t m = gather_bits(c, d.cm, d.mb), n = gather_bits(c, d.cn, d.nb), b = gather_bits(c, d.cb, d.bb);
-  uint64_t ao = scatter_bits(m, d.am, d.mb) + scatter_bits(b, d.ab, d.bb);
-  uint64_t bo = scatter_bits(n, d.bn, d.nb) + scatter_bits(b, d.bbt, d.bb);
-  const uint64_t K = 1ull << d.kb;
-  float2 s = make_float2(0.f, 0.f);
-  for (uint64_t k = 0; k < K; ++k) {
-    float2 a = A[ao + scatter_bits(k, d.ak, d.kb)];
-    float2 bv = B[bo + scatter_bits(k, d.bk, d.kb)];
-    s.x += a.x * bv.x - a.y * bv.y;
-    s.y += a.x * bv.y + a.y * bv.x;
+  float mx = 0.f;
+  if (c < c_elems) {
+    const uint64_t m = gather_bits(c, tab + T_CM, d.mb), n = gather_bits(c, tab + T_CN, d.nb),
+                   b = gather_bits(c, tab + T_CB, d.bb);
+    const uint64_t ao = scatter_bits(m, tab + T_AM, d.mb) + scatter_bits(b, tab + T_AB, d.bb);
+    const uint64_t bo = scatter_bits(n, tab + T_BN, d.nb) + scatter_bits(b, tab + T_BB, d.bb);
+    // The k loop runs in groups of up to 8 independent loads so that memory
+    // latency is paid once per group rather than once per term.
+    const int kl = d.kb < 3 ? d.kb : 3;
+    const int KL = 1 << kl;
+    uint32_t ak_lo[8], bk_lo[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      ak_lo[j] = (uint32_t)scatter_bits(j, tab + T_AK, kl);
+      bk_lo[j] = (uint32_t)scatter_bits(j, tab + T_BK, kl);
+    }
+    const uint64_t KH = 1ull << (d.kb - kl);
+    float2 s = make_float2(0.f, 0.f);
+    for (uint64_t kh = 0; kh < KH; ++kh) {
+      const uint64_t ah = ao + scatter_bits(kh, tab + T_AK + kl, d.kb - kl);
+      const uint64_t bh = bo + scatter_bits(kh, tab + T_BK + kl, d.kb - kl);
+      float2 a[8], bv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < KL) {
+          a[j] = load_c<P>(d.A, ah + ak_lo[j]);
+          bv[j] = load_c<P>(d.B, bh + bk_lo[j]);
+        }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < KL) {
+          s.x += a[j].x * bv[j].x - a[j].y * bv[j].y;
+          s.y += a[j].x * bv[j].y + a[j].y * bv[j].x;
+        }
+    }
+    mx = epilogue_store<P>(d, c, s, 0, c_elems);
   }
-  epilogue_store(d, c, s, 0, c_elems);
+  record_max(d, mx);
 }
 
 // ---------------------------------------------------------------- stem steps
@@ -77,70 +186,147 @@ __global__ __launch_bounds__(256) void k_small(StepDesc d) {
 // (and batch index), the small matrix in LDS.  Consecutive threads take
 // consecutive m, whose bits are A's lowest non-contracted address bits, so
 // loads and stores are coalesced whatever the bit positions of k and n.
-template <int KB, int NB>
+template <int P, int KB, int NB>
 __global__ __launch_bounds__(256) void k_stem(StepDesc d) {
   constexpr int K = 1 << KB, N = 1 << NB;
+  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   __shared__ float2 Bs[K * N];
   __shared__ uint32_t ka[K], nc[N];
+  load_tables(d, tab);
+  __syncthreads();
   const uint64_t batch = blockIdx.y;
   const int t = threadIdx.x;
-  const float2* A = reinterpret_cast<const float2*>(d.A);
-  const float2* B = reinterpret_cast<const float2*>(d.B);
-  const uint64_t bB = scatter_bits(batch, d.bbt, d.bb);
   if (t < K * N) {
-    int k = t / N, n = t % N;
-    Bs[t] = B[bB + scatter_bits(k, d.bk, KB) + scatter_bits(n, d.bn, NB)];
+    const int k = t / N, n = t % N;
+    Bs[t] = load_c<P>(d.B, scatter_bits(batch, tab + T_BB, d.bb) + scatter_bits(k, tab + T_BK, KB) +
+                               scatter_bits(n, tab + T_BN, NB));
   }
-  if (t < K) ka[t] = (uint32_t)scatter_bits(t, d.ak, KB);
-  if (t < N) nc[t] = (uint32_t)scatter_bits(t, d.cn, NB);
+  if (t < K) ka[t] = (uint32_t)scatter_bits(t, tab + T_AK, KB);
+  if (t < N) nc[t] = (uint32_t)scatter_bits(t, tab + T_CN, NB);
   __syncthreads();
   const int lowb = d.mb < 8 ? d.mb : 8;
-  if (t >= (1 << lowb)) return;
-  const uint64_t mhi = blockIdx.x;  // high m bits (uniform)
-  uint64_t aoff = scatter_bits(mhi, d.am + lowb, d.mb - lowb) + scatter_bits(batch, d.ab, d.bb);
-  uint64_t coff = scatter_bits(mhi, d.cm + lowb, d.mb - lowb) + scatter_bits(batch, d.cb, d.bb);
-  aoff += scatter_bits(t, d.am, lowb);
-  coff += scatter_bits(t, d.cm, lowb);
-  float2 a[K];
+  float mx = 0.f;
+  if (t < (1 << lowb)) {
+    const uint64_t mhi = blockIdx.x;  // high m bits (uniform)
+    uint64_t aoff = scatter_bits(mhi, tab + T_AM + lowb, d.mb - lowb) + scatter_bits(batch, tab + T_AB, d.bb);
+    uint64_t coff = scatter_bits(mhi, tab + T_CM + lowb, d.mb - lowb) + scatter_bits(batch, tab + T_CB, d.bb);
+    aoff += scatter_bits(t, tab + T_AM, lowb);
+    coff += scatter_bits(t, tab + T_CM, lowb);
+    float2 a[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) a[k] = A[aoff + ka[k]];
+    for (int k = 0; k < K; ++k) a[k] = load_c<P>(d.A, aoff + ka[k]);
+    const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
 #pragma unroll
-  for (int n = 0; n < N; ++n) {
-    float2 s = make_float2(0.f, 0.f);
+    for (int n = 0; n < N; ++n) {
+      float2 s = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      float2 b = Bs[k * N + n];
-      s.x += a[k].x * b.x - a[k].y * b.y;
-      s.y += a[k].x * b.y + a[k].y * b.x;
+      for (int k = 0; k < K; ++k) {
+        const float2 b = Bs[k * N + n];
+        s.x += a[k].x * b.x - a[k].y * b.y;
+        s.y += a[k].x * b.y + a[k].y * b.x;
+      }
+      mx = fmaxf(mx, epilogue_store<P>(d, coff + nc[n], s, 0, c_elems));
     }
-    epilogue_store(d, coff + nc[n], s, 0, 1ull << (d.mb + d.nb + d.bb));
   }
+  record_max(d, mx);
 }
 
-// ---------------------------------------------------------------- MFMA tiles
+// ---------------------------------------------------------------- tile helpers
+// Decodes a tile element number into its logical coordinates and address
+// offset; codes/tables live in LDS.
+struct TileSlot {
+  uint32_t off;
+  int lo, hi;  // (m, k) for A tiles, (k, n) for B tiles, (m, n) for C tiles
+};
+
+__device__ __forceinline__ TileSlot decode_slot(int e, int nbits, const uint8_t* codes, const uint8_t* tab,
+                                                int first_cls, int off_first, int off_second) {
+  TileSlot r{0, 0, 0};
+  for (int b = 0; b < nbits; ++b) {
+    const int bit = (e >> b) & 1;
+    const uint8_t code = codes[b];
+    const int idx = code & 31;
+    if ((code >> 5) == first_cls) {
+      r.lo |= bit << idx;
+      r.off |= (uint32_t)bit << tab[off_first + idx];
+    } else {
+      r.hi |= bit << idx;
+      r.off |= (uint32_t)bit << tab[off_second + idx];
+    }
+  }
+  return r;
+}
+
+// Stores the staged C tile (LDS, complex float, row stride SC) to the output,
+// enumerating the tile in C's address order; WK partial tiles are summed.
+template <int P, int TM, int WK, int SC, int C_ITEMS>
+__device__ __forceinline__ void store_c_tile(const StepDesc& d, const uint8_t* tab, const float2* Cs, uint64_t mt,
+                                             uint64_t nt, uint64_t batch) {
+  const int tid = threadIdx.x;
+  const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
+  const uint64_t baseC = scatter_bits(mt, tab + T_CM + d.tm, d.mb - d.tm) +
+                         scatter_bits(nt, tab + T_CN + d.tn, d.nb - d.tn) + scatter_bits(batch, tab + T_CB, d.bb);
+  const int nc = d.tm + d.tn;
+  // Element e = tid + 256 j: the low 8 tile bits come from tid (decoded once
+  // per thread), the others from j (uniform across the workgroup).
+  const int nlo = nc < 8 ? nc : 8;
+  const bool active = tid < (1 << nlo);
+  const TileSlot lo = decode_slot(tid & ((1 << nlo) - 1), nlo, tab + T_CTILE, tab, TB_M, T_CM, T_CN);
+  const int n_hi = 1 << (nc - nlo);
+  float mx = 0.f;
+#pragma unroll
+  for (int j = 0; j < C_ITEMS; ++j) {
+    if (j >= n_hi) break;
+    const TileSlot hi = decode_slot(j << nlo, nc, tab + T_CTILE, tab, TB_M, T_CM, T_CN);  // uniform
+    const int mi = lo.lo | hi.lo, ni = lo.hi | hi.hi;
+    float2 v = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int w = 0; w < WK; ++w) {
+      const float2 c = Cs[(w * TM + mi) * SC + ni];
+      v.x += c.x;
+      v.y += c.y;
+    }
+    if (active) mx = fmaxf(mx, epilogue_store<P>(d, baseC + (lo.off | hi.off), v, blockIdx.y, c_elems));
+  }
+  record_max(d, mx);
+}
+
+// ---------------------------------------------------------------- FP32 MFMA tiles
 // Workgroup of 4 waves computes a TM x TN complex tile of C over a range of
 // TK-wide k tiles.  WM x WN x WK waves: WM x WN split the tile, WK split each
 // k tile (their partial tiles are summed in LDS in a fixed order).
+//
 // Global -> LDS: each thread owns fixed tile elements enumerated in the
 // operand's address order (coalesced), and writes them to the LDS position of
-// their logical (m, k) / (k, n) coordinate: the permutation happens here.
+// their logical (m, k) / (k, n) coordinate: the permutation happens here
+// (Sec. V-A, in-kernel permutation; on a SIMT machine the shuffle is the
+// scattered LDS write).  LDS holds two stages, so one barrier per k tile
+// suffices and the next tile's global loads overlap the MFMAs.
+//
+// Complex product by the 3M split: T1 = Ar Br, T2 = Ai Bi,
+// T3 = (Ar + Ai)(Br + Bi), Re C = T1 - T2, Im C = T3 - T1 - T2: three real
+// 16 x 16 x 4 FP32 MFMAs per 16 x 16 complex block and 4 complex k, instead of
+// the four of the 4M split.
 template <int WM, int WN, int WK, int BM, int BN, int TK>
 __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
   constexpr int TM = WM * BM * 16;
-  constexpr int TN = WN * BN * 8;
-  constexpr int SA = TM + (TM >= 64 ? 16 : 0);  // floats per LDS row of A (row = 2k + part)
-  constexpr int SB = TN + (TN >= 32 ? 8 : 0);   // float2 per LDS row of B (row = k)
-  constexpr int SC = 2 * TN + 2;                // floats per LDS row of the C tile
+  constexpr int TN = WN * BN * 16;
+  constexpr int KW = TK / WK;                   // complex k per wave and k tile
+  static_assert(KW % 4 == 0, "k per wave must be a multiple of 4");
+  constexpr int SA = TM + (TM >= 64 ? 16 : 0);  // float2 per LDS row of A (row = k)
+  constexpr int SB = TN + (TN >= 64 ? 16 : 0);  // float2 per LDS row of B (row = k)
+  constexpr int STAGE = TK * SA + TK * SB;      // float2 per stage
+  constexpr int SC = TN + 4;                    // float2 per LDS row of the C tile
   constexpr int A_LOADS = TM * TK / 256;
   constexpr int B_LOADS = (TK * TN + 255) / 256;
   constexpr int C_ITEMS = TM * TN / 256;
-  constexpr int SMEM_AB = 2 * TK * SA + 2 * TK * SB;
+  constexpr int SMEM_AB = 2 * STAGE;
   constexpr int SMEM_C = WK * TM * SC;
   constexpr int SMEM = SMEM_AB > SMEM_C ? SMEM_AB : SMEM_C;
   static_assert(A_LOADS >= 1 && C_ITEMS >= 1, "tile too small");
-  __shared__ float smem[SMEM];
-  float* As = smem;
-  float2* Bs = reinterpret_cast<float2*>(smem + 2 * TK * SA);
+  __shared__ float2 smem[SMEM];
+  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  __shared__ uint64_t flip[2][32];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -148,38 +334,36 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
   const float2* A = reinterpret_cast<const float2*>(d.A);
   const float2* B = reinterpret_cast<const float2*>(d.B);
 
+  load_tables(d, tab);
+  // Zero both stages once: entries outside the valid tile stay zero, so
+  // padded k never contributes and padded rows/columns only feed outputs that
+  // are never stored.
+  for (int i = tid; i < SMEM_AB; i += 256) smem[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+
   const uint64_t n_mt = 1ull << (d.mb - d.tm);
   const uint64_t mt = blockIdx.x % n_mt, nt = blockIdx.x / n_mt;
   const uint64_t batch = blockIdx.z;
-  const uint64_t baseA = scatter_bits(mt, d.am + d.tm, d.mb - d.tm) + scatter_bits(batch, d.ab, d.bb);
-  const uint64_t baseB = scatter_bits(nt, d.bn + d.tn, d.nb - d.tn) + scatter_bits(batch, d.bbt, d.bb);
+  const uint64_t baseA =
+      scatter_bits(mt, tab + T_AM + d.tm, d.mb - d.tm) + scatter_bits(batch, tab + T_AB, d.bb);
+  const uint64_t baseB =
+      scatter_bits(nt, tab + T_BN + d.tn, d.nb - d.tn) + scatter_bits(batch, tab + T_BB, d.bb);
 
-  // Per-thread load slots.
+  // Per-thread load slots: global offset inside the tile and LDS index.
+  // Slots outside a tile smaller than the template keep offset 0, so their
+  // (unused) loads stay in bounds and the loads need no branches.
   uint32_t a_off[A_LOADS];
   int a_lds[A_LOADS];
   const int na = d.tm + d.tk;
 #pragma unroll
   for (int j = 0; j < A_LOADS; ++j) {
-    int e = tid + 256 * j;
+    const int e = tid + 256 * j;
     a_lds[j] = -1;
     a_off[j] = 0;
     if (e < (1 << na)) {
-      uint32_t off = 0;
-      int mi = 0, ki = 0;
-      for (int b = 0; b < na; ++b) {
-        int bit = (e >> b) & 1;
-        uint8_t code = d.a_tile[b];
-        int idx = code & 31;
-        if ((code >> 5) == TB_M) {
-          mi |= bit << idx;
-          off |= (uint32_t)bit << d.am[idx];
-        } else {
-          ki |= bit << idx;
-          off |= (uint32_t)bit << d.ak[idx];
-        }
-      }
-      a_off[j] = off;
-      a_lds[j] = 2 * ki * SA + mi;
+      const TileSlot s = decode_slot(e, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK);
+      a_off[j] = s.off;
+      a_lds[j] = s.hi * SA + s.lo;
     }
   }
   uint32_t b_off[B_LOADS];
@@ -187,46 +371,226 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
   const int nbt = d.tk + d.tn;
 #pragma unroll
   for (int j = 0; j < B_LOADS; ++j) {
-    int e = tid + 256 * j;
+    const int e = tid + 256 * j;
     b_lds[j] = -1;
     b_off[j] = 0;
     if (e < (1 << nbt)) {
-      uint32_t off = 0;
-      int ni = 0, ki = 0;
-      for (int b = 0; b < nbt; ++b) {
-        int bit = (e >> b) & 1;
-        uint8_t code = d.b_tile[b];
-        int idx = code & 31;
-        if ((code >> 5) == TB_N) {
-          ni |= bit << idx;
-          off |= (uint32_t)bit << d.bn[idx];
-        } else {
-          ki |= bit << idx;
-          off |= (uint32_t)bit << d.bk[idx];
-        }
-      }
-      b_off[j] = off;
-      b_lds[j] = ki * SB + ni;
+      const TileSlot s = decode_slot(e, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN);
+      b_off[j] = s.off;
+      b_lds[j] = TK * SA + s.lo * SB + s.hi;
     }
   }
-  // Zero the LDS tiles once: entries outside the valid tile stay zero, so
-  // padded k never contributes and padded rows/columns only feed outputs that
-  // are never stored.
-  for (int i = tid; i < SMEM_AB; i += 256) smem[i] = 0.f;
 
   const uint64_t k_tiles = 1ull << (d.kb - d.tk);
   const uint64_t per = k_tiles >> d.ks_bits;
-  const uint64_t kt0 = (uint64_t)blockIdx.y * per, kt1 = kt0 + per;
+  const uint64_t kt0 = (uint64_t)blockIdx.y * per;
   const int khb = d.kb - d.tk;
+  // Address offsets of the current k tile in A and B.  Going from k tile t
+  // to t + 1 flips the logical high-k bits 0 .. ctz(t + 1); flip[.][j] holds
+  // the address bits of logical bits 0 .. j, so each step is one XOR.
+  if (tid < khb) {
+    uint64_t fa = 0, fb = 0;
+    for (int i = 0; i <= tid; ++i) {
+      fa |= 1ull << tab[T_AK + d.tk + i];
+      fb |= 1ull << tab[T_BK + d.tk + i];
+    }
+    flip[0][tid] = fa;
+    flip[1][tid] = fb;
+  }
+  uint64_t ka = scatter_bits(kt0, tab + T_AK + d.tk, khb);
+  uint64_t kbo = scatter_bits(kt0, tab + T_BK + d.tk, khb);
 
   float2 ra[A_LOADS], rb[B_LOADS];
-  auto load = [&](uint64_t kt) {
-    uint64_t ka = scatter_bits(kt, d.ak + d.tk, khb);
-    uint64_t kbo = scatter_bits(kt, d.bk + d.tk, khb);
+  auto load = [&]() {
 #pragma unroll
-    for (int j = 0; j < A_LOADS; ++j) ra[j] = a_lds[j] >= 0 ? A[baseA + ka + a_off[j]] : make_float2(0.f, 0.f);
+    for (int j = 0; j < A_LOADS; ++j) ra[j] = A[baseA + ka + a_off[j]];
 #pragma unroll
-    for (int j = 0; j < B_LOADS; ++j) rb[j] = b_lds[j] >= 0 ? B[baseB + kbo + b_off[j]] : make_float2(0.f, 0.f);
+    for (int j = 0; j < B_LOADS; ++j) rb[j] = B[baseB + kbo + b_off[j]];
+  };
+  auto store = [&](int stage) {
+    float2* S = smem + stage * STAGE;
+#pragma unroll
+    for (int j = 0; j < A_LOADS; ++j)
+      if (a_lds[j] >= 0) S[a_lds[j]] = ra[j];
+#pragma unroll
+    for (int j = 0; j < B_LOADS; ++j)
+      if (b_lds[j] >= 0) S[b_lds[j]] = rb[j];
+  };
+
+  v4f acc[3][BM][BN];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) acc[p][i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  load();
+  store(0);
+  __syncthreads();
+  const int row = lane & 15, kq = lane >> 4;
+  for (uint64_t it = 0; it < per; ++it) {
+    const int cur = (int)(it & 1);
+    const bool more = it + 1 < per;
+    if (more) {
+      const int fl = __builtin_ctzll(kt0 + it + 1);
+      ka ^= flip[0][fl];
+      kbo ^= flip[1][fl];
+      load();
+    }
+    const float2* As = smem + cur * STAGE;
+    const float2* Bs = As + TK * SA;
+    float2 av[KW / 4][BM], bv[KW / 4][BN];
+#pragma unroll
+    for (int ks = 0; ks < KW / 4; ++ks) {
+      const int k = wk * KW + ks * 4 + kq;
+#pragma unroll
+      for (int bm = 0; bm < BM; ++bm) av[ks][bm] = As[k * SA + (wm * BM + bm) * 16 + row];
+#pragma unroll
+      for (int bn = 0; bn < BN; ++bn) bv[ks][bn] = Bs[k * SB + (wn * BN + bn) * 16 + row];
+    }
+#pragma unroll
+    for (int ks = 0; ks < KW / 4; ++ks)
+#pragma unroll
+      for (int bm = 0; bm < BM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < BN; ++bn) {
+          const float2 a = av[ks][bm], b = bv[ks][bn];
+          acc[0][bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[0][bm][bn], 0, 0, 0);
+          acc[1][bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[1][bm][bn], 0, 0, 0);
+          acc[2][bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, acc[2][bm][bn], 0, 0, 0);
+        }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+  }
+  // Accumulators -> LDS tile: Re = T1 - T2, Im = T3 - T1 - T2.
+  float2* Cs = smem;
+#pragma unroll
+  for (int bm = 0; bm < BM; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < BN; ++bn)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = (wm * BM + bm) * 16 + 4 * kq + i;
+        const int n = (wn * BN + bn) * 16 + row;
+        const float t1 = acc[0][bm][bn][i], t2 = acc[1][bm][bn][i], t3 = acc[2][bm][bn][i];
+        Cs[(wk * TM + m) * SC + n] = make_float2(t1 - t2, t3 - t1 - t2);
+      }
+  __syncthreads();
+  store_c_tile<0, TM, WK, SC, C_ITEMS>(d, tab, Cs, mt, nt, batch);
+}
+
+// ---------------------------------------------------------------- FP16 / BF16 MFMA tiles
+// Same structure with 16-bit storage and the 4M split on the 16 x 16 x 32
+// FP16/BF16 MFMA (FP32 accumulate): A is viewed as the real M x 2K matrix
+// A'[m][2k + p] = (Re, Im)[p] of A[m][k] -- exactly the interleaved storage --
+// and B is expanded in LDS into 2 x 2 real blocks [[br, bi], [-bi, br]]
+// (rows 2k, 2k+1; columns 2n, 2n+1), so A' B' holds Re C in even and Im C in
+// odd columns.  One MFMA covers 16 rows, 8 complex columns and 16 complex k.
+// LDS rows are k-contiguous: A row m holds A[m][k] as 32-bit words, B' row
+// 2n + c holds the words (br, -bi) (c = 0) or (bi, br) (c = 1) of B[k][n].
+template <int P, int WM, int WN, int WK, int BM, int BN, int TK>
+__global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
+  constexpr int TM = WM * BM * 16;              // complex rows
+  constexpr int TN = WN * BN * 8;               // complex columns
+  constexpr int KW = TK / WK;                   // complex k per wave and k tile
+  static_assert(KW % 16 == 0, "k per wave must be a multiple of 16");
+  constexpr int SW = TK + 4;                    // 32-bit words per LDS row (k contiguous)
+  constexpr int STAGE = TM * SW + 2 * TN * SW;  // words per stage
+  constexpr int SC = TN + 2;                    // float2 per LDS row of the C tile
+  constexpr int A_LOADS = TM * TK / 256;
+  constexpr int B_LOADS = (TK * TN + 255) / 256;
+  constexpr int C_ITEMS = TM * TN / 256;
+  constexpr int SMEM_AB = 2 * STAGE;
+  constexpr int SMEM_C = WK * TM * SC * 2;
+  constexpr int SMEM = SMEM_AB > SMEM_C ? SMEM_AB : SMEM_C;
+  static_assert(A_LOADS >= 1 && C_ITEMS >= 1, "tile too small");
+  __shared__ __align__(16) uint32_t smem[SMEM];
+  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  __shared__ uint64_t flip[2][32];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = (wave / WM) % WN, wk = wave / (WM * WN);
+  const uint32_t* A = reinterpret_cast<const uint32_t*>(d.A);
+  const uint32_t* B = reinterpret_cast<const uint32_t*>(d.B);
+
+  load_tables(d, tab);
+  for (int i = tid; i < SMEM_AB; i += 256) smem[i] = 0u;
+  __syncthreads();
+
+  const uint64_t n_mt = 1ull << (d.mb - d.tm);
+  const uint64_t mt = blockIdx.x % n_mt, nt = blockIdx.x / n_mt;
+  const uint64_t batch = blockIdx.z;
+  const uint64_t baseA =
+      scatter_bits(mt, tab + T_AM + d.tm, d.mb - d.tm) + scatter_bits(batch, tab + T_AB, d.bb);
+  const uint64_t baseB =
+      scatter_bits(nt, tab + T_BN + d.tn, d.nb - d.tn) + scatter_bits(batch, tab + T_BB, d.bb);
+
+  uint32_t a_off[A_LOADS];
+  int a_lds[A_LOADS];
+  const int na = d.tm + d.tk;
+#pragma unroll
+  for (int j = 0; j < A_LOADS; ++j) {
+    const int e = tid + 256 * j;
+    a_lds[j] = -1;
+    a_off[j] = 0;
+    if (e < (1 << na)) {
+      const TileSlot s = decode_slot(e, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK);
+      a_off[j] = s.off;
+      a_lds[j] = s.lo * SW + s.hi;
+    }
+  }
+  uint32_t b_off[B_LOADS];
+  int b_lds[B_LOADS];
+  const int nbt = d.tk + d.tn;
+#pragma unroll
+  for (int j = 0; j < B_LOADS; ++j) {
+    const int e = tid + 256 * j;
+    b_lds[j] = -1;
+    b_off[j] = 0;
+    if (e < (1 << nbt)) {
+      const TileSlot s = decode_slot(e, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN);
+      b_off[j] = s.off;
+      b_lds[j] = TM * SW + (2 * s.hi) * SW + s.lo;  // row 2n; row 2n + 1 is SW further
+    }
+  }
+
+  const uint64_t k_tiles = 1ull << (d.kb - d.tk);
+  const uint64_t per = k_tiles >> d.ks_bits;
+  const uint64_t kt0 = (uint64_t)blockIdx.y * per;
+  const int khb = d.kb - d.tk;
+  if (tid < khb) {
+    uint64_t fa = 0, fb = 0;
+    for (int i = 0; i <= tid; ++i) {
+      fa |= 1ull << tab[T_AK + d.tk + i];
+      fb |= 1ull << tab[T_BK + d.tk + i];
+    }
+    flip[0][tid] = fa;
+    flip[1][tid] = fb;
+  }
+  uint64_t ka = scatter_bits(kt0, tab + T_AK + d.tk, khb);
+  uint64_t kbo = scatter_bits(kt0, tab + T_BK + d.tk, khb);
+
+  uint32_t ra[A_LOADS], rb[B_LOADS];
+  auto load = [&]() {
+#pragma unroll
+    for (int j = 0; j < A_LOADS; ++j) ra[j] = A[baseA + ka + a_off[j]];
+#pragma unroll
+    for (int j = 0; j < B_LOADS; ++j) rb[j] = B[baseB + kbo + b_off[j]];
+  };
+  auto store = [&](int stage) {
+    uint32_t* S = smem + stage * STAGE;
+#pragma unroll
+    for (int j = 0; j < A_LOADS; ++j)
+      if (a_lds[j] >= 0) S[a_lds[j]] = ra[j];
+#pragma unroll
+    for (int j = 0; j < B_LOADS; ++j)
+      if (b_lds[j] >= 0) {
+        const uint32_t w = rb[j];                  // (br, bi)
+        S[b_lds[j]] = w ^ 0x80000000u;             // (br, -bi)
+        S[b_lds[j] + SW] = (w >> 16) | (w << 16);  // (bi, br)
+      }
   };
 
   v4f acc[BM][BN];
@@ -235,120 +599,104 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
 #pragma unroll
     for (int j = 0; j < BN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  load(kt0);
-  const int q = lane >> 4;  // which of the 4 real k of the MFMA k-slice
-  for (uint64_t kt = kt0; kt < kt1; ++kt) {
-    __syncthreads();
+  load();
+  store(0);
+  __syncthreads();
+  const int row = lane & 15, kg = lane >> 4;
+  for (uint64_t it = 0; it < per; ++it) {
+    const int cur = (int)(it & 1);
+    const bool more = it + 1 < per;
+    if (more) {
+      const int fl = __builtin_ctzll(kt0 + it + 1);
+      ka ^= flip[0][fl];
+      kbo ^= flip[1][fl];
+      load();
+    }
+    const uint32_t* As = smem + cur * STAGE;
+    const uint32_t* Bs = As + TM * SW;
 #pragma unroll
-    for (int j = 0; j < A_LOADS; ++j)
-      if (a_lds[j] >= 0) {
-        As[a_lds[j]] = ra[j].x;
-        As[a_lds[j] + SA] = ra[j].y;
-      }
+    for (int ks = 0; ks < KW / 16; ++ks) {
+      const int kw = wk * KW + ks * 16 + 4 * kg;  // first of this lane's 4 complex k
+      uint4 av[BM], bv[BN];
 #pragma unroll
-    for (int j = 0; j < B_LOADS; ++j)
-      if (b_lds[j] >= 0) Bs[b_lds[j]] = rb[j];
-    __syncthreads();
-    if (kt + 1 < kt1) load(kt + 1);
+      for (int bm = 0; bm < BM; ++bm)
+        av[bm] = *reinterpret_cast<const uint4*>(As + ((wm * BM + bm) * 16 + row) * SW + kw);
 #pragma unroll
-    for (int kk = 0; kk < TK / WK; kk += 2) {
-      const int ck = wk * (TK / WK) + kk + (q >> 1);
-      const int part = q & 1;
-      float av[BM], bv[BN];
-#pragma unroll
-      for (int bm = 0; bm < BM; ++bm) av[bm] = As[(2 * ck + part) * SA + (wm * BM + bm) * 16 + (lane & 15)];
-#pragma unroll
-      for (int bn = 0; bn < BN; ++bn) {
-        const int col = lane & 15;
-        float2 b = Bs[ck * SB + (wn * BN + bn) * 8 + (col >> 1)];
-        float v = part == 0 ? ((col & 1) ? b.y : b.x) : ((col & 1) ? b.x : -b.y);
-        bv[bn] = v;
-      }
+      for (int bn = 0; bn < BN; ++bn)
+        bv[bn] = *reinterpret_cast<const uint4*>(Bs + ((wn * BN + bn) * 16 + row) * SW + kw);
 #pragma unroll
       for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
-        for (int bn = 0; bn < BN; ++bn)
-          acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bm], bv[bn], acc[bm][bn], 0, 0, 0);
+        for (int bn = 0; bn < BN; ++bn) {
+          if constexpr (P == 1)
+            acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av[bm]),
+                                                                 __builtin_bit_cast(v8h, bv[bn]), acc[bm][bn], 0, 0, 0);
+          else
+            acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(v8bf, av[bm]), __builtin_bit_cast(v8bf, bv[bn]), acc[bm][bn], 0, 0, 0);
+        }
     }
+    if (more) store(cur ^ 1);
+    __syncthreads();
   }
-  __syncthreads();
   // Accumulators -> LDS tile (rows m, interleaved re/im columns).
-  float* Cs = smem;
+  float* Cf = reinterpret_cast<float*>(smem);
 #pragma unroll
   for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
     for (int bn = 0; bn < BN; ++bn)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        int m = (wm * BM + bm) * 16 + 4 * (lane >> 4) + i;
-        int col = (wn * BN + bn) * 16 + (lane & 15);
-        Cs[(wk * TM + m) * SC + col] = acc[bm][bn][i];
+        const int m = (wm * BM + bm) * 16 + 4 * kg + i;
+        const int col = (wn * BN + bn) * 16 + row;  // 2n + part
+        Cf[(wk * TM + m) * (2 * SC) + col] = acc[bm][bn][i];
       }
   __syncthreads();
-  // LDS -> C, enumerated in C's address order.
-  const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
-  const uint64_t baseC = scatter_bits(mt, d.cm + d.tm, d.mb - d.tm) + scatter_bits(nt, d.cn + d.tn, d.nb - d.tn) +
-                         scatter_bits(batch, d.cb, d.bb);
-  const int nc = d.tm + d.tn;
-#pragma unroll
-  for (int j = 0; j < C_ITEMS; ++j) {
-    int e = tid + 256 * j;
-    if (e >= (1 << nc)) break;
-    uint32_t off = 0;
-    int mi = 0, ni = 0;
-    for (int b = 0; b < nc; ++b) {
-      int bit = (e >> b) & 1;
-      uint8_t code = d.c_tile[b];
-      int idx = code & 31;
-      if ((code >> 5) == TB_M) {
-        mi |= bit << idx;
-        off |= (uint32_t)bit << d.cm[idx];
-      } else {
-        ni |= bit << idx;
-        off |= (uint32_t)bit << d.cn[idx];
-      }
-    }
-    float2 v = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int w = 0; w < WK; ++w) {
-      v.x += Cs[(w * TM + mi) * SC + 2 * ni];
-      v.y += Cs[(w * TM + mi) * SC + 2 * ni + 1];
-    }
-    epilogue_store(d, baseC + off, v, blockIdx.y, c_elems);
-  }
+  store_c_tile<P, TM, WK, SC, C_ITEMS>(d, tab, reinterpret_cast<const float2*>(smem), mt, nt, batch);
 }
 
 // Deterministic FP64 sum of split-K partials in split order (blocked
 // summation, Sec. V-B / Eq. 3: each FP32 chain covers only K / splits terms).
+template <int P>
 __global__ __launch_bounds__(256) void k_reduce(StepDesc d) {
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
   const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= c_elems) return;
-  const float2* part = reinterpret_cast<const float2*>(d.part);
-  const uint64_t splits = 1ull << d.ks_bits;
-  double sx = 0, sy = 0;
-  for (uint64_t s = 0; s < splits; ++s) {
-    float2 v = part[s * c_elems + c];
-    sx += v.x;
-    sy += v.y;
+  float mx = 0.f;
+  if (c < c_elems) {
+    const float2* part = reinterpret_cast<const float2*>(d.part);
+    const uint64_t splits = 1ull << d.ks_bits;
+    double sx = 0, sy = 0;
+    for (uint64_t s = 0; s < splits; ++s) {
+      const float2 v = part[s * c_elems + c];
+      sx += v.x;
+      sy += v.y;
+    }
+    if (d.mode == EPI_ACC64) {
+      double2* acc = reinterpret_cast<double2*>(d.acc);
+      double2 o = acc[c];
+      o.x += sx * d.acc_scale;
+      o.y += sy * d.acc_scale;
+      acc[c] = o;
+    } else if constexpr (P == 0) {
+      const float2 v = make_float2((float)sx, (float)sy);
+      reinterpret_cast<float2*>(d.C)[c] = v;
+      mx = absmax2(v);
+    } else {
+      const float2 v = make_float2((float)(sx * d.out_scale), (float)(sy * d.out_scale));
+      reinterpret_cast<uint32_t*>(d.C)[c] = pack<P>(v);
+      mx = absmax2(v);
+    }
   }
-  if (d.mode == EPI_ACC64) {
-    double2* acc = reinterpret_cast<double2*>(d.acc);
-    double2 o = acc[c];
-    o.x += sx;
-    o.y += sy;
-    acc[c] = o;
-  } else {
-    reinterpret_cast<float2*>(d.C)[c] = make_float2((float)sx, (float)sy);
-  }
+  record_max(d, mx);
 }
 
 // ---------------------------------------------------------------- launch
+template <int P>
 static hipError_t launch_stem(const StepDesc& d, dim3 grid, hipStream_t s) {
-#define MITNC_STEM(KB, NB)                                              \
-  if (d.kb == KB && d.nb == NB) {                                       \
-    hipLaunchKernelGGL((k_stem<KB, NB>), grid, dim3(256), 0, s, d);     \
-    return hipGetLastError();                                           \
+#define MITNC_STEM(KB, NB)                                                \
+  if (d.kb == KB && d.nb == NB) {                                         \
+    hipLaunchKernelGGL((k_stem<P, KB, NB>), grid, dim3(256), 0, s, d);    \
+    return hipGetLastError();                                             \
   }
   MITNC_STEM(0, 0) MITNC_STEM(0, 1) MITNC_STEM(0, 2)
   MITNC_STEM(1, 0) MITNC_STEM(1, 1) MITNC_STEM(1, 2)
@@ -359,30 +707,22 @@ static hipError_t launch_stem(const StepDesc& d, dim3 grid, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_step(int kclass, const StepDesc& d_in, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  StepDesc d = d_in;
-  if (ev0) hipEventRecord(ev0, s);
-  struct Rec {  // records ev1 right after the main kernel of the step
-    hipEvent_t e;
-    hipStream_t s;
-    void operator()() const {
-      if (e) hipEventRecord(e, s);
-    }
-  } rec{ev1, s};
+template <int P>
+static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1) {
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
+  hipError_t e = hipSuccess;
   switch (kclass) {
     case MITNC_K_SMALL: {
       dim3 grid((unsigned)((c_elems + 255) / 256));
-      hipLaunchKernelGGL(k_small, grid, dim3(256), 0, s, d);
-      rec();
-      return hipGetLastError();
+      hipLaunchKernelGGL((k_small<P>), grid, dim3(256), 0, s, d);
+      e = hipGetLastError();
+      break;
     }
     case MITNC_K_STEM: {
-      int lowb = d.mb < 8 ? d.mb : 8;
+      const int lowb = d.mb < 8 ? d.mb : 8;
       dim3 grid((unsigned)(1ull << (d.mb - lowb)), (unsigned)(1ull << d.bb));
-      hipError_t e = launch_stem(d, grid, s);
-      rec();
-      return e;
+      e = launch_stem<P>(d, grid, s);
+      break;
     }
     case MITNC_K_TILE:
     case MITNC_K_TALL:
@@ -391,21 +731,42 @@ hipError_t launch_step(int kclass, const StepDesc& d_in, hipStream_t s, hipEvent
       if (d.ks_bits > 0) d.mode = EPI_PARTIAL;
       dim3 grid((unsigned)(1ull << ((d.mb - d.tm) + (d.nb - d.tn))), (unsigned)(1ull << d.ks_bits),
                 (unsigned)(1ull << d.bb));
-      if (kclass == MITNC_K_TILE)
-        hipLaunchKernelGGL((k_tile<2, 2, 1, 2, 4, 16>), grid, dim3(256), 0, s, d);
-      else if (kclass == MITNC_K_TALL)
-        hipLaunchKernelGGL((k_tile<4, 1, 1, 2, 2, 16>), grid, dim3(256), 0, s, d);
-      else
-        hipLaunchKernelGGL((k_tile<1, 1, 4, 1, 2, 64>), grid, dim3(256), 0, s, d);
-      rec();
-      hipError_t e = hipGetLastError();
+      if constexpr (P == 0) {
+        if (kclass == MITNC_K_TILE)
+          hipLaunchKernelGGL((k_tile<4, 1, 1, 2, 4, 8>), grid, dim3(256), 0, s, d);
+        else if (kclass == MITNC_K_TALL)
+          hipLaunchKernelGGL((k_tile<4, 1, 1, 2, 1, 16>), grid, dim3(256), 0, s, d);
+        else
+          hipLaunchKernelGGL((k_tile<1, 1, 4, 1, 1, 64>), grid, dim3(256), 0, s, d);
+      } else {
+        if (kclass == MITNC_K_TILE)
+          hipLaunchKernelGGL((k_tile_h<P, 2, 2, 1, 4, 4, 32>), grid, dim3(256), 0, s, d);
+        else if (kclass == MITNC_K_TALL)
+          hipLaunchKernelGGL((k_tile_h<P, 4, 1, 1, 2, 2, 32>), grid, dim3(256), 0, s, d);
+        else
+          hipLaunchKernelGGL((k_tile_h<P, 1, 1, 4, 1, 2, 128>), grid, dim3(256), 0, s, d);
+      }
+      e = hipGetLastError();
+      if (ev1) (void)hipEventRecord(ev1, s);
       if (e != hipSuccess || d.ks_bits == 0) return e;
       d.mode = final_mode;
-      hipLaunchKernelGGL(k_reduce, dim3((unsigned)((c_elems + 255) / 256)), dim3(256), 0, s, d);
+      hipLaunchKernelGGL((k_reduce<P>), dim3((unsigned)((c_elems + 255) / 256)), dim3(256), 0, s, d);
       return hipGetLastError();
     }
     default:
       return hipErrorInvalidValue;
+  }
+  if (ev1) (void)hipEventRecord(ev1, s);
+  return e;
+}
+
+hipError_t launch_step(int kclass, const StepDesc& d, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0) (void)hipEventRecord(ev0, s);
+  switch (d.prec) {
+    case MITNC_C64: return launch_p<0>(kclass, d, s, ev1);
+    case MITNC_CF16: return launch_p<1>(kclass, d, s, ev1);
+    case MITNC_CBF16: return launch_p<2>(kclass, d, s, ev1);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -140,8 +140,10 @@ void validate_path(int n_leaves, const Path& path) {
 
 // Randomised greedy: repeatedly contract the connected pair with the lowest
 // cost size(out) - alpha * (size(a) + size(b)); with temperature > 0 every
-// cost is perturbed by temperature * |cost| * Gumbel noise.
-Path greedy_path(const SymNet& sn, double alpha, double temperature, uint64_t seed) {
+// cost is perturbed by temperature * |cost| * Gumbel noise.  Labels marked in
+// `removed` (sliced indices) are ignored.
+Path greedy_path(const SymNet& sn, double alpha, double temperature, uint64_t seed,
+                 const std::vector<char>* removed) {
   std::mt19937_64 rng(seed);
   std::uniform_real_distribution<double> uni(1e-12, 1.0 - 1e-12);
   size_t n = sn.leaf.size();
@@ -150,7 +152,8 @@ Path greedy_path(const SymNet& sn, double alpha, double temperature, uint64_t se
   std::vector<int> count(sn.n_labels, 0);
   std::vector<std::vector<int>> holders(sn.n_labels);
   for (size_t i = 0; i < n; ++i) {
-    t[i] = sn.leaf[i];
+    for (int x : sn.leaf[i])
+      if (!removed || !(*removed)[x]) t[i].push_back(x);
     alive[i] = 1;
     for (int x : t[i]) {
       count[x]++;

@@ -43,13 +43,32 @@ static void tile_order(uint8_t* dst, std::vector<std::pair<int, uint8_t>> v) {
   for (size_t i = 0; i < v.size(); ++i) dst[i] = v[i].second;
 }
 
-static TileGeom geom_of(int kclass) {
+static TileGeom geom_of(int kclass, int precision) {
+  const bool h = precision != MITNC_C64;
   switch (kclass) {
-    case MITNC_K_TILE: return geom_tile();
-    case MITNC_K_TALL: return geom_tall();
-    case MITNC_K_SPLITK: return geom_splitk();
+    case MITNC_K_TILE: return h ? geom_tile_h() : geom_tile();
+    case MITNC_K_TALL: return h ? geom_tall_h() : geom_tall();
+    case MITNC_K_SPLITK: return h ? geom_splitk_h() : geom_splitk();
     default: return {0, 0, 0};
   }
+}
+
+// 16-bit storage of a complex entry (re in the low half).
+static uint32_t host_f16(float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f); }
+static uint32_t host_bf16(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// Exponent e so that max * 2^-e lies in [2^13, 2^14): two bits of headroom
+// below the FP16 maximum (65504) for slice-to-slice variation.
+int mantissa_exponent(double max_abs) {
+  if (!(max_abs > 0) || !std::isfinite(max_abs)) return 0;
+  int e2;
+  std::frexp(max_abs, &e2);  // max = f * 2^e2, f in [0.5, 1)
+  return (e2 - 1) - 13;
 }
 
 static int choose_class(int mb, int nb, int kb, int bb) {
@@ -63,7 +82,7 @@ static int choose_class(int mb, int nb, int kb, int bb) {
 
 // Builds the descriptor of a step given the operand layouts.
 static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& c_labels_set,
-                       const std::vector<int64_t>* root_layout, int force_kernel) {
+                       const std::vector<int64_t>* root_layout, int force_kernel, int precision) {
   PlanNode& A0 = P->nodes[st.a];
   PlanNode& B0 = P->nodes[st.b];
   std::map<int64_t, int> pa, pb, inC;
@@ -159,7 +178,10 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   if (st.kclass < MITNC_K_SMALL || st.kclass > MITNC_K_SPLITK) fail(MITNC_INVALID_ARG, "unknown kernel class");
   if (st.kclass == MITNC_K_STEM && (d.kb > 4 || d.nb > 2))
     fail(MITNC_UNSUPPORTED, "stem kernel needs at most 4 contracted and 2 new indices");
-  TileGeom g = geom_of(st.kclass);
+  TileGeom g = geom_of(st.kclass, precision);
+  d.prec = precision;
+  d.out_scale = 1.f;
+  d.acc_scale = 1.0;
   d.tm = std::min(g.tm_bits, d.mb);
   d.tn = std::min(g.tn_bits, d.nb);
   d.tk = std::min(g.tk_bits, d.kb);
@@ -175,11 +197,16 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     tile_order(d.b_tile, tb);
     tile_order(d.c_tile, tc);
     // Split K over workgroups when there are too few output tiles to fill the
-    // chip; keep at least 4 k-tiles per workgroup.
+    // chip (Sec. V-B: partition along the common indices); keep at least 4 k
+    // tiles per workgroup.
+    // Workgroup target: two resident 128 x 64 tiles per CU (512 on 256
+    // CUs) fill the chip for TILE; the smaller tiles of TALL / SPLITK fit
+    // four to five per CU.
     int tiles_bits = (d.mb - d.tm) + (d.nb - d.tn) + d.bb;
     int khigh = d.kb - d.tk;
+    int target_bits = st.kclass == MITNC_K_TILE ? 9 : 11;
     int ks = 0;
-    while (tiles_bits + ks < 11 && ks + 2 < khigh) ++ks;
+    while (tiles_bits + ks < target_bits && ks + 2 < khigh) ++ks;
     uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
     while (ks > 0 && (c_elems << ks) * 8 > (256ull << 20)) --ks;
     d.ks_bits = ks;
@@ -238,8 +265,8 @@ static void verify_memory_plan(const mitnc_plan* P, uint64_t n_slices) {
 }
 
 void build_step_for(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& c_labels,
-                    const std::vector<int64_t>* root_layout, int force_kernel) {
-  build_step(P, st, c_labels, root_layout, force_kernel);
+                    const std::vector<int64_t>* root_layout, int force_kernel, int precision) {
+  build_step(P, st, c_labels, root_layout, force_kernel, precision);
 }
 
 mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
@@ -248,7 +275,8 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   if (n < 2) fail(MITNC_UNSUPPORTED, "network needs at least two tensors");
   if (net->path.empty()) fail(MITNC_PATH_INVALID, "no path set");
   validate_path(n, net->path);
-  if (opts.precision != MITNC_C64) fail(MITNC_UNSUPPORTED, "precision not supported by this plan builder");
+  if (opts.precision != MITNC_C64 && opts.precision != MITNC_CF16 && opts.precision != MITNC_CBF16)
+    fail(MITNC_INVALID_ARG, "unknown precision");
   auto P = std::make_unique<mitnc_plan>();
   P->opts = opts;
   P->n_leaves = n;
@@ -293,6 +321,18 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
       h[2 * e] = (float)L.data[e].real();
       h[2 * e + 1] = (float)L.data[e].imag();
     }
+    if (opts.precision != MITNC_C64) {
+      double mx = 0;
+      for (auto& z : L.data) mx = std::max(mx, std::max(std::fabs(z.real()), std::fabs(z.imag())));
+      nd.exp = mantissa_exponent(mx);
+      std::vector<uint32_t> w(L.data.size());
+      for (size_t e = 0; e < L.data.size(); ++e) {
+        float re = (float)std::ldexp(L.data[e].real(), -nd.exp), im = (float)std::ldexp(L.data[e].imag(), -nd.exp);
+        w[e] = opts.precision == MITNC_CF16 ? (host_f16(re) | (host_f16(im) << 16))
+                                            : (host_bf16(re) | (host_bf16(im) << 16));
+      }
+      P->leaf_half.push_back(std::move(w));
+    }
     P->leaf_data.push_back(std::move(h));
     nd.offset = off;
     off = align_up(off + L.data.size() * 8, 256);
@@ -311,7 +351,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
     P->nodes[st.b].parent = st.out;
     std::vector<int64_t> cset;
     for (int x : sym[s].c) cset.push_back(sn.label_id[x]);
-    build_step(P.get(), st, cset, st.root ? &net->output_lsb : nullptr, opts.force_kernel);
+    build_step(P.get(), st, cset, st.root ? &net->output_lsb : nullptr, opts.force_kernel, opts.precision);
     PlanNode& O = P->nodes[st.out];
     O.dmask = P->nodes[st.a].dmask | P->nodes[st.b].dmask;
   }
@@ -395,11 +435,19 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   uint64_t part = 0;
   for (auto& st : P->steps) part = std::max(part, st.part_bytes);
   P->part_bytes = align_up(part, 256);
-  P->off_persist = align_up(P->leaf_bytes, 256);
+  P->result_elems = 1ull << net->output_lsb.size();
+  const bool half = opts.precision != MITNC_C64;
+  // The 16-bit leaf region mirrors the complex64 one at half the offsets;
+  // intermediates keep complex64 sizing so a calibration slice can run in
+  // complex64 inside the same workspace.
+  P->off_leaf_half = align_up(P->leaf_bytes, 256);
+  P->off_persist = align_up(P->off_leaf_half + (half ? P->leaf_bytes / 2 : 0), 256);
   P->off_arena = align_up(P->off_persist + P->persist_bytes, 256);
   P->off_part = align_up(P->off_arena + P->arena_bytes, 256);
-  P->ws_bytes = align_up(P->off_part + P->part_bytes, 256);
-  P->result_elems = 1ull << net->output_lsb.size();
+  P->off_stats = align_up(P->off_part + P->part_bytes, 256);
+  P->off_calib = align_up(P->off_stats + 4 * P->steps.size(), 256);
+  P->ws_bytes = align_up(P->off_calib + (half ? 16 * P->result_elems : 0), 256);
+  P->calibrated = !half;
   verify_memory_plan(P.get(), std::min<uint64_t>(1ull << P->S, 64));
   return P.release();
 }

@@ -23,7 +23,8 @@ struct PlanNode {
   int lo = kLevelNever;         // recompute when a slice-id bit <= lo changes
   int parent = -1;
   int region = 0;               // 0 leaf, 1 persistent, 2 transient, 3 result accumulator
-  uint64_t offset = 0;          // byte offset inside the workspace
+  uint64_t offset = 0;          // byte offset inside the region (complex64 sizing)
+  int exp = 0;                  // FP16/BF16 storage: value = mantissa * 2^exp
 };
 
 struct PlanStep {
@@ -45,8 +46,13 @@ struct mitnc_plan {
   std::vector<mitnc::PlanNode> nodes;        // leaves then step outputs
   std::vector<mitnc::PlanStep> steps;
   std::vector<std::vector<float>> leaf_data; // complex64 interleaved, full (unsliced) leaves
+  std::vector<std::vector<uint32_t>> leaf_half;  // FP16/BF16 mantissas (precision plans)
   uint64_t leaf_bytes = 0, persist_bytes = 0, arena_bytes = 0, part_bytes = 0;
-  uint64_t off_persist = 0, off_arena = 0, off_part = 0, ws_bytes = 0;
+  // Workspace: [complex64 leaves | 16-bit leaves | persistent | arena |
+  //             split-K partials | per-step maxima | calibration result]
+  uint64_t off_leaf_half = 0, off_persist = 0, off_arena = 0, off_part = 0, off_stats = 0, off_calib = 0;
+  uint64_t ws_bytes = 0;
+  bool calibrated = false;
   uint64_t result_elems = 0;
   int max_log2 = 0;
   bool uploaded = false;
@@ -63,6 +69,8 @@ namespace mitnc {
 mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts);
 // Builds the descriptor and output layout of one step (operands P->nodes[st.a],
 // P->nodes[st.b]; output labels c_labels, in root_layout order if given).
+// Exponent e with max * 2^-e in [2^13, 2^14) (0 for max 0).
+int mantissa_exponent(double max_abs);
 void build_step_for(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& c_labels,
-                    const std::vector<int64_t>* root_layout, int force_kernel);
+                    const std::vector<int64_t>* root_layout, int force_kernel, int precision);
 }

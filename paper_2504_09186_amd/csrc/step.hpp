@@ -23,28 +23,45 @@ enum TileCls : uint8_t { TB_M = 0, TB_K = 1, TB_N = 2 };
 inline constexpr uint8_t tile_code(int cls, int idx) { return (uint8_t)((cls << 5) | idx); }
 
 struct StepDesc {
-  const float* A;
-  const float* B;
-  float* C;
+  const void* A;
+  const void* B;
+  void* C;
   double* acc;
   float* part;
+  float* stats;            // optional per-step max |Re|,|Im| of stored outputs (float bits, atomicMax)
   int32_t mb, nb, kb, bb;  // bit counts of m, n, k, batch
   int32_t tm, tn, tk;      // tile bits (tiled kernels)
   int32_t ks_bits;         // K split over 2^ks_bits workgroups (high k bits)
   int32_t mode;            // EpilogueMode
-  int32_t pad_;
+  int32_t prec;            // storage of A, B, C: MITNC_C64, MITNC_CF16 or MITNC_CBF16
+  int32_t step_index;      // slot in stats
+  float out_scale;         // stored C = result * out_scale (a power of two)
+  double acc_scale;        // EPI_ACC64: acc += result * acc_scale (a power of two)
+  // Position tables; kernels copy them to LDS once (TAB_BYTES bytes from am).
   uint8_t am[32], ak[32], ab[32];
   uint8_t bk[32], bn[32], bbt[32];
   uint8_t cm[32], cn[32], cb[32];
   uint8_t a_tile[16], b_tile[16], c_tile[16];  // tile bits sorted by address position
 };
 
-// Tile geometry of the MFMA kernel classes.
+// Byte offsets of the tables relative to StepDesc::am.
+enum TabOff : int {
+  T_AM = 0, T_AK = 32, T_AB = 64, T_BK = 96, T_BN = 128, T_BB = 160,
+  T_CM = 192, T_CN = 224, T_CB = 256, T_ATILE = 288, T_BTILE = 304, T_CTILE = 320,
+  TAB_BYTES = 336
+};
+
+// Tile geometry of the MFMA kernel classes (bits of the m, n, k tile).
 struct TileGeom {
   int tm_bits, tn_bits, tk_bits;
 };
-inline constexpr TileGeom geom_tile() { return {6, 6, 4}; }    // 64 x 64 complex, k 16
+// complex64 (3M split on FP32 MFMA)
+inline constexpr TileGeom geom_tile() { return {7, 6, 3}; }    // 128 x 64 complex, k 8
 inline constexpr TileGeom geom_tall() { return {7, 4, 4}; }    // 128 x 16, k 16
 inline constexpr TileGeom geom_splitk() { return {4, 4, 6}; }  // 16 x 16, k 64 (4 waves split k)
+// complex FP16 / BF16 (4M split on 16x16x32 MFMA)
+inline constexpr TileGeom geom_tile_h() { return {7, 6, 5}; }    // 128 x 64, k 32
+inline constexpr TileGeom geom_tall_h() { return {7, 4, 5}; }    // 128 x 16, k 32
+inline constexpr TileGeom geom_splitk_h() { return {4, 4, 7}; }  // 16 x 16, k 128 (4 waves split k)
 
 }  // namespace mitnc

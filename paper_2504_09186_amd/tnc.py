@@ -61,8 +61,8 @@ class Network:
             self.h = None
 
     def path_search(self, seed: int = 0, trials: int = 32, max_log2: int = 30, min_sliced: int = 0,
-                    max_sliced: int = 40) -> None:
-        o = mitnc_search_opts(seed, trials, max_log2, min_sliced, max_sliced)
+                    max_sliced: int = 40, keep_slicing: bool = False) -> None:
+        o = mitnc_search_opts(seed, trials, max_log2, min_sliced, max_sliced, 1 if keep_slicing else 0)
         call("mitnc_path_search", self.h, C.byref(o))
 
     def path(self) -> List[Tuple[int, int]]:
@@ -142,6 +142,19 @@ class Plan:
         call("mitnc_plan_timing_read", self.h, *ptrs)
         return tuple(arrs)
 
+    def calibrate(self, slice_begin: int = 0, slice_end: int = 1, stream=None) -> None:
+        """FP16/BF16 plans: choose the per-tensor exponents from a complex64
+        run of the given slices."""
+        call("mitnc_calibrate", self.h, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+             int(slice_begin), int(slice_end), _stream_handle(stream))
+
+    def step_maxima(self, reset: bool = False, stream=None) -> np.ndarray:
+        """Largest stored |Re|, |Im| per step since the last reset (FP16/BF16)."""
+        out = np.zeros(self.stats.n_steps, dtype=np.float32)
+        call("mitnc_step_maxima", self.h, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+             out.ctypes.data_as(C.POINTER(C.c_float)), 1 if reset else 0, _stream_handle(stream))
+        return out
+
     def execute(self, acc, slice_begin: int = 0, slice_end: Optional[int] = None, stream=None):
         """acc += sum of slices [slice_begin, slice_end) (complex128 device tensor)."""
         import torch
@@ -156,43 +169,52 @@ class Plan:
         return acc
 
 
+_ELEM_BYTES = {_lib.MITNC_C64: 8, _lib.MITNC_CF16: 4, _lib.MITNC_CBF16: 4}
+
+
 def contract(a, la: Sequence[int], b, lb: Sequence[int], lc: Sequence[int], kernel: int = -1,
-             stream=None):
-    """One pairwise contraction on the GPU.  a, b: contiguous complex64 device
-    tensors with 2^len(la) / 2^len(lb) entries; address bit i carries label
-    la[i] (LSB first).  Returns C (complex64) with address bits lc."""
+             precision: int = _lib.MITNC_C64, out_scale: float = 1.0, stream=None):
+    """One pairwise contraction on the GPU.  a, b: contiguous device tensors
+    holding 2^len(la) / 2^len(lb) complex entries in the storage of
+    `precision` (complex64, or interleaved FP16/BF16 halves in any 4-byte-per-
+    entry dtype); address bit i carries label la[i] (LSB first).  Returns C
+    with address bits lc (complex64 tensor, or int32 words of 16-bit pairs),
+    scaled by out_scale."""
     import torch
-    lib = _lib.load()
-    la = (C.c_int64 * max(1, len(la)))(*la), len(la)
-    lb = (C.c_int64 * max(1, len(lb)))(*lb), len(lb)
-    lcv = (C.c_int64 * max(1, len(lc)))(*lc), len(lc)
+    eb = _ELEM_BYTES[precision]
+    la_ = (C.c_int64 * max(1, len(la)))(*la)
+    lb_ = (C.c_int64 * max(1, len(lb)))(*lb)
+    lc_ = (C.c_int64 * max(1, len(lc)))(*lc)
     need = C.c_size_t()
-    call("mitnc_contract", None, la[1], la[0], None, lb[1], lb[0], None, lcv[1], lcv[0], kernel, None, 0,
-         C.byref(need), None)
-    out = torch.empty(1 << lcv[1], dtype=torch.complex64, device=a.device)
+    call("mitnc_contract", None, len(la), la_, None, len(lb), lb_, None, len(lc), lc_, precision,
+         C.c_float(out_scale), kernel, None, 0, C.byref(need), None)
+    for t, r in ((a, len(la)), (b, len(lb))):
+        if not t.is_contiguous() or t.numel() * t.element_size() != (1 << r) * eb:
+            raise ValueError("operand size does not match its labels and precision")
+    if precision == _lib.MITNC_C64:
+        out = torch.empty(1 << len(lc), dtype=torch.complex64, device=a.device)
+    else:
+        out = torch.empty(1 << len(lc), dtype=torch.int32, device=a.device)
     work = torch.empty(max(256, need.value), dtype=torch.uint8, device=a.device) if need.value else None
-    if a.dtype != torch.complex64 or b.dtype != torch.complex64:
-        raise ValueError("operands must be complex64")
-    if a.numel() != (1 << la[1]) or b.numel() != (1 << lb[1]):
-        raise ValueError("operand sizes do not match their labels")
-    call("mitnc_contract", C.c_void_p(a.data_ptr()), la[1], la[0], C.c_void_p(b.data_ptr()), lb[1], lb[0],
-         C.c_void_p(out.data_ptr()), lcv[1], lcv[0], kernel,
+    call("mitnc_contract", C.c_void_p(a.data_ptr()), len(la), la_, C.c_void_p(b.data_ptr()), len(lb), lb_,
+         C.c_void_p(out.data_ptr()), len(lc), lc_, precision, C.c_float(out_scale), kernel,
          C.c_void_p(work.data_ptr()) if work is not None else None, need.value, None,
          _stream_handle(stream))
-    del lib
     return out
 
 
 def amplitudes(circuit, spec, batch_bits=None, seed: int = 0, trials: int = 32, max_log2: int = 30,
                min_sliced: int = 0, slices: Optional[Tuple[int, int]] = None, reuse: bool = True,
-               device="cuda"):
+               precision: int = _lib.MITNC_C64, device="cuda"):
     """Requested amplitudes (complex128 device tensor in the canonical result
     order), or the partial sum over ``slices = (begin, end)``."""
     net = Network(circuit, spec, batch_bits)
     net.path_search(seed=seed, trials=trials, max_log2=max_log2, min_sliced=min_sliced)
-    plan = Plan(net, reuse=reuse)
+    plan = Plan(net, precision=precision, reuse=reuse)
     plan.upload(device)
-    acc = plan.new_result(device)
     s0, s1 = slices if slices is not None else (0, plan.n_slices)
+    if precision != _lib.MITNC_C64:
+        plan.calibrate(s0, min(s1, s0 + 2))
+    acc = plan.new_result(device)
     plan.execute(acc, s0, s1)
     return acc

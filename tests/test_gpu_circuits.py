@@ -112,3 +112,34 @@ def test_forced_kernel_class(force):
     got, _ = _run(net, force=force)
     ref = oracle.sv_amplitudes(c, spec).reshape(-1)
     assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_precision_form_circuit(prec):
+    """Scaled complex FP16 / BF16 form on a 4x4 lattice (16 open amplitudes):
+    calibrated on slices 0-1, all slices summed in FP64.  Reported and bounded:
+    relative L2 error and linear-XEB fidelity loss against the FP64 oracle.
+    FP16 (11-bit significand) is held to the 1e-3 XEB-loss target; BF16
+    (8-bit significand, about 8x coarser) to 1e-2."""
+    require_gpu()
+    import torch
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(4, 4, 10, seed=81)
+    spec = synth.output_spec(16, [12, 13, 14, 15], seed=82)
+    net = _lib_net(c, spec)
+    net.path_search(seed=83, trials=8, max_log2=10, min_sliced=4)
+    plan = tnc.Plan(net, precision=prec)
+    plan.upload()
+    plan.calibrate(0, 2)
+    acc = plan.new_result()
+    plan.execute(acc)
+    torch.cuda.synchronize()
+    got = acc.cpu().numpy()
+    mx = plan.step_maxima()
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    rel = oracle.rel_l2(got, ref)
+    xeb_loss = abs(1.0 - oracle.xeb_ratio(got, ref))
+    print(f"precision {prec}: rel-L2 {rel:.3e}, XEB loss {xeb_loss:.3e}, max stored {mx.max():.3e}")
+    assert np.all(np.isfinite(mx)) and mx.max() < 65504
+    assert rel < (5e-3 if prec == 1 else 5e-2)
+    assert xeb_loss < (1e-3 if prec == 1 else 1e-2)

@@ -2,8 +2,13 @@
 
 Each kernel class gets random bit layouts (the permutation is fused into the
 loads), ragged tiles, batch bits and degenerate ranks.  Bound: the elementwise
-GEMM error bound of Eq. (3), |C^ - C| <= gamma_n |A||B|, with n = 2K + 2 for
-complex FP32 arithmetic on the complex64 inputs actually fed to the kernel.
+GEMM error bound of Eq. (3), |C^ - C| <= gamma_K |A||B|, applied to the
+complex arithmetic the kernels use, on the complex64 inputs actually fed to
+them.  The MFMA kernels use the 3M split: Re C = T1 - T2, Im C = T3 - T1 - T2
+with T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); each real product has
+error <= gamma_{K+2} times its absolute product, |Ar||Br| + |Ai||Bi| <= |a||b|
+and (|Ar| + |Ai|)(|Br| + |Bi|) <= 2|a||b|, so |C^ - C| <= 6 gamma_{K+4} |A||B|
+covers them and the direct 4-multiply form of the other kernels.
 """
 import numpy as np
 import pytest
@@ -42,7 +47,7 @@ def _run(mb, nb, kb, bb, kernel, seed):
     torch.cuda.synchronize()
     got = c.cpu().numpy().astype(np.complex128)
     ref = ref_contract(a, la, b, lb, lc)
-    bound = ref_contract(a, la, b, lb, lc, absval=True).real * gamma(2 * (1 << kb) + 2) * 2.0
+    bound = ref_contract(a, la, b, lb, lc, absval=True).real * gamma((1 << kb) + 4) * 6.0
     err = np.abs(got - ref)
     assert np.all(err <= bound + 1e-30), f"max err/bound {np.max(err / (bound + 1e-30))}"
     rel = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
@@ -91,3 +96,51 @@ def test_splitk_long_k_accuracy():
     below a single FP32 chain over K."""
     rel = _run(3, 3, 22, 0, SPLITK, seed=4242)
     assert rel < 2e-6
+
+
+# ---------------------------------------------------------------- FP16 / BF16 storage
+def _to_half_words(x, prec):
+    """complex entries -> int32 words of two 16-bit halves (re low)."""
+    import torch
+    re = torch.from_numpy(np.ascontiguousarray(x.real.astype(np.float32)))
+    im = torch.from_numpy(np.ascontiguousarray(x.imag.astype(np.float32)))
+    dt = torch.float16 if prec == 1 else torch.bfloat16
+    h = torch.stack([re.to(dt), im.to(dt)], dim=1).contiguous()  # rounding to nearest even
+    back = h.float().numpy()
+    return h.view(torch.int32).reshape(-1).clone(), back[:, 0] + 1j * back[:, 1]
+
+
+def _from_half_words(w, prec):
+    import torch
+    dt = torch.float16 if prec == 1 else torch.bfloat16
+    h = w.cpu().view(dt).reshape(-1, 2).float().numpy()
+    return h[:, 0] + 1j * h[:, 1]
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("mb,nb,kb,bb,kernel", [
+    (8, 8, 7, 0, TILE), (9, 3, 6, 0, TALL), (3, 3, 14, 0, SPLITK), (10, 2, 2, 0, STEM), (3, 2, 4, 1, SMALL),
+    (7, 6, 9, 1, TILE), (0, 0, 9, 0, SPLITK), (5, 5, 0, 0, TILE)])
+def test_half_storage(prec, mb, nb, kb, bb, kernel):
+    """16-bit storage, FP32 accumulate.  Inputs are mantissas of values around
+    2^-30 (scaled by 2^30 into range); the output is rescaled by out_scale.
+    Bound: FP32 accumulation error 6 gamma_{K+4} |A||B| plus one rounding of
+    the output (2^-11 FP16, 2^-8 BF16 relative)."""
+    require_gpu()
+    import torch
+    from paper_2504_09186_amd import tnc
+    la, lb, lc, a, b = _case(mb, nb, kb, bb, 77 + mb + 10 * nb + 100 * kb + prec)
+    a = a.astype(np.complex128) * 2.0 ** -30 * 2.0 ** 30  # mantissas of 2^-30-sized values
+    wa, ar = _to_half_words(a, prec)
+    wb, br = _to_half_words(b.astype(np.complex128), prec)
+    scale = 2.0 ** -3
+    print(f"half contract m{mb} n{nb} k{kb} b{bb} kernel {kernel} prec {prec}", flush=True)
+    c = tnc.contract(wa.cuda(), la, wb.cuda(), lb, lc, kernel=kernel, precision=prec, out_scale=scale)
+    torch.cuda.synchronize()
+    got = _from_half_words(c, prec) / scale
+    ref = ref_contract(ar, la, br, lb, lc)
+    absab = ref_contract(ar, la, br, lb, lc, absval=True).real
+    u_out = 2.0 ** -11 if prec == 1 else 2.0 ** -8
+    bound = absab * gamma((1 << kb) + 4) * 6.0 + np.abs(ref) * u_out * 1.01 + 1e-30
+    err = np.abs(got - ref)
+    assert np.all(err <= bound), f"max err/bound {np.max(err / bound)}"

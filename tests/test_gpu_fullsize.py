@@ -1,0 +1,81 @@
+"""Full-size parity: the bench workload (5x6 lattice, 14 cycles, 64
+amplitudes, 256 slices, max intermediate <= 2^26) in the launch configuration
+bench.py times, against values written by tests/golden/make_golden.py with the
+oracle only.
+
+* All 256 slices with the bench plan: the sum is the 64 amplitudes, which do
+  not depend on the plan; compared within 1e-5 relative L2.
+* Slices 0..15 of the oracle's own 8-index slicing, one by one: the library
+  keeps that slicing and searches its own path for it.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_amplitudes.json")
+
+
+def _golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden file not generated")
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    to_c = lambda v: np.array([a + 1j * b for a, b in v])  # noqa: E731
+    return g, to_c
+
+
+def _workload():
+    c = synth.lattice_circuit(5, 6, 14, seed=1001)
+    spec = synth.output_spec(30, list(range(24, 30)), seed=2001)
+    return c, spec
+
+
+def test_config2_all_slices_bench_plan():
+    require_gpu()
+    import torch
+    from paper_2504_09186_amd import tnc
+    g, to_c = _golden()
+    c, spec = _workload()
+    net = tnc.Network(c, spec)
+    net.path_search(seed=3001, trials=64, max_log2=26, min_sliced=8, max_sliced=8)
+    plan = tnc.Plan(net)
+    assert plan.n_slices == 256
+    plan.upload()
+    acc = plan.new_result()
+    print("config 2: all 256 slices, bench plan", flush=True)
+    plan.execute(acc)
+    torch.cuda.synchronize()
+    got = acc.cpu().numpy()
+    ref = to_c(g["amplitudes"])
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"rel-L2 {rel:.3e}")
+    assert rel <= 1e-5
+
+
+def test_config2_oracle_slicing_first_16_slices():
+    require_gpu()
+    import torch
+    from paper_2504_09186_amd import tnc
+    g, to_c = _golden()
+    c, spec = _workload()
+    net = tnc.Network(c, spec)
+    net.set_slicing(g["oracle_sliced_labels"])
+    net.path_search(seed=3001, trials=32, max_log2=28, min_sliced=8, max_sliced=8, keep_slicing=True)
+    assert net.slicing() == g["oracle_sliced_labels"]
+    plan = tnc.Plan(net)
+    plan.upload()
+    for s in range(16):
+        acc = plan.new_result()
+        print(f"config 2: oracle slicing, slice {s}", flush=True)
+        plan.execute(acc, s, s + 1)
+        torch.cuda.synchronize()
+        got = acc.cpu().numpy()
+        ref = to_c(g["slice_results"][str(s)])
+        assert np.linalg.norm(got - ref) <= 1e-5 * max(np.linalg.norm(ref), 1e-30), f"slice {s}"
