@@ -5,9 +5,14 @@ Workload: the 5x6-qubit (30 qubits), 14-cycle random lattice circuit
 (sqrt-X/Y/W + fSim(pi/2, pi/6), ABCD couplers, seed 1001), 64 amplitudes
 (qubits 24-29 open, the other 24 output bits fixed at random, seed 2001),
 randomised-greedy path with the largest intermediate <= 2^26 entries and 8
-sliced indices (256 slices), complex64 storage with FP32 MFMA arithmetic and
-an FP64 cross-slice sum.  One step = all 256 slices (the whole sliced tree),
-inputs resident in HBM.  Prints one JSON line.
+sliced indices (256 slices).  One step = all 256 slices (the whole sliced
+tree, FP64 cross-slice sum), inputs resident in HBM.
+
+Two forms are timed on the same plan: complex64 (FP32 MFMA; the headline
+`value`) and scaled complex FP16 (FP16 MFMA, FP32 accumulate, per-tensor
+power-of-two exponents calibrated on slices 0-1), each with its amplitude
+error against the oracle's values stored in tests/golden.  Prints one JSON
+line.
 """
 import argparse
 import json
@@ -19,10 +24,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "slices/s + % MFMA peak, complex64 vs scaled complex-FP16 at stated amp error"
-PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK = {"c64": 157.3, "cf16": 2500.0}  # dense MFMA TFLOP/s: FP32, FP16
 PEAK_HBM_GBS = 8000.0
 CLASS_NAMES = ["small", "stem", "tile", "tall", "splitk"]
 MFMA_CLASSES = (2, 3)
+GOLDEN = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.json")
 
 
 def workload():
@@ -32,11 +38,86 @@ def workload():
     return c, spec
 
 
+def golden_amplitudes():
+    import numpy as np
+    if not os.path.exists(GOLDEN):
+        return None
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    return np.array([a + 1j * b for a, b in g["amplitudes"]])
+
+
+def amp_error(got, ref):
+    import numpy as np
+    if ref is None:
+        return None
+    p = np.abs(ref) ** 2
+    p /= p.sum()
+    q = np.abs(got) ** 2
+    q /= q.sum()
+    xeb = (ref.size * np.sum(p * q) - 1.0) / (ref.size * np.sum(p * p) - 1.0)
+    return {"rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), "xeb_loss": float(abs(1.0 - xeb)),
+            "against": "FP64 oracle, all 64 amplitudes"}
+
+
+def run_form(net, precision, steps, warmup, label):
+    import torch
+
+    from paper_2504_09186_amd import tnc
+    plan = tnc.Plan(net, precision=precision)
+    st = plan.stats
+    n_slices = plan.n_slices
+    plan.upload()
+    if precision != 0:
+        plan.calibrate(0, 2)
+    acc = plan.new_result()
+    for _ in range(warmup):
+        acc.zero_()
+        plan.execute(acc)
+    # one untimed step with event timing on allocates the event pool
+    plan.timing(True)
+    acc.zero_()
+    plan.execute(acc)
+    torch.cuda.synchronize()
+    plan.timing(True)  # reset: record the timed region only
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        acc.zero_()
+        plan.execute(acc)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, launches, flops, nbytes = plan.timing_read()
+    plan.timing(False)
+    result = acc.cpu().numpy()
+    overflow = None
+    if precision != 0:
+        overflow = bool(float(plan.step_maxima().max()) >= 65504.0)
+    dom = int(max(range(5), key=lambda k: ms[k]))
+    peak = PEAK[label]
+    if dom in MFMA_CLASSES:
+        achieved = flops[dom] / (ms[dom] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None}
+    else:
+        achieved = nbytes[dom] / (ms[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    roof["kernel"] = CLASS_NAMES[dom]
+    roof["launches"] = int(launches[dom])
+    roof["avg_launch_ms"] = ms[dom] / max(1.0, launches[dom])
+    total_flops = st.flops_reused_slice * n_slices * steps
+    return {
+        "value": n_slices * steps / el, "unit": "slices/s", "ms_per_step": el / steps * 1e3,
+        "tflops": total_flops / el / 1e12, "mfma_frac": total_flops / el / 1e12 / peak,
+        "kernel_ms_by_class": {CLASS_NAMES[k]: ms[k] / steps for k in range(5)},
+        "roofline": roof, "n_slices": n_slices, "stats": st, "result": result, "fp16_overflow": overflow,
+    }
+
+
 def cpu_baseline(c, spec, path, sliced, seconds: float):
     """The FP64 oracle, as it stands, on the same path and slicing: slices
     0, 1, 2, ... until about `seconds` of host time are spent."""
-    import numpy as np
-
     import oracle
     onet = oracle.build_network(c, spec)
     done = 0
@@ -49,10 +130,10 @@ def cpu_baseline(c, spec, path, sliced, seconds: float):
     el = time.perf_counter() - t0
     try:
         from threadpoolctl import threadpool_info
-        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
+        info = threadpool_info()
+        cores = max(int(i.get("num_threads", 1)) for i in info) if info else 1
     except Exception:
         cores = os.cpu_count() or 1
-    del np
     return {"value": done / el, "unit": "slices/s", "cores": cores, "kind": "oracle",
             "sample": f"slices 0..{done - 1} of the same 256-slice workload, same path and sliced "
                       f"indices, numpy complex128 ({el:.1f} s)"}
@@ -66,6 +147,7 @@ def main():
     ap.add_argument("--trials", type=int, default=64, help="path-search trials")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -80,60 +162,32 @@ def main():
     c, spec = workload()
     net = tnc.Network(c, spec)
     net.path_search(seed=3001, trials=args.trials, max_log2=26, min_sliced=8, max_sliced=8)
-    plan = tnc.Plan(net)
-    st = plan.stats
-    n_slices = plan.n_slices
-    plan.upload()
-    acc = plan.new_result()
+    ref = golden_amplitudes()
 
-    for _ in range(args.warmup):
-        acc.zero_()
-        plan.execute(acc)
-    # one untimed step with event timing on allocates the event pool
-    plan.timing(True)
-    acc.zero_()
-    plan.execute(acc)
-    torch.cuda.synchronize()
-    plan.timing(True)  # reset: record the timed region only
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        acc.zero_()
-        plan.execute(acc)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms, launches, flops, nbytes = plan.timing_read()
-    plan.timing(False)
-
-    slices_per_s = n_slices * args.steps / el
-    dom = int(max(range(5), key=lambda k: ms[k]))
-    if dom in MFMA_CLASSES:
-        achieved = flops[dom] / (ms[dom] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None}
-    else:
-        achieved = nbytes[dom] / (ms[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["kernel"] = CLASS_NAMES[dom]
-    roof["launches"] = int(launches[dom])
-    roof["avg_launch_ms"] = ms[dom] / max(1.0, launches[dom])
-    total_flops = st.flops_reused_slice * n_slices * args.steps
+    r64 = run_form(net, 0, args.steps, args.warmup, "c64")
+    st = r64["stats"]
     out = {
-        "metric": METRIC, "value": slices_per_s, "unit": "slices/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "metric": METRIC, "value": r64["value"], "unit": "slices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": "rqc-5x6-14cyc-64amp-256slices", "qubits": 30, "cycles": 14,
-                   "open_qubits": 6, "slices_per_step": n_slices, "max_log2_elems": st.max_log2_elems,
+                   "open_qubits": 6, "slices_per_step": r64["n_slices"], "max_log2_elems": st.max_log2_elems,
                    "steps_per_slice": st.n_steps, "flops_per_slice": st.flops_reused_slice,
-                   "precision": "complex64, FP32 MFMA, FP64 cross-slice sum"},
-        "tflops": total_flops / el / 1e12,
-        "mfma_frac": total_flops / el / 1e12 / PEAK_FP32_MFMA_TFLOPS,
-        "kernel_ms_by_class": {CLASS_NAMES[k]: ms[k] / args.steps for k in range(5)},
-        "roofline": roof,
+                   "precision": "complex64, FP32 MFMA (3M), FP64 cross-slice sum"},
+        "tflops": r64["tflops"], "mfma_frac": r64["mfma_frac"],
+        "amp_error": amp_error(r64["result"], ref),
+        "kernel_ms_by_class": r64["kernel_ms_by_class"],
+        "roofline": r64["roofline"],
     }
+    if not args.no_fp16:
+        r16 = run_form(net, 1, args.steps, args.warmup, "cf16")
+        out["cf16"] = {"value": r16["value"], "unit": "slices/s", "ms_per_step": r16["ms_per_step"],
+                       "tflops": r16["tflops"], "mfma_frac": r16["mfma_frac"],
+                       "amp_error": amp_error(r16["result"], ref), "fp16_overflow": r16["fp16_overflow"],
+                       "kernel_ms_by_class": r16["kernel_ms_by_class"], "roofline": r16["roofline"],
+                       "precision": "complex FP16 storage, FP16 MFMA (4M) with FP32 accumulate, "
+                                    "per-tensor 2^e scaling, FP64 cross-slice sum"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, spec, net.path(), net.slicing(), args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -390,7 +390,7 @@ mitnc_plan::~mitnc_plan() {
 // or complex64 for a calibration slice of an FP16/BF16 plan).
 static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t slice, double* acc,
                              hipStream_t s, int prec, bool stats) {
-  StepDesc d = st.d;
+  StepDesc d = (prec == MITNC_C64 && P->opts.precision != MITNC_C64) ? st.d64 : st.d;
   const bool half = prec != MITNC_C64;
   auto ptr = [&](int node) -> char* {
     const PlanNode& nd = P->nodes[node];

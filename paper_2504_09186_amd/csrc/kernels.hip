@@ -727,6 +727,14 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1
     case MITNC_K_TILE:
     case MITNC_K_TALL:
     case MITNC_K_SPLITK: {
+      // The descriptor's tile bits must fit the tile the kernel was compiled
+      // for (LDS slots are sized from it).
+      const TileGeom g = P == 0 ? (kclass == MITNC_K_TILE ? geom_tile() : kclass == MITNC_K_TALL ? geom_tall() : geom_splitk())
+                                : (kclass == MITNC_K_TILE ? geom_tile_h()
+                                   : kclass == MITNC_K_TALL ? geom_tall_h() : geom_splitk_h());
+      if (d.tm > g.tm_bits || d.tn > g.tn_bits || d.tk > g.tk_bits || d.tm < 0 || d.tn < 0 || d.tk < 0 ||
+          d.ks_bits > d.kb - d.tk)
+        return hipErrorInvalidValue;
       const int final_mode = d.mode;
       if (d.ks_bits > 0) d.mode = EPI_PARTIAL;
       dim3 grid((unsigned)(1ull << ((d.mb - d.tm) + (d.nb - d.tn))), (unsigned)(1ull << d.ks_bits),

@@ -351,7 +351,16 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
     P->nodes[st.b].parent = st.out;
     std::vector<int64_t> cset;
     for (int x : sym[s].c) cset.push_back(sn.label_id[x]);
-    build_step(P.get(), st, cset, st.root ? &net->output_lsb : nullptr, opts.force_kernel, opts.precision);
+    if (opts.precision != MITNC_C64) {
+      // Calibration slices run in complex64, whose tiles differ: keep both.
+      build_step(P.get(), st, cset, st.root ? &net->output_lsb : nullptr, opts.force_kernel, MITNC_C64);
+      st.d64 = st.d;
+      const uint64_t pb64 = st.part_bytes;
+      build_step(P.get(), st, cset, st.root ? &net->output_lsb : nullptr, opts.force_kernel, opts.precision);
+      st.part_bytes = std::max(st.part_bytes, pb64);
+    } else {
+      build_step(P.get(), st, cset, st.root ? &net->output_lsb : nullptr, opts.force_kernel, opts.precision);
+    }
     PlanNode& O = P->nodes[st.out];
     O.dmask = P->nodes[st.a].dmask | P->nodes[st.b].dmask;
   }

@@ -33,8 +33,9 @@ struct PlanStep {
   bool root = false;
   int kclass = MITNC_K_SMALL;
   StepDesc d{};                  // pointer fields filled at launch
+  StepDesc d64{};                // FP16/BF16 plans: complex64 geometry for calibration slices
   double flops = 0, bytes = 0;
-  uint64_t part_bytes = 0;
+  uint64_t part_bytes = 0;       // split-K partials, max over d and d64
 };
 
 }  // namespace mitnc

@@ -143,3 +143,25 @@ def test_precision_form_circuit(prec):
     assert np.all(np.isfinite(mx)) and mx.max() < 65504
     assert rel < (5e-3 if prec == 1 else 5e-2)
     assert xeb_loss < (1e-3 if prec == 1 else 1e-2)
+
+
+@pytest.mark.parametrize("force", [2, 3, 4])
+def test_precision_form_forced_tiles(force):
+    """FP16 plans whose every step runs on one MFMA tile class: the complex64
+    calibration slice uses tiles of the complex64 geometry, the FP16 run its
+    own (regression for a calibration launched with FP16 tile descriptors)."""
+    require_gpu()
+    import torch
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(4, 4, 8, seed=91)
+    spec = synth.output_spec(16, [14, 15], seed=92)
+    net = _lib_net(c, spec)
+    net.path_search(seed=93, trials=4, max_log2=30, min_sliced=3)
+    plan = tnc.Plan(net, precision=1, force_kernel=force)
+    plan.upload()
+    plan.calibrate(0, 1)
+    acc = plan.new_result()
+    plan.execute(acc)
+    torch.cuda.synchronize()
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    assert oracle.rel_l2(acc.cpu().numpy(), ref) < 5e-3
