@@ -122,14 +122,20 @@ __device__ __forceinline__ float epilogue_store(const StepDesc& d, uint64_t addr
   }
 }
 
-// Per-step maximum of stored magnitudes: wave reduction, one atomic per wave.
-// Every lane of the wave must call it (no early returns before it).
+// Per-step maximum of stored magnitudes: wave and workgroup reduction, one
+// atomic per workgroup (grids are capped so that one address sees few of
+// them).  Every thread of the workgroup must call it.
 __device__ __forceinline__ void record_max(const StepDesc& d, float m) {
   if (!d.stats) return;
+  __shared__ float red[4];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-  if ((threadIdx.x & 63) == 0 && m > 0.f)
-    atomicMax(reinterpret_cast<unsigned int*>(d.stats) + d.step_index, __float_as_uint(m));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    if (m > 0.f) atomicMax(reinterpret_cast<unsigned int*>(d.stats) + d.step_index, __float_as_uint(m));
+  }
 }
 
 // ---------------------------------------------------------------- small steps
@@ -205,9 +211,9 @@ __global__ __launch_bounds__(256) void k_stem(StepDesc d) {
   if (t < N) nc[t] = (uint32_t)scatter_bits(t, tab + T_CN, NB);
   __syncthreads();
   const int lowb = d.mb < 8 ? d.mb : 8;
+  const uint64_t n_mhi = 1ull << (d.mb - lowb);
   float mx = 0.f;
-  if (t < (1 << lowb)) {
-    const uint64_t mhi = blockIdx.x;  // high m bits (uniform)
+  for (uint64_t mhi = blockIdx.x; t < (1 << lowb) && mhi < n_mhi; mhi += gridDim.x) {  // high m bits (uniform)
     uint64_t aoff = scatter_bits(mhi, tab + T_AM + lowb, d.mb - lowb) + scatter_bits(batch, tab + T_AB, d.bb);
     uint64_t coff = scatter_bits(mhi, tab + T_CM + lowb, d.mb - lowb) + scatter_bits(batch, tab + T_CB, d.bb);
     aoff += scatter_bits(t, tab + T_AM, lowb);
@@ -660,9 +666,8 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
 template <int P>
 __global__ __launch_bounds__(256) void k_reduce(StepDesc d) {
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
-  const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   float mx = 0.f;
-  if (c < c_elems) {
+  for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < c_elems; c += (uint64_t)gridDim.x * 256) {
     const float2* part = reinterpret_cast<const float2*>(d.part);
     const uint64_t splits = 1ull << d.ks_bits;
     double sx = 0, sy = 0;
@@ -680,11 +685,11 @@ __global__ __launch_bounds__(256) void k_reduce(StepDesc d) {
     } else if constexpr (P == 0) {
       const float2 v = make_float2((float)sx, (float)sy);
       reinterpret_cast<float2*>(d.C)[c] = v;
-      mx = absmax2(v);
+      mx = fmaxf(mx, absmax2(v));
     } else {
       const float2 v = make_float2((float)(sx * d.out_scale), (float)(sy * d.out_scale));
       reinterpret_cast<uint32_t*>(d.C)[c] = pack<P>(v);
-      mx = absmax2(v);
+      mx = fmaxf(mx, absmax2(v));
     }
   }
   record_max(d, mx);
@@ -720,7 +725,8 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1
     }
     case MITNC_K_STEM: {
       const int lowb = d.mb < 8 ? d.mb : 8;
-      dim3 grid((unsigned)(1ull << (d.mb - lowb)), (unsigned)(1ull << d.bb));
+      const uint64_t n_mhi = 1ull << (d.mb - lowb);
+      dim3 grid((unsigned)(n_mhi < 16384 ? n_mhi : 16384), (unsigned)(1ull << d.bb));
       e = launch_stem<P>(d, grid, s);
       break;
     }
@@ -758,7 +764,8 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1
       if (ev1) (void)hipEventRecord(ev1, s);
       if (e != hipSuccess || d.ks_bits == 0) return e;
       d.mode = final_mode;
-      hipLaunchKernelGGL((k_reduce<P>), dim3((unsigned)((c_elems + 255) / 256)), dim3(256), 0, s, d);
+      const uint64_t rb = (c_elems + 255) / 256;
+      hipLaunchKernelGGL((k_reduce<P>), dim3((unsigned)(rb < 8192 ? rb : 8192)), dim3(256), 0, s, d);
       return hipGetLastError();
     }
     default:
