@@ -142,6 +142,8 @@ typedef struct mitnc_plan_opts {
   int32_t reuse;
   uint64_t cache_budget_bytes;
   int32_t force_kernel;
+  int32_t differentiable; /* 1: keep every node's value for the reverse pass
+                             (mitnc_backward); complex64 only */
 } mitnc_plan_opts;
 
 int32_t mitnc_plan_create(const mitnc_network* net, const mitnc_plan_opts* opts, mitnc_plan** out);
@@ -159,6 +161,9 @@ typedef struct mitnc_plan_stats {
   double bytes_reused_slice;
   int32_t steps_by_class[8];  /* step count per kernel class */
   double flops_by_class[8];   /* full-slice flops per kernel class */
+  int32_t n_grad_gates;       /* differentiable plans: single-qubit gates (gradient entries / 4) */
+  int32_t n_reverse_ops;      /* adjoint contractions per slice */
+  double flops_reverse_slice; /* real flops of the reverse pass of one slice */
 } mitnc_plan_stats;
 int32_t mitnc_plan_query(const mitnc_plan* plan, mitnc_plan_stats* stats);
 
@@ -196,6 +201,27 @@ int32_t mitnc_calibrate(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t sl
  * them if reset != 0.  A value >= 65504 means FP16 overflow. */
 int32_t mitnc_step_maxima(mitnc_plan* plan, void* ws, size_t ws_bytes, float* out, int32_t reset,
                           void* stream);
+
+/* Differentiation form (not in the paper; see the oracle's definition):
+ * for slices slice_begin .. slice_end-1, recomputes the forward contraction
+ * of the slice (nodes whose sliced indices did not change are reused) and
+ * runs the reverse pass: for every step C = A (x) B with a single-qubit gate
+ * leaf below, adj(A) = adj(C) contracted with B onto A's indices (and the same
+ * for B), subtrees without such leaves pruned.  Adds the holomorphic VJP
+ *   grad[g][i][j] += sum_r w[r] * d result[r] / d U_g[i][j]
+ * to grad_accum (device complex128, n_grad_gates x 4 entries, U[out][in]
+ * row-major, gates in circuit order of the single-qubit gates).  w: device
+ * complex128, result_elems entries in result order; no conjugation is
+ * applied.  Needs a plan created with differentiable = 1 and uploaded. */
+int32_t mitnc_backward(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t slice_begin,
+                       uint64_t slice_end, const double* w, double* grad_accum, void* stream);
+
+/* Replaces the matrices of all single-qubit gates of an uploaded plan
+ * (host complex128, n_grad_gates x 4 entries U[out][in], circuit order) and
+ * re-uploads those leaves; the cross-slice cache restarts at the next
+ * execute.  Complex64 plans only. */
+int32_t mitnc_plan_set_gates(mitnc_plan* plan, void* ws, size_t ws_bytes, const double* mats,
+                             void* stream);
 
 /* Single pairwise contraction on the GPU (the TTGT step of Sec. II-A /
  * Sec. V with the permutation fused into the loads).  A, B, C: device

@@ -37,7 +37,8 @@ class mitnc_search_opts(C.Structure):
 
 class mitnc_plan_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("reuse", C.c_int32),
-                ("cache_budget_bytes", C.c_uint64), ("force_kernel", C.c_int32)]
+                ("cache_budget_bytes", C.c_uint64), ("force_kernel", C.c_int32),
+                ("differentiable", C.c_int32)]
 
 
 class mitnc_plan_stats(C.Structure):
@@ -46,7 +47,9 @@ class mitnc_plan_stats(C.Structure):
                 ("n_kernel_classes", C.c_int32),
                 ("flops_full_slice", C.c_double), ("flops_reused_slice", C.c_double),
                 ("bytes_full_slice", C.c_double), ("bytes_reused_slice", C.c_double),
-                ("steps_by_class", C.c_int32 * 8), ("flops_by_class", C.c_double * 8)]
+                ("steps_by_class", C.c_int32 * 8), ("flops_by_class", C.c_double * 8),
+                ("n_grad_gates", C.c_int32), ("n_reverse_ops", C.c_int32),
+                ("flops_reverse_slice", C.c_double)]
 
 
 _VP = C.c_void_p
@@ -72,6 +75,8 @@ _SIGS = {
                                C.POINTER(C.c_double)],
     "mitnc_calibrate": [_VP, _VP, C.c_size_t, C.c_uint64, C.c_uint64, _VP],
     "mitnc_step_maxima": [_VP, _VP, C.c_size_t, C.POINTER(C.c_float), _I32, _VP],
+    "mitnc_backward": [_VP, _VP, C.c_size_t, C.c_uint64, C.c_uint64, _VP, _VP, _VP],
+    "mitnc_plan_set_gates": [_VP, _VP, C.c_size_t, C.POINTER(C.c_double), _VP],
     "mitnc_contract": [_VP, _I32, C.POINTER(C.c_int64), _VP, _I32, C.POINTER(C.c_int64), _VP, _I32,
                        C.POINTER(C.c_int64), _I32, C.c_float, _I32, _VP, C.c_size_t, C.POINTER(C.c_size_t),
                        _VP],

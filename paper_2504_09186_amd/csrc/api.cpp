@@ -330,6 +330,9 @@ int32_t mitnc_plan_query(const mitnc_plan* P, mitnc_plan_stats* st) {
       st->flops_reused_slice += s.flops * runs / nsl;
       st->bytes_reused_slice += s.bytes * runs / nsl;
     }
+    st->n_grad_gates = P->n_grad_gates;
+    st->n_reverse_ops = (int32_t)P->rev.size();
+    st->flops_reverse_slice = P->rev_flops;
   });
 }
 
@@ -376,6 +379,10 @@ int32_t mitnc_plan_upload(mitnc_plan* P, void* ws, size_t ws_bytes, void* stream
       }
     }
     hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * P->steps.size(), s), "stats reset");
+    if (!P->gtab.empty())
+      hip_check(hipMemcpyAsync(base + P->off_gtab, P->gtab.data(), sizeof(GradEntry) * P->gtab.size(),
+                               hipMemcpyHostToDevice, s),
+                "gradient table upload");
     hip_check(hipStreamSynchronize(s), "leaf upload sync");
     P->uploaded = true;
     P->uploaded_ws = ws;
@@ -516,6 +523,83 @@ int32_t mitnc_step_maxima(mitnc_plan* P, void* ws, size_t ws_bytes, float* out, 
     hip_check(hipMemcpyAsync(out, base + P->off_stats, 4 * nst, hipMemcpyDeviceToHost, s), "stats read");
     hip_check(hipStreamSynchronize(s), "stats sync");
     if (reset) hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * nst, s), "stats reset");
+  });
+}
+
+static char* node_value_ptr(mitnc_plan* P, char* base, int node, uint64_t slice) {
+  const PlanNode& nd = P->nodes[node];
+  if (nd.region == 0) {
+    uint64_t e = 0;
+    for (auto& [sb, pb] : nd.slice_bits) e += ((slice >> sb) & 1ull) << pb;
+    return base + nd.offset + e * 8;
+  }
+  return base + (nd.region == 1 ? P->off_persist : P->off_arena) + nd.offset;
+}
+
+int32_t mitnc_backward(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, uint64_t s1, const double* w,
+                       double* grad, void* stream) {
+  return guarded([&] {
+    check_ws(P, ws, ws_bytes);
+    if (!P->opts.differentiable) fail(MITNC_INVALID_ARG, "plan was not created with differentiable = 1");
+    if (!w || !grad) fail(MITNC_INVALID_ARG, "null argument");
+    uint64_t n_slices = 1ull << P->S;
+    if (s0 >= s1 || s1 > n_slices) fail(MITNC_INVALID_ARG, "slice range out of bounds");
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    const int root = P->steps.back().out;
+    for (uint64_t sl = s0; sl < s1; ++sl) {
+      // forward: recompute the nodes whose sliced indices changed (the root's
+      // value itself is not needed)
+      int level = (sl == s0) ? kLevelFirst : __builtin_ctzll(sl);
+      for (auto& st : P->steps) {
+        if (st.root || P->nodes[st.out].lo > level) continue;
+        launch_plan_step(P, st, base, sl, nullptr, s, MITNC_C64, false);
+      }
+      // reverse
+      hip_check(launch_seed(w, (float*)(base + P->off_adj + P->adj_offset[root]), P->result_elems, s), "seed");
+      for (RevOp& r : P->rev) {
+        StepDesc d = r.d;
+        char* adj_c = base + P->off_adj + P->adj_offset[P->steps[r.step].out];
+        char* other = node_value_ptr(P, base, r.other, sl);
+        d.A = r.adj_is_a ? adj_c : other;
+        d.B = r.adj_is_a ? other : adj_c;
+        d.C = base + P->off_adj + P->adj_offset[r.target];
+        d.acc = nullptr;
+        d.part = (float*)(base + P->off_part);
+        d.stats = nullptr;
+        d.mode = EPI_STORE;
+        d.prec = MITNC_C64;
+        d.out_scale = 1.f;
+        d.acc_scale = 1.0;
+        hip_check(launch_step(r.kclass, d, s), "reverse kernel launch");
+      }
+      hip_check(launch_grad((const GradEntry*)(base + P->off_gtab), (int)P->gtab.size(), base, sl, grad, s),
+                "gradient accumulation");
+    }
+  });
+}
+
+int32_t mitnc_plan_set_gates(mitnc_plan* P, void* ws, size_t ws_bytes, const double* mats, void* stream) {
+  return guarded([&] {
+    check_ws(P, ws, ws_bytes);
+    if (!mats) fail(MITNC_INVALID_ARG, "null matrices");
+    if (P->opts.precision != MITNC_C64) fail(MITNC_UNSUPPORTED, "gate updates need a complex64 plan");
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    int g = 0;
+    for (int i = 0; i < P->n_leaves; ++i) {
+      if (!P->leaf_is_1q[i]) continue;
+      std::vector<float>& h = P->leaf_data[i];
+      for (int e = 0; e < 4; ++e) {
+        h[2 * e] = (float)mats[8 * g + 2 * e];
+        h[2 * e + 1] = (float)mats[8 * g + 2 * e + 1];
+      }
+      hip_check(hipMemcpyAsync(base + P->nodes[i].offset, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice,
+                               s),
+                "gate upload");
+      ++g;
+    }
+    hip_check(hipStreamSynchronize(s), "gate upload sync");
   });
 }
 

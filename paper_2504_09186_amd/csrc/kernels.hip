@@ -695,6 +695,48 @@ __global__ __launch_bounds__(256) void k_reduce(StepDesc d) {
   record_max(d, mx);
 }
 
+// ---------------------------------------------------------------- reverse pass
+__global__ __launch_bounds__(256) void k_seed(const double2* w, float2* adj, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) adj[i] = make_float2((float)w[i].x, (float)w[i].y);
+}
+
+// One thread per single-qubit gate leaf: its adjoint (at most 4 entries) is
+// added into the gate's 4 gradient entries at the positions its sliced
+// indices take in this slice.
+__global__ __launch_bounds__(256) void k_grad(const GradEntry* tab, int n_entries, const char* ws, uint64_t slice,
+                                              double2* grad) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_entries) return;
+  const GradEntry e = tab[i];
+  const float2* adj = reinterpret_cast<const float2*>(ws + e.adj_offset);
+  uint32_t base = 0;
+  for (int j = 0; j < e.n_sliced; ++j) base |= (uint32_t)((slice >> e.slice_bit[j]) & 1ull) << e.slice_pos[j];
+  for (int r = 0; r < (1 << e.rank); ++r) {
+    uint32_t full = base;
+    for (int b = 0; b < e.rank; ++b) full |= (uint32_t)((r >> b) & 1) << e.full_pos[b];
+    const float2 v = adj[r];
+    double2 o = grad[4 * e.gate + full];
+    o.x += v.x;
+    o.y += v.y;
+    grad[4 * e.gate + full] = o;
+  }
+}
+
+hipError_t launch_seed(const double* w, float* adj, uint64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_seed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(w), reinterpret_cast<float2*>(adj), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const GradEntry* tab, int n_entries, const char* ws, uint64_t slice, double* grad,
+                       hipStream_t s) {
+  if (n_entries == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad, dim3((unsigned)((n_entries + 255) / 256)), dim3(256), 0, s, tab, n_entries, ws, slice,
+                     reinterpret_cast<double2*>(grad));
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launch
 template <int P>
 static hipError_t launch_stem(const StepDesc& d, dim3 grid, hipStream_t s) {

@@ -269,6 +269,85 @@ void build_step_for(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& c_l
   build_step(P, st, c_labels, root_layout, force_kernel, precision);
 }
 
+// Reverse pass of the differentiation form: which nodes need an adjoint
+// (a single-qubit gate leaf below them), where adjoints live, one adjoint
+// contraction per (step, child needing it) in reverse step order, and the
+// leaf-to-gradient table.
+static void build_reverse(mitnc_plan* P, const mitnc_network* net, const mitnc_plan_opts& opts) {
+  const int n = P->n_leaves;
+  P->has_grad.assign(P->nodes.size(), 0);
+  std::vector<int> gate_of_leaf(n, -1);
+  int g1 = 0;
+  for (int i = 0; i < n; ++i) {
+    const Leaf& L = net->leaves[i];
+    if (L.gate >= 0 && L.arity == 1) {
+      P->has_grad[i] = 1;
+      gate_of_leaf[i] = g1++;
+    }
+  }
+  P->n_grad_gates = g1;
+  for (auto& st : P->steps) P->has_grad[st.out] = P->has_grad[st.a] || P->has_grad[st.b];
+  P->adj_offset.assign(P->nodes.size(), 0);
+  uint64_t off = 0;
+  for (size_t v = 0; v < P->nodes.size(); ++v) {
+    if (!P->has_grad[v]) continue;
+    P->adj_offset[v] = off;
+    off = align_up(off + (8ull << P->nodes[v].rank), 256);
+  }
+  P->adj_bytes = off;
+  for (int si = (int)P->steps.size() - 1; si >= 0; --si) {
+    const PlanStep& st = P->steps[si];
+    if (!P->has_grad[st.out]) continue;
+    for (int which = 0; which < 2; ++which) {
+      const int target = which == 0 ? st.a : st.b;
+      const int other = which == 0 ? st.b : st.a;
+      if (!P->has_grad[target]) continue;
+      mitnc_plan T;
+      T.nodes.resize(3);
+      const PlanNode& O = P->nodes[st.out];
+      T.nodes[0].labels = O.labels;
+      T.nodes[0].pos = O.pos;
+      T.nodes[0].rank = O.rank;
+      T.nodes[1].labels = P->nodes[other].labels;
+      T.nodes[1].pos = P->nodes[other].pos;
+      T.nodes[1].rank = P->nodes[other].rank;
+      const std::vector<int64_t>& tl = P->nodes[target].labels;  // physical order, dense adjoint layout
+      PlanStep rs;
+      rs.a = 0;
+      rs.b = 1;
+      rs.out = 2;
+      build_step(&T, rs, tl, &tl, opts.force_kernel, MITNC_C64);
+      RevOp r;
+      r.step = si;
+      r.target = target;
+      r.other = other;
+      r.adj_is_a = rs.a == 0;
+      r.kclass = rs.kclass;
+      r.d = rs.d;
+      r.part_bytes = rs.part_bytes;
+      r.flops = rs.flops;
+      P->rev_flops += rs.flops;
+      P->rev.push_back(r);
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    if (gate_of_leaf[i] < 0) continue;
+    const PlanNode& nd = P->nodes[i];
+    GradEntry e;
+    std::memset(&e, 0, sizeof(e));
+    e.adj_offset = P->adj_offset[i];  // made absolute once the workspace layout is known
+    e.gate = gate_of_leaf[i];
+    e.rank = nd.rank;
+    for (int b = 0; b < nd.rank; ++b) e.full_pos[b] = (int8_t)nd.pos[b];
+    e.n_sliced = (int8_t)nd.slice_bits.size();
+    for (size_t j = 0; j < nd.slice_bits.size(); ++j) {
+      e.slice_bit[j] = (int8_t)nd.slice_bits[j].first;
+      e.slice_pos[j] = (int8_t)nd.slice_bits[j].second;
+    }
+    P->gtab.push_back(e);
+  }
+}
+
 mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   if (!net->output_set) fail(MITNC_INVALID_ARG, "output not set");
   int n = (int)net->leaves.size();
@@ -334,6 +413,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
       P->leaf_half.push_back(std::move(w));
     }
     P->leaf_data.push_back(std::move(h));
+    P->leaf_is_1q.push_back(L.gate >= 0 && L.arity == 1);
     nd.offset = off;
     off = align_up(off + L.data.size() * 8, 256);
   }
@@ -399,6 +479,12 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
       pbytes = assign_regions();
     }
   }
+  // Differentiable plans keep every node (the reverse pass reads them all).
+  if (opts.differentiable) {
+    if (opts.precision != MITNC_C64) fail(MITNC_UNSUPPORTED, "differentiable plans are complex64 only");
+    for (auto& st : P->steps)
+      if (!st.root) P->nodes[st.out].region = 1;
+  }
   // Memory: persistent slots, then a transient arena with first-fit reuse.
   uint64_t poff = 0;
   for (auto& st : P->steps) {
@@ -445,6 +531,8 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   for (auto& st : P->steps) part = std::max(part, st.part_bytes);
   P->part_bytes = align_up(part, 256);
   P->result_elems = 1ull << net->output_lsb.size();
+  if (opts.differentiable) build_reverse(P.get(), net, opts);
+  for (auto& r : P->rev) P->part_bytes = std::max(P->part_bytes, align_up(r.part_bytes, 256));
   const bool half = opts.precision != MITNC_C64;
   // The 16-bit leaf region mirrors the complex64 one at half the offsets;
   // intermediates keep complex64 sizing so a calibration slice can run in
@@ -455,7 +543,10 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   P->off_part = align_up(P->off_arena + P->arena_bytes, 256);
   P->off_stats = align_up(P->off_part + P->part_bytes, 256);
   P->off_calib = align_up(P->off_stats + 4 * P->steps.size(), 256);
-  P->ws_bytes = align_up(P->off_calib + (half ? 16 * P->result_elems : 0), 256);
+  P->off_adj = align_up(P->off_calib + (half ? 16 * P->result_elems : 0), 256);
+  P->off_gtab = align_up(P->off_adj + P->adj_bytes, 256);
+  P->ws_bytes = align_up(P->off_gtab + sizeof(GradEntry) * P->gtab.size(), 256);
+  for (auto& g : P->gtab) g.adj_offset += P->off_adj;
   P->calibrated = !half;
   verify_memory_plan(P.get(), std::min<uint64_t>(1ull << P->S, 64));
   return P.release();

@@ -38,6 +38,20 @@ struct PlanStep {
   uint64_t part_bytes = 0;       // split-K partials, max over d and d64
 };
 
+// One adjoint contraction of the reverse pass: for a step C = A (x) B the
+// adjoint of A is the contraction of adj(C) with B onto A's indices.
+struct RevOp {
+  int step = -1;                 // forward step
+  int target = -1;               // node whose adjoint is written
+  int other = -1;                // forward value used (the target's sibling)
+  bool adj_is_a = true;          // descriptor operand A is adj(C) (else the sibling)
+  int kclass = MITNC_K_SMALL;
+  StepDesc d{};
+  uint64_t part_bytes = 0;
+  double flops = 0;
+};
+
+
 }  // namespace mitnc
 
 struct mitnc_plan {
@@ -47,6 +61,7 @@ struct mitnc_plan {
   std::vector<mitnc::PlanNode> nodes;        // leaves then step outputs
   std::vector<mitnc::PlanStep> steps;
   std::vector<std::vector<float>> leaf_data; // complex64 interleaved, full (unsliced) leaves
+  std::vector<char> leaf_is_1q;              // leaf is a single-qubit gate
   std::vector<std::vector<uint32_t>> leaf_half;  // FP16/BF16 mantissas (precision plans)
   uint64_t leaf_bytes = 0, persist_bytes = 0, arena_bytes = 0, part_bytes = 0;
   // Workspace: [complex64 leaves | 16-bit leaves | persistent | arena |
@@ -54,6 +69,15 @@ struct mitnc_plan {
   uint64_t off_leaf_half = 0, off_persist = 0, off_arena = 0, off_part = 0, off_stats = 0, off_calib = 0;
   uint64_t ws_bytes = 0;
   bool calibrated = false;
+  // Differentiation form (opts.differentiable): every node keeps its own
+  // buffer, adjoints live in [off_adj, off_adj + adj_bytes).
+  std::vector<char> has_grad;          // per node: a single-qubit gate leaf below
+  std::vector<uint64_t> adj_offset;    // per node with has_grad
+  std::vector<mitnc::RevOp> rev;       // reverse pass in execution order
+  std::vector<mitnc::GradEntry> gtab;  // per single-qubit gate leaf
+  int32_t n_grad_gates = 0;
+  uint64_t off_adj = 0, adj_bytes = 0, off_gtab = 0;
+  double rev_flops = 0;
   uint64_t result_elems = 0;
   int max_log2 = 0;
   bool uploaded = false;

@@ -51,6 +51,19 @@ enum TabOff : int {
   TAB_BYTES = 336
 };
 
+// Device table entry mapping a single-qubit gate leaf's adjoint into the
+// gradient accumulator (complex128, 4 entries U[out][in] per gate).
+struct GradEntry {
+  uint64_t adj_offset;           // byte offset of the leaf adjoint in the workspace
+  int32_t gate;                  // index among single-qubit gates, circuit order
+  int32_t rank;                  // unsliced bits of the leaf (0..2)
+  int8_t full_pos[2];            // leaf address bit of each adjoint bit
+  int8_t n_sliced;
+  int8_t slice_bit[2];           // slice-id bit of each sliced leaf bit
+  int8_t slice_pos[2];           // its leaf address bit
+  int8_t pad_[7];
+};
+
 // Tile geometry of the MFMA kernel classes (bits of the m, n, k tile).
 struct TileGeom {
   int tm_bits, tn_bits, tk_bits;

@@ -97,8 +97,9 @@ class Plan:
     """Execution plan; owns nothing on the device."""
 
     def __init__(self, net: Network, precision: int = _lib.MITNC_C64, reuse: bool = True,
-                 cache_budget_bytes: int = 0, force_kernel: int = -1):
-        o = mitnc_plan_opts(precision, 1 if reuse else 0, cache_budget_bytes, force_kernel)
+                 cache_budget_bytes: int = 0, force_kernel: int = -1, differentiable: bool = False):
+        o = mitnc_plan_opts(precision, 1 if reuse else 0, cache_budget_bytes, force_kernel,
+                            1 if differentiable else 0)
         h = C.c_void_p()
         call("mitnc_plan_create", net.h, C.byref(o), C.byref(h))
         self.h = h
@@ -154,6 +155,29 @@ class Plan:
         call("mitnc_step_maxima", self.h, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
              out.ctypes.data_as(C.POINTER(C.c_float)), 1 if reset else 0, _stream_handle(stream))
         return out
+
+    def set_gates(self, mats, stream=None) -> None:
+        """Replace all single-qubit gate matrices (n_grad_gates x 2 x 2, U[out, in])."""
+        m = np.ascontiguousarray(np.asarray(mats, dtype=np.complex128).reshape(-1)).view(np.float64)
+        if m.size != 8 * self.stats.n_grad_gates:
+            raise ValueError("expected n_grad_gates x 2 x 2 matrices")
+        call("mitnc_plan_set_gates", self.h, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+             m.ctypes.data_as(C.POINTER(C.c_double)), _stream_handle(stream))
+
+    def backward(self, w, grad, slice_begin: int = 0, slice_end: Optional[int] = None, stream=None):
+        """grad += sum_r w[r] d result[r] / d U_g (holomorphic VJP; complex128
+        device tensors: w with result_elems entries, grad with 4 n_grad_gates)."""
+        import torch
+        if w.dtype != torch.complex128 or not w.is_contiguous() or w.numel() != self.stats.result_elems:
+            raise ValueError("w must be a contiguous complex128 tensor of result_elems entries")
+        if grad.dtype != torch.complex128 or not grad.is_contiguous() or grad.numel() != 4 * self.stats.n_grad_gates:
+            raise ValueError("grad must be a contiguous complex128 tensor of 4 n_grad_gates entries")
+        if slice_end is None:
+            slice_end = self.n_slices
+        call("mitnc_backward", self.h, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+             int(slice_begin), int(slice_end), C.c_void_p(w.data_ptr()), C.c_void_p(grad.data_ptr()),
+             _stream_handle(stream))
+        return grad
 
     def execute(self, acc, slice_begin: int = 0, slice_end: Optional[int] = None, stream=None):
         """acc += sum of slices [slice_begin, slice_end) (complex128 device tensor)."""
@@ -218,3 +242,48 @@ def amplitudes(circuit, spec, batch_bits=None, seed: int = 0, trials: int = 32, 
     acc = plan.new_result(device)
     plan.execute(acc, s0, s1)
     return acc
+
+
+def _amplitude_fn():
+    import torch
+
+    class AmplitudeFn(torch.autograd.Function):
+        """amplitudes = AmplitudeFn.apply(gates, plan): the requested amplitudes
+        (complex128, result order) as a function of the single-qubit gate
+        matrices (complex128 tensor n_grad_gates x 2 x 2).  The backward pass
+        runs the library's reverse contraction (recomputing each slice's
+        forward) and returns conj of the holomorphic VJP with weights
+        conj(grad_output), which is torch's convention for complex inputs."""
+
+        @staticmethod
+        def forward(ctx, gates, plan):
+            plan.set_gates(gates.detach().cpu().numpy())
+            acc = plan.new_result(plan.workspace.device)
+            plan.execute(acc)
+            ctx.plan = plan
+            ctx.gates_device = gates.device
+            return acc
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            plan = ctx.plan
+            # conj_physical: a lazy conj() view would hand the library the
+            # unconjugated bytes
+            w = torch.conj_physical(grad_out.to(torch.complex128)).contiguous()
+            grad = torch.zeros(4 * plan.stats.n_grad_gates, dtype=torch.complex128, device=w.device)
+            plan.backward(w, grad)
+            g = grad.conj().reshape(-1, 2, 2).to(ctx.gates_device)
+            return g, None
+
+    return AmplitudeFn
+
+
+_AMPFN = None
+
+
+def AmplitudeFn():
+    """The torch.autograd.Function class (created on first use)."""
+    global _AMPFN
+    if _AMPFN is None:
+        _AMPFN = _amplitude_fn()
+    return _AMPFN
