@@ -179,6 +179,13 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
       double a = t == 0 ? 1.0 : alphas[rng() % 4];
       double tau = t == 0 ? 0.0 : temps[rng() % 4];
       Path p = greedy_path(sn, a, tau, rng(), o->keep_slicing ? &fixed : nullptr);
+      {
+        // local refinement before slicing: no intermediate may grow
+        std::vector<char> none(sn.n_labels, 0);
+        const std::vector<char>& rm = o->keep_slicing ? fixed : none;
+        const int width = sym_max_bits(sn, sym_run(sn, p, rm), rm);
+        p = optimize_path(sn, p, &rm, width, 4);
+      }
       bool ok;
       std::vector<int> sl;
       if (o->keep_slicing) {
@@ -201,6 +208,8 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
       if (!ok) continue;
       std::vector<char> m(sn.n_labels, 0);
       for (int x : sl) m[x] = 1;
+      // refine again for the per-slice network, keeping the size cap
+      p = optimize_path(sn, p, &m, std::max(o->max_log2_elems, sym_max_bits(sn, sym_run(sn, p, m), m)), 4);
       double f = sym_total_flops(sym_run(sn, p, m)) * std::ldexp(1.0, (int)sl.size());
       if (best < 0 || f < best) {
         best = f;

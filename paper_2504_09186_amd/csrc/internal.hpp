@@ -64,6 +64,10 @@ Path greedy_path(const SymNet& sn, double alpha, double temperature, uint64_t se
 std::vector<int> greedy_slices(const SymNet& sn, const Path& path, int cap, int min_sliced,
                                int max_sliced, bool* ok);
 std::vector<int> order_slices(const SymNet& sn, const Path& path, const std::vector<int>& sl);
+// Subtree reconfiguration (reconf.cpp): locally optimal re-ordering of the
+// tree, flops measured with `removed` labels (sliced) absent, intermediates
+// kept at most 2^cap_bits entries.
+Path optimize_path(const SymNet& sn, const Path& path, const std::vector<char>* removed, int cap_bits, int passes);
 void validate_path(int n_leaves, const Path& path);
 
 }  // namespace mitnc
