@@ -74,12 +74,6 @@ def run_form(net, precision, steps, warmup, label):
     for _ in range(warmup):
         acc.zero_()
         plan.execute(acc)
-    # one untimed step with event timing on allocates the event pool
-    plan.timing(True)
-    acc.zero_()
-    plan.execute(acc)
-    torch.cuda.synchronize()
-    plan.timing(True)  # reset: record the timed region only
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -87,9 +81,21 @@ def run_form(net, precision, steps, warmup, label):
         plan.execute(acc)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    result = acc.cpu().numpy()
+    # Kernel durations: the same steps again with a hipEvent pair around every
+    # launch (the events add host-side launch cost, so `value` above is taken
+    # without them).
+    plan.timing(True)
+    acc.zero_()
+    plan.execute(acc)  # allocates the event pool
+    torch.cuda.synchronize()
+    plan.timing(True)
+    for _ in range(steps):
+        acc.zero_()
+        plan.execute(acc)
+    torch.cuda.synchronize()
     ms, launches, flops, nbytes = plan.timing_read()
     plan.timing(False)
-    result = acc.cpu().numpy()
     overflow = None
     if precision != 0:
         overflow = bool(float(plan.step_maxima().max()) >= 65504.0)
