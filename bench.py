@@ -24,10 +24,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "slices/s + % MFMA peak, complex64 vs scaled complex-FP16 at stated amp error"
-PEAK = {"c64": 157.3, "cf16": 2500.0}  # dense MFMA TFLOP/s: FP32, FP16
+PEAK_FP32 = 157.3   # dense MFMA (and vector) TFLOP/s, FP32
+PEAK_FP16 = 2500.0  # dense MFMA TFLOP/s, FP16
 PEAK_HBM_GBS = 8000.0
-CLASS_NAMES = ["small", "stem", "tile", "tall", "splitk"]
-MFMA_CLASSES = (2, 3)
+CLASS_NAMES = ["small", "stem", "tile", "tall", "splitk", "stream"]
+
+
+def class_peak(label, cls):
+    """Compute peak of the units a kernel class runs on: the FP16 form's tile
+    kernels use FP16 MFMA; everything else computes in FP32."""
+    return PEAK_FP16 if label == "cf16" and cls in (2, 3, 4) else PEAK_FP32
 GOLDEN = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.json")
 
 
@@ -99,9 +105,13 @@ def run_form(net, precision, steps, warmup, label):
     overflow = None
     if precision != 0:
         overflow = bool(float(plan.step_maxima().max()) >= 65504.0)
-    dom = int(max(range(5), key=lambda k: ms[k]))
-    peak = PEAK[label]
-    if dom in MFMA_CLASSES:
+    nc = len(CLASS_NAMES)
+    dom = int(max(range(nc), key=lambda k: ms[k]))
+    # Bound of the dominant kernel: its arithmetic intensity against the
+    # ridge point peak_flops / peak_bandwidth.
+    peak = class_peak(label, dom)
+    ai = flops[dom] / max(nbytes[dom], 1.0)
+    if ai >= peak * 1e12 / (PEAK_HBM_GBS * 1e9):
         achieved = flops[dom] / (ms[dom] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None}
@@ -109,14 +119,17 @@ def run_form(net, precision, steps, warmup, label):
         achieved = nbytes[dom] / (ms[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    roof["flop_per_byte"] = ai
     roof["kernel"] = CLASS_NAMES[dom]
     roof["launches"] = int(launches[dom])
     roof["avg_launch_ms"] = ms[dom] / max(1.0, launches[dom])
     total_flops = st.flops_reused_slice * n_slices * steps
+    total_bytes = sum(nbytes[:nc])
     return {
         "value": n_slices * steps / el, "unit": "slices/s", "ms_per_step": el / steps * 1e3,
-        "tflops": total_flops / el / 1e12, "mfma_frac": total_flops / el / 1e12 / peak,
-        "kernel_ms_by_class": {CLASS_NAMES[k]: ms[k] / steps for k in range(5)},
+        "tflops": total_flops / el / 1e12, "hbm_gbs": total_bytes / el / 1e9,
+        "mfma_frac": total_flops / el / 1e12 / (PEAK_FP16 if label == "cf16" else PEAK_FP32),
+        "kernel_ms_by_class": {CLASS_NAMES[k]: ms[k] / steps for k in range(nc)},
         "roofline": roof, "n_slices": n_slices, "stats": st, "result": result, "fp16_overflow": overflow,
     }
 
@@ -181,7 +194,7 @@ def main():
                    "open_qubits": 6, "slices_per_step": r64["n_slices"], "max_log2_elems": st.max_log2_elems,
                    "steps_per_slice": st.n_steps, "flops_per_slice": st.flops_reused_slice,
                    "precision": "complex64, FP32 MFMA (3M), FP64 cross-slice sum"},
-        "tflops": r64["tflops"], "mfma_frac": r64["mfma_frac"],
+        "tflops": r64["tflops"], "mfma_frac": r64["mfma_frac"], "hbm_gbs": r64["hbm_gbs"],
         "amp_error": amp_error(r64["result"], ref),
         "kernel_ms_by_class": r64["kernel_ms_by_class"],
         "roofline": r64["roofline"],
@@ -189,7 +202,7 @@ def main():
     if not args.no_fp16:
         r16 = run_form(net, 1, args.steps, args.warmup, "cf16")
         out["cf16"] = {"value": r16["value"], "unit": "slices/s", "ms_per_step": r16["ms_per_step"],
-                       "tflops": r16["tflops"], "mfma_frac": r16["mfma_frac"],
+                       "tflops": r16["tflops"], "mfma_frac": r16["mfma_frac"], "hbm_gbs": r16["hbm_gbs"],
                        "amp_error": amp_error(r16["result"], ref), "fp16_overflow": r16["fp16_overflow"],
                        "kernel_ms_by_class": r16["kernel_ms_by_class"], "roofline": r16["roofline"],
                        "precision": "complex FP16 storage, FP16 MFMA (4M) with FP32 accumulate, "

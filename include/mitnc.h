@@ -261,7 +261,10 @@ enum {
   MITNC_K_STEM = 1,   /* big tensor times small matrix: vector FMA, one thread per row */
   MITNC_K_TILE = 2,   /* LDS-staged, bit-permuted tiles, complex GEMM on FP32 MFMA */
   MITNC_K_TALL = 3,   /* as TILE with a 128 x 16 tile for narrow N */
-  MITNC_K_SPLITK = 4  /* small M, N, long K: K split over workgroups, FP64 reduction */
+  MITNC_K_SPLITK = 4, /* small M, N, long K: K split over workgroups, FP64 reduction */
+  MITNC_K_STREAM = 5  /* big tensor times small matrix on MFMA, streamed with no LDS staging:
+                         needs no batch indices, M >= 2^12, K <= 64, N <= 64,
+                         max(K/4, 1) * max(N/16, 1) <= 16 */
 };
 
 #ifdef __cplusplus

@@ -16,7 +16,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "PATH_INVALID", -3: "WORKSPACE_T
                 -4: "HIP_ERROR", -5: "UNSUPPORTED", -6: "NUMERIC"}
 MITNC_C64, MITNC_CF16, MITNC_CBF16 = 0, 1, 2
 K_SMALL, K_STEM, K_TILE, K_TALL, K_SPLITK = 0, 1, 2, 3, 4
-KERNEL_NAMES = {0: "small", 1: "stem", 2: "tile", 3: "tall", 4: "splitk"}
+KERNEL_NAMES = {0: "small", 1: "stem", 2: "tile", 3: "tall", 4: "splitk", 5: "stream"}
 
 
 class MitncError(RuntimeError):

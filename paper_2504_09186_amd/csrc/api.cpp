@@ -323,7 +323,7 @@ int32_t mitnc_plan_query(const mitnc_plan* P, mitnc_plan_stats* st) {
     st->n_sliced = P->S;
     st->n_steps = (int32_t)P->steps.size();
     st->max_log2_elems = P->max_log2;
-    st->n_kernel_classes = 5;
+    st->n_kernel_classes = 6;
     double nsl = std::ldexp(1.0, P->S);
     for (auto& s : P->steps) {
       st->flops_full_slice += s.flops;

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -56,6 +57,12 @@ __device__ __forceinline__ uint64_t gather_bits(uint64_t a, const uint8_t* pos, 
   for (int i = 0; i < 32; ++i)
     if (i < n) r |= ((a >> pos[i]) & 1ull) << i;
   return r;
+}
+
+// A wave-uniform 64-bit value moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
+         (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
 }
 
 // ---------------------------------------------------------------- element I/O
@@ -232,6 +239,120 @@ __global__ __launch_bounds__(256) void k_stem(StepDesc d) {
         s.y += a[k].x * b.y + a[k].y * b.x;
       }
       mx = fmaxf(mx, epilogue_store<P>(d, coff + nc[n], s, 0, c_elems));
+    }
+  }
+  record_max(d, mx);
+}
+
+// ---------------------------------------------------------------- stream steps
+// A large tensor absorbs a small matrix (K, N <= 64, K N <= 16 x 4 x 16): the
+// HBM-bound steps that dominate a stem (Sec. V-A).  No LDS staging: the small
+// matrix sits in registers for the whole kernel and every wave streams 16-row
+// blocks of A from HBM straight into MFMA operands and writes C straight
+// back.  The MFMA computes C^T = B^T A^T, so that the 16 lanes of a lane
+// group walk 16 rows m of both A and C; those are the four lowest-address m
+// bits, and a load or store instruction moves whole 128-byte lines whatever
+// the positions of k and n.  3M split as in the tile kernels; padded k and n
+// carry zero B entries and padded n are never stored.
+//
+// Each wave owns a contiguous run of iters * R row blocks (R blocks per
+// iteration, all R * KS loads issued before the MFMAs; 8 loads of 8 bytes or
+// 16 of 4 bytes per lane).  Block j + 1 of A is
+// the scattered-bit successor of block j, ((x | ~mask) + 1) & mask, because
+// m bits are sorted by A position; C uses the same step when its m bits are
+// in address order too, and a full scatter otherwise.
+template <int P, int KS, int NBLK>
+__global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
+  constexpr int R = (P == 0 ? 8 : 16) / KS > 0 ? (P == 0 ? 8 : 16) / KS : 1;  // row blocks per iteration
+  using Raw = typename std::conditional<P == 0, float2, uint32_t>::type;
+  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  load_tables(d, tab);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int K = 1 << d.kb, N = 1 << d.nb;
+  // B^T operand: lane holds B[k = 4 ks + lq][n = 16 cb + lr]
+  float br[NBLK][KS], bi[NBLK][KS], bsum[NBLK][KS];
+#pragma unroll
+  for (int cb = 0; cb < NBLK; ++cb)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + lq, n = 16 * cb + lr;
+      float2 v = make_float2(0.f, 0.f);
+      if (k < K && n < N) v = load_c<P>(d.B, scatter_bits(k, tab + T_BK, d.kb) + scatter_bits(n, tab + T_BN, d.nb));
+      br[cb][ks] = v.x;
+      bi[cb][ks] = v.y;
+      bsum[cb][ks] = v.x + v.y;
+    }
+  const bool kvalid = lq < K;  // only K < 4 pads inside a k step
+  const uint32_t a_lane = (uint32_t)scatter_bits(lr, tab + T_AM, 4);
+  const uint32_t c_lane = (uint32_t)scatter_bits(lr, tab + T_CM, 4);
+  uint32_t a_k[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) a_k[ks] = a_lane + (uint32_t)scatter_bits(4 * ks + lq, tab + T_AK, d.kb);
+  uint32_t c_n[NBLK][4];
+#pragma unroll
+  for (int cb = 0; cb < NBLK; ++cb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      c_n[cb][i] = c_lane + (uint32_t)scatter_bits(16 * cb + 4 * lq + i, tab + T_CN, d.nb);
+  // Row-block addresses are wave-uniform: keep them in scalar registers.
+  const int hb = d.mb - 4;
+  uint64_t mask_a = 0, mask_c = 0;
+  int c_sorted = 1;
+  for (int i = 0; i < hb; ++i) {
+    mask_a |= 1ull << tab[T_AM + 4 + i];
+    mask_c |= 1ull << tab[T_CM + 4 + i];
+    if (i > 0 && tab[T_CM + 4 + i] < tab[T_CM + 3 + i]) c_sorted = 0;
+  }
+  mask_a = uniform64(mask_a);
+  mask_c = uniform64(mask_c);
+  c_sorted = __builtin_amdgcn_readfirstlane(c_sorted);
+  const uint64_t blk0 = uniform64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * iters * R);
+  uint64_t xa = uniform64(scatter_bits(blk0, tab + T_AM + 4, hb));
+  uint64_t xc = uniform64(scatter_bits(blk0, tab + T_CM + 4, hb));
+  const uint64_t c_elems = 1ull << (d.mb + d.nb);
+  float mx = 0.f;
+  for (uint32_t it = 0; it < iters; ++it) {
+    Raw raw[R][KS];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) raw[r][ks] = reinterpret_cast<const Raw*>(d.A)[xa + a_k[ks]];
+      xa = ((xa | ~mask_a) + 1) & mask_a;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v4f acc[3][NBLK];
+#pragma unroll
+      for (int cb = 0; cb < NBLK; ++cb)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) acc[p][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        float2 a;
+        if constexpr (P == 0) a = raw[r][ks];
+        else a = unpack<P>(raw[r][ks]);
+        if (!kvalid) a = make_float2(0.f, 0.f);
+        const float as = a.x + a.y;
+#pragma unroll
+        for (int cb = 0; cb < NBLK; ++cb) {
+          acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(br[cb][ks], a.x, acc[0][cb], 0, 0, 0);
+          acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bi[cb][ks], a.y, acc[1][cb], 0, 0, 0);
+          acc[2][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bsum[cb][ks], as, acc[2][cb], 0, 0, 0);
+        }
+      }
+      // lane holds C[m = lr][n = 16 cb + 4 lq + i] in register i
+#pragma unroll
+      for (int cb = 0; cb < NBLK; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (16 * cb + 4 * lq + i < N) {
+            const float t1 = acc[0][cb][i], t2 = acc[1][cb][i], t3 = acc[2][cb][i];
+            mx = fmaxf(mx, epilogue_store<P>(d, xc + c_n[cb][i], make_float2(t1 - t2, t3 - t1 - t2), 0, c_elems));
+          }
+      if (c_sorted) xc = ((xc | ~mask_c) + 1) & mask_c;
+      else xc = uniform64(scatter_bits(blk0 + (uint64_t)it * R + r + 1, tab + T_CM + 4, hb));
     }
   }
   record_max(d, mx);
@@ -754,6 +875,30 @@ static hipError_t launch_stem(const StepDesc& d, dim3 grid, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+// Stream steps: KS = 2^ksl k steps of 4, NBLK = 2^nbl column blocks of 16.
+// The grid holds up to 4096 waves (16 per CU); each wave takes iters
+// iterations of R row blocks.
+template <int P>
+static hipError_t launch_stream(const StepDesc& d, hipStream_t s) {
+  const int ksl = d.kb > 2 ? d.kb - 2 : 0, nbl = d.nb > 4 ? d.nb - 4 : 0;
+  if (!stream_fits(d.mb, d.nb, d.kb, d.bb)) return hipErrorInvalidValue;
+  const int rl = (P == 0 ? 3 : 4) > ksl ? (P == 0 ? 3 : 4) - ksl : 0;  // log2 R, as in the kernel
+  const int ngl = d.mb - 4 - rl;           // log2 of row-block groups
+  const int wl = ngl < 12 ? ngl : 12;      // log2 waves (>= 3 since mb >= 12)
+  const uint32_t iters = 1u << (ngl - wl);
+  const dim3 grid(1u << (wl - 2));
+#define MITNC_STREAM(KSL, NBL)                                                                 \
+  if (ksl == KSL && nbl == NBL) {                                                              \
+    hipLaunchKernelGGL((k_stream<P, 1 << KSL, 1 << NBL>), grid, dim3(256), 0, s, d, iters);    \
+    return hipGetLastError();                                                                  \
+  }
+  MITNC_STREAM(0, 0) MITNC_STREAM(1, 0) MITNC_STREAM(2, 0) MITNC_STREAM(3, 0) MITNC_STREAM(4, 0)
+  MITNC_STREAM(0, 1) MITNC_STREAM(1, 1) MITNC_STREAM(2, 1) MITNC_STREAM(3, 1)
+  MITNC_STREAM(0, 2) MITNC_STREAM(1, 2) MITNC_STREAM(2, 2)
+#undef MITNC_STREAM
+  return hipErrorInvalidValue;
+}
+
 template <int P>
 static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1) {
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
@@ -772,6 +917,9 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1
       e = launch_stem<P>(d, grid, s);
       break;
     }
+    case MITNC_K_STREAM:
+      e = launch_stream<P>(d, s);
+      break;
     case MITNC_K_TILE:
     case MITNC_K_TALL:
     case MITNC_K_SPLITK: {

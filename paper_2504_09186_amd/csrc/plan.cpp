@@ -15,8 +15,9 @@
 //    s the bits 0..ctz(s) change, so a node is recomputed iff its lowest
 //    dependency bit is <= ctz(s).  A node recomputed less often than its parent
 //    is kept across slices (one stored tensor per fork).
-//  * Kernel classes: tiny steps, stem steps (a big tensor times a small
-//    matrix, HBM bound), square-ish GEMM tiles on MFMA, narrow tiles, and
+//  * Kernel classes: tiny steps, stream steps (a big tensor times a small
+//    matrix on MFMA, HBM bound), stem steps (the same on vector FMA, for
+//    batched or short ones), square-ish GEMM tiles on MFMA, narrow tiles, and
 //    split-K for K >> M, N (Sec. V-B, split-common TTGT).
 #include <algorithm>
 #include <cmath>
@@ -74,6 +75,7 @@ int mantissa_exponent(double max_abs) {
 static int choose_class(int mb, int nb, int kb, int bb) {
   int out_bits = mb + nb + bb;
   if (out_bits <= 10 && kb <= 6) return MITNC_K_SMALL;
+  if (stream_fits(mb, nb, kb, bb)) return MITNC_K_STREAM;
   if (nb <= 2 && kb <= 4) return MITNC_K_STEM;
   if (mb <= 4 && nb <= 4) return MITNC_K_SPLITK;
   if (nb <= 4) return MITNC_K_TALL;
@@ -175,9 +177,11 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   put(d.cb, Bt, pc);
 
   st.kclass = force_kernel >= 0 ? force_kernel : choose_class(d.mb, d.nb, d.kb, d.bb);
-  if (st.kclass < MITNC_K_SMALL || st.kclass > MITNC_K_SPLITK) fail(MITNC_INVALID_ARG, "unknown kernel class");
+  if (st.kclass < MITNC_K_SMALL || st.kclass > MITNC_K_STREAM) fail(MITNC_INVALID_ARG, "unknown kernel class");
   if (st.kclass == MITNC_K_STEM && (d.kb > 4 || d.nb > 2))
     fail(MITNC_UNSUPPORTED, "stem kernel needs at most 4 contracted and 2 new indices");
+  if (st.kclass == MITNC_K_STREAM && !stream_fits(d.mb, d.nb, d.kb, d.bb))
+    fail(MITNC_UNSUPPORTED, "stream kernel needs no batch indices, >= 12 row bits, K, N <= 64, K N / 64 <= 16");
   TileGeom g = geom_of(st.kclass, precision);
   d.prec = precision;
   d.out_scale = 1.f;
@@ -213,7 +217,11 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     st.part_bytes = ks > 0 ? (c_elems << ks) * 8 : 0;
   }
   st.flops = 8.0 * std::ldexp(1.0, d.mb + d.nb + d.kb + d.bb);
-  st.bytes = 8.0 * (std::ldexp(1.0, A.rank) + std::ldexp(1.0, B.rank) + std::ldexp(1.0, O.rank));
+  // Algorithmic HBM bytes: each operand read once, the output written once
+  // (the last step of a slice reads and writes the complex128 sum instead).
+  const double esz = precision == MITNC_C64 ? 8.0 : 4.0;
+  st.bytes = esz * (std::ldexp(1.0, A.rank) + std::ldexp(1.0, B.rank)) +
+             (st.root ? 32.0 : esz) * std::ldexp(1.0, O.rank);
 }
 
 // Replays the launch schedule of slices 0 .. n_slices-1 on the host with a

@@ -77,4 +77,11 @@ inline constexpr TileGeom geom_tile_h() { return {7, 6, 5}; }    // 128 x 64, k 
 inline constexpr TileGeom geom_tall_h() { return {7, 4, 5}; }    // 128 x 16, k 32
 inline constexpr TileGeom geom_splitk_h() { return {4, 4, 7}; }  // 16 x 16, k 128 (4 waves split k)
 
+// Stream class limits: no batch bits, at least 2^12 rows, K, N <= 64 and at
+// most 16 (k step, column block) pairs of B held in registers per lane.
+inline constexpr int kStreamMinM = 12;
+inline constexpr bool stream_fits(int mb, int nb, int kb, int bb) {
+  return bb == 0 && mb >= kStreamMinM && kb <= 6 && nb <= 6 && (kb > 2 ? kb - 2 : 0) + (nb > 4 ? nb - 4 : 0) <= 4;
+}
+
 }  // namespace mitnc

@@ -18,10 +18,12 @@ from helpers import gamma, ref_contract, require_gpu
 
 pytestmark = pytest.mark.gpu
 
-SMALL, STEM, TILE, TALL, SPLITK = 0, 1, 2, 3, 4
+SMALL, STEM, TILE, TALL, SPLITK, STREAM = 0, 1, 2, 3, 4, 5
 
 
-def _case(mb, nb, kb, bb, seed):
+def _case(mb, nb, kb, bb, seed, in_place=False):
+    """Random layouts; with in_place, C takes A's layout with the k bits
+    replaced by n bits (the planner's output policy)."""
     rng = np.random.default_rng(seed)
     M = [1000 + i for i in range(mb)]
     N = [2000 + i for i in range(nb)]
@@ -30,16 +32,19 @@ def _case(mb, nb, kb, bb, seed):
     la = list(rng.permutation(M + K + Bt)) if (mb + kb + bb) else []
     lb = list(rng.permutation(K + N + Bt)) if (kb + nb + bb) else []
     lc = list(rng.permutation(M + N + Bt)) if (mb + nb + bb) else []
+    if in_place:
+        nit = iter(N)
+        lc = [x for x in (next(nit, None) if x in K else x for x in la) if x is not None] + list(nit)
     a = synth.complex_normal(1 << len(la), seed=seed + 1).astype(np.complex64)
     b = synth.complex_normal(1 << len(lb), seed=seed + 2).astype(np.complex64)
     return [int(x) for x in la], [int(x) for x in lb], [int(x) for x in lc], a, b
 
 
-def _run(mb, nb, kb, bb, kernel, seed):
+def _run(mb, nb, kb, bb, kernel, seed, in_place=False):
     require_gpu()
     import torch
     from paper_2504_09186_amd import tnc
-    la, lb, lc, a, b = _case(mb, nb, kb, bb, seed)
+    la, lb, lc, a, b = _case(mb, nb, kb, bb, seed, in_place)
     print(f"contract case m{mb} n{nb} k{kb} b{bb} kernel {kernel} seed {seed}", flush=True)
     ta = torch.from_numpy(a).cuda()
     tb = torch.from_numpy(b).cuda()
@@ -85,6 +90,19 @@ def test_splitk(mb, nb, kb, bb):
     _run(mb, nb, kb, bb, SPLITK, seed=9 + mb + 10 * nb + 100 * kb)
 
 
+# Every (k steps, column blocks) instantiation, K < 4 and N < 16 padding, and
+# runs long enough for several iterations per wave (m20 n2 k2, m18 n4 k6).
+@pytest.mark.parametrize("mb,nb,kb,bb", [(12, 0, 0, 0), (12, 1, 1, 0), (13, 2, 2, 0), (14, 5, 5, 0),
+                                         (12, 4, 6, 0), (12, 6, 4, 0), (15, 3, 3, 0), (12, 5, 3, 0),
+                                         (16, 4, 5, 0), (12, 6, 2, 0), (12, 5, 4, 0), (12, 6, 3, 0),
+                                         (20, 2, 2, 0), (18, 4, 6, 0)])
+@pytest.mark.parametrize("in_place", [False, True])
+def test_stream(mb, nb, kb, bb, in_place):
+    """Random C layouts take the scattered-address path for row blocks, the
+    planner's in-place layout the incremental one."""
+    _run(mb, nb, kb, bb, STREAM, seed=13 + mb + 10 * nb + 100 * kb, in_place=in_place)
+
+
 @pytest.mark.parametrize("mb,nb,kb,bb", [(10, 10, 8, 0), (3, 3, 17, 0), (16, 2, 2, 0), (4, 4, 4, 0),
                                          (11, 4, 6, 0)])
 def test_auto(mb, nb, kb, bb):
@@ -120,7 +138,8 @@ def _from_half_words(w, prec):
 @pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("mb,nb,kb,bb,kernel", [
     (8, 8, 7, 0, TILE), (9, 3, 6, 0, TALL), (3, 3, 14, 0, SPLITK), (10, 2, 2, 0, STEM), (3, 2, 4, 1, SMALL),
-    (7, 6, 9, 1, TILE), (0, 0, 9, 0, SPLITK), (5, 5, 0, 0, TILE)])
+    (7, 6, 9, 1, TILE), (0, 0, 9, 0, SPLITK), (5, 5, 0, 0, TILE), (13, 5, 5, 0, STREAM), (12, 2, 1, 0, STREAM),
+    (12, 4, 6, 0, STREAM)])
 def test_half_storage(prec, mb, nb, kb, bb, kernel):
     """16-bit storage, FP32 accumulate.  Inputs are mantissas of values around
     2^-30 (scaled by 2^30 into range); the output is rescaled by out_scale.

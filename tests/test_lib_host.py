@@ -123,3 +123,21 @@ def test_plan_workspace_and_reuse_levels(lib):
     # budget 0 bytes of cache except unavoidable: still plans
     p2 = tnc.Plan(net, reuse=True, cache_budget_bytes=256)
     assert p2.stats.flops_reused_slice >= p1.stats.flops_reused_slice - 1e-9
+
+
+def test_stream_class_rejects_unsupported_shapes():
+    """The stream kernel class refuses shapes outside its limits (batch bits,
+    fewer than 2^12 rows, N > 64, too many B entries per lane) when the step
+    is built, before any device work."""
+    import torch
+    from paper_2504_09186_amd import tnc
+    from paper_2504_09186_amd._lib import MitncError
+    for mb, nb, kb, bb in [(12, 6, 6, 0), (11, 2, 2, 0), (12, 2, 2, 1), (12, 7, 2, 0)]:
+        M = [1000 + i for i in range(mb)]
+        N = [2000 + i for i in range(nb)]
+        K = [3000 + i for i in range(kb)]
+        Bt = [-1 - i for i in range(bb)]
+        a = torch.zeros(1 << (mb + kb + bb), dtype=torch.complex64)
+        b = torch.zeros(1 << (kb + nb + bb), dtype=torch.complex64)
+        with pytest.raises(MitncError, match="stream kernel"):
+            tnc.contract(a, M + K + Bt, b, K + N + Bt, M + N + Bt, kernel=5)
