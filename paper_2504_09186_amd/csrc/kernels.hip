@@ -250,9 +250,10 @@ __global__ __launch_bounds__(256) void k_stem(StepDesc d) {
 // matrix sits in registers for the whole kernel and every wave streams 16-row
 // blocks of A from HBM straight into MFMA operands and writes C straight
 // back.  The MFMA computes C^T = B^T A^T, so that the 16 lanes of a lane
-// group walk 16 rows m of both A and C; those are the four lowest-address m
-// bits, and a load or store instruction moves whole 128-byte lines whatever
-// the positions of k and n.  3M split as in the tile kernels; padded k and n
+// group walk 16 rows m of both A and C: the four lowest-address m bits.  The
+// four lane groups take the two lowest-address k bits (loads) and n bits
+// (stores), so with those six bits low in the address an instruction moves
+// whole 128-byte lines.  3M split as in the tile kernels; padded k and n
 // carry zero B entries and padded n are never stored.
 //
 // Each wave owns a contiguous run of iters * R row blocks (R blocks per
@@ -261,9 +262,12 @@ __global__ __launch_bounds__(256) void k_stem(StepDesc d) {
 // the scattered-bit successor of block j, ((x | ~mask) + 1) & mask, because
 // m bits are sorted by A position; C uses the same step when its m bits are
 // in address order too, and a full scatter otherwise.
-template <int P, int KS, int NBLK>
+template <int P>
+inline constexpr int stream_loads() { return P == 0 ? 8 : 16; }
+
+template <int P, int KS, int NBLK, int LD = stream_loads<P>(), bool PIPE = false>
 __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
-  constexpr int R = (P == 0 ? 8 : 16) / KS > 0 ? (P == 0 ? 8 : 16) / KS : 1;  // row blocks per iteration
+  constexpr int R = LD / KS > 0 ? LD / KS : 1;  // row blocks per iteration
   using Raw = typename std::conditional<P == 0, float2, uint32_t>::type;
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   load_tables(d, tab);
@@ -271,13 +275,16 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lq = lane >> 4;
   const int K = 1 << d.kb, N = 1 << d.nb;
-  // B^T operand: lane holds B[k = 4 ks + lq][n = 16 cb + lr]
+  // MFMA row r of a column block is column n = (r >> 2) + 4 (r & 3) of it, so
+  // that output register i of lane group lq is column lq + 4 i: the lowest
+  // two n bits sit on lanes and a store instruction covers them.
+  // B^T operand: lane holds B[k = 4 ks + lq][n of row lr]
   float br[NBLK][KS], bi[NBLK][KS], bsum[NBLK][KS];
 #pragma unroll
   for (int cb = 0; cb < NBLK; ++cb)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + lq, n = 16 * cb + lr;
+      const int k = 4 * ks + lq, n = 16 * cb + (lr >> 2) + 4 * (lr & 3);
       float2 v = make_float2(0.f, 0.f);
       if (k < K && n < N) v = load_c<P>(d.B, scatter_bits(k, tab + T_BK, d.kb) + scatter_bits(n, tab + T_BN, d.nb));
       br[cb][ks] = v.x;
@@ -295,7 +302,7 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   for (int cb = 0; cb < NBLK; ++cb)
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      c_n[cb][i] = c_lane + (uint32_t)scatter_bits(16 * cb + 4 * lq + i, tab + T_CN, d.nb);
+      c_n[cb][i] = c_lane + (uint32_t)scatter_bits(16 * cb + lq + 4 * i, tab + T_CN, d.nb);
   // Row-block addresses are wave-uniform: keep them in scalar registers.
   const int hb = d.mb - 4;
   uint64_t mask_a = 0, mask_c = 0;
@@ -313,13 +320,21 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   uint64_t xc = uniform64(scatter_bits(blk0, tab + T_CM + 4, hb));
   const uint64_t c_elems = 1ull << (d.mb + d.nb);
   float mx = 0.f;
-  for (uint32_t it = 0; it < iters; ++it) {
-    Raw raw[R][KS];
+  Raw raw[R][KS], nxt[R][KS];
+  auto load = [&](Raw (&dst)[R][KS]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) raw[r][ks] = reinterpret_cast<const Raw*>(d.A)[xa + a_k[ks]];
+      for (int ks = 0; ks < KS; ++ks) dst[r][ks] = reinterpret_cast<const Raw*>(d.A)[xa + a_k[ks]];
       xa = ((xa | ~mask_a) + 1) & mask_a;
+    }
+  };
+  if (PIPE) load(raw);
+  for (uint32_t it = 0; it < iters; ++it) {
+    if (PIPE) {
+      if (it + 1 < iters) load(nxt);
+    } else {
+      load(raw);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -342,17 +357,23 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
           acc[2][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bsum[cb][ks], as, acc[2][cb], 0, 0, 0);
         }
       }
-      // lane holds C[m = lr][n = 16 cb + 4 lq + i] in register i
+      // lane holds C[m = lr][n = 16 cb + lq + 4 i] in register i
 #pragma unroll
       for (int cb = 0; cb < NBLK; ++cb)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (16 * cb + 4 * lq + i < N) {
+          if (16 * cb + lq + 4 * i < N) {
             const float t1 = acc[0][cb][i], t2 = acc[1][cb][i], t3 = acc[2][cb][i];
             mx = fmaxf(mx, epilogue_store<P>(d, xc + c_n[cb][i], make_float2(t1 - t2, t3 - t1 - t2), 0, c_elems));
           }
       if (c_sorted) xc = ((xc | ~mask_c) + 1) & mask_c;
       else xc = uniform64(scatter_bits(blk0 + (uint64_t)it * R + r + 1, tab + T_CM + 4, hb));
+    }
+    if (PIPE) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) raw[r][ks] = nxt[r][ks];
     }
   }
   record_max(d, mx);
@@ -782,36 +803,67 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
   store_c_tile<P, TM, WK, SC, C_ITEMS>(d, tab, reinterpret_cast<const float2*>(smem), mt, nt, batch);
 }
 
-// Deterministic FP64 sum of split-K partials in split order (blocked
-// summation, Sec. V-B / Eq. 3: each FP32 chain covers only K / splits terms).
+// Deterministic FP64 sum of split-K partials (blocked summation, Sec. V-B /
+// Eq. 3: each FP32 chain covers only K / splits terms).  A workgroup takes
+// 256 / 2^rb consecutive output entries and 2^rb split rows (rb <= 4): thread
+// (row r, column c) sums splits r, r + 2^rb, ... of entry c in FP64, then row
+// 0 adds the row sums in row order, so the result does not depend on timing.
+// Loads of one row are consecutive entries (coalesced); the 2^rb rows keep
+// that many independent load streams per entry in flight.
 template <int P>
-__global__ __launch_bounds__(256) void k_reduce(StepDesc d) {
+__global__ __launch_bounds__(256) void k_reduce(StepDesc d, int rb) {
+  __shared__ double2 red[256];
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
+  const float2* part = reinterpret_cast<const float2*>(d.part);
+  const uint64_t splits = 1ull << d.ks_bits;
+  const int cols = 256 >> rb;
+  const int r = threadIdx.x / cols, cl = threadIdx.x % cols;
   float mx = 0.f;
-  for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < c_elems; c += (uint64_t)gridDim.x * 256) {
-    const float2* part = reinterpret_cast<const float2*>(d.part);
-    const uint64_t splits = 1ull << d.ks_bits;
+  for (uint64_t c0 = (uint64_t)blockIdx.x * cols; c0 < c_elems; c0 += (uint64_t)gridDim.x * cols) {
+    const uint64_t c = c0 + cl;
     double sx = 0, sy = 0;
-    for (uint64_t s = 0; s < splits; ++s) {
-      const float2 v = part[s * c_elems + c];
-      sx += v.x;
-      sy += v.y;
+    if (c < c_elems) {
+      uint64_t sp = r;
+      for (; sp + 3 * (1ull << rb) < splits; sp += 4ull << rb) {
+        float2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = part[(sp + ((uint64_t)u << rb)) * c_elems + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          sx += v[u].x;
+          sy += v[u].y;
+        }
+      }
+      for (; sp < splits; sp += 1ull << rb) {
+        const float2 v = part[sp * c_elems + c];
+        sx += v.x;
+        sy += v.y;
+      }
     }
-    if (d.mode == EPI_ACC64) {
-      double2* acc = reinterpret_cast<double2*>(d.acc);
-      double2 o = acc[c];
-      o.x += sx * d.acc_scale;
-      o.y += sy * d.acc_scale;
-      acc[c] = o;
-    } else if constexpr (P == 0) {
-      const float2 v = make_float2((float)sx, (float)sy);
-      reinterpret_cast<float2*>(d.C)[c] = v;
-      mx = fmaxf(mx, absmax2(v));
-    } else {
-      const float2 v = make_float2((float)(sx * d.out_scale), (float)(sy * d.out_scale));
-      reinterpret_cast<uint32_t*>(d.C)[c] = pack<P>(v);
-      mx = fmaxf(mx, absmax2(v));
+    red[threadIdx.x] = make_double2(sx, sy);
+    __syncthreads();
+    if (r == 0 && c < c_elems) {
+      for (int q = 1; q < (1 << rb); ++q) {
+        sx += red[q * cols + cl].x;
+        sy += red[q * cols + cl].y;
+      }
+      if (d.mode == EPI_ACC64) {
+        double2* acc = reinterpret_cast<double2*>(d.acc);
+        double2 o = acc[c];
+        o.x += sx * d.acc_scale;
+        o.y += sy * d.acc_scale;
+        acc[c] = o;
+      } else if constexpr (P == 0) {
+        const float2 v = make_float2((float)sx, (float)sy);
+        reinterpret_cast<float2*>(d.C)[c] = v;
+        mx = fmaxf(mx, absmax2(v));
+      } else {
+        const float2 v = make_float2((float)(sx * d.out_scale), (float)(sy * d.out_scale));
+        reinterpret_cast<uint32_t*>(d.C)[c] = pack<P>(v);
+        mx = fmaxf(mx, absmax2(v));
+      }
     }
+    __syncthreads();
   }
   record_max(d, mx);
 }
@@ -954,8 +1006,10 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1
       if (ev1) (void)hipEventRecord(ev1, s);
       if (e != hipSuccess || d.ks_bits == 0) return e;
       d.mode = final_mode;
-      const uint64_t rb = (c_elems + 255) / 256;
-      hipLaunchKernelGGL((k_reduce<P>), dim3((unsigned)(rb < 8192 ? rb : 8192)), dim3(256), 0, s, d);
+      // split rows per workgroup: up to 16, fewer when the splits are few
+      const int rb = d.ks_bits < 4 ? d.ks_bits : 4;
+      const uint64_t groups = (c_elems + (256 >> rb) - 1) / (256 >> rb);
+      hipLaunchKernelGGL((k_reduce<P>), dim3((unsigned)(groups < 8192 ? groups : 8192)), dim3(256), 0, s, d, rb);
       return hipGetLastError();
     }
     default:

@@ -115,14 +115,22 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   std::sort(M.begin(), M.end(), by(pa));
   std::sort(N.begin(), N.end(), by(pb));
   std::sort(Bt.begin(), Bt.end(), by(pa));
-  // K order: indices among the lowest 4 address bits of A or B first (they
-  // must be inside every tile for coalesced loads), then by A position.
-  std::sort(K.begin(), K.end(), [&](int64_t u, int64_t v) {
-    int lu = std::min(pa[u], pb[u]) < 4 ? 0 : 1, lv = std::min(pa[v], pb[v]) < 4 ? 0 : 1;
-    if (lu != lv) return lu < lv;
-    if (lu == 0) return std::min(pa[u], pb[u]) < std::min(pa[v], pb[v]);
-    return pa[u] < pa[v];
-  });
+  const int kclass = force_kernel >= 0 ? force_kernel
+                                       : choose_class((int)M.size(), (int)N.size(), (int)K.size(), (int)Bt.size());
+  if (kclass == MITNC_K_STREAM) {
+    // Stream kernel: the two lowest k bits ride on lanes next to the four
+    // lowest m bits, so K goes by A position (B is small and cached).
+    std::sort(K.begin(), K.end(), by(pa));
+  } else {
+    // K order: indices among the lowest 4 address bits of A or B first (they
+    // must be inside every tile for coalesced loads), then by A position.
+    std::sort(K.begin(), K.end(), [&](int64_t u, int64_t v) {
+      int lu = std::min(pa[u], pb[u]) < 4 ? 0 : 1, lv = std::min(pa[v], pb[v]) < 4 ? 0 : 1;
+      if (lu != lv) return lu < lv;
+      if (lu == 0) return std::min(pa[u], pb[u]) < std::min(pa[v], pb[v]);
+      return pa[u] < pa[v];
+    });
+  }
   // Output layout.
   std::vector<int64_t> C;
   if (root_layout) {
@@ -176,7 +184,7 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   put(d.cn, N, pc);
   put(d.cb, Bt, pc);
 
-  st.kclass = force_kernel >= 0 ? force_kernel : choose_class(d.mb, d.nb, d.kb, d.bb);
+  st.kclass = kclass;
   if (st.kclass < MITNC_K_SMALL || st.kclass > MITNC_K_STREAM) fail(MITNC_INVALID_ARG, "unknown kernel class");
   if (st.kclass == MITNC_K_STEM && (d.kb > 4 || d.nb > 2))
     fail(MITNC_UNSUPPORTED, "stem kernel needs at most 4 contracted and 2 new indices");
