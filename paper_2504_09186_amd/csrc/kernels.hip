@@ -265,13 +265,32 @@ __global__ __launch_bounds__(256) void k_stem(StepDesc d) {
 template <int P>
 inline constexpr int stream_loads() { return P == 0 ? 8 : 16; }
 
-template <int P, int KS, int NBLK, int LD = stream_loads<P>(), bool PIPE = false>
-__global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
+// Output entry of a stream step.  EPI: 0 = store, 1 = store and return the
+// stored magnitude (statistics), 2 = add into the FP64 result.
+template <int P, int EPI>
+__device__ __forceinline__ float stream_store(const StepDesc& d, uint64_t addr, float2 v) {
+  if constexpr (EPI == 2) {
+    double2* acc = reinterpret_cast<double2*>(d.acc);
+    double2 o = acc[addr];
+    o.x += (double)v.x * d.acc_scale;
+    o.y += (double)v.y * d.acc_scale;
+    acc[addr] = o;
+    return 0.f;
+  } else {
+    if constexpr (P == 0) {
+      reinterpret_cast<float2*>(d.C)[addr] = v;
+    } else {
+      v = make_float2(v.x * d.out_scale, v.y * d.out_scale);
+      reinterpret_cast<uint32_t*>(d.C)[addr] = pack<P>(v);
+    }
+    return EPI == 1 ? absmax2(v) : 0.f;
+  }
+}
+
+template <int P, int KS, int NBLK, int LD, bool PIPE, int EPI>
+__device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* tab, uint32_t iters) {
   constexpr int R = LD / KS > 0 ? LD / KS : 1;  // row blocks per iteration
   using Raw = typename std::conditional<P == 0, float2, uint32_t>::type;
-  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
-  load_tables(d, tab);
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lq = lane >> 4;
   const int K = 1 << d.kb, N = 1 << d.nb;
@@ -291,7 +310,9 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
       bi[cb][ks] = v.y;
       bsum[cb][ks] = v.x + v.y;
     }
-  const bool kvalid = lq < K;  // only K < 4 pads inside a k step
+  // Only K < 4 (one k step) pads inside a k step; the padded lanes read an
+  // aliased in-bounds entry and are zeroed.
+  const bool kvalid = KS > 1 || lq < K;
   const uint32_t a_lane = (uint32_t)scatter_bits(lr, tab + T_AM, 4);
   const uint32_t c_lane = (uint32_t)scatter_bits(lr, tab + T_CM, 4);
   uint32_t a_k[KS];
@@ -301,8 +322,7 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
 #pragma unroll
   for (int cb = 0; cb < NBLK; ++cb)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      c_n[cb][i] = c_lane + (uint32_t)scatter_bits(16 * cb + lq + 4 * i, tab + T_CN, d.nb);
+    for (int i = 0; i < 4; ++i) c_n[cb][i] = c_lane + (uint32_t)scatter_bits(16 * cb + lq + 4 * i, tab + T_CN, d.nb);
   // Row-block addresses are wave-uniform: keep them in scalar registers.
   const int hb = d.mb - 4;
   uint64_t mask_a = 0, mask_c = 0;
@@ -318,24 +338,27 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   const uint64_t blk0 = uniform64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * iters * R);
   uint64_t xa = uniform64(scatter_bits(blk0, tab + T_AM + 4, hb));
   uint64_t xc = uniform64(scatter_bits(blk0, tab + T_CM + 4, hb));
-  const uint64_t c_elems = 1ull << (d.mb + d.nb);
+  const Raw* A = reinterpret_cast<const Raw*>(d.A);
   float mx = 0.f;
   Raw raw[R][KS], nxt[R][KS];
   auto load = [&](Raw (&dst)[R][KS]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) dst[r][ks] = reinterpret_cast<const Raw*>(d.A)[xa + a_k[ks]];
+      for (int ks = 0; ks < KS; ++ks) dst[r][ks] = A[xa + a_k[ks]];
       xa = ((xa | ~mask_a) + 1) & mask_a;
     }
   };
   if (PIPE) load(raw);
   for (uint32_t it = 0; it < iters; ++it) {
+    // All loads of an iteration are issued before any of them is used, so a
+    // wave waits for memory once per iteration.
     if (PIPE) {
       if (it + 1 < iters) load(nxt);
     } else {
       load(raw);
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       v4f acc[3][NBLK];
@@ -364,7 +387,7 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
         for (int i = 0; i < 4; ++i)
           if (16 * cb + lq + 4 * i < N) {
             const float t1 = acc[0][cb][i], t2 = acc[1][cb][i], t3 = acc[2][cb][i];
-            mx = fmaxf(mx, epilogue_store<P>(d, xc + c_n[cb][i], make_float2(t1 - t2, t3 - t1 - t2), 0, c_elems));
+            mx = fmaxf(mx, stream_store<P, EPI>(d, xc + c_n[cb][i], make_float2(t1 - t2, t3 - t1 - t2)));
           }
       if (c_sorted) xc = ((xc | ~mask_c) + 1) & mask_c;
       else xc = uniform64(scatter_bits(blk0 + (uint64_t)it * R + r + 1, tab + T_CM + 4, hb));
@@ -376,6 +399,18 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
         for (int ks = 0; ks < KS; ++ks) raw[r][ks] = nxt[r][ks];
     }
   }
+  return mx;
+}
+
+template <int P, int KS, int NBLK, int LD = stream_loads<P>(), bool PIPE = false>
+__global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
+  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  load_tables(d, tab);
+  __syncthreads();
+  float mx;
+  if (d.mode == EPI_ACC64) mx = stream_body<P, KS, NBLK, LD, PIPE, 2>(d, tab, iters);
+  else if (d.stats) mx = stream_body<P, KS, NBLK, LD, PIPE, 1>(d, tab, iters);
+  else mx = stream_body<P, KS, NBLK, LD, PIPE, 0>(d, tab, iters);
   record_max(d, mx);
 }
 
@@ -387,19 +422,22 @@ struct TileSlot {
   int lo, hi;  // (m, k) for A tiles, (k, n) for B tiles, (m, n) for C tiles
 };
 
+// Unrolled over the at most 16 tile bits so that the LDS reads of one decode
+// are independent of each other (two round trips instead of two per bit).
 __device__ __forceinline__ TileSlot decode_slot(int e, int nbits, const uint8_t* codes, const uint8_t* tab,
                                                 int first_cls, int off_first, int off_second) {
   TileSlot r{0, 0, 0};
-  for (int b = 0; b < nbits; ++b) {
-    const int bit = (e >> b) & 1;
-    const uint8_t code = codes[b];
-    const int idx = code & 31;
-    if ((code >> 5) == first_cls) {
-      r.lo |= bit << idx;
-      r.off |= (uint32_t)bit << tab[off_first + idx];
-    } else {
-      r.hi |= bit << idx;
-      r.off |= (uint32_t)bit << tab[off_second + idx];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    if (b < nbits) {
+      const uint8_t code = codes[b];
+      const int idx = code & 31;
+      const bool first = (code >> 5) == first_cls;
+      const int pos = tab[(first ? off_first : off_second) + idx];
+      const int bit = (e >> b) & 1;
+      if (first) r.lo |= bit << idx;
+      else r.hi |= bit << idx;
+      r.off |= (uint32_t)bit << pos;
     }
   }
   return r;
@@ -421,11 +459,15 @@ __device__ __forceinline__ void store_c_tile(const StepDesc& d, const uint8_t* t
   const bool active = tid < (1 << nlo);
   const TileSlot lo = decode_slot(tid & ((1 << nlo) - 1), nlo, tab + T_CTILE, tab, TB_M, T_CM, T_CN);
   const int n_hi = 1 << (nc - nlo);
+  // The high parts (uniform per j) are decoded once, one per thread, into LDS.
+  __shared__ TileSlot hi_tab[C_ITEMS];
+  if (tid < n_hi && tid < C_ITEMS) hi_tab[tid] = decode_slot(tid << nlo, nc, tab + T_CTILE, tab, TB_M, T_CM, T_CN);
+  __syncthreads();
   float mx = 0.f;
 #pragma unroll
   for (int j = 0; j < C_ITEMS; ++j) {
     if (j >= n_hi) break;
-    const TileSlot hi = decode_slot(j << nlo, nc, tab + T_CTILE, tab, TB_M, T_CM, T_CN);  // uniform
+    const TileSlot hi = hi_tab[j];
     const int mi = lo.lo | hi.lo, ni = lo.hi | hi.hi;
     float2 v = make_float2(0.f, 0.f);
 #pragma unroll
