@@ -132,7 +132,10 @@ int32_t mitnc_index_overhead(const mitnc_network* net, int64_t label, double* ov
  * FP16/BF16 MFMA with FP32 accumulation, FP64 cross-slice sum; requires
  * mitnc_calibrate after upload); reuse: 1 = recompute a tree node only when
  * the sliced indices below it change between consecutive slices (Sec. III-B,
- * pre-lifetime reuse), 0 = recompute every node for every slice;
+ * pre-lifetime reuse), and contract small subtrees that depend on sliced
+ * indices once for all slices, keeping those indices (at most 2^14 entries
+ * per intermediate; not in differentiable plans), 0 = recompute every node
+ * for every slice;
  * cache_budget_bytes: maximum device bytes of tensors kept across slices
  * (0 = unlimited; Sec. III-B dynamic tuning demotes the largest cached
  * tensors); force_kernel: -1 = automatic kernel choice, otherwise a kernel
@@ -155,8 +158,9 @@ typedef struct mitnc_plan_stats {
   int32_t n_steps;            /* contraction steps per full slice */
   int32_t max_log2_elems;     /* largest intermediate */
   int32_t n_kernel_classes;
-  double flops_full_slice;    /* real flops of one slice without reuse */
-  double flops_reused_slice;  /* average real flops per slice with reuse over 2^S slices */
+  double flops_full_slice;    /* real flops of one slice without reuse or hoisting */
+  double flops_reused_slice;  /* average real flops per slice actually executed over 2^S slices
+                                 (reuse of unchanged subtrees, hoisted subtrees run once) */
   double bytes_full_slice;    /* algorithmic HBM bytes of one slice without reuse */
   double bytes_reused_slice;
   int32_t steps_by_class[8];  /* step count per kernel class */

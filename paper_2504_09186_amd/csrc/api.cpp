@@ -326,10 +326,10 @@ int32_t mitnc_plan_query(const mitnc_plan* P, mitnc_plan_stats* st) {
     st->n_kernel_classes = 6;
     double nsl = std::ldexp(1.0, P->S);
     for (auto& s : P->steps) {
-      st->flops_full_slice += s.flops;
-      st->bytes_full_slice += s.bytes;
+      st->flops_full_slice += s.flops_slice;
+      st->bytes_full_slice += s.bytes_slice;
       st->steps_by_class[s.kclass] += 1;
-      st->flops_by_class[s.kclass] += s.flops;
+      st->flops_by_class[s.kclass] += s.flops_slice;
       // how many of the 2^S slices (run in order from 0) recompute this step
       int lo = P->nodes[s.out].lo;
       double runs;
@@ -408,22 +408,27 @@ static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t s
                              hipStream_t s, int prec, bool stats) {
   StepDesc d = (prec == MITNC_C64 && P->opts.precision != MITNC_C64) ? st.d64 : st.d;
   const bool half = prec != MITNC_C64;
-  auto ptr = [&](int node) -> char* {
+  // Sliced leaves and hoisted results hold every value of their sliced
+  // indices: a slice reads the sub-tensor at its own values (a hoisted step
+  // writes the whole tensor).
+  auto ptr = [&](int node, bool operand) -> char* {
     const PlanNode& nd = P->nodes[node];
+    uint64_t e = 0;
+    if (operand)
+      for (auto& [sb, pb] : nd.slice_bits) e += ((slice >> sb) & 1ull) << pb;
+    const uint64_t esz = half ? 4 : 8;
     uint64_t off;
     if (nd.region == 0) {
-      uint64_t e = 0;
-      for (auto& [sb, pb] : nd.slice_bits) e += ((slice >> sb) & 1ull) << pb;
-      off = half ? P->off_leaf_half + nd.offset / 2 + e * 4 : nd.offset + e * 8;
+      off = half ? P->off_leaf_half + nd.offset / 2 : nd.offset;
     } else if (nd.region == 1) {
       off = P->off_persist + nd.offset;
     } else {
       off = P->off_arena + nd.offset;
     }
-    return base + off;
+    return base + off + e * esz;
   };
-  d.A = ptr(st.a);
-  d.B = ptr(st.b);
+  d.A = ptr(st.a, true);
+  d.B = ptr(st.b, true);
   d.prec = prec;
   if (!half) {
     d.out_scale = 1.f;
@@ -434,7 +439,7 @@ static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t s
     d.acc = acc;
     d.mode = EPI_ACC64;
   } else {
-    d.C = ptr(st.out);
+    d.C = ptr(st.out, false);
     d.acc = nullptr;
     d.mode = EPI_STORE;
   }

@@ -160,6 +160,7 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   O.pos.resize(C.size());
   std::iota(O.pos.begin(), O.pos.end(), 0);
   O.rank = (int)C.size();
+  O.full_rank = O.rank;
 
   StepDesc& d = st.d;
   std::memset(&d, 0, sizeof(d));
@@ -246,7 +247,7 @@ static void verify_memory_plan(const mitnc_plan* P, uint64_t n_slices) {
     const PlanNode& nd = P->nodes[node];
     uint64_t base = nd.region == 0 ? 0 : nd.region == 1 ? P->off_persist : P->off_arena;
     lo = base + nd.offset;
-    hi = lo + (nd.region == 0 ? P->leaf_data[nd.leaf_id].size() * 4 : (8ull << nd.rank));
+    hi = lo + (nd.region == 0 ? P->leaf_data[nd.leaf_id].size() * 4 : (8ull << nd.full_rank));
   };
   for (int i = 0; i < P->n_leaves; ++i) {
     uint64_t lo, hi;
@@ -391,6 +392,49 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   auto sym = sym_run(sn, net->path, slm);
   P->max_log2 = sym_max_bits(sn, sym, slm);
 
+  // Hoisting (same aim as the reuse of Sec. III-B, applied to sliced indices):
+  // a small subtree that depends on sliced indices would be recomputed for
+  // every slice, one tiny launch per step.  Instead it is contracted once
+  // with its sliced indices kept as ordinary (batch) indices, and each slice
+  // reads the sub-tensor of its index values, as it does for a sliced leaf.
+  // Chosen: maximal non-root subtrees whose every intermediate, sliced bits
+  // included, has at most 2^kHoistBits entries.
+  constexpr int kHoistBits = 14;
+  const int nsteps = (int)net->path.size();
+  std::vector<uint64_t> smask(n + nsteps, 0);  // slice-id bits below each node
+  for (int i = 0; i < n; ++i)
+    for (int64_t x : net->leaves[i].labels) {
+      auto it = slice_bit.find(x);
+      if (it != slice_bit.end()) smask[i] |= 1ull << it->second;
+    }
+  std::vector<char> fits(n + nsteps, 1);  // whole subtree within the size cap
+  for (int s = 0; s < nsteps; ++s) {
+    const int a = net->path[s].first, b = net->path[s].second, o = n + s;
+    smask[o] = smask[a] | smask[b];
+    const int bits = (int)sym[s].c.size() + __builtin_popcountll(smask[o]);
+    fits[o] = fits[a] && fits[b] && bits <= kHoistBits;
+  }
+  std::vector<char> in_hoist(n + nsteps, 0);
+  std::vector<int> hoist_root(n + nsteps, 0);
+  if (opts.reuse && !opts.differentiable) {
+    std::vector<int> parent(n + nsteps, -1);
+    for (int s = 0; s < nsteps; ++s) parent[net->path[s].first] = parent[net->path[s].second] = n + s;
+    for (int s = 0; s < nsteps - 1; ++s) {
+      const int o = n + s;
+      const int p = parent[o];
+      const bool parent_hoistable = p >= 0 && p != n + nsteps - 1 && fits[p] && smask[p] != 0;
+      if (fits[o] && smask[o] != 0 && !parent_hoistable) hoist_root[o] = 1;
+    }
+    // mark subtrees (children come before parents in path order)
+    for (int s = nsteps - 1; s >= 0; --s) {
+      const int o = n + s;
+      if (hoist_root[o]) in_hoist[o] = 1;
+      if (in_hoist[o]) in_hoist[net->path[s].first] = in_hoist[net->path[s].second] = 1;
+    }
+  }
+  std::map<int, int64_t> label_of_bit;
+  for (auto& [x, b] : slice_bit) label_of_bit[b] = x;
+
   // Leaves.
   P->nodes.resize(n + net->path.size());
   uint64_t off = 0;
@@ -402,15 +446,17 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
     nd.region = 0;
     for (size_t b = 0; b < L.labels.size(); ++b) {
       auto it = slice_bit.find(L.labels[b]);
-      if (it != slice_bit.end()) {
+      if (it != slice_bit.end()) nd.dmask |= 1ull << it->second;
+      if (it != slice_bit.end() && !in_hoist[i]) {
         nd.slice_bits.push_back({it->second, (int)b});
-        nd.dmask |= 1ull << it->second;
       } else {
         nd.labels.push_back(L.labels[b]);
         nd.pos.push_back((int)b);
       }
     }
     nd.rank = (int)nd.labels.size();
+    nd.full_rank = (int)L.labels.size();
+    nd.hoisted = in_hoist[i];
     std::vector<float> h(L.data.size() * 2);
     for (size_t e = 0; e < L.data.size(); ++e) {
       h[2 * e] = (float)L.data[e].real();
@@ -447,6 +493,10 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
     P->nodes[st.b].parent = st.out;
     std::vector<int64_t> cset;
     for (int x : sym[s].c) cset.push_back(sn.label_id[x]);
+    const bool hz = in_hoist[st.out];
+    if (hz)  // sliced indices below stay open
+      for (int b = 0; b < S; ++b)
+        if (smask[st.out] >> b & 1) cset.push_back(label_of_bit[b]);
     if (opts.precision != MITNC_C64) {
       // Calibration slices run in complex64, whose tiles differ: keep both.
       build_step(P.get(), st, cset, st.root ? &net->output_lsb : nullptr, opts.force_kernel, MITNC_C64);
@@ -459,6 +509,29 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
     }
     PlanNode& O = P->nodes[st.out];
     O.dmask = P->nodes[st.a].dmask | P->nodes[st.b].dmask;
+    O.hoisted = hz;
+    // Work of the step inside one slice: a hoisted step covers 2^(sliced
+    // indices below it) slices at once.
+    const double per = hz ? std::ldexp(1.0, -__builtin_popcountll(smask[st.out])) : 1.0;
+    st.flops_slice = st.flops * per;
+    st.bytes_slice = st.bytes * per;
+    if (hoist_root[st.out]) {
+      // Seen from its consumer the hoisted result is sliced like a leaf.
+      std::vector<int64_t> lab;
+      std::vector<int> pos;
+      for (size_t i = 0; i < O.labels.size(); ++i) {
+        auto it = slice_bit.find(O.labels[i]);
+        if (it != slice_bit.end()) {
+          O.slice_bits.push_back({it->second, O.pos[i]});
+        } else {
+          lab.push_back(O.labels[i]);
+          pos.push_back(O.pos[i]);
+        }
+      }
+      O.labels = lab;
+      O.pos = pos;
+      O.rank = (int)lab.size();
+    }
   }
   // Recompute levels.
   for (auto& nd : P->nodes) {
@@ -467,6 +540,8 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   }
   if (!opts.reuse)
     for (auto& nd : P->nodes) nd.lo = 0;
+  for (auto& nd : P->nodes)
+    if (nd.hoisted) nd.lo = kLevelNever;
   // Region choice: a node recomputed less often than its parent is kept.
   auto assign_regions = [&]() {
     uint64_t pb = 0;
@@ -478,7 +553,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
       }
       int lp = P->nodes[O.parent].lo;
       O.region = (O.lo > lp) ? 1 : 2;
-      if (O.region == 1) pb += std::ldexp(8.0, O.rank);
+      if (O.region == 1) pb += std::ldexp(8.0, O.full_rank);
     }
     return pb;
   };
@@ -488,7 +563,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
       int best = -1;
       for (size_t s = 0; s < P->steps.size(); ++s) {
         PlanNode& O = P->nodes[P->steps[s].out];
-        if (O.region == 1 && (best < 0 || O.rank > P->nodes[best].rank)) best = P->steps[s].out;
+        if (O.region == 1 && !O.hoisted && (best < 0 || O.rank > P->nodes[best].rank)) best = P->steps[s].out;
       }
       if (best < 0) break;
       P->nodes[best].lo = P->nodes[P->nodes[best].parent].lo;
@@ -507,7 +582,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
     PlanNode& O = P->nodes[st.out];
     if (O.region == 1) {
       O.offset = poff;
-      poff = align_up(poff + (8ull << O.rank), 256);
+      poff = align_up(poff + (8ull << O.full_rank), 256);
     }
   }
   P->persist_bytes = poff;
@@ -520,7 +595,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
     // never write over its own inputs); the operands are released afterwards.
     PlanNode& O = P->nodes[st.out];
     if (O.region == 2) {
-      uint64_t sz = align_up(8ull << O.rank, 256);
+      uint64_t sz = align_up(8ull << O.full_rank, 256);
       std::vector<std::pair<uint64_t, uint64_t>> sorted = live;
       std::sort(sorted.begin(), sorted.end());
       uint64_t cand = 0;

@@ -19,6 +19,8 @@ struct PlanNode {
   std::vector<int> pos;         // physical address bit of each label
   std::vector<std::pair<int, int>> slice_bits;  // (slice-id bit, physical bit) of sliced labels
   int rank = 0;                 // labels.size()
+  int full_rank = 0;            // address bits of the stored tensor (rank plus sliced bits kept, see hoisted)
+  bool hoisted = false;         // computed once for all slices, sliced indices kept as ordinary ones
   uint64_t dmask = 0;           // slice-id bits this node depends on
   int lo = kLevelNever;         // recompute when a slice-id bit <= lo changes
   int parent = -1;
@@ -35,6 +37,7 @@ struct PlanStep {
   StepDesc d{};                  // pointer fields filled at launch
   StepDesc d64{};                // FP16/BF16 plans: complex64 geometry for calibration slices
   double flops = 0, bytes = 0;
+  double flops_slice = 0, bytes_slice = 0;  // the same step within one slice (differs when hoisted)
   uint64_t part_bytes = 0;       // split-K partials, max over d and d64
 };
 
