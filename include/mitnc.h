@@ -177,6 +177,51 @@ int32_t mitnc_plan_query(const mitnc_plan* plan, mitnc_plan_stats* stats);
  * output log2 size, is-root. */
 int32_t mitnc_plan_steps(const mitnc_plan* plan, double* info);
 
+/* Introspection of a plan's address maps and schedule (host only; used to
+ * re-execute a plan independently on the host and to inspect layouts).
+ * Nodes: leaves 0 .. n_leaves-1 in canonical order, then the output of step
+ * s is node n_leaves + s.  A node's tensor is a flat array whose address
+ * bits are binary indices (Sec. V-A); a step computes
+ *   C[b, m, n] = sum_k A[b, m, k] B[b, k, n]
+ * with logical bit i of m at address bit am[i] of A and cm[i] of C, and so
+ * on (TTGT with the permutation applied as an address map, Sec. II-A).
+ * Errors: INVALID_ARG for a null pointer or an id out of range. */
+typedef struct mitnc_step_info {
+  int32_t a, b, out;               /* node ids; a is the larger operand */
+  int32_t root;                    /* 1: adds C into the complex128 result */
+  int32_t kernel_class;
+  int32_t mb, nb, kb, bb;          /* bit counts of m, n, k and batch */
+  uint8_t am[32], ak[32], ab[32];  /* A address bit of each m, k, batch bit */
+  uint8_t bk[32], bn[32], bbt[32]; /* B address bit of each k, n, batch bit */
+  uint8_t cm[32], cn[32], cb[32];  /* C address bit of each m, n, batch bit */
+} mitnc_step_info;
+int32_t mitnc_plan_step_info(const mitnc_plan* plan, int32_t step, mitnc_step_info* info);
+
+/* ws_offset: byte offset of the node's tensor in the workspace of a
+ * complex64 run (UINT64_MAX for the root, which is the caller's result);
+ * level: -1 = computed once per slice range, else recomputed for slice s
+ * when ctz(s) >= level (Sec. III-B); a slice reads the sub-tensor at
+ * element offset sum_j ((s >> slice_bit[j]) & 1) << slice_pos[j] (sliced
+ * leaves and hoisted results; the step that writes a hoisted result writes
+ * all 2^full_rank entries). */
+typedef struct mitnc_node_info {
+  int32_t is_leaf;
+  int32_t rank;                    /* address bits seen by one slice */
+  int32_t full_rank;               /* address bits stored */
+  int32_t level;
+  int32_t hoisted;                 /* contracted once for all slices */
+  int32_t n_slice_bits;
+  int32_t slice_bit[64];
+  int32_t slice_pos[64];
+  uint64_t ws_offset;
+} mitnc_node_info;
+int32_t mitnc_plan_node_info(const mitnc_plan* plan, int32_t node, mitnc_node_info* info);
+
+/* The complex64 entries (re, im interleaved) a plan uploads for leaf
+ * `leaf`: 2^full_rank entries; out may be null to query n_floats. */
+int32_t mitnc_plan_leaf_data(const mitnc_plan* plan, int32_t leaf, float* out, uint64_t capacity_floats,
+                             uint64_t* n_floats);
+
 /* Copies leaves into the caller-owned device workspace (ws, ws_bytes) and
  * resets the cross-slice cache.  Errors: WORKSPACE_TOO_SMALL, HIP_ERROR. */
 int32_t mitnc_plan_upload(mitnc_plan* plan, void* ws, size_t ws_bytes, void* stream);

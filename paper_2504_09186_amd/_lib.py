@@ -52,6 +52,19 @@ class mitnc_plan_stats(C.Structure):
                 ("flops_reverse_slice", C.c_double)]
 
 
+class mitnc_step_info(C.Structure):
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32), ("out", C.c_int32), ("root", C.c_int32),
+                ("kernel_class", C.c_int32), ("mb", C.c_int32), ("nb", C.c_int32), ("kb", C.c_int32),
+                ("bb", C.c_int32)] + [(f, C.c_uint8 * 32) for f in ("am", "ak", "ab", "bk", "bn", "bbt",
+                                                                     "cm", "cn", "cb")]
+
+
+class mitnc_node_info(C.Structure):
+    _fields_ = [("is_leaf", C.c_int32), ("rank", C.c_int32), ("full_rank", C.c_int32), ("level", C.c_int32),
+                ("hoisted", C.c_int32), ("n_slice_bits", C.c_int32), ("slice_bit", C.c_int32 * 64),
+                ("slice_pos", C.c_int32 * 64), ("ws_offset", C.c_uint64)]
+
+
 _VP = C.c_void_p
 _I32 = C.c_int32
 _SIGS = {
@@ -68,6 +81,9 @@ _SIGS = {
     "mitnc_plan_create": [_VP, C.POINTER(mitnc_plan_opts), C.POINTER(_VP)],
     "mitnc_plan_query": [_VP, C.POINTER(mitnc_plan_stats)],
     "mitnc_plan_steps": [_VP, C.POINTER(C.c_double)],
+    "mitnc_plan_step_info": [_VP, _I32, C.POINTER(mitnc_step_info)],
+    "mitnc_plan_node_info": [_VP, _I32, C.POINTER(mitnc_node_info)],
+    "mitnc_plan_leaf_data": [_VP, _I32, C.POINTER(C.c_float), C.c_uint64, C.POINTER(C.c_uint64)],
     "mitnc_plan_upload": [_VP, _VP, C.c_size_t, _VP],
     "mitnc_execute": [_VP, _VP, C.c_size_t, C.c_uint64, C.c_uint64, _VP, _VP],
     "mitnc_plan_timing": [_VP, _I32],

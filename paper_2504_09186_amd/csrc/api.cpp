@@ -368,6 +368,73 @@ int32_t mitnc_plan_steps(const mitnc_plan* P, double* info) {
   });
 }
 
+int32_t mitnc_plan_step_info(const mitnc_plan* P, int32_t step, mitnc_step_info* info) {
+  return guarded([&] {
+    if (!P || !info) fail(MITNC_INVALID_ARG, "null argument");
+    if (step < 0 || step >= (int32_t)P->steps.size()) fail(MITNC_INVALID_ARG, "step out of range");
+    const PlanStep& s = P->steps[step];
+    const StepDesc& d = s.d;
+    std::memset(info, 0, sizeof(*info));
+    info->a = s.a;
+    info->b = s.b;
+    info->out = s.out;
+    info->root = s.root;
+    info->kernel_class = s.kclass;
+    info->mb = d.mb;
+    info->nb = d.nb;
+    info->kb = d.kb;
+    info->bb = d.bb;
+    std::memcpy(info->am, d.am, 32);
+    std::memcpy(info->ak, d.ak, 32);
+    std::memcpy(info->ab, d.ab, 32);
+    std::memcpy(info->bk, d.bk, 32);
+    std::memcpy(info->bn, d.bn, 32);
+    std::memcpy(info->bbt, d.bbt, 32);
+    std::memcpy(info->cm, d.cm, 32);
+    std::memcpy(info->cn, d.cn, 32);
+    std::memcpy(info->cb, d.cb, 32);
+  });
+}
+
+int32_t mitnc_plan_node_info(const mitnc_plan* P, int32_t node, mitnc_node_info* info) {
+  return guarded([&] {
+    if (!P || !info) fail(MITNC_INVALID_ARG, "null argument");
+    if (node < 0 || node >= (int32_t)P->nodes.size()) fail(MITNC_INVALID_ARG, "node out of range");
+    const PlanNode& nd = P->nodes[node];
+    std::memset(info, 0, sizeof(*info));
+    info->is_leaf = nd.leaf;
+    info->rank = nd.rank;
+    info->full_rank = nd.full_rank;
+    info->level = nd.lo >= kLevelNever ? -1 : nd.lo;
+    info->hoisted = nd.hoisted;
+    info->n_slice_bits = (int32_t)nd.slice_bits.size();
+    for (size_t j = 0; j < nd.slice_bits.size() && j < 64; ++j) {
+      info->slice_bit[j] = nd.slice_bits[j].first;
+      info->slice_pos[j] = nd.slice_bits[j].second;
+    }
+    switch (nd.region) {
+      case 0: info->ws_offset = nd.offset; break;
+      case 1: info->ws_offset = P->off_persist + nd.offset; break;
+      case 2: info->ws_offset = P->off_arena + nd.offset; break;
+      default: info->ws_offset = UINT64_MAX;
+    }
+  });
+}
+
+int32_t mitnc_plan_leaf_data(const mitnc_plan* P, int32_t leaf, float* out, uint64_t capacity_floats,
+                             uint64_t* n_floats) {
+  return guarded([&] {
+    if (!P || !n_floats) fail(MITNC_INVALID_ARG, "null argument");
+    if (leaf < 0 || leaf >= P->n_leaves) fail(MITNC_INVALID_ARG, "leaf out of range");
+    const auto& v = P->leaf_data[leaf];
+    *n_floats = v.size();
+    if (out) {
+      if (capacity_floats < v.size()) fail(MITNC_INVALID_ARG, "output buffer too small");
+      std::memcpy(out, v.data(), v.size() * sizeof(float));
+    }
+  });
+}
+
 int32_t mitnc_plan_upload(mitnc_plan* P, void* ws, size_t ws_bytes, void* stream) {
   return guarded([&] {
     if (!P || !ws) fail(MITNC_INVALID_ARG, "null argument");

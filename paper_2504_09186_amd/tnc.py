@@ -120,6 +120,33 @@ class Plan:
         call("mitnc_plan_steps", self.h, info.ctypes.data_as(C.POINTER(C.c_double)))
         return info
 
+    def step_info(self, step: int) -> dict:
+        """Address maps of one step (see mitnc_step_info)."""
+        si = _lib.mitnc_step_info()
+        call("mitnc_plan_step_info", self.h, step, C.byref(si))
+        r = {f: int(getattr(si, f)) for f in ("a", "b", "out", "root", "kernel_class", "mb", "nb", "kb", "bb")}
+        for f, cnt in (("am", "mb"), ("ak", "kb"), ("ab", "bb"), ("bk", "kb"), ("bn", "nb"), ("bbt", "bb"),
+                       ("cm", "mb"), ("cn", "nb"), ("cb", "bb")):
+            r[f] = list(getattr(si, f))[:r[cnt]]
+        return r
+
+    def node_info(self, node: int) -> dict:
+        """Storage and schedule of one node (see mitnc_node_info)."""
+        ni = _lib.mitnc_node_info()
+        call("mitnc_plan_node_info", self.h, node, C.byref(ni))
+        k = ni.n_slice_bits
+        return {"is_leaf": bool(ni.is_leaf), "rank": ni.rank, "full_rank": ni.full_rank, "level": ni.level,
+                "hoisted": bool(ni.hoisted), "slice_bits": list(zip(list(ni.slice_bit)[:k], list(ni.slice_pos)[:k])),
+                "ws_offset": None if ni.ws_offset == 2 ** 64 - 1 else int(ni.ws_offset)}
+
+    def leaf_data(self, leaf: int) -> np.ndarray:
+        """The complex64 entries the plan uploads for one leaf."""
+        n = C.c_uint64()
+        call("mitnc_plan_leaf_data", self.h, leaf, None, 0, C.byref(n))
+        buf = np.zeros(n.value, dtype=np.float32)
+        call("mitnc_plan_leaf_data", self.h, leaf, buf.ctypes.data_as(C.POINTER(C.c_float)), n.value, C.byref(n))
+        return (buf[0::2] + 1j * buf[1::2]).astype(np.complex64)
+
     def upload(self, device="cuda", stream=None):
         import torch
         ws = torch.empty(max(256, int(self.stats.workspace_bytes)), dtype=torch.uint8, device=device)

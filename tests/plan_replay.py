@@ -1,0 +1,69 @@
+"""Host re-execution of a plan's schedule, for CPU tests of the planner.
+
+Test infrastructure only.  It reads a plan's address maps, node storage and
+recompute levels through the library's introspection entry points and
+replays the launch schedule on a complex128 copy of the workspace with
+numpy: every step gathers its operands through the bit-position tables,
+contracts them (einsum over batch, m, k, n) and scatters the result, the
+last step of a slice adding into the result.  Independent of the kernels,
+it checks the host logic that decides what the kernels are given: layouts,
+workspace offsets (overlaps corrupt values), reuse levels, hoisting and the
+per-slice sub-tensor offsets.
+"""
+import numpy as np
+
+
+def _scatter(vals, pos):
+    r = np.zeros(vals.shape, dtype=np.int64)
+    for i, p in enumerate(pos):
+        r |= ((vals >> i) & 1) << p
+    return r
+
+
+class PlanReplay:
+    def __init__(self, plan):
+        self.plan = plan
+        st = plan.stats
+        self.n_steps = st.n_steps
+        self.steps = [plan.step_info(i) for i in range(self.n_steps)]
+        n_nodes = self.steps[-1]["out"] + 1
+        self.nodes = [plan.node_info(i) for i in range(n_nodes)]
+        self.ws = np.zeros(int(st.workspace_bytes) // 8 + 1, dtype=np.complex128)
+        self.n_leaves = sum(1 for nd in self.nodes if nd["is_leaf"])
+        for i in range(self.n_leaves):
+            z = plan.leaf_data(i)
+            o = self.nodes[i]["ws_offset"] // 8
+            self.ws[o:o + z.size] = z
+        self.result_elems = int(st.result_elems)
+        self.executed = 0  # step executions so far
+
+    def _ptr(self, node, s, operand):
+        nd = self.nodes[node]
+        e = sum(((s >> b) & 1) << p for b, p in nd["slice_bits"]) if operand else 0
+        return nd["ws_offset"] // 8 + e
+
+    def run(self, s0, s1):
+        """Slices s0 .. s1-1 in order, as the library runs them; returns the
+        complex128 sum of their results."""
+        acc = np.zeros(self.result_elems, dtype=np.complex128)
+        for s in range(s0, s1):
+            for st in self.steps:
+                lv = self.nodes[st["out"]]["level"]
+                if s != s0 and (lv < 0 or (s & -s).bit_length() - 1 < lv):
+                    continue  # unchanged since the previous slice
+                self.executed += 1
+                b_, m_, k_, n_ = (np.arange(1 << st[x]) for x in ("bb", "mb", "kb", "nb"))
+                ia = (_scatter(b_, st["ab"])[:, None, None] + _scatter(m_, st["am"])[None, :, None]
+                      + _scatter(k_, st["ak"])[None, None, :])
+                ib = (_scatter(b_, st["bbt"])[:, None, None] + _scatter(k_, st["bk"])[None, :, None]
+                      + _scatter(n_, st["bn"])[None, None, :])
+                ic = (_scatter(b_, st["cb"])[:, None, None] + _scatter(m_, st["cm"])[None, :, None]
+                      + _scatter(n_, st["cn"])[None, None, :])
+                a = self.ws[self._ptr(st["a"], s, True) + ia]
+                b = self.ws[self._ptr(st["b"], s, True) + ib]
+                c = np.einsum("bmk,bkn->bmn", a, b)
+                if st["root"]:
+                    np.add.at(acc, ic.reshape(-1), c.reshape(-1))
+                else:
+                    self.ws[self._ptr(st["out"], s, False) + ic] = c
+        return acc

@@ -141,3 +141,74 @@ def test_stream_class_rejects_unsupported_shapes():
         b = torch.zeros(1 << (kb + nb + bb), dtype=torch.complex64)
         with pytest.raises(MitncError, match="stream kernel"):
             tnc.contract(a, M + K + Bt, b, K + N + Bt, M + N + Bt, kernel=5)
+
+
+# ---------------------------------------------------------------- plan replay
+# The plan's schedule re-executed on the host from its address maps
+# (tests/plan_replay.py) against the oracle: per slice, over ranges, with and
+# without cross-slice reuse and hoisting.
+@pytest.mark.parametrize("rows,cols,cycles,nopen,nsl,seed", [
+    (2, 3, 5, 2, 2, 1), (3, 3, 6, 3, 3, 2), (3, 4, 8, 4, 3, 3), (2, 4, 10, 0, 4, 4)])
+def test_plan_replay_per_slice(lib, rows, cols, cycles, nopen, nsl, seed):
+    from plan_replay import PlanReplay
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(rows, cols, cycles, seed=seed)
+    n = c.n_qubits
+    spec = synth.output_spec(n, list(range(n - nopen, n)), seed=seed + 50)
+    onet = oracle.build_network(c, spec)
+    rng = np.random.default_rng(seed + 99)
+    sliced = [int(x) for x in rng.choice(onet.closed_labels(), size=nsl, replace=False)]
+    total, parts = oracle.contract_sliced(onet, oracle.greedy_path(onet), sliced, per_slice=True)
+    net = tnc.Network(c, spec)
+    net.path_search(seed=seed, trials=4, max_log2=30)
+    net.set_slicing(sliced)
+    for reuse in (True, False):
+        plan = tnc.Plan(net, reuse=reuse)
+        for s in range(1 << nsl):
+            got = PlanReplay(plan).run(s, s + 1)
+            ref = np.asarray(parts[s]).reshape(-1)
+            assert np.linalg.norm(got - ref) <= 1e-6 * max(np.linalg.norm(ref), 1e-12), (reuse, s)
+        got = PlanReplay(plan).run(0, 1 << nsl)
+        assert np.linalg.norm(got - np.asarray(total).reshape(-1)) <= 1e-6 * np.linalg.norm(total)
+
+
+def test_plan_replay_reuse_and_hoisting(lib):
+    """4x4 lattice, 10 cycles, 5 sliced indices: hoisted subtrees exist, run
+    once per range, and the replayed sums over any split of the range equal
+    the state-vector amplitudes; reuse and hoisting execute fewer steps."""
+    from plan_replay import PlanReplay
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(4, 4, 10, seed=7)
+    spec = synth.output_spec(16, [13, 14, 15], seed=8)
+    net = tnc.Network(c, spec)
+    net.path_search(seed=9, trials=8, max_log2=11, min_sliced=5)
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    plan = tnc.Plan(net, reuse=True)
+    n = plan.n_slices
+    hoisted = [i for i in range(plan.stats.n_steps + net.n_leaves) if plan.node_info(i)["hoisted"]]
+    assert hoisted, "expected hoisted subtrees"
+    for i in hoisted:
+        assert plan.node_info(i)["level"] == -1
+    r = PlanReplay(plan)
+    full = r.run(0, n)
+    split = PlanReplay(plan).run(0, 5) + PlanReplay(plan).run(5, n)
+    plain = PlanReplay(tnc.Plan(net, reuse=False))
+    full_plain = plain.run(0, n)
+    budget = PlanReplay(tnc.Plan(net, reuse=True, cache_budget_bytes=256)).run(0, n)  # cached nodes demoted
+    for x in (full, split, full_plain, budget):
+        assert np.linalg.norm(x - ref) <= 1e-6 * np.linalg.norm(ref)
+    assert r.executed < plain.executed
+
+
+def test_plan_replay_batched_bitstrings(lib):
+    from plan_replay import PlanReplay
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(3, 3, 6, seed=21)
+    bits = synth.random_bitstrings(9, 16, seed=22)
+    spec = np.full(9, -2, dtype=np.int8)
+    net = tnc.Network(c, spec, bits)
+    net.path_search(seed=23, trials=8, max_log2=30, min_sliced=2)
+    plan = tnc.Plan(net)
+    got = PlanReplay(plan).run(0, plan.n_slices)
+    ref = oracle.sv_amplitudes(c, spec, bits).reshape(-1)
+    assert np.linalg.norm(got - ref) <= 1e-6 * np.linalg.norm(ref)
