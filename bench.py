@@ -27,7 +27,7 @@ METRIC = "slices/s + % MFMA peak, complex64 vs scaled complex-FP16 at stated amp
 PEAK_FP32 = 157.3   # dense MFMA (and vector) TFLOP/s, FP32
 PEAK_FP16 = 2500.0  # dense MFMA TFLOP/s, FP16
 PEAK_HBM_GBS = 8000.0
-CLASS_NAMES = ["small", "stem", "tile", "tall", "splitk", "stream"]
+CLASS_NAMES = ["small", "stem", "tile", "tall", "splitk", "stream", "section"]
 
 
 def class_peak(label, cls):

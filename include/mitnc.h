@@ -147,6 +147,12 @@ typedef struct mitnc_plan_opts {
   int32_t force_kernel;
   int32_t differentiable; /* 1: keep every node's value for the reverse pass
                              (mitnc_backward); complex64 only */
+  int32_t fuse_sections;  /* 1: run chains of steps that contract one large tensor
+                             with small ones as fused sections (Sec. IV: the
+                             tensor's tile stays in LDS across the chain);
+                             ignored with force_kernel >= 0 or differentiable.
+                             0 (recommended on MI355X): one stream launch per
+                             step, which measured faster */
 } mitnc_plan_opts;
 
 int32_t mitnc_plan_create(const mitnc_network* net, const mitnc_plan_opts* opts, mitnc_plan** out);
@@ -190,6 +196,10 @@ typedef struct mitnc_step_info {
   int32_t a, b, out;               /* node ids; a is the larger operand */
   int32_t root;                    /* 1: adds C into the complex128 result */
   int32_t kernel_class;
+  int32_t section;                 /* fused section id, or -1 */
+  int32_t section_pos, section_len;/* place in the section; the whole section
+                                      runs when its last step is reached, and
+                                      only its last output is stored */
   int32_t mb, nb, kb, bb;          /* bit counts of m, n, k and batch */
   uint8_t am[32], ak[32], ab[32];  /* A address bit of each m, k, batch bit */
   uint8_t bk[32], bn[32], bbt[32]; /* B address bit of each k, n, batch bit */
@@ -294,8 +304,9 @@ int32_t mitnc_contract(const void* A, int32_t ra, const int64_t* la, const void*
  * mitnc_execute (events are created on first use and reused after a reset);
  * calling it again (enable 0 or 1) discards the recorded pairs.
  * mitnc_plan_timing_read waits for the recorded events and fills, per kernel
- * class (8 entries each): summed kernel milliseconds, launch count, and the
- * algorithmic real flops and HBM bytes of those launches. */
+ * class (8 entries each; entry 6 = fused sections): summed kernel
+ * milliseconds, launch count, and the algorithmic real flops and HBM bytes
+ * of those launches (for a section: its input, small tensors and output). */
 int32_t mitnc_plan_timing(mitnc_plan* plan, int32_t enable);
 int32_t mitnc_plan_timing_read(mitnc_plan* plan, double* ms, double* launches, double* flops,
                                double* bytes);

@@ -16,7 +16,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "PATH_INVALID", -3: "WORKSPACE_T
                 -4: "HIP_ERROR", -5: "UNSUPPORTED", -6: "NUMERIC"}
 MITNC_C64, MITNC_CF16, MITNC_CBF16 = 0, 1, 2
 K_SMALL, K_STEM, K_TILE, K_TALL, K_SPLITK = 0, 1, 2, 3, 4
-KERNEL_NAMES = {0: "small", 1: "stem", 2: "tile", 3: "tall", 4: "splitk", 5: "stream"}
+KERNEL_NAMES = {0: "small", 1: "stem", 2: "tile", 3: "tall", 4: "splitk", 5: "stream", 6: "section"}
 
 
 class MitncError(RuntimeError):
@@ -38,7 +38,7 @@ class mitnc_search_opts(C.Structure):
 class mitnc_plan_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("reuse", C.c_int32),
                 ("cache_budget_bytes", C.c_uint64), ("force_kernel", C.c_int32),
-                ("differentiable", C.c_int32)]
+                ("differentiable", C.c_int32), ("fuse_sections", C.c_int32)]
 
 
 class mitnc_plan_stats(C.Structure):
@@ -54,7 +54,8 @@ class mitnc_plan_stats(C.Structure):
 
 class mitnc_step_info(C.Structure):
     _fields_ = [("a", C.c_int32), ("b", C.c_int32), ("out", C.c_int32), ("root", C.c_int32),
-                ("kernel_class", C.c_int32), ("mb", C.c_int32), ("nb", C.c_int32), ("kb", C.c_int32),
+                ("kernel_class", C.c_int32), ("section", C.c_int32), ("section_pos", C.c_int32),
+                ("section_len", C.c_int32), ("mb", C.c_int32), ("nb", C.c_int32), ("kb", C.c_int32),
                 ("bb", C.c_int32)] + [(f, C.c_uint8 * 32) for f in ("am", "ak", "ab", "bk", "bn", "bbt",
                                                                      "cm", "cn", "cb")]
 

@@ -380,6 +380,13 @@ int32_t mitnc_plan_step_info(const mitnc_plan* P, int32_t step, mitnc_step_info*
     info->out = s.out;
     info->root = s.root;
     info->kernel_class = s.kclass;
+    info->section = P->step_section.empty() ? -1 : P->step_section[step];
+    info->section_pos = info->section_len = 0;
+    if (info->section >= 0) {
+      const auto& m = P->sections[info->section].steps;
+      info->section_len = (int32_t)m.size();
+      info->section_pos = (int32_t)(std::find(m.begin(), m.end(), step) - m.begin());
+    }
     info->mb = d.mb;
     info->nb = d.nb;
     info->kb = d.kb;
@@ -529,13 +536,55 @@ static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t s
   hip_check(launch_step(st.kclass, d, s, e0, e1), "kernel launch");
 }
 
+// Launches a fused section (at the position of its last step).
+static void launch_plan_section(mitnc_plan* P, PlanSection& sec, char* base, uint64_t slice, hipStream_t s,
+                                int prec, bool stats) {
+  const bool half = prec != MITNC_C64;
+  auto ptr = [&](int node, bool operand) -> char* {
+    const PlanNode& nd = P->nodes[node];
+    uint64_t e = 0;
+    if (operand)
+      for (auto& [sb, pb] : nd.slice_bits) e += ((slice >> sb) & 1ull) << pb;
+    uint64_t off = nd.region == 0 ? (half ? P->off_leaf_half + nd.offset / 2 : nd.offset)
+                                  : (nd.region == 1 ? P->off_persist : P->off_arena) + nd.offset;
+    return base + off + e * (half ? 4 : 8);
+  };
+  SectionDesc sd = sec.sd;
+  sd.A = ptr(P->steps[sec.steps[0]].a, true);
+  sd.C = ptr(P->steps[sec.steps.back()].out, false);
+  sd.prec = prec;
+  sd.stats = stats ? (float*)(base + P->off_stats) : nullptr;
+  for (size_t j = 0; j < sec.steps.size(); ++j) {
+    const PlanStep& st = P->steps[sec.steps[j]];
+    sd.st[j].B = ptr(st.b, true);
+    sd.st[j].out_scale = half ? st.d.out_scale : 1.f;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (P->timing) {
+    size_t need = 2 * (P->ev_used + 1);
+    while (P->ev_pool.size() < need) {
+      hipEvent_t e;
+      hip_check(hipEventCreate(&e), "event create");
+      P->ev_pool.push_back((void*)e);
+    }
+    e0 = (hipEvent_t)P->ev_pool[2 * P->ev_used];
+    e1 = (hipEvent_t)P->ev_pool[2 * P->ev_used + 1];
+    P->ev_step.push_back(-1 - (int)(&sec - P->sections.data()));
+    P->ev_used++;
+  }
+  hip_check(launch_section(sd, s, e0, e1), "section launch");
+}
+
 static void run_slices(mitnc_plan* P, char* base, uint64_t s0, uint64_t s1, double* acc, hipStream_t s, int prec,
                        bool stats) {
   for (uint64_t sl = s0; sl < s1; ++sl) {
     int level = (sl == s0) ? kLevelFirst : __builtin_ctzll(sl);
-    for (auto& st : P->steps) {
+    for (size_t i = 0; i < P->steps.size(); ++i) {
+      PlanStep& st = P->steps[i];
       if (P->nodes[st.out].lo > level) continue;
-      launch_plan_step(P, st, base, sl, acc, s, prec, stats);
+      const int sec = P->step_section.empty() ? -1 : P->step_section[i];
+      if (sec < 0) launch_plan_step(P, st, base, sl, acc, s, prec, stats);
+      else if (P->sections[sec].steps.back() == (int)i) launch_plan_section(P, P->sections[sec], base, sl, s, prec, stats);
     }
   }
 }
@@ -757,7 +806,16 @@ int32_t mitnc_plan_timing_read(mitnc_plan* P, double* ms, double* launches, doub
       hip_check(hipEventSynchronize(e1), "event sync");
       float t = 0;
       hip_check(hipEventElapsedTime(&t, e0, e1), "event time");
-      const PlanStep& st = P->steps[P->ev_step[i]];
+      const int id = P->ev_step[i];
+      if (id < 0) {  // fused section: its own class
+        const PlanSection& sec = P->sections[-1 - id];
+        ms[kSectionClass] += t;
+        launches[kSectionClass] += 1;
+        flops[kSectionClass] += sec.flops;
+        bytes[kSectionClass] += sec.bytes;
+        continue;
+      }
+      const PlanStep& st = P->steps[id];
       ms[st.kclass] += t;
       launches[st.kclass] += 1;
       flops[st.kclass] += st.flops;

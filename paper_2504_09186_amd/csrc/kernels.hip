@@ -414,6 +414,288 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   record_max(d, mx);
 }
 
+// ---------------------------------------------------------------- fused stem sections
+// A chain of stream-like steps on one large tensor T run in one kernel
+// (Sec. IV: the stem tensor stays on chip while small tensors are absorbed;
+// a section of n steps saves 2 (n - 1) passes over T).  Each workgroup takes
+// tiles of T in turn: it loads the tile (every bit the section contracts,
+// plus low address bits, enumerated in A's address order so the loads are
+// coalesced) into an LDS buffer, applies the steps between two LDS buffers
+// and writes the final tile in C's address order.  Inside a step the MFMA
+// mapping is the stream kernel's (C^T = B^T A^T, 3M split), with A read from
+// LDS and each step's padded B^T kept in LDS for the whole kernel.
+
+// Deposits the low n bits of x at the bits pos[0..n) (n <= 16); pos is a
+// 4-byte aligned byte table in LDS, read a word at a time.
+__device__ __forceinline__ uint32_t scatter16(uint32_t x, const uint8_t* pos, int n) {
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(pos);
+  uint32_t r = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (4 * q < n) {
+      const uint32_t word = w[q];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (4 * q + b < n) r |= ((x >> (4 * q + b)) & 1u) << ((word >> (8 * b)) & 31u);
+    }
+  }
+  return r;
+}
+
+static_assert(offsetof(TileStep, am) % 4 == 0 && offsetof(TileStep, ak) % 4 == 0 && offsetof(TileStep, cm) % 4 == 0 &&
+                  offsetof(TileStep, cn) % 4 == 0 && offsetof(TileStep, bk) % 4 == 0 &&
+                  offsetof(TileStep, bn) % 4 == 0 && sizeof(TileStep) % 8 == 0,
+              "tile-step tables must be word aligned");
+static_assert(offsetof(SectionDesc, p_in) % 4 == 0 && offsetof(SectionDesc, p_out) % 4 == 0 &&
+                  offsetof(SectionDesc, st) % 8 == 0 && sizeof(SectionDesc) % 4 == 0,
+              "section tables must be word aligned");
+
+__device__ __forceinline__ void record_max_at(float* stats, int idx, float m) {
+  __shared__ float red[16];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
+    if (m > 0.f) atomicMax(reinterpret_cast<unsigned int*>(stats) + idx, __float_as_uint(m));
+  }
+}
+
+// A byte table in LDS (4-byte aligned) read as NW wave-uniform words, so
+// that scatters of wave-uniform values through it are scalar work.
+template <int NW>
+struct UTab {
+  uint32_t w[NW];
+  __device__ __forceinline__ explicit UTab(const uint8_t* p) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) w[q] = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t*>(p)[q]);
+  }
+  __device__ __forceinline__ uint32_t pos(int i) const { return (w[i >> 2] >> (8 * (i & 3))) & 31u; }
+  // deposits bit i of x at pos(first + i), i < n (first + n <= 4 NW)
+  __device__ __forceinline__ uint32_t scatter(uint32_t x, int first, int n) const {
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < 4 * NW; ++i)
+      if (i >= first && i < first + n) r |= ((x >> (i - first)) & 1u) << pos(i);
+    return r;
+  }
+};
+
+// One step of a section on LDS-resident tiles (KS k steps of 4, NBLK column
+// blocks of 16, as in the stream kernel); returns the largest stored
+// magnitude of this thread when `want_max`.
+template <int KS, int NBLK>
+__device__ __forceinline__ float section_step_t(const TileStep& ts, const float2* in, float2* out, const float2* Bl,
+                                                bool want_max, int tb_bits, int stride_bits) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nwaves = blockDim.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int kb = __builtin_amdgcn_readfirstlane(ts.kb), nb = __builtin_amdgcn_readfirstlane(ts.nb);
+  const int mb = __builtin_amdgcn_readfirstlane(ts.mb);
+  const uint32_t kpad = __builtin_amdgcn_readfirstlane(ts.kpad), b_lds = __builtin_amdgcn_readfirstlane(ts.b_lds);
+  const float osc = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, ts.out_scale)));
+  const int K = 1 << kb, N = 1 << nb;
+  const bool kvalid = KS > 1 || lq < K;
+  const UTab<4> am(ts.am), cm(ts.cm);
+  const UTab<2> ak(ts.ak), cn(ts.cn);
+  // B fragments in registers: column (lr >> 2) + 4 (lr & 3) of column block
+  // cb; LDS holds B as [cb][k][16 columns] (64 consecutive entries per read)
+  float br[NBLK][KS], bi[NBLK][KS], bs[NBLK][KS];
+  const uint32_t b_lane = b_lds + (uint32_t)lq * 16 + (uint32_t)((lr >> 2) + 4 * (lr & 3));
+#pragma unroll
+  for (int cb = 0; cb < NBLK; ++cb)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const float2 b = Bl[b_lane + ((uint32_t)cb * kpad + 4 * ks) * 16];
+      br[cb][ks] = b.x;
+      bi[cb][ks] = b.y;
+      bs[cb][ks] = b.x + b.y;
+    }
+  // lane parts (4 rows bits, 2 k bits, 2 n bits) plus scalar parts
+  const int kl = kb < 2 ? kb : 2, nl = nb < 2 ? nb : 2;
+  const uint32_t a_lane = am.scatter(lr, 0, 4) + ak.scatter(lq, 0, kl);
+  const uint32_t c_lane = cm.scatter(lr, 0, 4) + cn.scatter(lq, 0, nl);
+  uint32_t a_k[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) a_k[ks] = a_lane + ak.scatter(ks, 2, kb - kl);
+  uint32_t c_n[NBLK][4];
+#pragma unroll
+  for (int cb = 0; cb < NBLK; ++cb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c_n[cb][i] = c_lane + cn.scatter(i + 4 * cb, 2, nb - nl);
+  const int hb = mb - 4;
+  const int nblk = 1 << (hb + tb_bits);  // row blocks of every tile of the group
+  float mx = 0.f;
+  for (int blk = wave; blk < nblk; blk += nwaves) {
+    const uint32_t tslot = (uint32_t)(blk >> hb) << stride_bits;
+    const uint32_t xa = tslot + am.scatter(blk, 4, hb), xc = tslot + cm.scatter(blk, 4, hb);
+    float2 av[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) av[ks] = in[xa + a_k[ks]];
+    v4f acc[3][NBLK];
+#pragma unroll
+    for (int cb = 0; cb < NBLK; ++cb)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) acc[p][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      float2 a = av[ks];
+      if (!kvalid) a = make_float2(0.f, 0.f);
+      const float as = a.x + a.y;
+#pragma unroll
+      for (int cb = 0; cb < NBLK; ++cb) {
+        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(br[cb][ks], a.x, acc[0][cb], 0, 0, 0);
+        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bi[cb][ks], a.y, acc[1][cb], 0, 0, 0);
+        acc[2][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bs[cb][ks], as, acc[2][cb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < NBLK; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (16 * cb + lq + 4 * i < N) {
+          const float t1 = acc[0][cb][i], t2 = acc[1][cb][i], t3 = acc[2][cb][i];
+          const float2 v = make_float2((t1 - t2) * osc, (t3 - t1 - t2) * osc);
+          out[xc + c_n[cb][i]] = v;
+          if (want_max) mx = fmaxf(mx, absmax2(v));
+        }
+  }
+  return mx;
+}
+
+__device__ __forceinline__ float section_step(const TileStep& ts, const float2* in, float2* out, const float2* Bl,
+                                              bool want_max, int tb_bits, int stride_bits) {
+  const int kb = __builtin_amdgcn_readfirstlane(ts.kb), nb = __builtin_amdgcn_readfirstlane(ts.nb);
+  const int ksl = kb > 2 ? kb - 2 : 0, nbl = nb > 4 ? nb - 4 : 0;
+#define MITNC_SEC(KSL, NBL) \
+  if (ksl == KSL && nbl == NBL) return section_step_t<1 << KSL, 1 << NBL>(ts, in, out, Bl, want_max, tb_bits, stride_bits);
+  MITNC_SEC(0, 0) MITNC_SEC(1, 0) MITNC_SEC(2, 0) MITNC_SEC(3, 0) MITNC_SEC(4, 0)
+  MITNC_SEC(0, 1) MITNC_SEC(1, 1) MITNC_SEC(2, 1) MITNC_SEC(3, 1)
+  MITNC_SEC(0, 2) MITNC_SEC(1, 2) MITNC_SEC(2, 2)
+#undef MITNC_SEC
+  return 0.f;  // not reached: the planner keeps K N within these
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_section(SectionDesc sd_arg) {
+  extern __shared__ float2 dyn[];
+  // Tables are read from an LDS copy (a dynamically indexed kernel argument
+  // would be copied to scratch); global pointers come from the argument
+  // itself (a pointer read back from LDS is generic, and generic accesses
+  // also count against the LDS wait counter).
+  __shared__ SectionDesc sd;
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&sd_arg);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&sd);
+    for (int i = threadIdx.x; i < (int)(sizeof(SectionDesc) / 4); i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  const int tile_max = __builtin_amdgcn_readfirstlane(sd.tile_max);
+  const int n_steps = __builtin_amdgcn_readfirstlane(sd.n_steps);
+  const int t_in = __builtin_amdgcn_readfirstlane(sd.t_in), t_out = __builtin_amdgcn_readfirstlane(sd.t_out);
+  const int outer_bits = __builtin_amdgcn_readfirstlane(sd.outer_bits);
+  float2* buf0 = dyn;
+  float2* buf1 = dyn + tile_max;
+  float2* Bl = dyn + 2 * tile_max;
+  const int tid = threadIdx.x;
+  // padded B of every step as [column block][k (kpad)][16 columns], zero
+  // outside K x N
+#pragma unroll
+  for (int j = 0; j < kMaxSectionSteps; ++j) {
+    if (j < n_steps) {
+      const TileStep& ts = sd.st[j];
+      const void* Bp = sd_arg.st[j].B;
+      const int K = 1 << ts.kb, N = 1 << ts.nb;
+      const int rows = N > 16 ? N : 16;
+      const UTab<2> bk(ts.bk), bn(ts.bn);
+      for (int idx = tid; idx < rows * (int)ts.kpad; idx += blockDim.x) {
+        const int c = idx & 15, k = (idx >> 4) % ts.kpad, n = (idx >> 4) / ts.kpad * 16 + c;
+        float2 v = make_float2(0.f, 0.f);
+        if (k < K && n < N) v = load_c<P>(Bp, bk.scatter(k, 0, ts.kb) + bn.scatter(n, 0, ts.nb));
+        Bl[ts.b_lds + idx] = v;
+      }
+    }
+  }
+  __syncthreads();
+  const UTab<4> pin(sd.p_in), pout(sd.p_out);
+  const UTab<8> qin(sd.q_in), qout(sd.q_out);
+  // element e = tid + 256 u of a tile: low 8 bits from tid, the rest uniform
+  const uint32_t lo_in = pin.scatter(tid, 0, 8), lo_out = pout.scatter(tid, 0, 8);
+  const int hi_in = 1 << (t_in - 8), hi_out = 1 << (t_out - 8);
+  auto outer_off = [](const UTab<8>& q, uint64_t tile, int n) {
+    uint64_t r = 0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+      if (i < n) r |= ((tile >> i) & 1ull) << q.pos(i);
+    return r;
+  };
+  float smx[kMaxSectionSteps];
+#pragma unroll
+  for (int j = 0; j < kMaxSectionSteps; ++j) smx[j] = 0.f;
+  const int tb_bits = __builtin_amdgcn_readfirstlane(sd.tb_bits);
+  const int stride_bits = __builtin_amdgcn_readfirstlane(sd.stride_bits);
+  // Tiles go in groups of 2^tb_bits; element E = tid + 256 u of a group is
+  // entry E mod 2^t of tile E >> t (t >= 8, so the tile index is uniform),
+  // stored at slot (tile << stride_bits) of a buffer.
+  const uint64_t n_groups = 1ull << (outer_bits - tb_bits);
+  const int n_in = 1 << (t_in + tb_bits - 8), n_out = 1 << (t_out + tb_bits - 8);  // <= 16 each
+  float2 pre[16];
+  uint64_t grp = blockIdx.x;
+  if (grp < n_groups) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int uu = u < n_in ? u : 0;  // past the group: entry 0 again, in bounds, not kept
+      const int t = uu >> (t_in - 8);
+      const uint64_t oin = outer_off(qin, (grp << tb_bits) + t, outer_bits);
+      pre[u] = load_c<P>(sd_arg.A, oin + lo_in + pin.scatter((uint32_t)uu, 8, t_in - 8));
+    }
+  }
+  for (; grp < n_groups; grp += gridDim.x) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (u < n_in) {
+        const int t = u >> (t_in - 8);
+        buf0[((uint32_t)t << stride_bits) + tid + 256 * (u & ((1 << (t_in - 8)) - 1))] = pre[u];
+      }
+    __syncthreads();
+    if (grp + gridDim.x < n_groups) {
+      const uint64_t nxt = grp + gridDim.x;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int uu = u < n_in ? u : 0;
+        const int t = uu >> (t_in - 8);
+        const uint64_t oin = outer_off(qin, (nxt << tb_bits) + t, outer_bits);
+        pre[u] = load_c<P>(sd_arg.A, oin + lo_in + pin.scatter((uint32_t)uu, 8, t_in - 8));
+      }
+    }
+    for (int j = 0; j < n_steps; ++j) {
+      smx[j & 7] = fmaxf(smx[j & 7], section_step(sd.st[j], (j & 1) ? buf1 : buf0, (j & 1) ? buf0 : buf1, Bl,
+                                                  sd_arg.stats != nullptr, tb_bits, stride_bits));
+      __syncthreads();
+    }
+    const float2* fin = (n_steps & 1) ? buf1 : buf0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (u < n_out) {
+        const int t = u >> (t_out - 8);
+        const uint64_t oout = outer_off(qout, (grp << tb_bits) + t, outer_bits);
+        const uint32_t hi = pout.scatter((uint32_t)u, 8, t_out - 8);
+        const float2 v = fin[((uint32_t)t << stride_bits) + tid + 256 * (u & ((1 << (t_out - 8)) - 1))];
+        if constexpr (P == 0) reinterpret_cast<float2*>(sd_arg.C)[oout + lo_out + hi] = v;
+        else reinterpret_cast<uint32_t*>(sd_arg.C)[oout + lo_out + hi] = pack<P>(v);
+      }
+    }
+    __syncthreads();
+  }
+  if (sd_arg.stats) {
+    for (int j = 0; j < n_steps; ++j) {
+      record_max_at(sd_arg.stats, sd.st[j].step_index, smx[j & 7]);
+      __syncthreads();
+    }
+  }
+}
+
 // ---------------------------------------------------------------- tile helpers
 // Decodes a tile element number into its logical coordinates and address
 // offset; codes/tables live in LDS.
@@ -1056,6 +1338,58 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1
     }
     default:
       return hipErrorInvalidValue;
+  }
+  if (ev1) (void)hipEventRecord(ev1, s);
+  return e;
+}
+
+template <int P>
+static hipError_t launch_section_p(const SectionDesc& sd, unsigned grid, size_t lds, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_section<P>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSectionMaxLds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_section<P>), dim3(grid), dim3(256), lds, s, sd);
+  return hipGetLastError();
+}
+
+hipError_t launch_section(const SectionDesc& sd, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  // Host checks of what the kernel assumes: tile sizes, step count, LDS.
+  if (sd.n_steps < 1 || sd.n_steps > kMaxSectionSteps || sd.t_in < 8 || sd.t_out < 8 || sd.t_in > 12 ||
+      sd.t_out > 12 ||
+      sd.t_in > kMaxTileBits || sd.t_out > kMaxTileBits || (1 << sd.t_in) > sd.tile_max ||
+      (1 << sd.t_out) > sd.tile_max || sd.tile_max > (1 << kMaxTileBits) || sd.outer_bits < 0 ||
+      sd.outer_bits > 32)
+    return hipErrorInvalidValue;
+  for (int j = 0; j < sd.n_steps; ++j) {
+    const TileStep& t = sd.st[j];
+    if (t.mb < 4 || t.mb + t.kb > kMaxTileBits || t.mb + t.nb > kMaxTileBits || t.kb > 6 || t.nb > 6 ||
+        (t.kb > 2 ? t.kb - 2 : 0) + (t.nb > 4 ? t.nb - 4 : 0) > 4 ||
+        (1 << (t.mb + t.kb)) > sd.tile_max || (1 << (t.mb + t.nb)) > sd.tile_max)
+      return hipErrorInvalidValue;
+  }
+  if (sd.tb_bits < 0 || sd.tb_bits > sd.outer_bits || sd.stride_bits < sd.t_in || sd.stride_bits < sd.t_out ||
+      sd.stride_bits + sd.tb_bits > 12 || (1 << (sd.stride_bits + sd.tb_bits)) > sd.tile_max)
+    return hipErrorInvalidValue;
+  for (int j = 0; j < sd.n_steps; ++j) {
+    const TileStep& t = sd.st[j];
+    if (t.mb + t.kb > sd.stride_bits || t.mb + t.nb > sd.stride_bits) return hipErrorInvalidValue;
+  }
+  const size_t lds = (2ull * sd.tile_max + sd.b_total) * sizeof(float2);
+  if (lds > kSectionMaxLds) return hipErrorInvalidValue;
+  const uint64_t tiles = 1ull << (sd.outer_bits - sd.tb_bits);
+  const unsigned per_cu = lds > kSectionMaxLds / 2 ? 1 : 2;
+  const unsigned grid = (unsigned)(tiles < 256ull * per_cu ? tiles : 256ull * per_cu);
+  if (ev0) (void)hipEventRecord(ev0, s);
+  hipError_t e;
+  switch (sd.prec) {
+    case MITNC_C64: e = launch_section_p<0>(sd, grid, lds, s); break;
+    case MITNC_CF16: e = launch_section_p<1>(sd, grid, lds, s); break;
+    case MITNC_CBF16: e = launch_section_p<2>(sd, grid, lds, s); break;
+    default: return hipErrorInvalidValue;
   }
   if (ev1) (void)hipEventRecord(ev1, s);
   return e;

@@ -15,6 +15,9 @@ namespace mitnc {
 hipError_t launch_step(int kclass, const StepDesc& d, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
 
+// Launches a fused stem section (checks the tile geometry it assumes).
+hipError_t launch_section(const SectionDesc& sd, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
 // Reverse pass helpers: adj = complex64(w) for n entries; gradient
 // accumulation of the single-qubit gate leaf adjoints of slice `slice`.
 hipError_t launch_seed(const double* w, float* adj, uint64_t n, hipStream_t s);

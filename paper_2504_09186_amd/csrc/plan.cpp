@@ -25,6 +25,7 @@
 #include <map>
 #include <memory>
 #include <numeric>
+#include <set>
 #include <tuple>
 
 #include "plan.hpp"
@@ -233,6 +234,237 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
              (st.root ? 32.0 : esz) * std::ldexp(1.0, O.rank);
 }
 
+// ---------------------------------------------------------------- fused sections
+// A step can join a section when it contracts a large tensor (A) with a small
+// matrix: no batch indices, K, N <= 64 and a padded B^T of at most
+// kMaxSectionB entries.
+static bool section_member_ok(const mitnc_plan* P, const PlanStep& st) {
+  const StepDesc& d = st.d;
+  if (st.root || d.bb != 0 || d.kb > 6 || d.nb > 6) return false;
+  if (std::max(1 << d.kb, 4) * std::max(1 << d.nb, 16) > kMaxSectionB) return false;
+  if ((d.kb > 2 ? d.kb - 2 : 0) + (d.nb > 4 ? d.nb - 4 : 0) > 4) return false;  // B fragments in registers
+  if (P->nodes[st.a].rank < 14 || P->nodes[st.out].hoisted) return false;
+  return true;
+}
+
+// Tile maps and step descriptors of a section over the chain `members`
+// (members[j + 1] consumes the output of members[j] as its A).  The tile
+// holds every label the section contracts that T already has, plus
+// "passengers": the labels on T's four lowest address bits (coalescing) and
+// more low labels until every step keeps at least 4 rows bits and the tile
+// has at least 2^8 entries.  Inter-tile labels (Sec. IV: the ones that live
+// longest) only select the tile.  Returns false when the tile would exceed
+// 2^kMaxTileBits entries or LDS.
+static bool build_section(const mitnc_plan* P, const std::vector<int>& members, int precision, PlanSection& sec) {
+  const int L = (int)members.size();
+  const PlanNode& Tin = P->nodes[P->steps[members[0]].a];
+  const PlanNode& Tout = P->nodes[P->steps[members.back()].out];
+  std::vector<std::vector<int64_t>> Kj(L), Nj(L);
+  for (int j = 0; j < L; ++j) {
+    const PlanStep& st = P->steps[members[j]];
+    const PlanNode& A = P->nodes[st.a];
+    const PlanNode& B = P->nodes[st.b];
+    std::set<int64_t> sa(A.labels.begin(), A.labels.end());
+    for (int64_t x : B.labels) (sa.count(x) ? Kj[j] : Nj[j]).push_back(x);
+  }
+  std::set<int64_t> tin(Tin.labels.begin(), Tin.labels.end()), tile;
+  for (int j = 0; j < L; ++j)
+    for (int64_t x : Kj[j])
+      if (tin.count(x)) tile.insert(x);
+  auto pos_in = [&](int64_t x) {
+    for (size_t i = 0; i < Tin.labels.size(); ++i)
+      if (Tin.labels[i] == x) return Tin.pos[i];
+    return -1;
+  };
+  auto pos_out = [&](int64_t x) {
+    for (size_t i = 0; i < Tout.labels.size(); ++i)
+      if (Tout.labels[i] == x) return Tout.pos[i];
+    return -1;
+  };
+  std::vector<std::pair<int, int64_t>> by_pos;  // T_in labels by address bit
+  for (size_t i = 0; i < Tin.labels.size(); ++i) by_pos.push_back({Tin.pos[i], Tin.labels[i]});
+  std::sort(by_pos.begin(), by_pos.end());
+  for (auto& [p, x] : by_pos)
+    if (p < 4) tile.insert(x);
+  for (size_t i = 0; i < Tout.labels.size(); ++i)
+    if (Tout.pos[i] < 4 && tin.count(Tout.labels[i])) tile.insert(Tout.labels[i]);
+  int max_bits = 0, out_bits = 0;
+  auto simulate = [&]() {
+    bool ok = true;
+    std::set<int64_t> cur = tile;
+    max_bits = (int)cur.size();
+    for (int j = 0; j < L; ++j) {
+      if ((int)cur.size() - (int)Kj[j].size() < 4) ok = false;
+      for (int64_t x : Kj[j]) cur.erase(x);
+      for (int64_t x : Nj[j]) cur.insert(x);
+      max_bits = std::max(max_bits, (int)cur.size());
+    }
+    out_bits = (int)cur.size();
+    return ok && (int)tile.size() >= 8 && out_bits >= 8;
+  };
+  size_t next = 0;
+  while (!simulate()) {
+    while (next < by_pos.size() && tile.count(by_pos[next].second)) ++next;
+    if (next >= by_pos.size()) return false;
+    tile.insert(by_pos[next].second);
+  }
+  if (max_bits > kTileBitsTarget) return false;
+  for (int64_t x : tin)
+    if (!tile.count(x) && pos_out(x) < 0) return false;  // an inter-tile label must survive
+
+  SectionDesc& sd = sec.sd;
+  std::memset(&sd, 0, sizeof(sd));
+  sd.n_steps = L;
+  // One tile per workgroup iteration (tb_bits = 0).  The kernel can also
+  // take 2^tb_bits tiles at a time (sharing each step's setup), but that
+  // leaves fewer workgroups in flight and measured slower on MI355X.
+  sd.stride_bits = max_bits;
+  sd.tb_bits = 0;
+  sd.tile_max = 1 << (max_bits + sd.tb_bits);
+  // buffer 0: tile labels by A address bit; outer labels likewise
+  std::vector<int64_t> lay;
+  int no = 0;
+  for (auto& [p, x] : by_pos) {
+    if (tile.count(x)) {
+      sd.p_in[lay.size()] = (uint8_t)p;
+      lay.push_back(x);
+    } else {
+      sd.q_in[no] = (uint8_t)p;
+      sd.q_out[no] = (uint8_t)pos_out(x);
+      ++no;
+    }
+  }
+  sd.t_in = (int)lay.size();
+  sd.outer_bits = no;
+  uint32_t b_off = 0;
+  std::set<int64_t> cur(tile.begin(), tile.end());
+  for (int j = 0; j < L; ++j) {
+    const PlanStep& st = P->steps[members[j]];
+    const PlanNode& B = P->nodes[st.b];
+    std::map<int64_t, int> in_bit, out_bit, b_pos;
+    for (size_t i = 0; i < lay.size(); ++i) in_bit[lay[i]] = (int)i;
+    for (size_t i = 0; i < B.labels.size(); ++i) b_pos[B.labels[i]] = B.pos[i];
+    std::set<int64_t> kset(Kj[j].begin(), Kj[j].end());
+    std::vector<int64_t> M, Kv(Kj[j]);
+    for (int64_t x : lay)
+      if (!kset.count(x)) M.push_back(x);  // ascending input bit
+    std::sort(Kv.begin(), Kv.end(), [&](int64_t u, int64_t v) { return in_bit[u] < in_bit[v]; });
+    for (int64_t x : Kj[j]) cur.erase(x);
+    for (int64_t x : Nj[j]) cur.insert(x);
+    // output layout: the final one in C's address order; otherwise the next
+    // step's four lane rows bits and two lane k bits lowest (conflict-free
+    // LDS reads there), then the rest
+    std::vector<int64_t> nlay;
+    if (j == L - 1) {
+      std::vector<std::pair<int, int64_t>> v;
+      for (int64_t x : cur) v.push_back({pos_out(x), x});
+      std::sort(v.begin(), v.end());
+      for (auto& [p, x] : v) {
+        sd.p_out[nlay.size()] = (uint8_t)p;
+        nlay.push_back(x);
+      }
+    } else {
+      // this step's lane rows bits, then its two lane n bits lowest: each
+      // store instruction writes 64 consecutive entries; in a stem the next
+      // step contracts the new bits, so its lane k bits are low as well
+      std::vector<int64_t> first(M.begin(), M.begin() + 4);
+      for (size_t i = 0; i < Nj[j].size() && i < 2; ++i) first.push_back(Nj[j][i]);
+      std::set<int64_t> fs(first.begin(), first.end());
+      nlay = first;
+      for (int64_t x : Kj[j + 1])
+        if (!fs.count(x) && cur.count(x)) {
+          nlay.push_back(x);
+          fs.insert(x);
+        }
+      for (int64_t x : cur)
+        if (!fs.count(x)) nlay.push_back(x);
+    }
+    for (size_t i = 0; i < nlay.size(); ++i) out_bit[nlay[i]] = (int)i;
+    std::vector<int64_t> Nv(Nj[j]);
+    std::sort(Nv.begin(), Nv.end(), [&](int64_t u, int64_t v) { return out_bit[u] < out_bit[v]; });
+    TileStep& ts = sd.st[j];
+    ts.mb = (int)M.size();
+    ts.kb = (int)Kv.size();
+    ts.nb = (int)Nv.size();
+    if (ts.mb > 16 || ts.kb > 8 || ts.nb > 8) return false;
+    for (int i = 0; i < ts.mb; ++i) {
+      ts.am[i] = (uint8_t)in_bit[M[i]];
+      ts.cm[i] = (uint8_t)out_bit[M[i]];
+    }
+    for (int i = 0; i < ts.kb; ++i) {
+      ts.ak[i] = (uint8_t)in_bit[Kv[i]];
+      ts.bk[i] = (uint8_t)b_pos[Kv[i]];
+    }
+    for (int i = 0; i < ts.nb; ++i) {
+      ts.cn[i] = (uint8_t)out_bit[Nv[i]];
+      ts.bn[i] = (uint8_t)b_pos[Nv[i]];
+    }
+    ts.kpad = (uint32_t)std::max(1 << ts.kb, 4);
+    ts.b_lds = b_off;
+    b_off += (uint32_t)std::max(1 << ts.nb, 16) * ts.kpad;
+    ts.out_scale = 1.f;
+    ts.step_index = members[j];
+    lay = nlay;
+  }
+  sd.t_out = (int)lay.size();
+  sd.b_total = b_off;
+  if ((2ull * sd.tile_max + sd.b_total) * 8 > kSectionMaxLds) return false;
+  sec.steps = members;
+  const double esz = precision == MITNC_C64 ? 8.0 : 4.0;
+  sec.flops = 0;
+  sec.bytes = esz * (std::ldexp(1.0, Tin.rank) + std::ldexp(1.0, Tout.rank));
+  for (int m : members) {
+    sec.flops += P->steps[m].flops;
+    sec.bytes += esz * std::ldexp(1.0, P->nodes[P->steps[m].b].rank);
+  }
+  return true;
+}
+
+static void form_sections(mitnc_plan* P, int precision) {
+  const int ns = (int)P->steps.size();
+  std::vector<int> consumer(P->nodes.size(), -1);
+  for (int s = 0; s < ns; ++s) consumer[P->steps[s].a] = consumer[P->steps[s].b] = s;
+  for (int s = 0; s < ns; ++s) {
+    if (P->step_section[s] >= 0 || !section_member_ok(P, P->steps[s])) continue;
+    std::vector<int> mem{s};
+    PlanSection best;
+    bool have = false;
+    while ((int)mem.size() < kMaxSectionSteps) {
+      const PlanStep& last = P->steps[mem.back()];
+      if (P->nodes[last.out].region != 2) break;  // a cached or final value must be stored
+      const int u = consumer[last.out];
+      if (u < 0) break;
+      const PlanStep& su = P->steps[u];
+      if (su.a != last.out || !section_member_ok(P, su) || P->nodes[su.out].lo != P->nodes[last.out].lo) break;
+      mem.push_back(u);
+      PlanSection cand;
+      if (!build_section(P, mem, precision, cand)) break;
+      best = cand;
+      have = true;
+    }
+    if (!have) continue;
+    const int id = (int)P->sections.size();
+    for (int m : best.steps) P->step_section[m] = id;
+    P->sections.push_back(best);
+  }
+}
+
+// Operands a launch reads: a step's two, or a section's input and small
+// tensors.  Returns false for steps that run inside a later launch.
+static bool launch_operands(const mitnc_plan* P, int s, std::vector<int>& ops) {
+  ops.clear();
+  const int sec = P->step_section.empty() ? -1 : P->step_section[s];
+  if (sec < 0) {
+    ops = {P->steps[s].a, P->steps[s].b};
+    return true;
+  }
+  const PlanSection& S = P->sections[sec];
+  if (S.steps.back() != s) return false;
+  ops.push_back(P->steps[S.steps[0]].a);
+  for (int m : S.steps) ops.push_back(P->steps[m].b);
+  return true;
+}
+
 // Replays the launch schedule of slices 0 .. n_slices-1 on the host with a
 // map of which node value every workspace byte range holds, and fails if a
 // step reads an operand whose bytes were overwritten since it was produced,
@@ -254,14 +486,16 @@ static void verify_memory_plan(const mitnc_plan* P, uint64_t n_slices) {
     range(i, lo, hi);
     held.push_back({lo, hi, i});
   }
+  std::vector<int> ops;
   for (uint64_t s = 0; s < n_slices; ++s) {
     int level = s == 0 ? kLevelFirst : __builtin_ctzll(s);
-    for (const PlanStep& st : P->steps) {
+    for (size_t si = 0; si < P->steps.size(); ++si) {
+      const PlanStep& st = P->steps[si];
       if (P->nodes[st.out].lo > level) continue;
-      uint64_t alo, ahi, blo, bhi;
-      range(st.a, alo, ahi);
-      range(st.b, blo, bhi);
-      for (auto [node, lo, hi] : {std::tuple<int, uint64_t, uint64_t>{st.a, alo, ahi}, {st.b, blo, bhi}}) {
+      if (!launch_operands(P, (int)si, ops)) continue;  // runs with its section
+      for (int node : ops) {
+        uint64_t lo, hi;
+        range(node, lo, hi);
         bool ok = false;
         for (auto& b : held)
           if (b.node == node && b.lo == lo && b.hi == hi) ok = true;
@@ -270,8 +504,11 @@ static void verify_memory_plan(const mitnc_plan* P, uint64_t n_slices) {
       if (st.root) continue;
       uint64_t olo, ohi;
       range(st.out, olo, ohi);
-      if ((olo < ahi && alo < ohi) || (olo < bhi && blo < ohi))
-        fail(MITNC_INVALID_ARG, "internal: step output overlaps an operand");
+      for (int node : ops) {
+        uint64_t lo, hi;
+        range(node, lo, hi);
+        if (olo < hi && lo < ohi) fail(MITNC_INVALID_ARG, "internal: step output overlaps an operand");
+      }
       std::vector<Buf> keep;
       for (auto& b : held)
         if (!(b.lo < ohi && olo < b.hi) && b.node != st.out) keep.push_back(b);
@@ -576,6 +813,10 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
     for (auto& st : P->steps)
       if (!st.root) P->nodes[st.out].region = 1;
   }
+  // Fused stem sections (Sec. IV): decided once regions are known (an
+  // intermediate inside a section must be transient).
+  P->step_section.assign(P->steps.size(), -1);
+  if (opts.fuse_sections && opts.force_kernel < 0 && !opts.differentiable) form_sections(P.get(), opts.precision);
   // Memory: persistent slots, then a transient arena with first-fit reuse.
   uint64_t poff = 0;
   for (auto& st : P->steps) {
@@ -589,8 +830,12 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   std::vector<std::pair<uint64_t, uint64_t>> live;  // (offset, size) of live transient buffers
   std::vector<int> live_node;
   uint64_t arena = 0;
+  std::vector<int> ops;
   for (size_t s = 0; s < P->steps.size(); ++s) {
     PlanStep& st = P->steps[s];
+    // A section's steps run at its last step: earlier ones store nothing and
+    // release nothing (the section's input and small tensors stay live).
+    if (!launch_operands(P.get(), (int)s, ops)) continue;
     // The output is placed while the operands are still live (a kernel must
     // never write over its own inputs); the operands are released afterwards.
     PlanNode& O = P->nodes[st.out];
@@ -608,7 +853,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
       live_node.push_back(st.out);
       arena = std::max(arena, cand + sz);
     }
-    for (int op : {st.a, st.b}) {
+    for (int op : ops) {
       for (size_t i = 0; i < live_node.size(); ++i)
         if (live_node[i] == op) {
           live.erase(live.begin() + i);

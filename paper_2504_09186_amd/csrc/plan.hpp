@@ -41,6 +41,15 @@ struct PlanStep {
   uint64_t part_bytes = 0;       // split-K partials, max over d and d64
 };
 
+// A fused stem section: consecutive steps of one chain run as one kernel.
+// sd holds the tile maps and step descriptors; pointers, scales and the
+// statistics slot are filled at launch.
+struct PlanSection {
+  std::vector<int> steps;        // plan step ids, chain order (the first step's A is the section input)
+  SectionDesc sd{};
+  double flops = 0, bytes = 0;   // summed step flops; algorithmic bytes of the fused pass
+};
+
 // One adjoint contraction of the reverse pass: for a step C = A (x) B the
 // adjoint of A is the contraction of adj(C) with B onto A's indices.
 struct RevOp {
@@ -63,6 +72,8 @@ struct mitnc_plan {
   int S = 0;                                 // number of sliced indices
   std::vector<mitnc::PlanNode> nodes;        // leaves then step outputs
   std::vector<mitnc::PlanStep> steps;
+  std::vector<mitnc::PlanSection> sections;  // fused stem sections
+  std::vector<int> step_section;             // per step: section id or -1
   std::vector<std::vector<float>> leaf_data; // complex64 interleaved, full (unsliced) leaves
   std::vector<char> leaf_is_1q;              // leaf is a single-qubit gate
   std::vector<std::vector<uint32_t>> leaf_half;  // FP16/BF16 mantissas (precision plans)

@@ -77,6 +77,49 @@ inline constexpr TileGeom geom_tile_h() { return {7, 6, 5}; }    // 128 x 64, k 
 inline constexpr TileGeom geom_tall_h() { return {7, 4, 5}; }    // 128 x 16, k 32
 inline constexpr TileGeom geom_splitk_h() { return {4, 4, 7}; }  // 16 x 16, k 128 (4 waves split k)
 
+// Fused stem section (Sec. IV): a chain of steps on one large tensor T, each
+// contracting T with a small matrix, run as one kernel.  A workgroup loads a
+// tile of T (its intra-tile bits: every bit the section contracts, plus low
+// address bits for coalescing) into LDS, applies the steps there and writes
+// the final tile; the other (inter-tile) bits only select the tile.
+inline constexpr int kMaxSectionSteps = 8;
+inline constexpr int kSectionClass = 6;    // timing slot of fused sections
+inline constexpr int kMaxTileBits = 13;    // 2^13 complex entries = 64 KB per LDS buffer
+inline constexpr int kTileBitsTarget = 12; // sections prefer 2^12-entry tiles (two workgroups per CU)
+inline constexpr int kMaxSectionB = 1024;  // padded B entries per step
+inline constexpr unsigned kSectionMaxLds = 160u * 1024u - 2048u;  // dynamic LDS bytes of a section kernel
+struct TileStep {
+  const void* B;       // small operand, storage of the run's precision
+  int32_t mb, kb, nb;  // tile bits kept (m), contracted (k), new (n)
+  int32_t step_index;  // plan step (statistics slot)
+  float out_scale;     // FP16/BF16: 2^(eA + eB - eC); 1 for complex64
+  uint32_t b_lds;      // float2 offset of the step's padded B^T in LDS
+  uint32_t kpad;       // row length of the padded B^T (max(K, 4))
+  uint8_t am[16];      // input LDS buffer bit of each m bit (bits 0-3 ride on lanes)
+  uint8_t ak[8];       // input LDS buffer bit of each k bit (bits 0-1 ride on lanes)
+  uint8_t cm[16];      // output LDS buffer bit of each m bit
+  uint8_t cn[8];       // output LDS buffer bit of each n bit
+  uint8_t bk[8], bn[8];  // B address bits of k and n
+};
+struct SectionDesc {
+  const void* A;       // T at the section's start
+  void* C;             // T at its end
+  float* stats;        // optional per-step maxima (as StepDesc::stats)
+  int32_t prec;
+  int32_t n_steps;
+  int32_t t_in, t_out;     // tile bits at start and end
+  int32_t outer_bits;      // inter-tile bits (the same labels in A and C)
+  int32_t tile_max;        // LDS buffer size in entries (power of two): tb tiles
+  int32_t tb_bits;         // log2 of the tiles processed together (a tile group)
+  int32_t stride_bits;     // log2 of a tile's slot in a buffer (largest tile of the section)
+  uint32_t b_total;        // float2 entries of all B^T copies
+  uint8_t p_in[16];        // A address bit of tile bit i (ascending)
+  uint8_t p_out[16];       // C address bit of tile bit i of the final buffer (ascending)
+  uint8_t q_in[32];        // A address bit of outer bit i
+  uint8_t q_out[32];       // C address bit of outer bit i
+  TileStep st[kMaxSectionSteps];
+};
+
 // Stream class limits: no batch bits, at least 2^12 rows, K, N <= 64 and at
 // most 16 (k step, column block) pairs of B held in registers per lane.
 inline constexpr int kStreamMinM = 12;

@@ -97,9 +97,10 @@ class Plan:
     """Execution plan; owns nothing on the device."""
 
     def __init__(self, net: Network, precision: int = _lib.MITNC_C64, reuse: bool = True,
-                 cache_budget_bytes: int = 0, force_kernel: int = -1, differentiable: bool = False):
+                 cache_budget_bytes: int = 0, force_kernel: int = -1, differentiable: bool = False,
+                 fuse_sections: bool = False):
         o = mitnc_plan_opts(precision, 1 if reuse else 0, cache_budget_bytes, force_kernel,
-                            1 if differentiable else 0)
+                            1 if differentiable else 0, 1 if fuse_sections else 0)
         h = C.c_void_p()
         call("mitnc_plan_create", net.h, C.byref(o), C.byref(h))
         self.h = h
@@ -124,7 +125,8 @@ class Plan:
         """Address maps of one step (see mitnc_step_info)."""
         si = _lib.mitnc_step_info()
         call("mitnc_plan_step_info", self.h, step, C.byref(si))
-        r = {f: int(getattr(si, f)) for f in ("a", "b", "out", "root", "kernel_class", "mb", "nb", "kb", "bb")}
+        r = {f: int(getattr(si, f)) for f in ("a", "b", "out", "root", "kernel_class", "section", "section_pos",
+                                              "section_len", "mb", "nb", "kb", "bb")}
         for f, cnt in (("am", "mb"), ("ak", "kb"), ("ab", "bb"), ("bk", "kb"), ("bn", "nb"), ("bbt", "bb"),
                        ("cm", "mb"), ("cn", "nb"), ("cb", "bb")):
             r[f] = list(getattr(si, f))[:r[cnt]]

@@ -42,28 +42,52 @@ class PlanReplay:
         e = sum(((s >> b) & 1) << p for b, p in nd["slice_bits"]) if operand else 0
         return nd["ws_offset"] // 8 + e
 
+    def _contract(self, st, a_flat, b_flat):
+        """One step on flat operands (address bits as in the step's maps);
+        returns (output address of each entry, value)."""
+        b_, m_, k_, n_ = (np.arange(1 << st[x]) for x in ("bb", "mb", "kb", "nb"))
+        ia = (_scatter(b_, st["ab"])[:, None, None] + _scatter(m_, st["am"])[None, :, None]
+              + _scatter(k_, st["ak"])[None, None, :])
+        ib = (_scatter(b_, st["bbt"])[:, None, None] + _scatter(k_, st["bk"])[None, :, None]
+              + _scatter(n_, st["bn"])[None, None, :])
+        ic = (_scatter(b_, st["cb"])[:, None, None] + _scatter(m_, st["cm"])[None, :, None]
+              + _scatter(n_, st["cn"])[None, None, :])
+        c = np.einsum("bmk,bkn->bmn", a_flat[ia], b_flat[ib])
+        return ic.reshape(-1), c.reshape(-1)
+
+    def _operand(self, node, s):
+        nd = self.nodes[node]
+        o = self._ptr(node, s, True)
+        return self.ws[o:o + (1 << nd["full_rank"])]  # a view; only the slice's address bits are used
+
     def run(self, s0, s1):
         """Slices s0 .. s1-1 in order, as the library runs them; returns the
-        complex128 sum of their results."""
+        complex128 sum of their results.  A fused section runs where its last
+        step is; its intermediates live outside the workspace, as on the GPU."""
         acc = np.zeros(self.result_elems, dtype=np.complex128)
+        sections = {}
+        for i, st in enumerate(self.steps):
+            if st["section"] >= 0:
+                sections.setdefault(st["section"], []).append(i)
         for s in range(s0, s1):
-            for st in self.steps:
+            for i, st in enumerate(self.steps):
                 lv = self.nodes[st["out"]]["level"]
                 if s != s0 and (lv < 0 or (s & -s).bit_length() - 1 < lv):
                     continue  # unchanged since the previous slice
-                self.executed += 1
-                b_, m_, k_, n_ = (np.arange(1 << st[x]) for x in ("bb", "mb", "kb", "nb"))
-                ia = (_scatter(b_, st["ab"])[:, None, None] + _scatter(m_, st["am"])[None, :, None]
-                      + _scatter(k_, st["ak"])[None, None, :])
-                ib = (_scatter(b_, st["bbt"])[:, None, None] + _scatter(k_, st["bk"])[None, :, None]
-                      + _scatter(n_, st["bn"])[None, None, :])
-                ic = (_scatter(b_, st["cb"])[:, None, None] + _scatter(m_, st["cm"])[None, :, None]
-                      + _scatter(n_, st["cn"])[None, None, :])
-                a = self.ws[self._ptr(st["a"], s, True) + ia]
-                b = self.ws[self._ptr(st["b"], s, True) + ib]
-                c = np.einsum("bmk,bkn->bmn", a, b)
+                if st["section"] >= 0 and st["section_pos"] != st["section_len"] - 1:
+                    continue  # runs with its section
+                chain = sections[st["section"]] if st["section"] >= 0 else [i]
+                a = self._operand(self.steps[chain[0]]["a"], s)
+                for j in chain:
+                    sj = self.steps[j]
+                    self.executed += 1
+                    idx, val = self._contract(sj, a, self._operand(sj["b"], s))
+                    out = np.zeros(1 << self.nodes[sj["out"]]["full_rank"], dtype=np.complex128)
+                    out[idx] = val
+                    a = out
                 if st["root"]:
-                    np.add.at(acc, ic.reshape(-1), c.reshape(-1))
+                    np.add.at(acc, idx, val)
                 else:
-                    self.ws[self._ptr(st["out"], s, False) + ic] = c
+                    o = self._ptr(st["out"], s, False)
+                    self.ws[o + idx] = val
         return acc

@@ -165,3 +165,56 @@ def test_precision_form_forced_tiles(force):
     torch.cuda.synchronize()
     ref = oracle.sv_amplitudes(c, spec).reshape(-1)
     assert oracle.rel_l2(acc.cpu().numpy(), ref) < 5e-3
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_sections(prec):
+    """4x5 lattice, 12 cycles, intermediates <= 2^17, 4 sliced indices: the
+    stem chain runs as fused sections (Sec. IV).  complex64: fused, unfused
+    and every slice range agree with the state vector to 1e-5; FP16: the
+    fused plan's XEB loss stays below 1e-3."""
+    require_gpu()
+    import torch
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(4, 5, 12, seed=12)
+    spec = synth.output_spec(20, [17, 18, 19], seed=13)
+    net = _lib_net(c, spec)
+    net.path_search(seed=12, trials=8, max_log2=17, min_sliced=4, max_sliced=4)
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    print(f"fused sections case prec {prec}", flush=True)
+    plan = tnc.Plan(net, precision=prec, fuse_sections=True)
+    assert any(plan.step_info(i)["section"] >= 0 for i in range(plan.stats.n_steps))
+    plan.upload()
+    if prec:
+        plan.calibrate(0, 2)
+    acc = plan.new_result()
+    plan.execute(acc)
+    torch.cuda.synchronize()
+    got = acc.cpu().numpy()
+    if prec == 0:
+        assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)
+        plain, _ = _run_opts(net, fuse_sections=False)
+        assert np.linalg.norm(plain - ref) <= TOL * np.linalg.norm(ref)
+        a = plan.new_result()
+        plan.execute(a, 0, 3)
+        plan.execute(a, 3, plan.n_slices)
+        torch.cuda.synchronize()
+        assert np.linalg.norm(a.cpu().numpy() - ref) <= TOL * np.linalg.norm(ref)
+    else:
+        assert oracle.rel_l2(got, ref) < 2e-2
+        p = np.abs(ref) ** 2
+        q = np.abs(got) ** 2
+        p, q = p / p.sum(), q / q.sum()
+        xeb = (ref.size * np.sum(p * q) - 1.0) / (ref.size * np.sum(p * p) - 1.0)
+        assert abs(1.0 - xeb) < 1e-3
+
+
+def _run_opts(net, **kw):
+    import torch
+    from paper_2504_09186_amd import tnc
+    plan = tnc.Plan(net, **kw)
+    plan.upload()
+    acc = plan.new_result()
+    plan.execute(acc)
+    torch.cuda.synchronize()
+    return acc.cpu().numpy(), plan

@@ -37,7 +37,10 @@ def _workload():
     return c, spec
 
 
-def test_config2_all_slices_bench_plan():
+@pytest.mark.parametrize("fuse", [False, True])
+def test_config2_all_slices_bench_plan(fuse):
+    """All 256 slices of the benchmark plan, one launch per step or with the
+    stem chains as fused sections, against the oracle's stored amplitudes."""
     require_gpu()
     import torch
     from paper_2504_09186_amd import tnc
@@ -45,11 +48,13 @@ def test_config2_all_slices_bench_plan():
     c, spec = _workload()
     net = tnc.Network(c, spec)
     net.path_search(seed=3001, trials=64, max_log2=26, min_sliced=8, max_sliced=8)
-    plan = tnc.Plan(net)
+    plan = tnc.Plan(net, fuse_sections=fuse)
     assert plan.n_slices == 256
+    if fuse:
+        assert any(plan.step_info(i)["section"] >= 0 for i in range(plan.stats.n_steps))
     plan.upload()
     acc = plan.new_result()
-    print("config 2: all 256 slices, bench plan", flush=True)
+    print(f"config 2: all 256 slices, bench plan, fused sections {fuse}", flush=True)
     plan.execute(acc)
     torch.cuda.synchronize()
     got = acc.cpu().numpy()
