@@ -66,6 +66,27 @@ def amp_error(got, ref):
             "against": "FP64 oracle, all 64 amplitudes"}
 
 
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(label, kernel):
+    """HBM bytes per launch of the dominant kernel from the committed
+    FETCH_SIZE/WRITE_SIZE counters, or None when they do not apply: another
+    kernel or form, or kernel sources changed since the counters were taken."""
+    import hashlib
+    if label != "c64" or kernel != "stream" or not os.path.exists(TRAFFIC):
+        return None
+    with open(TRAFFIC) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for rel in ("paper_2504_09186_amd/csrc/kernels.hip", "paper_2504_09186_amd/csrc/step.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("kernels_sha256"):
+        return None
+    return rec.get("stream_c64_bytes_per_launch")
+
+
 def run_form(net, precision, steps, warmup, label):
     import torch
 
@@ -121,6 +142,8 @@ def run_form(net, precision, steps, warmup, label):
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
     roof["flop_per_byte"] = ai
     roof["kernel"] = CLASS_NAMES[dom]
+    roof["algorithmic_bytes_per_launch"] = nbytes[dom] / max(1.0, launches[dom])
+    roof["traffic"] = measured_traffic(label, CLASS_NAMES[dom])
     roof["launches"] = int(launches[dom])
     roof["avg_launch_ms"] = ms[dom] / max(1.0, launches[dom])
     total_flops = st.flops_reused_slice * n_slices * steps
@@ -167,7 +190,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer 3 times (reference for HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(slices would be sharded by their outer sliced indices, one FP64 all-reduce at the end).",

@@ -19,6 +19,7 @@
 //
 // Flop counts reported by the library use the 4M convention, 8 M K N real
 // flops per complex contraction, whichever split executes.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -1235,11 +1236,23 @@ hipError_t launch_grad(const GradEntry* tab, int n_entries, const char* ws, uint
 }
 
 // ---------------------------------------------------------------- launch
+// Launch with optional timing: with an event pair the launch goes through
+// hipExtLaunchKernelGGL, whose events carry the kernel's own start and end
+// (no dispatch gap inside the measured interval).
+struct Timing {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+template <typename F, typename... Args>
+static void launch_k(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, Timing t, Args... args) {
+  if (t.e0) hipExtLaunchKernelGGL(kernel, grid, block, lds, s, t.e0, t.e1, 0, args...);
+  else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
 template <int P>
-static hipError_t launch_stem(const StepDesc& d, dim3 grid, hipStream_t s) {
+static hipError_t launch_stem(const StepDesc& d, dim3 grid, hipStream_t s, Timing t) {
 #define MITNC_STEM(KB, NB)                                                \
   if (d.kb == KB && d.nb == NB) {                                         \
-    hipLaunchKernelGGL((k_stem<P, KB, NB>), grid, dim3(256), 0, s, d);    \
+    launch_k(k_stem<P, KB, NB>, grid, dim3(256), 0, s, t, d);             \
     return hipGetLastError();                                             \
   }
   MITNC_STEM(0, 0) MITNC_STEM(0, 1) MITNC_STEM(0, 2)
@@ -1255,7 +1268,7 @@ static hipError_t launch_stem(const StepDesc& d, dim3 grid, hipStream_t s) {
 // The grid holds up to 4096 waves (16 per CU); each wave takes iters
 // iterations of R row blocks.
 template <int P>
-static hipError_t launch_stream(const StepDesc& d, hipStream_t s) {
+static hipError_t launch_stream(const StepDesc& d, hipStream_t s, Timing t) {
   const int ksl = d.kb > 2 ? d.kb - 2 : 0, nbl = d.nb > 4 ? d.nb - 4 : 0;
   if (!stream_fits(d.mb, d.nb, d.kb, d.bb)) return hipErrorInvalidValue;
   const int rl = (P == 0 ? 3 : 4) > ksl ? (P == 0 ? 3 : 4) - ksl : 0;  // log2 R, as in the kernel
@@ -1265,7 +1278,7 @@ static hipError_t launch_stream(const StepDesc& d, hipStream_t s) {
   const dim3 grid(1u << (wl - 2));
 #define MITNC_STREAM(KSL, NBL)                                                                 \
   if (ksl == KSL && nbl == NBL) {                                                              \
-    hipLaunchKernelGGL((k_stream<P, 1 << KSL, 1 << NBL>), grid, dim3(256), 0, s, d, iters);    \
+    launch_k(k_stream<P, 1 << KSL, 1 << NBL>, grid, dim3(256), 0, s, t, d, iters);             \
     return hipGetLastError();                                                                  \
   }
   MITNC_STREAM(0, 0) MITNC_STREAM(1, 0) MITNC_STREAM(2, 0) MITNC_STREAM(3, 0) MITNC_STREAM(4, 0)
@@ -1276,13 +1289,13 @@ static hipError_t launch_stream(const StepDesc& d, hipStream_t s) {
 }
 
 template <int P>
-static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1) {
+static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
   hipError_t e = hipSuccess;
   switch (kclass) {
     case MITNC_K_SMALL: {
       dim3 grid((unsigned)((c_elems + 255) / 256));
-      hipLaunchKernelGGL((k_small<P>), grid, dim3(256), 0, s, d);
+      launch_k(k_small<P>, grid, dim3(256), 0, s, t, d);
       e = hipGetLastError();
       break;
     }
@@ -1290,11 +1303,11 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1
       const int lowb = d.mb < 8 ? d.mb : 8;
       const uint64_t n_mhi = 1ull << (d.mb - lowb);
       dim3 grid((unsigned)(n_mhi < 16384 ? n_mhi : 16384), (unsigned)(1ull << d.bb));
-      e = launch_stem<P>(d, grid, s);
+      e = launch_stem<P>(d, grid, s, t);
       break;
     }
     case MITNC_K_STREAM:
-      e = launch_stream<P>(d, s);
+      e = launch_stream<P>(d, s, t);
       break;
     case MITNC_K_TILE:
     case MITNC_K_TALL:
@@ -1313,21 +1326,20 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1
                 (unsigned)(1ull << d.bb));
       if constexpr (P == 0) {
         if (kclass == MITNC_K_TILE)
-          hipLaunchKernelGGL((k_tile<4, 1, 1, 2, 4, 8>), grid, dim3(256), 0, s, d);
+          launch_k(k_tile<4, 1, 1, 2, 4, 8>, grid, dim3(256), 0, s, t, d);
         else if (kclass == MITNC_K_TALL)
-          hipLaunchKernelGGL((k_tile<4, 1, 1, 2, 1, 16>), grid, dim3(256), 0, s, d);
+          launch_k(k_tile<4, 1, 1, 2, 1, 16>, grid, dim3(256), 0, s, t, d);
         else
-          hipLaunchKernelGGL((k_tile<1, 1, 4, 1, 1, 64>), grid, dim3(256), 0, s, d);
+          launch_k(k_tile<1, 1, 4, 1, 1, 64>, grid, dim3(256), 0, s, t, d);
       } else {
         if (kclass == MITNC_K_TILE)
-          hipLaunchKernelGGL((k_tile_h<P, 2, 2, 1, 4, 4, 32>), grid, dim3(256), 0, s, d);
+          launch_k(k_tile_h<P, 2, 2, 1, 4, 4, 32>, grid, dim3(256), 0, s, t, d);
         else if (kclass == MITNC_K_TALL)
-          hipLaunchKernelGGL((k_tile_h<P, 4, 1, 1, 2, 2, 32>), grid, dim3(256), 0, s, d);
+          launch_k(k_tile_h<P, 4, 1, 1, 2, 2, 32>, grid, dim3(256), 0, s, t, d);
         else
-          hipLaunchKernelGGL((k_tile_h<P, 1, 1, 4, 1, 2, 128>), grid, dim3(256), 0, s, d);
+          launch_k(k_tile_h<P, 1, 1, 4, 1, 2, 128>, grid, dim3(256), 0, s, t, d);
       }
       e = hipGetLastError();
-      if (ev1) (void)hipEventRecord(ev1, s);
       if (e != hipSuccess || d.ks_bits == 0) return e;
       d.mode = final_mode;
       // split rows per workgroup: up to 16, fewer when the splits are few
@@ -1339,12 +1351,11 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, hipEvent_t ev1
     default:
       return hipErrorInvalidValue;
   }
-  if (ev1) (void)hipEventRecord(ev1, s);
   return e;
 }
 
 template <int P>
-static hipError_t launch_section_p(const SectionDesc& sd, unsigned grid, size_t lds, hipStream_t s) {
+static hipError_t launch_section_p(const SectionDesc& sd, unsigned grid, size_t lds, hipStream_t s, Timing t) {
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_section<P>),
@@ -1352,7 +1363,7 @@ static hipError_t launch_section_p(const SectionDesc& sd, unsigned grid, size_t 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_section<P>), dim3(grid), dim3(256), lds, s, sd);
+  launch_k(k_section<P>, dim3(grid), dim3(256), (uint32_t)lds, s, t, sd);
   return hipGetLastError();
 }
 
@@ -1383,24 +1394,21 @@ hipError_t launch_section(const SectionDesc& sd, hipStream_t s, hipEvent_t ev0, 
   const uint64_t tiles = 1ull << (sd.outer_bits - sd.tb_bits);
   const unsigned per_cu = lds > kSectionMaxLds / 2 ? 1 : 2;
   const unsigned grid = (unsigned)(tiles < 256ull * per_cu ? tiles : 256ull * per_cu);
-  if (ev0) (void)hipEventRecord(ev0, s);
-  hipError_t e;
+  const Timing t{ev0, ev1};
   switch (sd.prec) {
-    case MITNC_C64: e = launch_section_p<0>(sd, grid, lds, s); break;
-    case MITNC_CF16: e = launch_section_p<1>(sd, grid, lds, s); break;
-    case MITNC_CBF16: e = launch_section_p<2>(sd, grid, lds, s); break;
+    case MITNC_C64: return launch_section_p<0>(sd, grid, lds, s, t);
+    case MITNC_CF16: return launch_section_p<1>(sd, grid, lds, s, t);
+    case MITNC_CBF16: return launch_section_p<2>(sd, grid, lds, s, t);
     default: return hipErrorInvalidValue;
   }
-  if (ev1) (void)hipEventRecord(ev1, s);
-  return e;
 }
 
 hipError_t launch_step(int kclass, const StepDesc& d, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  if (ev0) (void)hipEventRecord(ev0, s);
+  const Timing t{ev0, ev1};
   switch (d.prec) {
-    case MITNC_C64: return launch_p<0>(kclass, d, s, ev1);
-    case MITNC_CF16: return launch_p<1>(kclass, d, s, ev1);
-    case MITNC_CBF16: return launch_p<2>(kclass, d, s, ev1);
+    case MITNC_C64: return launch_p<0>(kclass, d, s, t);
+    case MITNC_CF16: return launch_p<1>(kclass, d, s, t);
+    case MITNC_CBF16: return launch_p<2>(kclass, d, s, t);
     default: return hipErrorInvalidValue;
   }
 }

@@ -10,8 +10,8 @@ namespace mitnc {
 
 // Launches the kernel(s) of one contraction step of class `kclass` on stream
 // `s` (for split-K: the partial-tile kernel, then the FP64 reduction).
-// With ev0/ev1 given, ev0 is recorded before and ev1 right after the main
-// kernel (before a split-K reduction).
+// With ev0/ev1 given, the main kernel (not a split-K reduction) is launched
+// with hipExtLaunchKernelGGL so that the pair brackets its execution.
 hipError_t launch_step(int kclass, const StepDesc& d, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
 
