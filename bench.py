@@ -157,6 +157,50 @@ def run_form(net, precision, steps, warmup, label):
     }
 
 
+def grad_timing(steps):
+    """Differentiation form: 6x6 lattice, 8 cycles, 256 random bitstrings as a
+    batch index (seeds 1003 / 2003 / 3003), intermediates <= 2^32 entries with
+    the batch bits.  Times the forward over all slices and the backward (per
+    slice: forward recompute, reverse pass, gate-gradient accumulation) with
+    w = 1 / a, the holomorphic seed of L = sum log|a|^2."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(6, 6, 8, seed=1003)
+    bits = synth.random_bitstrings(36, 256, seed=2003)
+    spec = np.full(36, -2, dtype=np.int8)
+    net = tnc.Network(c, spec, bits)
+    net.path_search(seed=3003, trials=32, max_log2=32)
+    plan = tnc.Plan(net, differentiable=True)
+    plan.upload()
+    acc = plan.new_result()
+    plan.execute(acc)
+    w = (1.0 / acc).contiguous()
+    grad = torch.zeros(4 * plan.stats.n_grad_gates, dtype=torch.complex128, device=acc.device)
+    plan.backward(w, grad)  # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        acc.zero_()
+        plan.execute(acc)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        grad.zero_()
+        plan.backward(w, grad)
+    torch.cuda.synchronize()
+    bwd = (time.perf_counter() - t0) / steps
+    st = plan.stats
+    return {"workload": "rqc-6x6-8cyc-256bitstrings-grad", "slices": plan.n_slices,
+            "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "backward_over_forward": bwd / fwd,
+            "forward_flops": st.flops_full_slice * plan.n_slices,
+            "reverse_flops": st.flops_reverse_slice * plan.n_slices, "n_grad_gates": st.n_grad_gates,
+            "finite": bool(torch.isfinite(torch.view_as_real(grad)).all())}
+
+
 def cpu_baseline(c, spec, path, sliced, seconds: float):
     """The FP64 oracle, as it stands, on the same path and slicing: slices
     0, 1, 2, ... until about `seconds` of host time are spent."""
@@ -190,6 +234,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--grad", action="store_true",
+                    help="only time the differentiation form (forward vs backward over all slices) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -212,6 +258,9 @@ def main():
 
     from paper_2504_09186_amd import tnc
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.grad:
+        print(json.dumps(grad_timing(args.steps)), flush=True)
+        return
     c, spec = workload()
     net = tnc.Network(c, spec)
     net.path_search(seed=3001, trials=args.trials, max_log2=26, min_sliced=8, max_sliced=8)
