@@ -32,8 +32,8 @@ CLASS_NAMES = ["small", "stem", "tile", "tall", "splitk", "stream", "section"]
 
 def class_peak(label, cls):
     """Compute peak of the units a kernel class runs on: the FP16 form's tile
-    kernels use FP16 MFMA; everything else computes in FP32."""
-    return PEAK_FP16 if label == "cf16" and cls in (2, 3, 4) else PEAK_FP32
+    and stream kernels use FP16 MFMA; everything else computes in FP32."""
+    return PEAK_FP16 if label == "cf16" and cls in (2, 3, 4, 5) else PEAK_FP32
 GOLDEN = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.json")
 
 

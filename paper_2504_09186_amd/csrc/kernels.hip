@@ -32,6 +32,8 @@ namespace mitnc {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
 
 static_assert(offsetof(StepDesc, am) % 4 == 0, "tables must be dword aligned");
 static_assert(offsetof(StepDesc, c_tile) + 16 - offsetof(StepDesc, am) == TAB_BYTES, "table layout");
@@ -412,6 +414,134 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   if (d.mode == EPI_ACC64) mx = stream_body<P, KS, NBLK, LD, PIPE, 2>(d, tab, iters);
   else if (d.stats) mx = stream_body<P, KS, NBLK, LD, PIPE, 1>(d, tab, iters);
   else mx = stream_body<P, KS, NBLK, LD, PIPE, 0>(d, tab, iters);
+  record_max(d, mx);
+}
+
+// ---------------------------------------------------------------- stream steps, 16-bit MFMA
+// FP16/BF16 storage: the same streaming scheme on the 16 x 16 x 16 FP16/BF16
+// MFMA (FP32 accumulate), complex product by the 4M split written as one real
+// GEMM: A' = A viewed as the real M x 2K matrix of its interleaved halves
+// (the storage itself), B'' = the real 2K x 2N expansion of B with 2 x 2
+// blocks [[br, bi], [-bi, br]].  C'^T = B''^T A'^T: one MFMA covers 16 rows m
+// (on lanes), 8 complex columns n and 8 complex k.  Lane group lq supplies
+// k = 8 ks + 2 lq + {0, 1}: two stored words, as 4 halves, straight from
+// HBM.  MFMA row r of a block holds column n = (r >> 2) + 4 ((r >> 1) & 1),
+// real (r even) or imaginary part, so output registers (0, 1) and (2, 3) of
+// lane group lq are the complex entries n = lq and n = lq + 4.
+template <int P, int KS8, int NB8, int EPI>
+__device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t* tab, uint32_t iters) {
+  constexpr int R = 8 / KS8 > 0 ? 8 / KS8 : 1;  // row blocks per iteration (16 dword loads)
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int K = 1 << d.kb, N = 1 << d.nb;
+  // B''^T fragments: row lr of each 16-row block, k' = 4 lq + t
+  v4h bf[NB8][KS8];
+  {
+    const int nl = (lr >> 2) + 4 * ((lr >> 1) & 1), c = lr & 1;
+#pragma unroll
+    for (int nb = 0; nb < NB8; ++nb)
+#pragma unroll
+      for (int ks = 0; ks < KS8; ++ks) {
+        const int n = 8 * nb + nl;
+        float2 b0 = make_float2(0.f, 0.f), b1 = make_float2(0.f, 0.f);
+        const int k0 = 8 * ks + 2 * lq;
+        if (n < N && k0 < K)
+          b0 = load_c<P>(d.B, scatter_bits(k0, tab + T_BK, d.kb) + scatter_bits(n, tab + T_BN, d.nb));
+        if (n < N && k0 + 1 < K)
+          b1 = load_c<P>(d.B, scatter_bits(k0 + 1, tab + T_BK, d.kb) + scatter_bits(n, tab + T_BN, d.nb));
+        // (c = 0): br, -bi per k; (c = 1): bi, br
+        const float e0 = c ? b0.y : b0.x, e1 = c ? b0.x : -b0.y, e2 = c ? b1.y : b1.x, e3 = c ? b1.x : -b1.y;
+        bf[nb][ks] = v4h{(_Float16)e0, (_Float16)e1, (_Float16)e2, (_Float16)e3};
+        if constexpr (P == 2) {
+          // BF16: the same four values as bfloat16 bit patterns
+          v4s w{(short)f_to_bf(e0), (short)f_to_bf(e1), (short)f_to_bf(e2), (short)f_to_bf(e3)};
+          bf[nb][ks] = __builtin_bit_cast(v4h, w);
+        }
+      }
+  }
+  const uint32_t a_lane = (uint32_t)scatter_bits(lr, tab + T_AM, 4);
+  const uint32_t c_lane = (uint32_t)scatter_bits(lr, tab + T_CM, 4);
+  uint32_t a_k[KS8][2];
+  bool kv[KS8][2];
+#pragma unroll
+  for (int ks = 0; ks < KS8; ++ks)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = 8 * ks + 2 * lq + h;
+      kv[ks][h] = k < K;
+      a_k[ks][h] = a_lane + (uint32_t)scatter_bits(k < K ? k : 0, tab + T_AK, d.kb);
+    }
+  uint32_t c_n[NB8][2];
+#pragma unroll
+  for (int nb = 0; nb < NB8; ++nb)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) c_n[nb][h] = c_lane + (uint32_t)scatter_bits(8 * nb + lq + 4 * h, tab + T_CN, d.nb);
+  const int hb = d.mb - 4;
+  uint64_t mask_a = 0, mask_c = 0;
+  int c_sorted = 1;
+  for (int i = 0; i < hb; ++i) {
+    mask_a |= 1ull << tab[T_AM + 4 + i];
+    mask_c |= 1ull << tab[T_CM + 4 + i];
+    if (i > 0 && tab[T_CM + 4 + i] < tab[T_CM + 3 + i]) c_sorted = 0;
+  }
+  mask_a = uniform64(mask_a);
+  mask_c = uniform64(mask_c);
+  c_sorted = __builtin_amdgcn_readfirstlane(c_sorted);
+  const uint64_t blk0 = uniform64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * iters * R);
+  uint64_t xa = uniform64(scatter_bits(blk0, tab + T_AM + 4, hb));
+  uint64_t xc = uniform64(scatter_bits(blk0, tab + T_CM + 4, hb));
+  const uint32_t* A = reinterpret_cast<const uint32_t*>(d.A);
+  float mx = 0.f;
+  for (uint32_t it = 0; it < iters; ++it) {
+    uint32_t raw[R][KS8][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int ks = 0; ks < KS8; ++ks)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) raw[r][ks][h] = A[xa + a_k[ks][h]];
+      xa = ((xa | ~mask_a) + 1) & mask_a;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v4f acc[NB8];
+#pragma unroll
+      for (int nb = 0; nb < NB8; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS8; ++ks) {
+        const uint32_t w0 = kv[ks][0] ? raw[r][ks][0] : 0u, w1 = kv[ks][1] ? raw[r][ks][1] : 0u;
+        const v4h a = __builtin_bit_cast(v4h, (uint64_t)w0 | ((uint64_t)w1 << 32));
+#pragma unroll
+        for (int nb = 0; nb < NB8; ++nb) {
+          if constexpr (P == 1) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(bf[nb][ks], a, acc[nb], 0, 0, 0);
+          else
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, bf[nb][ks]),
+                                                                __builtin_bit_cast(v4s, a), acc[nb], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB8; ++nb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (8 * nb + lq + 4 * h < N)
+            mx = fmaxf(mx, stream_store<P, EPI>(d, xc + c_n[nb][h], make_float2(acc[nb][2 * h], acc[nb][2 * h + 1])));
+      if (c_sorted) xc = ((xc | ~mask_c) + 1) & mask_c;
+      else xc = uniform64(scatter_bits(blk0 + (uint64_t)it * R + r + 1, tab + T_CM + 4, hb));
+    }
+  }
+  return mx;
+}
+
+template <int P, int KS8, int NB8>
+__global__ __launch_bounds__(256) void k_stream_h(StepDesc d, uint32_t iters) {
+  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  load_tables(d, tab);
+  __syncthreads();
+  float mx;
+  if (d.mode == EPI_ACC64) mx = stream_body_h<P, KS8, NB8, 2>(d, tab, iters);
+  else if (d.stats) mx = stream_body_h<P, KS8, NB8, 1>(d, tab, iters);
+  else mx = stream_body_h<P, KS8, NB8, 0>(d, tab, iters);
   record_max(d, mx);
 }
 
@@ -1264,14 +1394,37 @@ static hipError_t launch_stem(const StepDesc& d, dim3 grid, hipStream_t s, Timin
   return hipErrorInvalidValue;
 }
 
-// Stream steps: KS = 2^ksl k steps of 4, NBLK = 2^nbl column blocks of 16.
-// The grid holds up to 4096 waves (16 per CU); each wave takes iters
-// iterations of R row blocks.
+// Stream steps.  The grid holds up to 4096 waves (16 per CU); each wave takes
+// iters iterations of R row blocks.
+// 16-bit storage: KS8 = 2^ksl k steps of 8, NB8 = 2^nbl column blocks of 8.
 template <int P>
-static hipError_t launch_stream(const StepDesc& d, hipStream_t s, Timing t) {
+static hipError_t launch_stream_h(const StepDesc& d, hipStream_t s, Timing t) {
+  const int ksl = d.kb > 3 ? d.kb - 3 : 0, nbl = d.nb > 3 ? d.nb - 3 : 0;
+  if (!stream_fits(d.mb, d.nb, d.kb, d.bb) || ksl + nbl > 4) return hipErrorInvalidValue;
+  const int rl = 3 > ksl ? 3 - ksl : 0;  // log2 R, as in the kernel
+  const int ngl = d.mb - 4 - rl;
+  const int wl = ngl < 12 ? ngl : 12;
+  const uint32_t iters = 1u << (ngl - wl);
+  const dim3 grid(1u << (wl - 2));
+#define MITNC_STREAMH(KSL, NBL)                                                                \
+  if (ksl == KSL && nbl == NBL) {                                                              \
+    launch_k(k_stream_h<P, 1 << KSL, 1 << NBL>, grid, dim3(256), 0, s, t, d, iters);           \
+    return hipGetLastError();                                                                  \
+  }
+  MITNC_STREAMH(0, 0) MITNC_STREAMH(0, 1) MITNC_STREAMH(0, 2) MITNC_STREAMH(0, 3)
+  MITNC_STREAMH(1, 0) MITNC_STREAMH(1, 1) MITNC_STREAMH(1, 2) MITNC_STREAMH(1, 3)
+  MITNC_STREAMH(2, 0) MITNC_STREAMH(2, 1) MITNC_STREAMH(2, 2)
+  MITNC_STREAMH(3, 0) MITNC_STREAMH(3, 1)
+#undef MITNC_STREAMH
+  return hipErrorInvalidValue;
+}
+
+// complex64: KS = 2^ksl k steps of 4, NBLK = 2^nbl column blocks of 16.
+static hipError_t launch_stream_f(const StepDesc& d, hipStream_t s, Timing t) {
+  constexpr int P = 0;
   const int ksl = d.kb > 2 ? d.kb - 2 : 0, nbl = d.nb > 4 ? d.nb - 4 : 0;
   if (!stream_fits(d.mb, d.nb, d.kb, d.bb)) return hipErrorInvalidValue;
-  const int rl = (P == 0 ? 3 : 4) > ksl ? (P == 0 ? 3 : 4) - ksl : 0;  // log2 R, as in the kernel
+  const int rl = 3 > ksl ? 3 - ksl : 0;  // log2 R, as in the kernel
   const int ngl = d.mb - 4 - rl;           // log2 of row-block groups
   const int wl = ngl < 12 ? ngl : 12;      // log2 waves (>= 3 since mb >= 12)
   const uint32_t iters = 1u << (ngl - wl);
@@ -1286,6 +1439,12 @@ static hipError_t launch_stream(const StepDesc& d, hipStream_t s, Timing t) {
   MITNC_STREAM(0, 2) MITNC_STREAM(1, 2) MITNC_STREAM(2, 2)
 #undef MITNC_STREAM
   return hipErrorInvalidValue;
+}
+
+template <int P>
+static hipError_t launch_stream(const StepDesc& d, hipStream_t s, Timing t) {
+  if constexpr (P == 0) return launch_stream_f(d, s, t);
+  else return launch_stream_h<P>(d, s, t);
 }
 
 template <int P>
