@@ -339,6 +339,7 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
   mask_c = uniform64(mask_c);
   c_sorted = __builtin_amdgcn_readfirstlane(c_sorted);
   const uint64_t blk0 = uniform64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * iters * R);
+  if (blk0 >= (1ull << hb)) iters = 0;  // a wave past the last row block (grids of one workgroup)
   uint64_t xa = uniform64(scatter_bits(blk0, tab + T_AM + 4, hb));
   uint64_t xc = uniform64(scatter_bits(blk0, tab + T_CM + 4, hb));
   const Raw* A = reinterpret_cast<const Raw*>(d.A);
@@ -488,6 +489,7 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
   mask_c = uniform64(mask_c);
   c_sorted = __builtin_amdgcn_readfirstlane(c_sorted);
   const uint64_t blk0 = uniform64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * iters * R);
+  if (blk0 >= (1ull << hb)) iters = 0;  // a wave past the last row block (grids of one workgroup)
   uint64_t xa = uniform64(scatter_bits(blk0, tab + T_AM + 4, hb));
   uint64_t xc = uniform64(scatter_bits(blk0, tab + T_CM + 4, hb));
   const uint32_t* A = reinterpret_cast<const uint32_t*>(d.A);
@@ -1405,7 +1407,7 @@ static hipError_t launch_stream_h(const StepDesc& d, hipStream_t s, Timing t) {
   const int ngl = d.mb - 4 - rl;
   const int wl = ngl < 12 ? ngl : 12;
   const uint32_t iters = 1u << (ngl - wl);
-  const dim3 grid(1u << (wl - 2));
+  const dim3 grid(wl >= 2 ? 1u << (wl - 2) : 1u);  // fewer than 4 waves: one workgroup, idle waves exit
 #define MITNC_STREAMH(KSL, NBL)                                                                \
   if (ksl == KSL && nbl == NBL) {                                                              \
     launch_k(k_stream_h<P, 1 << KSL, 1 << NBL>, grid, dim3(256), 0, s, t, d, iters);           \
@@ -1426,9 +1428,9 @@ static hipError_t launch_stream_f(const StepDesc& d, hipStream_t s, Timing t) {
   if (!stream_fits(d.mb, d.nb, d.kb, d.bb)) return hipErrorInvalidValue;
   const int rl = 3 > ksl ? 3 - ksl : 0;  // log2 R, as in the kernel
   const int ngl = d.mb - 4 - rl;           // log2 of row-block groups
-  const int wl = ngl < 12 ? ngl : 12;      // log2 waves (>= 3 since mb >= 12)
+  const int wl = ngl < 12 ? ngl : 12;      // log2 waves (>= 0 since mb >= 8)
   const uint32_t iters = 1u << (ngl - wl);
-  const dim3 grid(1u << (wl - 2));
+  const dim3 grid(wl >= 2 ? 1u << (wl - 2) : 1u);  // fewer than 4 waves: one workgroup, idle waves exit
 #define MITNC_STREAM(KSL, NBL)                                                                 \
   if (ksl == KSL && nbl == NBL) {                                                              \
     launch_k(k_stream<P, 1 << KSL, 1 << NBL>, grid, dim3(256), 0, s, t, d, iters);             \

@@ -191,7 +191,7 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   if (st.kclass == MITNC_K_STEM && (d.kb > 4 || d.nb > 2))
     fail(MITNC_UNSUPPORTED, "stem kernel needs at most 4 contracted and 2 new indices");
   if (st.kclass == MITNC_K_STREAM && !stream_fits(d.mb, d.nb, d.kb, d.bb))
-    fail(MITNC_UNSUPPORTED, "stream kernel needs no batch indices, >= 12 row bits, K, N <= 64, K N / 64 <= 16");
+    fail(MITNC_UNSUPPORTED, "stream kernel needs no batch indices, >= 8 row bits, K, N <= 64, K N / 64 <= 16");
   TileGeom g = geom_of(st.kclass, precision);
   d.prec = precision;
   d.out_scale = 1.f;
@@ -213,12 +213,12 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     // Split K over workgroups when there are too few output tiles to fill the
     // chip (Sec. V-B: partition along the common indices); keep at least 4 k
     // tiles per workgroup.
-    // Workgroup target: two resident 128 x 64 tiles per CU (512 on 256
-    // CUs) fill the chip for TILE; the smaller tiles of TALL / SPLITK fit
-    // four to five per CU.
+    // Workgroup target: one 128 x 64 tile per CU (256) for TILE (measured
+    // better than two: half the partials to write and reduce); the smaller
+    // tiles of TALL / SPLITK fit four to five per CU.
     int tiles_bits = (d.mb - d.tm) + (d.nb - d.tn) + d.bb;
     int khigh = d.kb - d.tk;
-    int target_bits = st.kclass == MITNC_K_TILE ? 9 : 11;
+    int target_bits = st.kclass == MITNC_K_TILE ? 8 : 11;
     int ks = 0;
     while (tiles_bits + ks < target_bits && ks + 2 < khigh) ++ks;
     uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);

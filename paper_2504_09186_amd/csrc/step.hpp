@@ -120,9 +120,9 @@ struct SectionDesc {
   TileStep st[kMaxSectionSteps];
 };
 
-// Stream class limits: no batch bits, at least 2^12 rows, K, N <= 64 and at
+// Stream class limits: no batch bits, at least 2^8 rows, K, N <= 64 and at
 // most 16 (k step, column block) pairs of B held in registers per lane.
-inline constexpr int kStreamMinM = 12;
+inline constexpr int kStreamMinM = 8;
 inline constexpr bool stream_fits(int mb, int nb, int kb, int bb) {
   return bb == 0 && mb >= kStreamMinM && kb <= 6 && nb <= 6 && (kb > 2 ? kb - 2 : 0) + (nb > 4 ? nb - 4 : 0) <= 4;
 }

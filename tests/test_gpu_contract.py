@@ -95,7 +95,8 @@ def test_splitk(mb, nb, kb, bb):
 @pytest.mark.parametrize("mb,nb,kb,bb", [(12, 0, 0, 0), (12, 1, 1, 0), (13, 2, 2, 0), (14, 5, 5, 0),
                                          (12, 4, 6, 0), (12, 6, 4, 0), (15, 3, 3, 0), (12, 5, 3, 0),
                                          (16, 4, 5, 0), (12, 6, 2, 0), (12, 5, 4, 0), (12, 6, 3, 0),
-                                         (20, 2, 2, 0), (18, 4, 6, 0)])
+                                         (20, 2, 2, 0), (18, 4, 6, 0), (8, 0, 0, 0), (8, 2, 2, 0), (9, 5, 5, 0),
+                                         (10, 4, 6, 0), (8, 6, 4, 0), (11, 3, 3, 0)])
 @pytest.mark.parametrize("in_place", [False, True])
 def test_stream(mb, nb, kb, bb, in_place):
     """Random C layouts take the scattered-address path for row blocks, the
@@ -139,7 +140,7 @@ def _from_half_words(w, prec):
 @pytest.mark.parametrize("mb,nb,kb,bb,kernel", [
     (8, 8, 7, 0, TILE), (9, 3, 6, 0, TALL), (3, 3, 14, 0, SPLITK), (10, 2, 2, 0, STEM), (3, 2, 4, 1, SMALL),
     (7, 6, 9, 1, TILE), (0, 0, 9, 0, SPLITK), (5, 5, 0, 0, TILE), (13, 5, 5, 0, STREAM), (12, 2, 1, 0, STREAM),
-    (12, 4, 6, 0, STREAM)])
+    (12, 4, 6, 0, STREAM), (8, 3, 2, 0, STREAM), (9, 6, 4, 0, STREAM)])
 def test_half_storage(prec, mb, nb, kb, bb, kernel):
     """16-bit storage, FP32 accumulate.  Inputs are mantissas of values around
     2^-30 (scaled by 2^30 into range); the output is rescaled by out_scale.

@@ -127,12 +127,12 @@ def test_plan_workspace_and_reuse_levels(lib):
 
 def test_stream_class_rejects_unsupported_shapes():
     """The stream kernel class refuses shapes outside its limits (batch bits,
-    fewer than 2^12 rows, N > 64, too many B entries per lane) when the step
+    fewer than 2^8 rows, N > 64, too many B entries per lane) when the step
     is built, before any device work."""
     import torch
     from paper_2504_09186_amd import tnc
     from paper_2504_09186_amd._lib import MitncError
-    for mb, nb, kb, bb in [(12, 6, 6, 0), (11, 2, 2, 0), (12, 2, 2, 1), (12, 7, 2, 0)]:
+    for mb, nb, kb, bb in [(12, 6, 6, 0), (7, 2, 2, 0), (12, 2, 2, 1), (12, 7, 2, 0)]:
         M = [1000 + i for i in range(mb)]
         N = [2000 + i for i in range(nb)]
         K = [3000 + i for i in range(kb)]
