@@ -290,8 +290,46 @@ __device__ __forceinline__ float stream_store(const StepDesc& d, uint64_t addr, 
   }
 }
 
+// Address tables of a stream step, built once per workgroup with one scatter
+// per thread (a lane would otherwise run ~50 serial bit scatters before its
+// first load): offsets of every k and n value in A, B and C, of the 16 lane
+// rows in A and C, and the masks of the row-block bits.
+struct StreamLut {
+  uint32_t ak[64], bk[64], bn[64], cn[64];
+  uint32_t am[16], cm[16];
+  unsigned long long mask_a, mask_c;
+  int c_sorted;
+};
+
+__device__ __forceinline__ void stream_lut_init(const StepDesc& d, const uint8_t* tab, StreamLut& L) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    L.mask_a = 0;
+    L.mask_c = 0;
+    L.c_sorted = 1;
+  }
+  __syncthreads();
+  const int K = 1 << d.kb, N = 1 << d.nb, hb = d.mb - 4;
+  if (t < 64) {
+    L.ak[t] = (uint32_t)scatter_bits(t & (K - 1), tab + T_AK, d.kb);
+    L.bk[t] = (uint32_t)scatter_bits(t & (K - 1), tab + T_BK, d.kb);
+    L.bn[t] = (uint32_t)scatter_bits(t & (N - 1), tab + T_BN, d.nb);
+    L.cn[t] = (uint32_t)scatter_bits(t & (N - 1), tab + T_CN, d.nb);
+  } else if (t < 80) {
+    L.am[t - 64] = (uint32_t)scatter_bits(t - 64, tab + T_AM, 4);
+    L.cm[t - 64] = (uint32_t)scatter_bits(t - 64, tab + T_CM, 4);
+  } else if (t >= 128 && t - 128 < hb) {
+    const int i = t - 128;
+    atomicOr(&L.mask_a, 1ull << tab[T_AM + 4 + i]);
+    atomicOr(&L.mask_c, 1ull << tab[T_CM + 4 + i]);
+    if (i > 0 && tab[T_CM + 4 + i] < tab[T_CM + 3 + i]) L.c_sorted = 0;
+  }
+  __syncthreads();
+}
+
 template <int P, int KS, int NBLK, int LD, bool PIPE, int EPI>
-__device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* tab, uint32_t iters) {
+__device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* tab, const StreamLut& L,
+                                             uint32_t iters) {
   constexpr int R = LD / KS > 0 ? LD / KS : 1;  // row blocks per iteration
   using Raw = typename std::conditional<P == 0, float2, uint32_t>::type;
   const int lane = threadIdx.x & 63;
@@ -308,7 +346,7 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + lq, n = 16 * cb + (lr >> 2) + 4 * (lr & 3);
       float2 v = make_float2(0.f, 0.f);
-      if (k < K && n < N) v = load_c<P>(d.B, scatter_bits(k, tab + T_BK, d.kb) + scatter_bits(n, tab + T_BN, d.nb));
+      if (k < K && n < N) v = load_c<P>(d.B, (uint64_t)L.bk[k] + L.bn[n]);
       br[cb][ks] = v.x;
       bi[cb][ks] = v.y;
       bsum[cb][ks] = v.x + v.y;
@@ -316,28 +354,20 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
   // Only K < 4 (one k step) pads inside a k step; the padded lanes read an
   // aliased in-bounds entry and are zeroed.
   const bool kvalid = KS > 1 || lq < K;
-  const uint32_t a_lane = (uint32_t)scatter_bits(lr, tab + T_AM, 4);
-  const uint32_t c_lane = (uint32_t)scatter_bits(lr, tab + T_CM, 4);
+  const uint32_t a_lane = L.am[lr];
+  const uint32_t c_lane = L.cm[lr];
   uint32_t a_k[KS];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) a_k[ks] = a_lane + (uint32_t)scatter_bits(4 * ks + lq, tab + T_AK, d.kb);
+  for (int ks = 0; ks < KS; ++ks) a_k[ks] = a_lane + L.ak[(4 * ks + lq) & 63];
   uint32_t c_n[NBLK][4];
 #pragma unroll
   for (int cb = 0; cb < NBLK; ++cb)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) c_n[cb][i] = c_lane + (uint32_t)scatter_bits(16 * cb + lq + 4 * i, tab + T_CN, d.nb);
+    for (int i = 0; i < 4; ++i) c_n[cb][i] = c_lane + L.cn[(16 * cb + lq + 4 * i) & 63];
   // Row-block addresses are wave-uniform: keep them in scalar registers.
   const int hb = d.mb - 4;
-  uint64_t mask_a = 0, mask_c = 0;
-  int c_sorted = 1;
-  for (int i = 0; i < hb; ++i) {
-    mask_a |= 1ull << tab[T_AM + 4 + i];
-    mask_c |= 1ull << tab[T_CM + 4 + i];
-    if (i > 0 && tab[T_CM + 4 + i] < tab[T_CM + 3 + i]) c_sorted = 0;
-  }
-  mask_a = uniform64(mask_a);
-  mask_c = uniform64(mask_c);
-  c_sorted = __builtin_amdgcn_readfirstlane(c_sorted);
+  const uint64_t mask_a = uniform64(L.mask_a), mask_c = uniform64(L.mask_c);
+  const int c_sorted = __builtin_amdgcn_readfirstlane(L.c_sorted);
   const uint64_t blk0 = uniform64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * iters * R);
   if (blk0 >= (1ull << hb)) iters = 0;  // a wave past the last row block (grids of one workgroup)
   uint64_t xa = uniform64(scatter_bits(blk0, tab + T_AM + 4, hb));
@@ -409,12 +439,13 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
 template <int P, int KS, int NBLK, int LD = stream_loads<P>(), bool PIPE = false>
 __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  __shared__ StreamLut lut;
   load_tables(d, tab);
-  __syncthreads();
+  stream_lut_init(d, tab, lut);
   float mx;
-  if (d.mode == EPI_ACC64) mx = stream_body<P, KS, NBLK, LD, PIPE, 2>(d, tab, iters);
-  else if (d.stats) mx = stream_body<P, KS, NBLK, LD, PIPE, 1>(d, tab, iters);
-  else mx = stream_body<P, KS, NBLK, LD, PIPE, 0>(d, tab, iters);
+  if (d.mode == EPI_ACC64) mx = stream_body<P, KS, NBLK, LD, PIPE, 2>(d, tab, lut, iters);
+  else if (d.stats) mx = stream_body<P, KS, NBLK, LD, PIPE, 1>(d, tab, lut, iters);
+  else mx = stream_body<P, KS, NBLK, LD, PIPE, 0>(d, tab, lut, iters);
   record_max(d, mx);
 }
 
@@ -430,7 +461,8 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
 // real (r even) or imaginary part, so output registers (0, 1) and (2, 3) of
 // lane group lq are the complex entries n = lq and n = lq + 4.
 template <int P, int KS8, int NB8, int EPI>
-__device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t* tab, uint32_t iters) {
+__device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t* tab, const StreamLut& L,
+                                               uint32_t iters) {
   constexpr int R = 8 / KS8 > 0 ? 8 / KS8 : 1;  // row blocks per iteration (16 dword loads)
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lq = lane >> 4;
@@ -446,10 +478,8 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
         const int n = 8 * nb + nl;
         float2 b0 = make_float2(0.f, 0.f), b1 = make_float2(0.f, 0.f);
         const int k0 = 8 * ks + 2 * lq;
-        if (n < N && k0 < K)
-          b0 = load_c<P>(d.B, scatter_bits(k0, tab + T_BK, d.kb) + scatter_bits(n, tab + T_BN, d.nb));
-        if (n < N && k0 + 1 < K)
-          b1 = load_c<P>(d.B, scatter_bits(k0 + 1, tab + T_BK, d.kb) + scatter_bits(n, tab + T_BN, d.nb));
+        if (n < N && k0 < K) b0 = load_c<P>(d.B, (uint64_t)L.bk[k0] + L.bn[n]);
+        if (n < N && k0 + 1 < K) b1 = load_c<P>(d.B, (uint64_t)L.bk[k0 + 1] + L.bn[n]);
         // (c = 0): br, -bi per k; (c = 1): bi, br
         const float e0 = c ? b0.y : b0.x, e1 = c ? b0.x : -b0.y, e2 = c ? b1.y : b1.x, e3 = c ? b1.x : -b1.y;
         bf[nb][ks] = v4h{(_Float16)e0, (_Float16)e1, (_Float16)e2, (_Float16)e3};
@@ -460,8 +490,8 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
         }
       }
   }
-  const uint32_t a_lane = (uint32_t)scatter_bits(lr, tab + T_AM, 4);
-  const uint32_t c_lane = (uint32_t)scatter_bits(lr, tab + T_CM, 4);
+  const uint32_t a_lane = L.am[lr];
+  const uint32_t c_lane = L.cm[lr];
   uint32_t a_k[KS8][2];
   bool kv[KS8][2];
 #pragma unroll
@@ -470,24 +500,16 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
     for (int h = 0; h < 2; ++h) {
       const int k = 8 * ks + 2 * lq + h;
       kv[ks][h] = k < K;
-      a_k[ks][h] = a_lane + (uint32_t)scatter_bits(k < K ? k : 0, tab + T_AK, d.kb);
+      a_k[ks][h] = a_lane + L.ak[k & 63];
     }
   uint32_t c_n[NB8][2];
 #pragma unroll
   for (int nb = 0; nb < NB8; ++nb)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) c_n[nb][h] = c_lane + (uint32_t)scatter_bits(8 * nb + lq + 4 * h, tab + T_CN, d.nb);
+    for (int h = 0; h < 2; ++h) c_n[nb][h] = c_lane + L.cn[(8 * nb + lq + 4 * h) & 63];
   const int hb = d.mb - 4;
-  uint64_t mask_a = 0, mask_c = 0;
-  int c_sorted = 1;
-  for (int i = 0; i < hb; ++i) {
-    mask_a |= 1ull << tab[T_AM + 4 + i];
-    mask_c |= 1ull << tab[T_CM + 4 + i];
-    if (i > 0 && tab[T_CM + 4 + i] < tab[T_CM + 3 + i]) c_sorted = 0;
-  }
-  mask_a = uniform64(mask_a);
-  mask_c = uniform64(mask_c);
-  c_sorted = __builtin_amdgcn_readfirstlane(c_sorted);
+  const uint64_t mask_a = uniform64(L.mask_a), mask_c = uniform64(L.mask_c);
+  const int c_sorted = __builtin_amdgcn_readfirstlane(L.c_sorted);
   const uint64_t blk0 = uniform64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * iters * R);
   if (blk0 >= (1ull << hb)) iters = 0;  // a wave past the last row block (grids of one workgroup)
   uint64_t xa = uniform64(scatter_bits(blk0, tab + T_AM + 4, hb));
@@ -538,12 +560,13 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
 template <int P, int KS8, int NB8>
 __global__ __launch_bounds__(256) void k_stream_h(StepDesc d, uint32_t iters) {
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  __shared__ StreamLut lut;
   load_tables(d, tab);
-  __syncthreads();
+  stream_lut_init(d, tab, lut);
   float mx;
-  if (d.mode == EPI_ACC64) mx = stream_body_h<P, KS8, NB8, 2>(d, tab, iters);
-  else if (d.stats) mx = stream_body_h<P, KS8, NB8, 1>(d, tab, iters);
-  else mx = stream_body_h<P, KS8, NB8, 0>(d, tab, iters);
+  if (d.mode == EPI_ACC64) mx = stream_body_h<P, KS8, NB8, 2>(d, tab, lut, iters);
+  else if (d.stats) mx = stream_body_h<P, KS8, NB8, 1>(d, tab, lut, iters);
+  else mx = stream_body_h<P, KS8, NB8, 0>(d, tab, lut, iters);
   record_max(d, mx);
 }
 
