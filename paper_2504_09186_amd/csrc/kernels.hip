@@ -261,19 +261,19 @@ __global__ __launch_bounds__(256) void k_stem(StepDesc d) {
 //
 // Each wave owns a contiguous run of iters * R row blocks (R blocks per
 // iteration, all R * KS loads issued before the MFMAs; 8 loads of 8 bytes or
-// 16 of 4 bytes per lane).  Block j + 1 of A is
-// the scattered-bit successor of block j, ((x | ~mask) + 1) & mask, because
-// m bits are sorted by A position; C uses the same step when its m bits are
-// in address order too, and a full scatter otherwise.
+// 16 of 4 bytes per lane).  Block j + 1 is the scattered-bit successor of
+// block j, ((x | ~mask) + 1) & mask, in A (m bits are sorted by A position)
+// and in C (the launcher requires its row bits in address order too).
 template <int P>
 inline constexpr int stream_loads() { return P == 0 ? 8 : 16; }
 
 // Output entry of a stream step.  EPI: 0 = store, 1 = store and return the
-// stored magnitude (statistics), 2 = add into the FP64 result.
+// stored magnitude (statistics), 2 = add into the FP64 result.  out is the
+// base of C (EPI 0, 1) or of the result (EPI 2) for this wave's batch index.
 template <int P, int EPI>
-__device__ __forceinline__ float stream_store(const StepDesc& d, uint64_t addr, float2 v) {
+__device__ __forceinline__ float stream_store(void* out, const StepDesc& d, uint64_t addr, float2 v) {
   if constexpr (EPI == 2) {
-    double2* acc = reinterpret_cast<double2*>(d.acc);
+    double2* acc = reinterpret_cast<double2*>(out);
     double2 o = acc[addr];
     o.x += (double)v.x * d.acc_scale;
     o.y += (double)v.y * d.acc_scale;
@@ -281,10 +281,10 @@ __device__ __forceinline__ float stream_store(const StepDesc& d, uint64_t addr, 
     return 0.f;
   } else {
     if constexpr (P == 0) {
-      reinterpret_cast<float2*>(d.C)[addr] = v;
+      reinterpret_cast<float2*>(out)[addr] = v;
     } else {
       v = make_float2(v.x * d.out_scale, v.y * d.out_scale);
-      reinterpret_cast<uint32_t*>(d.C)[addr] = pack<P>(v);
+      reinterpret_cast<uint32_t*>(out)[addr] = pack<P>(v);
     }
     return EPI == 1 ? absmax2(v) : 0.f;
   }
@@ -292,21 +292,29 @@ __device__ __forceinline__ float stream_store(const StepDesc& d, uint64_t addr, 
 
 // Address tables of a stream step, built once per workgroup with one scatter
 // per thread (a lane would otherwise run ~50 serial bit scatters before its
-// first load): offsets of every k and n value in A, B and C, of the 16 lane
-// rows in A and C, and the masks of the row-block bits.
+// first load, and scalar scatters of 64-bit values spill scalar registers):
+// offsets of every k and n value in A, B and C, of the 16 lane rows in A and
+// C, the mask of the row-block bits, and for each of the four waves the
+// offsets of its first row block and of its batch index.
+//
+// Row blocks of all batch indices are numbered (batch << hb) | block; a
+// wave's run of blocks never crosses a batch index (the launcher makes runs
+// at most 2^hb blocks long), so its batch index and B are fixed.  C's row
+// bits must be in address order like A's (the launcher checks), so the next
+// block's offset is the scattered-bit successor in both.
 struct StreamLut {
   uint32_t ak[64], bk[64], bn[64], cn[64];
   uint32_t am[16], cm[16];
   unsigned long long mask_a, mask_c;
-  int c_sorted;
+  unsigned long long xa0[4], xc0[4], a_b[4], b_b[4], c_b[4];
 };
 
-__device__ __forceinline__ void stream_lut_init(const StepDesc& d, const uint8_t* tab, StreamLut& L) {
+__device__ __forceinline__ void stream_lut_init(const StepDesc& d, const uint8_t* tab, StreamLut& L,
+                                                uint64_t blocks_per_wave) {
   const int t = threadIdx.x;
   if (t == 0) {
     L.mask_a = 0;
     L.mask_c = 0;
-    L.c_sorted = 1;
   }
   __syncthreads();
   const int K = 1 << d.kb, N = 1 << d.nb, hb = d.mb - 4;
@@ -318,11 +326,18 @@ __device__ __forceinline__ void stream_lut_init(const StepDesc& d, const uint8_t
   } else if (t < 80) {
     L.am[t - 64] = (uint32_t)scatter_bits(t - 64, tab + T_AM, 4);
     L.cm[t - 64] = (uint32_t)scatter_bits(t - 64, tab + T_CM, 4);
+  } else if (t < 84) {
+    const uint64_t blk0 = ((uint64_t)blockIdx.x * 4 + (t - 80)) * blocks_per_wave;
+    const uint64_t batch = blk0 >> hb;
+    L.xa0[t - 80] = scatter_bits(blk0, tab + T_AM + 4, hb);
+    L.xc0[t - 80] = scatter_bits(blk0, tab + T_CM + 4, hb);
+    L.a_b[t - 80] = scatter_bits(batch, tab + T_AB, d.bb);
+    L.b_b[t - 80] = scatter_bits(batch, tab + T_BB, d.bb);
+    L.c_b[t - 80] = scatter_bits(batch, tab + T_CB, d.bb);
   } else if (t >= 128 && t - 128 < hb) {
     const int i = t - 128;
     atomicOr(&L.mask_a, 1ull << tab[T_AM + 4 + i]);
     atomicOr(&L.mask_c, 1ull << tab[T_CM + 4 + i]);
-    if (i > 0 && tab[T_CM + 4 + i] < tab[T_CM + 3 + i]) L.c_sorted = 0;
   }
   __syncthreads();
 }
@@ -334,7 +349,11 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
   using Raw = typename std::conditional<P == 0, float2, uint32_t>::type;
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lq = lane >> 4;
+  const int w = threadIdx.x >> 6;
   const int K = 1 << d.kb, N = 1 << d.nb;
+  if (((uint64_t)blockIdx.x * 4 + w) * iters * R >= (1ull << (d.mb - 4 + d.bb)))
+    iters = 0;  // a wave past the last row block (grids of one workgroup)
+  const uint64_t b_b = L.b_b[w];
   // MFMA row r of a column block is column n = (r >> 2) + 4 (r & 3) of it, so
   // that output register i of lane group lq is column lq + 4 i: the lowest
   // two n bits sit on lanes and a store instruction covers them.
@@ -346,7 +365,7 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + lq, n = 16 * cb + (lr >> 2) + 4 * (lr & 3);
       float2 v = make_float2(0.f, 0.f);
-      if (k < K && n < N) v = load_c<P>(d.B, (uint64_t)L.bk[k] + L.bn[n]);
+      if (k < K && n < N) v = load_c<P>(d.B, b_b + L.bk[k] + L.bn[n]);
       br[cb][ks] = v.x;
       bi[cb][ks] = v.y;
       bsum[cb][ks] = v.x + v.y;
@@ -365,14 +384,11 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
 #pragma unroll
     for (int i = 0; i < 4; ++i) c_n[cb][i] = c_lane + L.cn[(16 * cb + lq + 4 * i) & 63];
   // Row-block addresses are wave-uniform: keep them in scalar registers.
-  const int hb = d.mb - 4;
   const uint64_t mask_a = uniform64(L.mask_a), mask_c = uniform64(L.mask_c);
-  const int c_sorted = __builtin_amdgcn_readfirstlane(L.c_sorted);
-  const uint64_t blk0 = uniform64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * iters * R);
-  if (blk0 >= (1ull << hb)) iters = 0;  // a wave past the last row block (grids of one workgroup)
-  uint64_t xa = uniform64(scatter_bits(blk0, tab + T_AM + 4, hb));
-  uint64_t xc = uniform64(scatter_bits(blk0, tab + T_CM + 4, hb));
-  const Raw* A = reinterpret_cast<const Raw*>(d.A);
+  uint64_t xa = uniform64(L.xa0[w]), xc = uniform64(L.xc0[w]);
+  const Raw* A = reinterpret_cast<const Raw*>(d.A) + uniform64(L.a_b[w]);
+  void* out = EPI == 2 ? (void*)(reinterpret_cast<double2*>(d.acc) + uniform64(L.c_b[w]))
+                       : (void*)(reinterpret_cast<char*>(d.C) + uniform64(L.c_b[w]) * (P == 0 ? 8 : 4));
   float mx = 0.f;
   Raw raw[R][KS], nxt[R][KS];
   auto load = [&](Raw (&dst)[R][KS]) {
@@ -421,10 +437,9 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
         for (int i = 0; i < 4; ++i)
           if (16 * cb + lq + 4 * i < N) {
             const float t1 = acc[0][cb][i], t2 = acc[1][cb][i], t3 = acc[2][cb][i];
-            mx = fmaxf(mx, stream_store<P, EPI>(d, xc + c_n[cb][i], make_float2(t1 - t2, t3 - t1 - t2)));
+            mx = fmaxf(mx, stream_store<P, EPI>(out, d, xc + c_n[cb][i], make_float2(t1 - t2, t3 - t1 - t2)));
           }
-      if (c_sorted) xc = ((xc | ~mask_c) + 1) & mask_c;
-      else xc = uniform64(scatter_bits(blk0 + (uint64_t)it * R + r + 1, tab + T_CM + 4, hb));
+      xc = ((xc | ~mask_c) + 1) & mask_c;
     }
     if (PIPE) {
 #pragma unroll
@@ -441,7 +456,8 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   __shared__ StreamLut lut;
   load_tables(d, tab);
-  stream_lut_init(d, tab, lut);
+  constexpr int R = LD / KS > 0 ? LD / KS : 1;
+  stream_lut_init(d, tab, lut, (uint64_t)iters * R);
   float mx;
   if (d.mode == EPI_ACC64) mx = stream_body<P, KS, NBLK, LD, PIPE, 2>(d, tab, lut, iters);
   else if (d.stats) mx = stream_body<P, KS, NBLK, LD, PIPE, 1>(d, tab, lut, iters);
@@ -466,7 +482,11 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
   constexpr int R = 8 / KS8 > 0 ? 8 / KS8 : 1;  // row blocks per iteration (16 dword loads)
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lq = lane >> 4;
+  const int w = threadIdx.x >> 6;
   const int K = 1 << d.kb, N = 1 << d.nb;
+  if (((uint64_t)blockIdx.x * 4 + w) * iters * R >= (1ull << (d.mb - 4 + d.bb)))
+    iters = 0;  // a wave past the last row block (grids of one workgroup)
+  const uint64_t b_b = L.b_b[w];
   // B''^T fragments: row lr of each 16-row block, k' = 4 lq + t
   v4h bf[NB8][KS8];
   {
@@ -478,8 +498,8 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
         const int n = 8 * nb + nl;
         float2 b0 = make_float2(0.f, 0.f), b1 = make_float2(0.f, 0.f);
         const int k0 = 8 * ks + 2 * lq;
-        if (n < N && k0 < K) b0 = load_c<P>(d.B, (uint64_t)L.bk[k0] + L.bn[n]);
-        if (n < N && k0 + 1 < K) b1 = load_c<P>(d.B, (uint64_t)L.bk[k0 + 1] + L.bn[n]);
+        if (n < N && k0 < K) b0 = load_c<P>(d.B, b_b + L.bk[k0] + L.bn[n]);
+        if (n < N && k0 + 1 < K) b1 = load_c<P>(d.B, b_b + L.bk[k0 + 1] + L.bn[n]);
         // (c = 0): br, -bi per k; (c = 1): bi, br
         const float e0 = c ? b0.y : b0.x, e1 = c ? b0.x : -b0.y, e2 = c ? b1.y : b1.x, e3 = c ? b1.x : -b1.y;
         bf[nb][ks] = v4h{(_Float16)e0, (_Float16)e1, (_Float16)e2, (_Float16)e3};
@@ -507,14 +527,11 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
   for (int nb = 0; nb < NB8; ++nb)
 #pragma unroll
     for (int h = 0; h < 2; ++h) c_n[nb][h] = c_lane + L.cn[(8 * nb + lq + 4 * h) & 63];
-  const int hb = d.mb - 4;
   const uint64_t mask_a = uniform64(L.mask_a), mask_c = uniform64(L.mask_c);
-  const int c_sorted = __builtin_amdgcn_readfirstlane(L.c_sorted);
-  const uint64_t blk0 = uniform64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * iters * R);
-  if (blk0 >= (1ull << hb)) iters = 0;  // a wave past the last row block (grids of one workgroup)
-  uint64_t xa = uniform64(scatter_bits(blk0, tab + T_AM + 4, hb));
-  uint64_t xc = uniform64(scatter_bits(blk0, tab + T_CM + 4, hb));
-  const uint32_t* A = reinterpret_cast<const uint32_t*>(d.A);
+  uint64_t xa = uniform64(L.xa0[w]), xc = uniform64(L.xc0[w]);
+  const uint32_t* A = reinterpret_cast<const uint32_t*>(d.A) + uniform64(L.a_b[w]);
+  void* out = EPI == 2 ? (void*)(reinterpret_cast<double2*>(d.acc) + uniform64(L.c_b[w]))
+                       : (void*)(reinterpret_cast<uint32_t*>(d.C) + uniform64(L.c_b[w]));
   float mx = 0.f;
   for (uint32_t it = 0; it < iters; ++it) {
     uint32_t raw[R][KS8][2];
@@ -549,9 +566,9 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
 #pragma unroll
         for (int h = 0; h < 2; ++h)
           if (8 * nb + lq + 4 * h < N)
-            mx = fmaxf(mx, stream_store<P, EPI>(d, xc + c_n[nb][h], make_float2(acc[nb][2 * h], acc[nb][2 * h + 1])));
-      if (c_sorted) xc = ((xc | ~mask_c) + 1) & mask_c;
-      else xc = uniform64(scatter_bits(blk0 + (uint64_t)it * R + r + 1, tab + T_CM + 4, hb));
+            mx = fmaxf(mx, stream_store<P, EPI>(out, d, xc + c_n[nb][h],
+                                                make_float2(acc[nb][2 * h], acc[nb][2 * h + 1])));
+      xc = ((xc | ~mask_c) + 1) & mask_c;
     }
   }
   return mx;
@@ -562,7 +579,8 @@ __global__ __launch_bounds__(256) void k_stream_h(StepDesc d, uint32_t iters) {
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   __shared__ StreamLut lut;
   load_tables(d, tab);
-  stream_lut_init(d, tab, lut);
+  constexpr int R = 8 / KS8 > 0 ? 8 / KS8 : 1;
+  stream_lut_init(d, tab, lut, (uint64_t)iters * R);
   float mx;
   if (d.mode == EPI_ACC64) mx = stream_body_h<P, KS8, NB8, 2>(d, tab, lut, iters);
   else if (d.stats) mx = stream_body_h<P, KS8, NB8, 1>(d, tab, lut, iters);
@@ -1427,8 +1445,10 @@ static hipError_t launch_stream_h(const StepDesc& d, hipStream_t s, Timing t) {
   const int ksl = d.kb > 3 ? d.kb - 3 : 0, nbl = d.nb > 3 ? d.nb - 3 : 0;
   if (!stream_fits(d.mb, d.nb, d.kb, d.bb) || ksl + nbl > 4) return hipErrorInvalidValue;
   const int rl = 3 > ksl ? 3 - ksl : 0;  // log2 R, as in the kernel
-  const int ngl = d.mb - 4 - rl;
+  if (!stream_rows_sorted(d)) return hipErrorInvalidValue;
+  const int ngl = d.mb - 4 + d.bb - rl;  // block groups of all batch indices
   const int wl = ngl < 12 ? ngl : 12;
+  if (wl < d.bb) return hipErrorInvalidValue;  // a wave's run must stay inside one batch index
   const uint32_t iters = 1u << (ngl - wl);
   const dim3 grid(wl >= 2 ? 1u << (wl - 2) : 1u);  // fewer than 4 waves: one workgroup, idle waves exit
 #define MITNC_STREAMH(KSL, NBL)                                                                \
@@ -1450,8 +1470,10 @@ static hipError_t launch_stream_f(const StepDesc& d, hipStream_t s, Timing t) {
   const int ksl = d.kb > 2 ? d.kb - 2 : 0, nbl = d.nb > 4 ? d.nb - 4 : 0;
   if (!stream_fits(d.mb, d.nb, d.kb, d.bb)) return hipErrorInvalidValue;
   const int rl = 3 > ksl ? 3 - ksl : 0;  // log2 R, as in the kernel
-  const int ngl = d.mb - 4 - rl;           // log2 of row-block groups
-  const int wl = ngl < 12 ? ngl : 12;      // log2 waves (>= 0 since mb >= 8)
+  if (!stream_rows_sorted(d)) return hipErrorInvalidValue;
+  const int ngl = d.mb - 4 + d.bb - rl;  // log2 of row-block groups of all batch indices
+  const int wl = ngl < 12 ? ngl : 12;    // log2 waves (>= 0 since mb >= 8)
+  if (wl < d.bb) return hipErrorInvalidValue;  // a wave's run must stay inside one batch index
   const uint32_t iters = 1u << (ngl - wl);
   const dim3 grid(wl >= 2 ? 1u << (wl - 2) : 1u);  // fewer than 4 waves: one workgroup, idle waves exit
 #define MITNC_STREAM(KSL, NBL)                                                                 \

@@ -73,6 +73,14 @@ int mantissa_exponent(double max_abs) {
   return (e2 - 1) - 13;
 }
 
+static int choose_class_no_stream(int mb, int nb, int kb, int bb) {
+  if (mb + nb + bb <= 10 && kb <= 6) return MITNC_K_SMALL;
+  if (nb <= 2 && kb <= 4) return MITNC_K_STEM;
+  if (mb <= 4 && nb <= 4) return MITNC_K_SPLITK;
+  if (nb <= 4) return MITNC_K_TALL;
+  return MITNC_K_TILE;
+}
+
 static int choose_class(int mb, int nb, int kb, int bb) {
   int out_bits = mb + nb + bb;
   if (out_bits <= 10 && kb <= 6) return MITNC_K_SMALL;
@@ -81,6 +89,16 @@ static int choose_class(int mb, int nb, int kb, int bb) {
   if (mb <= 4 && nb <= 4) return MITNC_K_SPLITK;
   if (nb <= 4) return MITNC_K_TALL;
   return MITNC_K_TILE;
+}
+
+// True when the row indices M (sorted by A position) above the lowest four
+// also come in ascending position in the output layout C.
+static bool rows_in_order(const std::vector<int64_t>& M, const std::vector<int64_t>& C) {
+  std::map<int64_t, int> pc;
+  for (size_t i = 0; i < C.size(); ++i) pc[C[i]] = (int)i;
+  for (size_t i = 5; i < M.size(); ++i)
+    if (pc[M[i]] <= pc[M[i - 1]]) return false;
+  return true;
 }
 
 // Builds the descriptor of a step given the operand layouts.
@@ -116,8 +134,10 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   std::sort(M.begin(), M.end(), by(pa));
   std::sort(N.begin(), N.end(), by(pb));
   std::sort(Bt.begin(), Bt.end(), by(pa));
-  const int kclass = force_kernel >= 0 ? force_kernel
-                                       : choose_class((int)M.size(), (int)N.size(), (int)K.size(), (int)Bt.size());
+  int kclass = force_kernel >= 0 ? force_kernel
+                                 : choose_class((int)M.size(), (int)N.size(), (int)K.size(), (int)Bt.size());
+  if (force_kernel < 0 && kclass == MITNC_K_STREAM && root_layout && !rows_in_order(M, *root_layout))
+    kclass = choose_class_no_stream((int)M.size(), (int)N.size(), (int)K.size(), (int)Bt.size());
   if (kclass == MITNC_K_STREAM) {
     // Stream kernel: the two lowest k bits ride on lanes next to the four
     // lowest m bits, so K goes by A position (B is small and cached).
@@ -190,8 +210,9 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   if (st.kclass < MITNC_K_SMALL || st.kclass > MITNC_K_STREAM) fail(MITNC_INVALID_ARG, "unknown kernel class");
   if (st.kclass == MITNC_K_STEM && (d.kb > 4 || d.nb > 2))
     fail(MITNC_UNSUPPORTED, "stem kernel needs at most 4 contracted and 2 new indices");
-  if (st.kclass == MITNC_K_STREAM && !stream_fits(d.mb, d.nb, d.kb, d.bb))
-    fail(MITNC_UNSUPPORTED, "stream kernel needs no batch indices, >= 8 row bits, K, N <= 64, K N / 64 <= 16");
+  if (st.kclass == MITNC_K_STREAM && (!stream_fits(d.mb, d.nb, d.kb, d.bb) || !stream_rows_sorted(d)))
+    fail(MITNC_UNSUPPORTED,
+         "stream kernel needs <= 10 batch bits, >= 8 row bits, K, N <= 64, K N / 64 <= 16 and C row bits in order");
   TileGeom g = geom_of(st.kclass, precision);
   d.prec = precision;
   d.out_scale = 1.f;

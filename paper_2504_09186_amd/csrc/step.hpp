@@ -120,11 +120,20 @@ struct SectionDesc {
   TileStep st[kMaxSectionSteps];
 };
 
-// Stream class limits: no batch bits, at least 2^8 rows, K, N <= 64 and at
-// most 16 (k step, column block) pairs of B held in registers per lane.
+// Stream class limits: at most 2^10 batch indices, at least 2^8 rows, K, N
+// <= 64 and at most 16 (k step, column block) pairs of B held in registers
+// per lane.
 inline constexpr int kStreamMinM = 8;
 inline constexpr bool stream_fits(int mb, int nb, int kb, int bb) {
-  return bb == 0 && mb >= kStreamMinM && kb <= 6 && nb <= 6 && (kb > 2 ? kb - 2 : 0) + (nb > 4 ? nb - 4 : 0) <= 4;
+  return bb <= 10 && mb >= kStreamMinM && kb <= 6 && nb <= 6 && (kb > 2 ? kb - 2 : 0) + (nb > 4 ? nb - 4 : 0) <= 4;
+}
+
+// The stream kernel steps C's rows with the same scattered-bit increment as
+// A's, so the row bits above the four lane bits must ascend in C as in A.
+inline bool stream_rows_sorted(const StepDesc& d) {
+  for (int i = 5; i < d.mb; ++i)
+    if (d.cm[i] <= d.cm[i - 1]) return false;
+  return true;
 }
 
 }  // namespace mitnc

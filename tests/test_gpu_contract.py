@@ -21,9 +21,11 @@ pytestmark = pytest.mark.gpu
 SMALL, STEM, TILE, TALL, SPLITK, STREAM = 0, 1, 2, 3, 4, 5
 
 
-def _case(mb, nb, kb, bb, seed, in_place=False):
+def _case(mb, nb, kb, bb, seed, in_place=False, rows_ordered=False):
     """Random layouts; with in_place, C takes A's layout with the k bits
-    replaced by n bits (the planner's output policy)."""
+    replaced by n bits (the planner's output policy).  With rows_ordered, the
+    row indices past the four lowest of A keep A's relative order in C (what
+    the stream kernel requires); the rest of C stays random."""
     rng = np.random.default_rng(seed)
     M = [1000 + i for i in range(mb)]
     N = [2000 + i for i in range(nb)]
@@ -32,6 +34,12 @@ def _case(mb, nb, kb, bb, seed, in_place=False):
     la = list(rng.permutation(M + K + Bt)) if (mb + kb + bb) else []
     lb = list(rng.permutation(K + N + Bt)) if (kb + nb + bb) else []
     lc = list(rng.permutation(M + N + Bt)) if (mb + nb + bb) else []
+    if rows_ordered and mb > 5:
+        by_a = sorted(M, key=la.index)
+        high = set(by_a[4:])
+        slots = sorted(i for i, x in enumerate(lc) if x in high)
+        for i, x in zip(slots, by_a[4:]):
+            lc[i] = x
     if in_place:
         nit = iter(N)
         lc = [x for x in (next(nit, None) if x in K else x for x in la) if x is not None] + list(nit)
@@ -44,7 +52,7 @@ def _run(mb, nb, kb, bb, kernel, seed, in_place=False):
     require_gpu()
     import torch
     from paper_2504_09186_amd import tnc
-    la, lb, lc, a, b = _case(mb, nb, kb, bb, seed, in_place)
+    la, lb, lc, a, b = _case(mb, nb, kb, bb, seed, in_place, rows_ordered=kernel == STREAM)
     print(f"contract case m{mb} n{nb} k{kb} b{bb} kernel {kernel} seed {seed}", flush=True)
     ta = torch.from_numpy(a).cuda()
     tb = torch.from_numpy(b).cuda()
@@ -96,11 +104,13 @@ def test_splitk(mb, nb, kb, bb):
                                          (12, 4, 6, 0), (12, 6, 4, 0), (15, 3, 3, 0), (12, 5, 3, 0),
                                          (16, 4, 5, 0), (12, 6, 2, 0), (12, 5, 4, 0), (12, 6, 3, 0),
                                          (20, 2, 2, 0), (18, 4, 6, 0), (8, 0, 0, 0), (8, 2, 2, 0), (9, 5, 5, 0),
-                                         (10, 4, 6, 0), (8, 6, 4, 0), (11, 3, 3, 0)])
+                                         (10, 4, 6, 0), (8, 6, 4, 0), (11, 3, 3, 0), (10, 2, 2, 2), (12, 5, 5, 3),
+                                         (9, 4, 6, 1), (8, 3, 3, 4), (8, 1, 2, 8)])
 @pytest.mark.parametrize("in_place", [False, True])
 def test_stream(mb, nb, kb, bb, in_place):
-    """Random C layouts take the scattered-address path for row blocks, the
-    planner's in-place layout the incremental one."""
+    """Random C layouts (row indices past the lane bits in A's order, the lane
+    bits, column and batch indices anywhere) and the planner's in-place
+    layout; batch indices split the waves' row runs."""
     _run(mb, nb, kb, bb, STREAM, seed=13 + mb + 10 * nb + 100 * kb, in_place=in_place)
 
 
@@ -140,7 +150,7 @@ def _from_half_words(w, prec):
 @pytest.mark.parametrize("mb,nb,kb,bb,kernel", [
     (8, 8, 7, 0, TILE), (9, 3, 6, 0, TALL), (3, 3, 14, 0, SPLITK), (10, 2, 2, 0, STEM), (3, 2, 4, 1, SMALL),
     (7, 6, 9, 1, TILE), (0, 0, 9, 0, SPLITK), (5, 5, 0, 0, TILE), (13, 5, 5, 0, STREAM), (12, 2, 1, 0, STREAM),
-    (12, 4, 6, 0, STREAM), (8, 3, 2, 0, STREAM), (9, 6, 4, 0, STREAM)])
+    (12, 4, 6, 0, STREAM), (8, 3, 2, 0, STREAM), (9, 6, 4, 0, STREAM), (10, 5, 5, 2, STREAM)])
 def test_half_storage(prec, mb, nb, kb, bb, kernel):
     """16-bit storage, FP32 accumulate.  Inputs are mantissas of values around
     2^-30 (scaled by 2^30 into range); the output is rescaled by out_scale.
@@ -149,7 +159,7 @@ def test_half_storage(prec, mb, nb, kb, bb, kernel):
     require_gpu()
     import torch
     from paper_2504_09186_amd import tnc
-    la, lb, lc, a, b = _case(mb, nb, kb, bb, 77 + mb + 10 * nb + 100 * kb + prec)
+    la, lb, lc, a, b = _case(mb, nb, kb, bb, 77 + mb + 10 * nb + 100 * kb + prec, rows_ordered=kernel == STREAM)
     a = a.astype(np.complex128) * 2.0 ** -30 * 2.0 ** 30  # mantissas of 2^-30-sized values
     wa, ar = _to_half_words(a, prec)
     wb, br = _to_half_words(b.astype(np.complex128), prec)

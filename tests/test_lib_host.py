@@ -126,13 +126,13 @@ def test_plan_workspace_and_reuse_levels(lib):
 
 
 def test_stream_class_rejects_unsupported_shapes():
-    """The stream kernel class refuses shapes outside its limits (batch bits,
-    fewer than 2^8 rows, N > 64, too many B entries per lane) when the step
+    """The stream kernel class refuses shapes outside its limits (more than
+    2^10 batch indices, fewer than 2^8 rows, N > 64, too many B entries per lane) when the step
     is built, before any device work."""
     import torch
     from paper_2504_09186_amd import tnc
     from paper_2504_09186_amd._lib import MitncError
-    for mb, nb, kb, bb in [(12, 6, 6, 0), (7, 2, 2, 0), (12, 2, 2, 1), (12, 7, 2, 0)]:
+    for mb, nb, kb, bb in [(12, 6, 6, 0), (7, 2, 2, 0), (8, 2, 2, 11), (12, 7, 2, 0)]:
         M = [1000 + i for i in range(mb)]
         N = [2000 + i for i in range(nb)]
         K = [3000 + i for i in range(kb)]
@@ -141,6 +141,13 @@ def test_stream_class_rejects_unsupported_shapes():
         b = torch.zeros(1 << (kb + nb + bb), dtype=torch.complex64)
         with pytest.raises(MitncError, match="stream kernel"):
             tnc.contract(a, M + K + Bt, b, K + N + Bt, M + N + Bt, kernel=5)
+    # Row indices past the four lowest out of A's order in C.
+    M = [1000 + i for i in range(10)]
+    a = torch.zeros(1 << 12, dtype=torch.complex64)
+    b = torch.zeros(1 << 4, dtype=torch.complex64)
+    lc = M[:5] + [M[6], M[5]] + M[7:] + [2000, 2001]
+    with pytest.raises(MitncError, match="C row bits in order"):
+        tnc.contract(a, M + [3000, 3001], b, [3000, 3001, 2000, 2001], lc, kernel=5)
 
 
 # ---------------------------------------------------------------- plan replay
