@@ -323,8 +323,10 @@ enum {
   MITNC_K_TALL = 3,   /* as TILE with a 128 x 16 tile for narrow N */
   MITNC_K_SPLITK = 4, /* small M, N, long K: K split over workgroups, FP64 reduction */
   MITNC_K_STREAM = 5  /* big tensor times small matrix on MFMA, streamed with no LDS staging:
-                         needs no batch indices, M >= 2^8, K <= 64, N <= 64,
-                         max(K/4, 1) * max(N/16, 1) <= 16 */
+                         needs at most 2^10 batch indices, M >= 2^8, K <= 64, N <= 64,
+                         max(K/4, 1) * max(N/16, 1) <= 16, and the row indices
+                         past the lowest four of A in the same relative order
+                         in C (the planner's own output layouts satisfy this) */
 };
 
 #ifdef __cplusplus
