@@ -74,7 +74,7 @@ def measured_traffic(label, kernel):
     FETCH_SIZE/WRITE_SIZE counters, or None when they do not apply: another
     kernel or form, or kernel sources changed since the counters were taken."""
     import hashlib
-    if label != "c64" or kernel != "stream" or not os.path.exists(TRAFFIC):
+    if kernel != "stream" or not os.path.exists(TRAFFIC):
         return None
     with open(TRAFFIC) as f:
         rec = json.load(f)
@@ -84,7 +84,7 @@ def measured_traffic(label, kernel):
             h.update(f.read())
     if h.hexdigest() != rec.get("kernels_sha256"):
         return None
-    return rec.get("stream_c64_bytes_per_launch")
+    return rec.get(f"stream_{label}_bytes_per_launch")
 
 
 def run_form(net, precision, steps, warmup, label):
