@@ -259,32 +259,45 @@ __global__ __launch_bounds__(256) void k_stem(StepDesc d) {
 // whole 128-byte lines.  3M split as in the tile kernels; padded k and n
 // carry zero B entries and padded n are never stored.
 //
-// Each wave owns a contiguous run of iters * R row blocks (R blocks per
-// iteration, all R * KS loads issued before the MFMAs; 8 loads of 8 bytes or
-// 16 of 4 bytes per lane).  Block j + 1 is the scattered-bit successor of
-// block j, ((x | ~mask) + 1) & mask, in A (m bits are sorted by A position)
-// and in C (the launcher requires its row bits in address order too).
+// Each wave takes iters iterations of R row blocks (all R * KS loads of an
+// iteration issued before the MFMAs; 8 loads of 8 bytes or 16 of 4 bytes per
+// lane); the blocks of successive iterations are a window of all waves
+// apart (see StreamLut).  Counters over scattered address bits advance by
+// ((x | ~mask) + 1) & mask, in A (m bits are sorted by A position) and in C
+// (the launcher requires its row bits in address order too).
+// log2 of the row blocks times k steps one iteration loads (R * KS, or
+// R * KS8 with 16-bit storage, when one row block has fewer k steps): the
+// bytes a wave keeps in flight per iteration.
+inline constexpr int kStreamRowsF = 3;
+inline constexpr int kStreamRowsH = 3;
+inline constexpr int ilog2c(int x) { return x > 1 ? 1 + ilog2c(x >> 1) : 0; }
+static_assert(kStreamRowsF <= kStreamMinM - 4 && kStreamRowsH <= kStreamMinM - 4,
+              "one iteration must not hold more row blocks than the smallest stream step has");
 template <int P>
-inline constexpr int stream_loads() { return P == 0 ? 8 : 16; }
+inline constexpr int stream_loads() { return 1 << kStreamRowsF; }
 
 // Output entry of a stream step.  EPI: 0 = store, 1 = store and return the
 // stored magnitude (statistics), 2 = add into the FP64 result.  out is the
-// base of C (EPI 0, 1) or of the result (EPI 2) for this wave's batch index.
+// row block's base in C (EPI 0, 1) or in the result (EPI 2), off the lane's
+// byte offset from it (32 bits: a scalar base plus a vector offset).
 template <int P, int EPI>
-__device__ __forceinline__ float stream_store(void* out, const StepDesc& d, uint64_t addr, float2 v) {
+inline constexpr uint32_t stream_out_bytes() { return EPI == 2 ? 16u : (P == 0 ? 8u : 4u); }
+
+template <int P, int EPI>
+__device__ __forceinline__ float stream_store(char* out, const StepDesc& d, uint32_t off, float2 v) {
   if constexpr (EPI == 2) {
-    double2* acc = reinterpret_cast<double2*>(out);
-    double2 o = acc[addr];
+    double2* acc = reinterpret_cast<double2*>(out + off);
+    double2 o = *acc;
     o.x += (double)v.x * d.acc_scale;
     o.y += (double)v.y * d.acc_scale;
-    acc[addr] = o;
+    *acc = o;
     return 0.f;
   } else {
     if constexpr (P == 0) {
-      reinterpret_cast<float2*>(out)[addr] = v;
+      *reinterpret_cast<float2*>(out + off) = v;
     } else {
       v = make_float2(v.x * d.out_scale, v.y * d.out_scale);
-      reinterpret_cast<uint32_t*>(out)[addr] = pack<P>(v);
+      *reinterpret_cast<uint32_t*>(out + off) = pack<P>(v);
     }
     return EPI == 1 ? absmax2(v) : 0.f;
   }
@@ -294,30 +307,37 @@ __device__ __forceinline__ float stream_store(void* out, const StepDesc& d, uint
 // per thread (a lane would otherwise run ~50 serial bit scatters before its
 // first load, and scalar scatters of 64-bit values spill scalar registers):
 // offsets of every k and n value in A, B and C, of the 16 lane rows in A and
-// C, the mask of the row-block bits, and for each of the four waves the
-// offsets of its first row block and of its batch index.
+// C, the masks of the row-block bits that count blocks inside an iteration
+// (r) and iterations (j), and for each of the four waves the offsets of its
+// slot and of its batch index.
 //
-// Row blocks of all batch indices are numbered (batch << hb) | block; a
-// wave's run of blocks never crosses a batch index (the launcher makes runs
-// at most 2^hb blocks long), so its batch index and B are fixed.  C's row
-// bits must be in address order like A's (the launcher checks), so the next
-// block's offset is the scattered-bit successor in both.
+// Row block numbering inside one batch index (hb = mb - 4 bits, low to high):
+// rl bits r (the R blocks of one iteration), wl - bb bits of the wave's slot,
+// then the iteration bits; the top bb bits of the wave id select the batch
+// index, so a wave's B is fixed.  At each iteration the waves of a batch
+// index cover one contiguous window of R * 2^(wl - bb) row blocks, which
+// keeps the HBM pages open at any moment few (a contiguous run per wave
+// would spread them over the whole tensor).  The r and j parts advance by
+// the scattered-bit successor on their masks; C's row bits must be in
+// address order like A's (the launcher checks) so the same counters serve.
 struct StreamLut {
   uint32_t ak[64], bk[64], bn[64], cn[64];
   uint32_t am[16], cm[16];
-  unsigned long long mask_a, mask_c;
+  unsigned long long mra, mja, mrc, mjc;
   unsigned long long xa0[4], xc0[4], a_b[4], b_b[4], c_b[4];
 };
 
-__device__ __forceinline__ void stream_lut_init(const StepDesc& d, const uint8_t* tab, StreamLut& L,
-                                                uint64_t blocks_per_wave) {
+// rl = log2 R; iters = 2^(hb + bb - rl - wl) fixes wl.
+__device__ __forceinline__ void stream_lut_init(const StepDesc& d, const uint8_t* tab, StreamLut& L, int rl,
+                                                uint32_t iters) {
   const int t = threadIdx.x;
   if (t == 0) {
-    L.mask_a = 0;
-    L.mask_c = 0;
+    L.mra = L.mja = L.mrc = L.mjc = 0;
   }
   __syncthreads();
   const int K = 1 << d.kb, N = 1 << d.nb, hb = d.mb - 4;
+  const int wl = hb + d.bb - rl - (31 - __builtin_clz(iters));
+  const int wlo = wl - d.bb;  // slot bits of the wave id
   if (t < 64) {
     L.ak[t] = (uint32_t)scatter_bits(t & (K - 1), tab + T_AK, d.kb);
     L.bk[t] = (uint32_t)scatter_bits(t & (K - 1), tab + T_BK, d.kb);
@@ -327,19 +347,45 @@ __device__ __forceinline__ void stream_lut_init(const StepDesc& d, const uint8_t
     L.am[t - 64] = (uint32_t)scatter_bits(t - 64, tab + T_AM, 4);
     L.cm[t - 64] = (uint32_t)scatter_bits(t - 64, tab + T_CM, 4);
   } else if (t < 84) {
-    const uint64_t blk0 = ((uint64_t)blockIdx.x * 4 + (t - 80)) * blocks_per_wave;
-    const uint64_t batch = blk0 >> hb;
-    L.xa0[t - 80] = scatter_bits(blk0, tab + T_AM + 4, hb);
-    L.xc0[t - 80] = scatter_bits(blk0, tab + T_CM + 4, hb);
+    const uint64_t wid = (uint64_t)blockIdx.x * 4 + (t - 80);
+    const uint64_t slot = (wid & ((1ull << wlo) - 1)) << rl;
+    const uint64_t batch = wid >> wlo;
+    L.xa0[t - 80] = scatter_bits(slot, tab + T_AM + 4, hb);
+    L.xc0[t - 80] = scatter_bits(slot, tab + T_CM + 4, hb);
     L.a_b[t - 80] = scatter_bits(batch, tab + T_AB, d.bb);
     L.b_b[t - 80] = scatter_bits(batch, tab + T_BB, d.bb);
     L.c_b[t - 80] = scatter_bits(batch, tab + T_CB, d.bb);
   } else if (t >= 128 && t - 128 < hb) {
     const int i = t - 128;
-    atomicOr(&L.mask_a, 1ull << tab[T_AM + 4 + i]);
-    atomicOr(&L.mask_c, 1ull << tab[T_CM + 4 + i]);
+    if (i < rl) {
+      atomicOr(&L.mra, 1ull << tab[T_AM + 4 + i]);
+      atomicOr(&L.mrc, 1ull << tab[T_CM + 4 + i]);
+    } else if (i >= rl + wlo) {
+      atomicOr(&L.mja, 1ull << tab[T_AM + 4 + i]);
+      atomicOr(&L.mjc, 1ull << tab[T_CM + 4 + i]);
+    }
   }
   __syncthreads();
+}
+
+// x + y recomputed where it is used: the empty volatile asm makes x opaque
+// at that point, so the compiler cannot hoist the sum of two loop-invariant
+// registers out of the row loop into a third register array (NBLK * KS
+// registers that would cost a wave slot per SIMD).  The asm emits no
+// instruction; the add stays an ordinary one the compiler schedules (hazard
+// checks against the MFMA that reads it included).
+__device__ __forceinline__ float add_in_loop(float x, float y) {
+  asm volatile("" : "+v"(x));
+  return x + y;
+}
+
+// A 32-bit lane offset passed through unchanged where it is used, so that
+// the compiler keeps it 32 bits wide (hoisted out of the loop it would be
+// widened to a 64-bit register pair) and addresses the access as a scalar
+// base plus one vector offset register.
+__device__ __forceinline__ uint32_t lane_offset(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
 }
 
 template <int P, int KS, int NBLK, int LD, bool PIPE, int EPI>
@@ -358,7 +404,7 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
   // that output register i of lane group lq is column lq + 4 i: the lowest
   // two n bits sit on lanes and a store instruction covers them.
   // B^T operand: lane holds B[k = 4 ks + lq][n of row lr]
-  float br[NBLK][KS], bi[NBLK][KS], bsum[NBLK][KS];
+  float br[NBLK][KS], bi[NBLK][KS];
 #pragma unroll
   for (int cb = 0; cb < NBLK; ++cb)
 #pragma unroll
@@ -368,36 +414,39 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
       if (k < K && n < N) v = load_c<P>(d.B, b_b + L.bk[k] + L.bn[n]);
       br[cb][ks] = v.x;
       bi[cb][ks] = v.y;
-      bsum[cb][ks] = v.x + v.y;
     }
   // Only K < 4 (one k step) pads inside a k step; the padded lanes read an
   // aliased in-bounds entry and are zeroed.
   const bool kvalid = KS > 1 || lq < K;
   const uint32_t a_lane = L.am[lr];
   const uint32_t c_lane = L.cm[lr];
+  // Lane offsets in bytes, 32 bits (the launcher checks they fit): the
+  // loads and stores take a scalar 64-bit base plus one vector register.
+  constexpr uint32_t ESA = sizeof(Raw), ESC = stream_out_bytes<P, EPI>();
   uint32_t a_k[KS];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) a_k[ks] = a_lane + L.ak[(4 * ks + lq) & 63];
+  for (int ks = 0; ks < KS; ++ks) a_k[ks] = (a_lane + L.ak[(4 * ks + lq) & 63]) * ESA;
   uint32_t c_n[NBLK][4];
 #pragma unroll
   for (int cb = 0; cb < NBLK; ++cb)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) c_n[cb][i] = c_lane + L.cn[(16 * cb + lq + 4 * i) & 63];
+    for (int i = 0; i < 4; ++i) c_n[cb][i] = (c_lane + L.cn[(16 * cb + lq + 4 * i) & 63]) * ESC;
   // Row-block addresses are wave-uniform: keep them in scalar registers.
-  const uint64_t mask_a = uniform64(L.mask_a), mask_c = uniform64(L.mask_c);
-  uint64_t xa = uniform64(L.xa0[w]), xc = uniform64(L.xc0[w]);
-  const Raw* A = reinterpret_cast<const Raw*>(d.A) + uniform64(L.a_b[w]);
-  void* out = EPI == 2 ? (void*)(reinterpret_cast<double2*>(d.acc) + uniform64(L.c_b[w]))
-                       : (void*)(reinterpret_cast<char*>(d.C) + uniform64(L.c_b[w]) * (P == 0 ? 8 : 4));
+  const uint64_t mra = uniform64(L.mra), mja = uniform64(L.mja), mrc = uniform64(L.mrc), mjc = uniform64(L.mjc);
+  uint64_t xra = 0, xja = 0, xrc = 0, xjc = 0;
+  const char* A = reinterpret_cast<const char*>(d.A) + (uniform64(L.a_b[w]) + uniform64(L.xa0[w])) * ESA;
+  char* out = reinterpret_cast<char*>(EPI == 2 ? (void*)d.acc : d.C) +
+              (uniform64(L.c_b[w]) + uniform64(L.xc0[w])) * ESC;
   float mx = 0.f;
   Raw raw[R][KS], nxt[R][KS];
   auto load = [&](Raw (&dst)[R][KS]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) dst[r][ks] = A[xa + a_k[ks]];
-      xa = ((xa | ~mask_a) + 1) & mask_a;
+      for (int ks = 0; ks < KS; ++ks) dst[r][ks] = *reinterpret_cast<const Raw*>(A + (xra | xja) * ESA + lane_offset(a_k[ks]));
+      xra = ((xra | ~mra) + 1) & mra;
     }
+    xja = ((xja | ~mja) + 1) & mja;
   };
   if (PIPE) load(raw);
   for (uint32_t it = 0; it < iters; ++it) {
@@ -427,7 +476,7 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
         for (int cb = 0; cb < NBLK; ++cb) {
           acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(br[cb][ks], a.x, acc[0][cb], 0, 0, 0);
           acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bi[cb][ks], a.y, acc[1][cb], 0, 0, 0);
-          acc[2][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bsum[cb][ks], as, acc[2][cb], 0, 0, 0);
+          acc[2][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(add_in_loop(br[cb][ks], bi[cb][ks]), as, acc[2][cb], 0, 0, 0);
         }
       }
       // lane holds C[m = lr][n = 16 cb + lq + 4 i] in register i
@@ -437,10 +486,11 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
         for (int i = 0; i < 4; ++i)
           if (16 * cb + lq + 4 * i < N) {
             const float t1 = acc[0][cb][i], t2 = acc[1][cb][i], t3 = acc[2][cb][i];
-            mx = fmaxf(mx, stream_store<P, EPI>(out, d, xc + c_n[cb][i], make_float2(t1 - t2, t3 - t1 - t2)));
+            mx = fmaxf(mx, stream_store<P, EPI>(out + (xrc | xjc) * ESC, d, lane_offset(c_n[cb][i]), make_float2(t1 - t2, t3 - t1 - t2)));
           }
-      xc = ((xc | ~mask_c) + 1) & mask_c;
+      xrc = ((xrc | ~mrc) + 1) & mrc;
     }
+    xjc = ((xjc | ~mjc) + 1) & mjc;
     if (PIPE) {
 #pragma unroll
       for (int r = 0; r < R; ++r)
@@ -456,8 +506,8 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   __shared__ StreamLut lut;
   load_tables(d, tab);
-  constexpr int R = LD / KS > 0 ? LD / KS : 1;
-  stream_lut_init(d, tab, lut, (uint64_t)iters * R);
+  constexpr int RL = LD / KS > 1 ? ilog2c(LD / KS) : 0;  // log2 R
+  stream_lut_init(d, tab, lut, RL, iters);
   float mx;
   if (d.mode == EPI_ACC64) mx = stream_body<P, KS, NBLK, LD, PIPE, 2>(d, tab, lut, iters);
   else if (d.stats) mx = stream_body<P, KS, NBLK, LD, PIPE, 1>(d, tab, lut, iters);
@@ -479,7 +529,7 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
 template <int P, int KS8, int NB8, int EPI>
 __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t* tab, const StreamLut& L,
                                                uint32_t iters) {
-  constexpr int R = 8 / KS8 > 0 ? 8 / KS8 : 1;  // row blocks per iteration (16 dword loads)
+  constexpr int R = (1 << kStreamRowsH) / KS8 > 0 ? (1 << kStreamRowsH) / KS8 : 1;  // row blocks per iteration
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lq = lane >> 4;
   const int w = threadIdx.x >> 6;
@@ -520,18 +570,19 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
     for (int h = 0; h < 2; ++h) {
       const int k = 8 * ks + 2 * lq + h;
       kv[ks][h] = k < K;
-      a_k[ks][h] = a_lane + L.ak[k & 63];
+      a_k[ks][h] = (a_lane + L.ak[k & 63]) * 4u;
     }
+  constexpr uint32_t ESC = stream_out_bytes<P, EPI>();  // 32-bit byte offsets, as in stream_body
   uint32_t c_n[NB8][2];
 #pragma unroll
   for (int nb = 0; nb < NB8; ++nb)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) c_n[nb][h] = c_lane + L.cn[(8 * nb + lq + 4 * h) & 63];
-  const uint64_t mask_a = uniform64(L.mask_a), mask_c = uniform64(L.mask_c);
-  uint64_t xa = uniform64(L.xa0[w]), xc = uniform64(L.xc0[w]);
-  const uint32_t* A = reinterpret_cast<const uint32_t*>(d.A) + uniform64(L.a_b[w]);
-  void* out = EPI == 2 ? (void*)(reinterpret_cast<double2*>(d.acc) + uniform64(L.c_b[w]))
-                       : (void*)(reinterpret_cast<uint32_t*>(d.C) + uniform64(L.c_b[w]));
+    for (int h = 0; h < 2; ++h) c_n[nb][h] = (c_lane + L.cn[(8 * nb + lq + 4 * h) & 63]) * ESC;
+  const uint64_t mra = uniform64(L.mra), mja = uniform64(L.mja), mrc = uniform64(L.mrc), mjc = uniform64(L.mjc);
+  uint64_t xra = 0, xja = 0, xrc = 0, xjc = 0;
+  const char* A = reinterpret_cast<const char*>(d.A) + (uniform64(L.a_b[w]) + uniform64(L.xa0[w])) * 4u;
+  char* out = reinterpret_cast<char*>(EPI == 2 ? (void*)d.acc : d.C) +
+              (uniform64(L.c_b[w]) + uniform64(L.xc0[w])) * ESC;
   float mx = 0.f;
   for (uint32_t it = 0; it < iters; ++it) {
     uint32_t raw[R][KS8][2];
@@ -540,9 +591,10 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
 #pragma unroll
       for (int ks = 0; ks < KS8; ++ks)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) raw[r][ks][h] = A[xa + a_k[ks][h]];
-      xa = ((xa | ~mask_a) + 1) & mask_a;
+        for (int h = 0; h < 2; ++h) raw[r][ks][h] = *reinterpret_cast<const uint32_t*>(A + (xra | xja) * 4u + lane_offset(a_k[ks][h]));
+      xra = ((xra | ~mra) + 1) & mra;
     }
+    xja = ((xja | ~mja) + 1) & mja;
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -566,10 +618,11 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
 #pragma unroll
         for (int h = 0; h < 2; ++h)
           if (8 * nb + lq + 4 * h < N)
-            mx = fmaxf(mx, stream_store<P, EPI>(out, d, xc + c_n[nb][h],
+            mx = fmaxf(mx, stream_store<P, EPI>(out + (xrc | xjc) * ESC, d, lane_offset(c_n[nb][h]),
                                                 make_float2(acc[nb][2 * h], acc[nb][2 * h + 1])));
-      xc = ((xc | ~mask_c) + 1) & mask_c;
+      xrc = ((xrc | ~mrc) + 1) & mrc;
     }
+    xjc = ((xjc | ~mjc) + 1) & mjc;
   }
   return mx;
 }
@@ -579,8 +632,8 @@ __global__ __launch_bounds__(256) void k_stream_h(StepDesc d, uint32_t iters) {
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   __shared__ StreamLut lut;
   load_tables(d, tab);
-  constexpr int R = 8 / KS8 > 0 ? 8 / KS8 : 1;
-  stream_lut_init(d, tab, lut, (uint64_t)iters * R);
+  constexpr int RL = kStreamRowsH > ilog2c(KS8) ? kStreamRowsH - ilog2c(KS8) : 0;  // log2 R
+  stream_lut_init(d, tab, lut, RL, iters);
   float mx;
   if (d.mode == EPI_ACC64) mx = stream_body_h<P, KS8, NB8, 2>(d, tab, lut, iters);
   else if (d.stats) mx = stream_body_h<P, KS8, NB8, 1>(d, tab, lut, iters);
@@ -1437,25 +1490,49 @@ static hipError_t launch_stem(const StepDesc& d, dim3 grid, hipStream_t s, Timin
   return hipErrorInvalidValue;
 }
 
-// Stream steps.  The grid holds up to 4096 waves (16 per CU); each wave takes
-// iters iterations of R row blocks.
+// Stream steps.  Each wave takes iters iterations of R row blocks.  The
+// grid holds as many waves as the device keeps resident at once for the
+// kernel (its occupancy times the SIMDs, rounded down to a power of two, at
+// most 4096), so no wave waits for a second round; fewer when the step has
+// fewer row-block groups.
+template <auto Kern>
+static int stream_wave_cap_log() {
+  static int cap = -1;  // per kernel; devices of one process are alike
+  if (cap < 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, Kern, 256, 0) != hipSuccess || per_cu < 1 || cus < 1)
+      return 12;
+    const long waves = (long)per_cu * 4 * cus;
+    int l = 0;
+    while (l < 12 && (2L << l) <= waves) ++l;
+    cap = l;
+  }
+  return cap;
+}
+
+template <auto Kern>
+static hipError_t launch_stream_k(const StepDesc& d, int rl, hipStream_t s, Timing t) {
+  const int ngl = d.mb - 4 + d.bb - rl;  // log2 of row-block groups of all batch indices
+  const int cap = stream_wave_cap_log<Kern>();
+  const int wl = ngl < cap ? ngl : cap;        // log2 waves (>= 0 since mb >= 8)
+  if (wl < d.bb) return hipErrorInvalidValue;  // a wave must stay inside one batch index
+  const uint32_t iters = 1u << (ngl - wl);
+  const dim3 grid(wl >= 2 ? 1u << (wl - 2) : 1u);  // fewer than 4 waves: one workgroup, idle waves exit
+  launch_k(Kern, grid, dim3(256), 0, s, t, d, iters);
+  return hipGetLastError();
+}
+
 // 16-bit storage: KS8 = 2^ksl k steps of 8, NB8 = 2^nbl column blocks of 8.
 template <int P>
 static hipError_t launch_stream_h(const StepDesc& d, hipStream_t s, Timing t) {
   const int ksl = d.kb > 3 ? d.kb - 3 : 0, nbl = d.nb > 3 ? d.nb - 3 : 0;
   if (!stream_fits(d.mb, d.nb, d.kb, d.bb) || ksl + nbl > 4) return hipErrorInvalidValue;
-  const int rl = 3 > ksl ? 3 - ksl : 0;  // log2 R, as in the kernel
-  if (!stream_rows_sorted(d)) return hipErrorInvalidValue;
-  const int ngl = d.mb - 4 + d.bb - rl;  // block groups of all batch indices
-  const int wl = ngl < 12 ? ngl : 12;
-  if (wl < d.bb) return hipErrorInvalidValue;  // a wave's run must stay inside one batch index
-  const uint32_t iters = 1u << (ngl - wl);
-  const dim3 grid(wl >= 2 ? 1u << (wl - 2) : 1u);  // fewer than 4 waves: one workgroup, idle waves exit
-#define MITNC_STREAMH(KSL, NBL)                                                                \
-  if (ksl == KSL && nbl == NBL) {                                                              \
-    launch_k(k_stream_h<P, 1 << KSL, 1 << NBL>, grid, dim3(256), 0, s, t, d, iters);           \
-    return hipGetLastError();                                                                  \
-  }
+  if (!stream_rows_sorted(d) || !stream_offsets_fit(d, 4, d.mode == EPI_ACC64 ? 16 : 4)) return hipErrorInvalidValue;
+  const int rl = kStreamRowsH > ksl ? kStreamRowsH - ksl : 0;  // log2 R, as in the kernel
+#define MITNC_STREAMH(KSL, NBL) \
+  if (ksl == KSL && nbl == NBL) return launch_stream_k<k_stream_h<P, 1 << KSL, 1 << NBL>>(d, rl, s, t);
   MITNC_STREAMH(0, 0) MITNC_STREAMH(0, 1) MITNC_STREAMH(0, 2) MITNC_STREAMH(0, 3)
   MITNC_STREAMH(1, 0) MITNC_STREAMH(1, 1) MITNC_STREAMH(1, 2) MITNC_STREAMH(1, 3)
   MITNC_STREAMH(2, 0) MITNC_STREAMH(2, 1) MITNC_STREAMH(2, 2)
@@ -1469,18 +1546,10 @@ static hipError_t launch_stream_f(const StepDesc& d, hipStream_t s, Timing t) {
   constexpr int P = 0;
   const int ksl = d.kb > 2 ? d.kb - 2 : 0, nbl = d.nb > 4 ? d.nb - 4 : 0;
   if (!stream_fits(d.mb, d.nb, d.kb, d.bb)) return hipErrorInvalidValue;
-  const int rl = 3 > ksl ? 3 - ksl : 0;  // log2 R, as in the kernel
-  if (!stream_rows_sorted(d)) return hipErrorInvalidValue;
-  const int ngl = d.mb - 4 + d.bb - rl;  // log2 of row-block groups of all batch indices
-  const int wl = ngl < 12 ? ngl : 12;    // log2 waves (>= 0 since mb >= 8)
-  if (wl < d.bb) return hipErrorInvalidValue;  // a wave's run must stay inside one batch index
-  const uint32_t iters = 1u << (ngl - wl);
-  const dim3 grid(wl >= 2 ? 1u << (wl - 2) : 1u);  // fewer than 4 waves: one workgroup, idle waves exit
-#define MITNC_STREAM(KSL, NBL)                                                                 \
-  if (ksl == KSL && nbl == NBL) {                                                              \
-    launch_k(k_stream<P, 1 << KSL, 1 << NBL>, grid, dim3(256), 0, s, t, d, iters);             \
-    return hipGetLastError();                                                                  \
-  }
+  if (!stream_rows_sorted(d) || !stream_offsets_fit(d, 8, d.mode == EPI_ACC64 ? 16 : 8)) return hipErrorInvalidValue;
+  const int rl = kStreamRowsF > ksl ? kStreamRowsF - ksl : 0;  // log2 R, as in the kernel
+#define MITNC_STREAM(KSL, NBL) \
+  if (ksl == KSL && nbl == NBL) return launch_stream_k<k_stream<P, 1 << KSL, 1 << NBL>>(d, rl, s, t);
   MITNC_STREAM(0, 0) MITNC_STREAM(1, 0) MITNC_STREAM(2, 0) MITNC_STREAM(3, 0) MITNC_STREAM(4, 0)
   MITNC_STREAM(0, 1) MITNC_STREAM(1, 1) MITNC_STREAM(2, 1) MITNC_STREAM(3, 1)
   MITNC_STREAM(0, 2) MITNC_STREAM(1, 2) MITNC_STREAM(2, 2)

@@ -210,9 +210,16 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   if (st.kclass < MITNC_K_SMALL || st.kclass > MITNC_K_STREAM) fail(MITNC_INVALID_ARG, "unknown kernel class");
   if (st.kclass == MITNC_K_STEM && (d.kb > 4 || d.nb > 2))
     fail(MITNC_UNSUPPORTED, "stem kernel needs at most 4 contracted and 2 new indices");
-  if (st.kclass == MITNC_K_STREAM && (!stream_fits(d.mb, d.nb, d.kb, d.bb) || !stream_rows_sorted(d)))
+  // Lane offsets of the stream kernels are 32-bit byte offsets (sized for
+  // the FP64 result, the largest entry an output may get).
+  const uint64_t stream_a_bytes = precision == MITNC_C64 ? 8 : 4;
+  if (st.kclass == MITNC_K_STREAM && force_kernel < 0 && !stream_offsets_fit(d, stream_a_bytes, 16))
+    return build_step(P, st, c_labels_set, root_layout, choose_class_no_stream(d.mb, d.nb, d.kb, d.bb), precision);
+  if (st.kclass == MITNC_K_STREAM &&
+      (!stream_fits(d.mb, d.nb, d.kb, d.bb) || !stream_rows_sorted(d) || !stream_offsets_fit(d, stream_a_bytes, 16)))
     fail(MITNC_UNSUPPORTED,
-         "stream kernel needs <= 10 batch bits, >= 8 row bits, K, N <= 64, K N / 64 <= 16 and C row bits in order");
+         "stream kernel needs <= 10 batch bits, >= 8 row bits, K, N <= 64, K N / 64 <= 16, C row bits in order "
+         "and lane offsets below 4 GiB");
   TileGeom g = geom_of(st.kclass, precision);
   d.prec = precision;
   d.out_scale = 1.f;

@@ -128,6 +128,24 @@ inline constexpr bool stream_fits(int mb, int nb, int kb, int bb) {
   return bb <= 10 && mb >= kStreamMinM && kb <= 6 && nb <= 6 && (kb > 2 ? kb - 2 : 0) + (nb > 4 ? nb - 4 : 0) <= 4;
 }
 
+// The stream kernels address a lane's entries as a scalar 64-bit base plus a
+// 32-bit byte offset that holds the lane-row and k (A) or lane-row and n (C)
+// address bits: those bits' largest offset must stay below 4 GiB at the
+// entry sizes (A, C or the FP64 result) the launch uses.
+inline bool stream_offsets_fit(const StepDesc& d, uint64_t a_bytes, uint64_t c_bytes) {
+  uint64_t a = 0, c = 0;
+  auto add = [](uint64_t& m, const uint8_t* pos, int n) {
+    for (int i = 0; i < n; ++i) {
+      if (pos[i] >= 40) return false;
+      m |= 1ull << pos[i];
+    }
+    return true;
+  };
+  const int lanes = d.mb < 4 ? d.mb : 4;
+  if (!add(a, d.am, lanes) || !add(a, d.ak, d.kb) || !add(c, d.cm, lanes) || !add(c, d.cn, d.nb)) return false;
+  return a * a_bytes < (1ull << 32) && c * c_bytes < (1ull << 32);
+}
+
 // The stream kernel steps C's rows with the same scattered-bit increment as
 // A's, so the row bits above the four lane bits must ascend in C as in A.
 inline bool stream_rows_sorted(const StepDesc& d) {
