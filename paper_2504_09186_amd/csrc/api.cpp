@@ -466,6 +466,14 @@ int32_t mitnc_plan_upload(mitnc_plan* P, void* ws, size_t ws_bytes, void* stream
       hip_check(hipMemcpyAsync(base + P->off_gtab, P->gtab.data(), sizeof(GradEntry) * P->gtab.size(),
                                hipMemcpyHostToDevice, s),
                 "gradient table upload");
+    if (!P->rtab.empty()) {
+      hip_check(hipMemcpyAsync(base + P->off_rtab, P->rtab.data(), sizeof(SmallRevOp) * P->rtab.size(),
+                               hipMemcpyHostToDevice, s),
+                "reverse table upload");
+      hip_check(hipMemcpyAsync(base + P->off_rblock, P->rblock.data(), sizeof(uint32_t) * P->rblock.size(),
+                               hipMemcpyHostToDevice, s),
+                "reverse block table upload");
+    }
     hip_check(hipStreamSynchronize(s), "leaf upload sync");
     P->uploaded = true;
     P->uploaded_ws = ws;
@@ -687,21 +695,27 @@ int32_t mitnc_backward(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, ui
       }
       // reverse
       hip_check(launch_seed(w, (float*)(base + P->off_adj + P->adj_offset[root]), P->result_elems, s), "seed");
-      for (RevOp& r : P->rev) {
-        StepDesc d = r.d;
-        char* adj_c = base + P->off_adj + P->adj_offset[P->steps[r.step].out];
-        char* other = node_value_ptr(P, base, r.other, sl);
-        d.A = r.adj_is_a ? adj_c : other;
-        d.B = r.adj_is_a ? other : adj_c;
-        d.C = base + P->off_adj + P->adj_offset[r.target];
-        d.acc = nullptr;
-        d.part = (float*)(base + P->off_part);
-        d.stats = nullptr;
-        d.mode = EPI_STORE;
-        d.prec = MITNC_C64;
-        d.out_scale = 1.f;
-        d.acc_scale = 1.0;
-        hip_check(launch_step(r.kclass, d, s), "reverse kernel launch");
+      for (const mitnc_plan::RevLevel& L : P->rev_levels) {
+        for (int ri : L.big) {
+          const RevOp& r = P->rev[ri];
+          StepDesc d = r.d;
+          char* adj_c = base + P->off_adj + P->adj_offset[P->steps[r.step].out];
+          char* other = node_value_ptr(P, base, r.other, sl);
+          d.A = r.adj_is_a ? adj_c : other;
+          d.B = r.adj_is_a ? other : adj_c;
+          d.C = base + P->off_adj + P->adj_offset[r.target];
+          d.acc = nullptr;
+          d.part = (float*)(base + P->off_part);
+          d.stats = nullptr;
+          d.mode = EPI_STORE;
+          d.prec = MITNC_C64;
+          d.out_scale = 1.f;
+          d.acc_scale = 1.0;
+          hip_check(launch_step(r.kclass, d, s), "reverse kernel launch");
+        }
+        hip_check(launch_small_multi((const SmallRevOp*)(base + P->off_rtab), (const uint32_t*)(base + P->off_rblock),
+                                     L.small_first, L.small_blocks, base, sl, s),
+                  "reverse small-step launch");
       }
       hip_check(launch_grad((const GradEntry*)(base + P->off_gtab), (int)P->gtab.size(), base, sl, grad, s),
                 "gradient accumulation");

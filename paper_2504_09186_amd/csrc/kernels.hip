@@ -149,7 +149,47 @@ __device__ __forceinline__ void record_max(const StepDesc& d, float m) {
 }
 
 // ---------------------------------------------------------------- small steps
-// One thread per output entry, direct loads; correct for any shape.
+// One thread per output entry, direct loads; correct for any shape.  Output
+// entry c of C (address bits by the tables in LDS) from operands A, B.
+template <int P>
+__device__ __forceinline__ float2 small_entry(const void* A, const void* B, const uint8_t* tab, int mb, int nb,
+                                              int kb, int bb, uint64_t c) {
+  const uint64_t m = gather_bits(c, tab + T_CM, mb), n = gather_bits(c, tab + T_CN, nb),
+                 b = gather_bits(c, tab + T_CB, bb);
+  const uint64_t ao = scatter_bits(m, tab + T_AM, mb) + scatter_bits(b, tab + T_AB, bb);
+  const uint64_t bo = scatter_bits(n, tab + T_BN, nb) + scatter_bits(b, tab + T_BB, bb);
+  // The k loop runs in groups of up to 8 independent loads so that memory
+  // latency is paid once per group rather than once per term.
+  const int kl = kb < 3 ? kb : 3;
+  const int KL = 1 << kl;
+  uint32_t ak_lo[8], bk_lo[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    ak_lo[j] = (uint32_t)scatter_bits(j, tab + T_AK, kl);
+    bk_lo[j] = (uint32_t)scatter_bits(j, tab + T_BK, kl);
+  }
+  const uint64_t KH = 1ull << (kb - kl);
+  float2 s = make_float2(0.f, 0.f);
+  for (uint64_t kh = 0; kh < KH; ++kh) {
+    const uint64_t ah = ao + scatter_bits(kh, tab + T_AK + kl, kb - kl);
+    const uint64_t bh = bo + scatter_bits(kh, tab + T_BK + kl, kb - kl);
+    float2 a[8], bv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < KL) {
+        a[j] = load_c<P>(A, ah + ak_lo[j]);
+        bv[j] = load_c<P>(B, bh + bk_lo[j]);
+      }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < KL) {
+        s.x += a[j].x * bv[j].x - a[j].y * bv[j].y;
+        s.y += a[j].x * bv[j].y + a[j].y * bv[j].x;
+      }
+  }
+  return s;
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_small(StepDesc d) {
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
@@ -158,43 +198,41 @@ __global__ __launch_bounds__(256) void k_small(StepDesc d) {
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
   const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   float mx = 0.f;
-  if (c < c_elems) {
-    const uint64_t m = gather_bits(c, tab + T_CM, d.mb), n = gather_bits(c, tab + T_CN, d.nb),
-                   b = gather_bits(c, tab + T_CB, d.bb);
-    const uint64_t ao = scatter_bits(m, tab + T_AM, d.mb) + scatter_bits(b, tab + T_AB, d.bb);
-    const uint64_t bo = scatter_bits(n, tab + T_BN, d.nb) + scatter_bits(b, tab + T_BB, d.bb);
-    // The k loop runs in groups of up to 8 independent loads so that memory
-    // latency is paid once per group rather than once per term.
-    const int kl = d.kb < 3 ? d.kb : 3;
-    const int KL = 1 << kl;
-    uint32_t ak_lo[8], bk_lo[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      ak_lo[j] = (uint32_t)scatter_bits(j, tab + T_AK, kl);
-      bk_lo[j] = (uint32_t)scatter_bits(j, tab + T_BK, kl);
-    }
-    const uint64_t KH = 1ull << (d.kb - kl);
-    float2 s = make_float2(0.f, 0.f);
-    for (uint64_t kh = 0; kh < KH; ++kh) {
-      const uint64_t ah = ao + scatter_bits(kh, tab + T_AK + kl, d.kb - kl);
-      const uint64_t bh = bo + scatter_bits(kh, tab + T_BK + kl, d.kb - kl);
-      float2 a[8], bv[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (j < KL) {
-          a[j] = load_c<P>(d.A, ah + ak_lo[j]);
-          bv[j] = load_c<P>(d.B, bh + bk_lo[j]);
-        }
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (j < KL) {
-          s.x += a[j].x * bv[j].x - a[j].y * bv[j].y;
-          s.y += a[j].x * bv[j].y + a[j].y * bv[j].x;
-        }
-    }
-    mx = epilogue_store<P>(d, c, s, 0, c_elems);
-  }
+  if (c < c_elems) mx = epilogue_store<P>(d, c, small_entry<P>(d.A, d.B, tab, d.mb, d.nb, d.kb, d.bb, c), 0, c_elems);
   record_max(d, mx);
+}
+
+// Many independent SMALL steps of the reverse pass (complex64) in one
+// launch: workgroup first + blockIdx.x of the block table names its op; the
+// op's operands are workspace offsets, a sliced leaf operand is offset by
+// the slice's values of its sliced indices.
+__global__ __launch_bounds__(256) void k_small_multi(const SmallRevOp* ops, const uint32_t* block_op, uint32_t first,
+                                                     char* ws, uint64_t slice) {
+  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  const uint32_t gb = first + blockIdx.x;
+  const SmallRevOp& op = ops[block_op[gb]];
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(op.d.am);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(tab);
+    for (int i = threadIdx.x; i < TAB_BYTES / 4; i += blockDim.x) dst[i] = src[i];
+  }
+  const int mb = op.d.mb, nb = op.d.nb, kb = op.d.kb, bb = op.d.bb;
+  uint64_t sl_off = 0;
+  for (int j = 0; j < op.sl_n; ++j) sl_off |= ((slice >> op.sl_bit[j]) & 1ull) << op.sl_pos[j];
+  const char* A = ws + op.a_off + (op.sl_which == 1 ? sl_off * 8 : 0);
+  const char* B = ws + op.b_off + (op.sl_which == 2 ? sl_off * 8 : 0);
+  float2* C = reinterpret_cast<float2*>(ws + op.c_off);
+  __syncthreads();
+  const uint64_t c_elems = 1ull << (mb + nb + bb);
+  const uint64_t c = (uint64_t)(gb - op.block0) * 256 + threadIdx.x;
+  if (c < c_elems) C[c] = small_entry<0>(A, B, tab, mb, nb, kb, bb, c);
+}
+
+hipError_t launch_small_multi(const SmallRevOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,
+                              char* ws, uint64_t slice, hipStream_t s) {
+  if (!blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_small_multi, dim3(blocks), dim3(256), 0, s, ops, block_op, first, ws, slice);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- stem steps

@@ -21,6 +21,10 @@ hipError_t launch_section(const SectionDesc& sd, hipStream_t s, hipEvent_t ev0 =
 // Reverse pass helpers: adj = complex64(w) for n entries; gradient
 // accumulation of the single-qubit gate leaf adjoints of slice `slice`.
 hipError_t launch_seed(const double* w, float* adj, uint64_t n, hipStream_t s);
+// Batched SMALL reverse ops: workgroups [first, first + blocks) of the block
+// table block_op (entries index ops), operands relative to the workspace ws.
+hipError_t launch_small_multi(const SmallRevOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,
+                              char* ws, uint64_t slice, hipStream_t s);
 hipError_t launch_grad(const GradEntry* tab, int n_entries, const char* ws, uint64_t slice, double* grad,
                        hipStream_t s);
 

@@ -630,6 +630,64 @@ static void build_reverse(mitnc_plan* P, const mitnc_network* net, const mitnc_p
   }
 }
 
+// Reverse pass by depth (needs the workspace offsets of nodes and adjoints):
+// an op's level is one more than that of the op writing the adjoint it reads
+// (0 for the root's).  SMALL ops of a level go into the batched-launch
+// tables, one block-table entry per workgroup of 256 outputs.
+static void build_reverse_levels(mitnc_plan* P) {
+  const int root = P->steps.back().out;
+  std::vector<int> level_of(P->nodes.size(), -1);  // level of the op writing a node's adjoint
+  for (size_t i = 0; i < P->rev.size(); ++i) {
+    const RevOp& r = P->rev[i];
+    const int in = P->steps[r.step].out;
+    int lv = 0;
+    if (in != root) {
+      if (level_of[in] < 0) fail(MITNC_INVALID_ARG, "reverse schedule reads an adjoint before it is written");
+      lv = level_of[in] + 1;
+    }
+    level_of[r.target] = lv;
+    if ((int)P->rev_levels.size() <= lv) P->rev_levels.resize(lv + 1);
+    if (r.kclass != MITNC_K_SMALL) P->rev_levels[lv].big.push_back((int)i);
+  }
+  for (size_t lv = 0; lv < P->rev_levels.size(); ++lv) {
+    mitnc_plan::RevLevel& L = P->rev_levels[lv];
+    L.small_first = (uint32_t)P->rblock.size();
+    for (size_t i = 0; i < P->rev.size(); ++i) {
+      const RevOp& r = P->rev[i];
+      if (r.kclass != MITNC_K_SMALL || level_of[r.target] != (int)lv) continue;
+      SmallRevOp e;
+      std::memset(&e, 0, sizeof(e));
+      e.d = r.d;
+      e.d.A = e.d.B = nullptr;
+      e.d.C = nullptr;
+      const uint64_t adj_in = P->off_adj + P->adj_offset[P->steps[r.step].out];
+      const PlanNode& o = P->nodes[r.other];
+      uint64_t other = o.offset;
+      if (o.region == 1) other += P->off_persist;
+      else if (o.region == 2) other += P->off_arena;
+      else if (o.region != 0) fail(MITNC_INVALID_ARG, "reverse operand outside the workspace");
+      e.a_off = r.adj_is_a ? adj_in : other;
+      e.b_off = r.adj_is_a ? other : adj_in;
+      e.c_off = P->off_adj + P->adj_offset[r.target];
+      if (o.region == 0 && !o.slice_bits.empty()) {
+        if (o.slice_bits.size() > 8) fail(MITNC_UNSUPPORTED, "leaf with more than 8 sliced indices");
+        e.sl_which = r.adj_is_a ? 2 : 1;
+        e.sl_n = (int8_t)o.slice_bits.size();
+        for (size_t j = 0; j < o.slice_bits.size(); ++j) {
+          e.sl_bit[j] = (int8_t)o.slice_bits[j].first;
+          e.sl_pos[j] = (int8_t)o.slice_bits[j].second;
+        }
+      }
+      const uint64_t c_elems = 1ull << (r.d.mb + r.d.nb + r.d.bb);
+      e.block0 = (uint32_t)P->rblock.size();
+      const uint32_t idx = (uint32_t)P->rtab.size();
+      for (uint64_t b = 0; b < (c_elems + 255) / 256; ++b) P->rblock.push_back(idx);
+      P->rtab.push_back(e);
+    }
+    L.small_blocks = (uint32_t)P->rblock.size() - L.small_first;
+  }
+}
+
 mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   if (!net->output_set) fail(MITNC_INVALID_ARG, "output not set");
   int n = (int)net->leaves.size();
@@ -909,8 +967,11 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   P->off_calib = align_up(P->off_stats + 4 * P->steps.size(), 256);
   P->off_adj = align_up(P->off_calib + (half ? 16 * P->result_elems : 0), 256);
   P->off_gtab = align_up(P->off_adj + P->adj_bytes, 256);
-  P->ws_bytes = align_up(P->off_gtab + sizeof(GradEntry) * P->gtab.size(), 256);
   for (auto& g : P->gtab) g.adj_offset += P->off_adj;
+  if (opts.differentiable) build_reverse_levels(P.get());
+  P->off_rtab = align_up(P->off_gtab + sizeof(GradEntry) * P->gtab.size(), 256);
+  P->off_rblock = align_up(P->off_rtab + sizeof(SmallRevOp) * P->rtab.size(), 256);
+  P->ws_bytes = align_up(P->off_rblock + sizeof(uint32_t) * P->rblock.size(), 256);
   P->calibrated = !half;
   verify_memory_plan(P.get(), std::min<uint64_t>(1ull << P->S, 64));
   return P.release();

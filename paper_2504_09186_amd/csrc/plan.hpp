@@ -89,6 +89,18 @@ struct mitnc_plan {
   std::vector<uint64_t> adj_offset;    // per node with has_grad
   std::vector<mitnc::RevOp> rev;       // reverse pass in execution order
   std::vector<mitnc::GradEntry> gtab;  // per single-qubit gate leaf
+  // Reverse pass by depth: the ops of one level read adjoints written at
+  // earlier levels only.  Each level runs its MFMA-class ops one by one and
+  // all its SMALL ops in one launch over the block table entries
+  // [small_first, small_first + small_blocks).
+  struct RevLevel {
+    std::vector<int> big;  // indices into rev
+    uint32_t small_first = 0, small_blocks = 0;
+  };
+  std::vector<RevLevel> rev_levels;
+  std::vector<mitnc::SmallRevOp> rtab;  // SMALL ops, uploaded at off_rtab
+  std::vector<uint32_t> rblock;         // workgroup -> rtab entry, uploaded at off_rblock
+  uint64_t off_rtab = 0, off_rblock = 0;
   int32_t n_grad_gates = 0;
   uint64_t off_adj = 0, adj_bytes = 0, off_gtab = 0;
   double rev_flops = 0;

@@ -64,6 +64,21 @@ struct GradEntry {
   int8_t pad_[7];
 };
 
+// One SMALL-class adjoint contraction of the reverse pass inside a batched
+// launch (device table in the workspace).  The descriptor gives the shape and
+// position tables; operands are workspace byte offsets, and the one operand
+// that may be a leaf with sliced indices gets its slice offset in the kernel.
+struct SmallRevOp {
+  StepDesc d;                    // A, B, C unused
+  uint64_t a_off, b_off, c_off;  // workspace byte offsets of A, B, C
+  uint32_t block0;               // index of the op's first workgroup in the block table
+  int8_t sl_which;               // 0: none, 1: A, 2: B is a leaf with sliced indices
+  int8_t sl_n;                   // its sliced indices (at most 8)
+  int8_t sl_bit[8];              // slice-id bit of each
+  int8_t sl_pos[8];              // its leaf address bit
+  int8_t pad_[6];
+};
+
 // Tile geometry of the MFMA kernel classes (bits of the m, n, k tile).
 struct TileGeom {
   int tm_bits, tn_bits, tk_bits;
