@@ -207,6 +207,16 @@ typedef struct mitnc_step_info {
 } mitnc_step_info;
 int32_t mitnc_plan_step_info(const mitnc_plan* plan, int32_t step, mitnc_step_info* info);
 
+/* Reverse pass of a differentiable plan (the adjoint contractions of
+ * mitnc_backward): n_ops receives the number of adjoint contractions; with
+ * info non-NULL, op (0 <= op < n_ops, execution order) is described in the
+ * step_info layout: a = node whose adjoint is read, b = forward value it is
+ * contracted with, out = node whose adjoint is written, root = the reverse
+ * level (ops of one level are independent; SMALL ops of a level share one
+ * launch), section = -1.  Errors: INVALID_ARG for a null plan or op out of
+ * range; n_ops = 0 for plans that are not differentiable.  Host only. */
+int32_t mitnc_plan_reverse_info(const mitnc_plan* plan, int32_t op, mitnc_step_info* info, int32_t* n_ops);
+
 /* ws_offset: byte offset of the node's tensor in the workspace of a
  * complex64 run (UINT64_MAX for the root, which is the caller's result);
  * level: -1 = computed once per slice range, else recomputed for slice s

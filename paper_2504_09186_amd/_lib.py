@@ -83,6 +83,7 @@ _SIGS = {
     "mitnc_plan_query": [_VP, C.POINTER(mitnc_plan_stats)],
     "mitnc_plan_steps": [_VP, C.POINTER(C.c_double)],
     "mitnc_plan_step_info": [_VP, _I32, C.POINTER(mitnc_step_info)],
+    "mitnc_plan_reverse_info": [_VP, _I32, C.POINTER(mitnc_step_info), C.POINTER(_I32)],
     "mitnc_plan_node_info": [_VP, _I32, C.POINTER(mitnc_node_info)],
     "mitnc_plan_leaf_data": [_VP, _I32, C.POINTER(C.c_float), C.c_uint64, C.POINTER(C.c_uint64)],
     "mitnc_plan_upload": [_VP, _VP, C.c_size_t, _VP],

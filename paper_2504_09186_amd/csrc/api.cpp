@@ -403,6 +403,45 @@ int32_t mitnc_plan_step_info(const mitnc_plan* P, int32_t step, mitnc_step_info*
   });
 }
 
+int32_t mitnc_plan_reverse_info(const mitnc_plan* P, int32_t op, mitnc_step_info* info, int32_t* n_ops) {
+  return guarded([&] {
+    if (!P || !n_ops) fail(MITNC_INVALID_ARG, "null argument");
+    // Execution order: level by level, each level's MFMA-class ops, then its
+    // SMALL ops in block-table order.
+    std::vector<std::pair<int, int>> order;  // (rev index, level)
+    for (size_t lv = 0; lv < P->rev_levels.size(); ++lv) {
+      for (int ri : P->rev_levels[lv].big) order.push_back({ri, (int)lv});
+      for (size_t i = 0; i < P->rev.size(); ++i)
+        if (P->rev[i].kclass == MITNC_K_SMALL && P->rev_level_of[i] == (int)lv) order.push_back({(int)i, (int)lv});
+    }
+    *n_ops = (int32_t)order.size();
+    if (!info) return;
+    if (op < 0 || op >= (int32_t)order.size()) fail(MITNC_INVALID_ARG, "reverse op out of range");
+    const RevOp& r = P->rev[order[op].first];
+    const StepDesc& d = r.d;
+    std::memset(info, 0, sizeof(*info));
+    info->a = P->steps[r.step].out;
+    info->b = r.other;
+    info->out = r.target;
+    info->root = order[op].second;
+    info->kernel_class = r.kclass;
+    info->section = -1;
+    info->mb = d.mb;
+    info->nb = d.nb;
+    info->kb = d.kb;
+    info->bb = d.bb;
+    std::memcpy(info->am, d.am, 32);
+    std::memcpy(info->ak, d.ak, 32);
+    std::memcpy(info->ab, d.ab, 32);
+    std::memcpy(info->bk, d.bk, 32);
+    std::memcpy(info->bn, d.bn, 32);
+    std::memcpy(info->bbt, d.bbt, 32);
+    std::memcpy(info->cm, d.cm, 32);
+    std::memcpy(info->cn, d.cn, 32);
+    std::memcpy(info->cb, d.cb, 32);
+  });
+}
+
 int32_t mitnc_plan_node_info(const mitnc_plan* P, int32_t node, mitnc_node_info* info) {
   return guarded([&] {
     if (!P || !info) fail(MITNC_INVALID_ARG, "null argument");

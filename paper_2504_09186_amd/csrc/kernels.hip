@@ -235,6 +235,133 @@ hipError_t launch_small_multi(const SmallRevOp* ops, const uint32_t* block_op, u
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- skinny split-K
+// C[b][m][n] = sum_k A[b][m][k] B[b][k][n] for M N <= 16 and long K (the
+// adjoints of small tensors under a large one in the reverse pass).  A tile
+// kernel would stage a mostly empty 16 x 16 tile per k step; here one wave
+// per (k split, batch index) streams both operands from HBM with no LDS:
+// lane = the six lowest k bits, kSkinnyUnroll values of the higher k bits
+// per iteration ((M + N) * 4 independent loads per lane in flight), the whole
+// M x N block of complex sums in registers, a shuffle reduction over the
+// wave at the end.  Split partials go through the FP64 reduction of the
+// split-K path.
+// Address change of one step of a counter whose bits 2.. sit at positions
+// pos[2..]: step setting bit j (and clearing bits 2..j-1), modulo 2^64.
+__device__ __forceinline__ unsigned long long skinny_step_delta(const uint8_t* pos, int j) {
+  unsigned long long v = 1ull << pos[j];
+  for (int i = 2; i < j; ++i) v -= 1ull << pos[i];
+  return v;
+}
+
+template <int MB, int NB>
+__global__ __launch_bounds__(64) void k_skinny(StepDesc d) {
+  constexpr int M = 1 << MB, N = 1 << NB, U = kSkinnyUnroll, LB = kSkinnyLaneBits;
+  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  load_tables(d, tab);
+  __syncthreads();
+  const int lane = threadIdx.x;
+  const int KH = d.kb - LB;        // high k bits
+  const int hl = KH - d.ks_bits;   // log2 of high k values per split (>= 2)
+  const uint64_t split = blockIdx.x, b = blockIdx.y;
+  const float2* A = reinterpret_cast<const float2*>(d.A) + scatter_bits(b, tab + T_AB, d.bb) +
+                    scatter_bits(lane, tab + T_AK, LB);
+  const float2* B = reinterpret_cast<const float2*>(d.B) + scatter_bits(b, tab + T_BB, d.bb) +
+                    scatter_bits(lane, tab + T_BK, LB);
+  // Offsets, one scatter per entry into LDS (wave-uniform values computed
+  // in scalar registers would spill them): every m in A and n in B, the four
+  // values of the two lowest high-k bits (one iteration) in A and B, this
+  // split's first high-k offsets (its run starts at split << hl), and the
+  // address change of a counter step: going from h to h + 1 sets bit
+  // j = ctz(h + 1) and clears the bits below it, i.e. adds 2^p(j) minus the
+  // sum of 2^p(i), 2 <= i < j, whatever order the positions p are in (A and
+  // B place the k bits differently, so a walk in address order would pair
+  // different k values).
+  enum { E_AM = 0, E_BN = 16, E_OA = 32, E_OB = 36, E_XA = 40, E_XB = 41, E_DA = 64, E_DB = 96, E_N = 128 };
+  __shared__ unsigned long long offs[E_N];
+  for (int e = lane; e < E_N; e += 64) {
+    unsigned long long v = 0;
+    if (e < E_AM + M) v = scatter_bits(e - E_AM, tab + T_AM, MB);
+    else if (e >= E_BN && e < E_BN + N) v = scatter_bits(e - E_BN, tab + T_BN, NB);
+    else if (e >= E_OA && e < E_OA + 4) v = scatter_bits(e - E_OA, tab + T_AK + LB, 2);
+    else if (e >= E_OB && e < E_OB + 4) v = scatter_bits(e - E_OB, tab + T_BK + LB, 2);
+    else if (e == E_XA) v = scatter_bits(split << hl, tab + T_AK + LB, KH);
+    else if (e == E_XB) v = scatter_bits(split << hl, tab + T_BK + LB, KH);
+    else if (e >= E_DA && e - E_DA < KH) v = skinny_step_delta(tab + T_AK + LB, e - E_DA);
+    else if (e >= E_DB && e - E_DB < KH) v = skinny_step_delta(tab + T_BK + LB, e - E_DB);
+    offs[e] = v;
+  }
+  __syncthreads();
+  uint64_t a_m[M], b_n[N], oa[U], ob[U];
+#pragma unroll
+  for (int m = 0; m < M; ++m) a_m[m] = offs[E_AM + m];
+#pragma unroll
+  for (int n = 0; n < N; ++n) b_n[n] = offs[E_BN + n];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    oa[u] = offs[E_OA + u];
+    ob[u] = offs[E_OB + u];
+  }
+  uint64_t xa = offs[E_XA], xb = offs[E_XB];
+  float2 acc[M][N];
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int n = 0; n < N; ++n) acc[m][n] = make_float2(0.f, 0.f);
+  const uint32_t iters = 1u << (hl - 2);
+  for (uint32_t it = 0; it < iters; ++it) {
+    float2 ra[U][M], rb[U][N];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) ra[u][m] = A[xa + oa[u] + a_m[m]];
+#pragma unroll
+      for (int n = 0; n < N; ++n) rb[u][n] = B[xb + ob[u] + b_n[n]];
+    }
+    if (it + 1 < iters) {
+      const int j = 2 + __builtin_ctz(it + 1);  // high-k bit the next iteration sets
+      xa += offs[E_DA + j];
+      xb += offs[E_DB + j];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+          acc[m][n].x += ra[u][m].x * rb[u][n].x - ra[u][m].y * rb[u][n].y;
+          acc[m][n].y += ra[u][m].x * rb[u][n].y + ra[u][m].y * rb[u][n].x;
+        }
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        acc[m][n].x += __shfl_xor(acc[m][n].x, o);
+        acc[m][n].y += __shfl_xor(acc[m][n].y, o);
+      }
+  // Every lane holds every sum; lane m N + n stores entry (m, n).
+  const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
+  const uint64_t cb = scatter_bits(b, tab + T_CB, d.bb);
+  float mx = 0.f;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+      if (lane == m * N + n) {
+        const uint64_t c = cb + scatter_bits(m, tab + T_CM, MB) + scatter_bits(n, tab + T_CN, NB);
+        mx = epilogue_store<0>(d, c, acc[m][n], split, c_elems);
+      }
+  if (d.stats) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (lane == 0 && mx > 0.f)
+      atomicMax(reinterpret_cast<unsigned int*>(d.stats) + d.step_index, __float_as_uint(mx));
+  }
+}
+
+
 // ---------------------------------------------------------------- stem steps
 // A big tensor absorbs a small matrix (K <= 16, N <= 4): one thread per row m
 // (and batch index), the small matrix in LDS.  Consecutive threads take
@@ -1601,6 +1728,24 @@ static hipError_t launch_stream(const StepDesc& d, hipStream_t s, Timing t) {
   else return launch_stream_h<P>(d, s, t);
 }
 
+// Skinny split-K: one 64-lane workgroup per (k split, batch index).
+static hipError_t launch_skinny(const StepDesc& d, hipStream_t s, Timing t) {
+  if (!skinny_fits(d.mb, d.nb, d.kb, d.bb, d.ks_bits)) return hipErrorInvalidValue;
+  const dim3 grid(1u << d.ks_bits, 1u << d.bb);
+#define MITNC_SKINNY(MB, NB)                                          \
+  if (d.mb == MB && d.nb == NB) {                                     \
+    launch_k(k_skinny<MB, NB>, grid, dim3(64), 0, s, t, d);           \
+    return hipGetLastError();                                         \
+  }
+  MITNC_SKINNY(0, 0) MITNC_SKINNY(0, 1) MITNC_SKINNY(0, 2) MITNC_SKINNY(0, 3) MITNC_SKINNY(0, 4)
+  MITNC_SKINNY(1, 0) MITNC_SKINNY(1, 1) MITNC_SKINNY(1, 2) MITNC_SKINNY(1, 3)
+  MITNC_SKINNY(2, 0) MITNC_SKINNY(2, 1) MITNC_SKINNY(2, 2)
+  MITNC_SKINNY(3, 0) MITNC_SKINNY(3, 1)
+  MITNC_SKINNY(4, 0)
+#undef MITNC_SKINNY
+  return hipErrorInvalidValue;
+}
+
 template <int P>
 static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
@@ -1642,6 +1787,8 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
           launch_k(k_tile<4, 1, 1, 2, 4, 8>, grid, dim3(256), 0, s, t, d);
         else if (kclass == MITNC_K_TALL)
           launch_k(k_tile<4, 1, 1, 2, 1, 16>, grid, dim3(256), 0, s, t, d);
+        else if (skinny_fits(d.mb, d.nb, d.kb, d.bb, d.ks_bits))
+          e = launch_skinny(d, s, t);
         else
           launch_k(k_tile<1, 1, 4, 1, 1, 64>, grid, dim3(256), 0, s, t, d);
       } else {
@@ -1652,7 +1799,7 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
         else
           launch_k(k_tile_h<P, 1, 1, 4, 1, 2, 128>, grid, dim3(256), 0, s, t, d);
       }
-      e = hipGetLastError();
+      if (e == hipSuccess) e = hipGetLastError();
       if (e != hipSuccess || d.ks_bits == 0) return e;
       d.mode = final_mode;
       // split rows per workgroup: up to 16, fewer when the splits are few

@@ -246,7 +246,11 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     // tiles of TALL / SPLITK fit four to five per CU.
     int tiles_bits = (d.mb - d.tm) + (d.nb - d.tn) + d.bb;
     int khigh = d.kb - d.tk;
-    int target_bits = st.kclass == MITNC_K_TILE ? 8 : 11;
+    // Skinny split-K (complex64 SPLITK steps the skinny kernel takes): one
+    // wave per split, 2^12 waves.
+    const bool skinny = st.kclass == MITNC_K_SPLITK && precision == MITNC_C64 && d.mb + d.nb <= 4 &&
+                        d.kb >= kSkinnyLaneBits + 2 && d.bb <= 16;
+    int target_bits = st.kclass == MITNC_K_TILE ? 8 : skinny ? 12 : 11;
     int ks = 0;
     while (tiles_bits + ks < target_bits && ks + 2 < khigh) ++ks;
     uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
@@ -646,6 +650,7 @@ static void build_reverse_levels(mitnc_plan* P) {
       lv = level_of[in] + 1;
     }
     level_of[r.target] = lv;
+    P->rev_level_of.push_back(lv);
     if ((int)P->rev_levels.size() <= lv) P->rev_levels.resize(lv + 1);
     if (r.kclass != MITNC_K_SMALL) P->rev_levels[lv].big.push_back((int)i);
   }
@@ -654,7 +659,7 @@ static void build_reverse_levels(mitnc_plan* P) {
     L.small_first = (uint32_t)P->rblock.size();
     for (size_t i = 0; i < P->rev.size(); ++i) {
       const RevOp& r = P->rev[i];
-      if (r.kclass != MITNC_K_SMALL || level_of[r.target] != (int)lv) continue;
+      if (r.kclass != MITNC_K_SMALL || P->rev_level_of[i] != (int)lv) continue;
       SmallRevOp e;
       std::memset(&e, 0, sizeof(e));
       e.d = r.d;

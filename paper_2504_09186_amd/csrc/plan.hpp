@@ -98,6 +98,7 @@ struct mitnc_plan {
     uint32_t small_first = 0, small_blocks = 0;
   };
   std::vector<RevLevel> rev_levels;
+  std::vector<int> rev_level_of;        // level of each rev entry
   std::vector<mitnc::SmallRevOp> rtab;  // SMALL ops, uploaded at off_rtab
   std::vector<uint32_t> rblock;         // workgroup -> rtab entry, uploaded at off_rblock
   uint64_t off_rtab = 0, off_rblock = 0;

@@ -64,6 +64,15 @@ struct GradEntry {
   int8_t pad_[7];
 };
 
+// Skinny split-K steps (complex64): at most 16 outputs per batch index and
+// long K.  One wave per (k split, batch index); lanes take the six lowest k
+// bits, each wave covers at least kSkinnyUnroll values of the higher ones.
+inline constexpr int kSkinnyLaneBits = 6, kSkinnyUnroll = 4;
+inline constexpr bool skinny_fits(int mb, int nb, int kb, int bb, int ks_bits) {
+  return mb + nb <= 4 && kb >= kSkinnyLaneBits + 2 && ks_bits >= 0 && ks_bits <= kb - kSkinnyLaneBits - 2 &&
+         bb <= 16;
+}
+
 // One SMALL-class adjoint contraction of the reverse pass inside a batched
 // launch (device table in the workspace).  The descriptor gives the shape and
 // position tables; operands are workspace byte offsets, and the one operand

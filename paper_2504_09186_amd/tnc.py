@@ -132,6 +132,23 @@ class Plan:
             r[f] = list(getattr(si, f))[:r[cnt]]
         return r
 
+    def reverse_info(self, op: Optional[int] = None):
+        """Number of adjoint contractions of the reverse pass (op None), or
+        the description of one (see mitnc_plan_reverse_info; 'root' holds the
+        reverse level)."""
+        n = C.c_int32()
+        if op is None:
+            call("mitnc_plan_reverse_info", self.h, 0, None, C.byref(n))
+            return n.value
+        si = _lib.mitnc_step_info()
+        call("mitnc_plan_reverse_info", self.h, op, C.byref(si), C.byref(n))
+        r = {f: int(getattr(si, f)) for f in ("a", "b", "out", "root", "kernel_class", "mb", "nb", "kb", "bb")}
+        r["level"] = r.pop("root")
+        for f, cnt in (("am", "mb"), ("ak", "kb"), ("ab", "bb"), ("bk", "kb"), ("bn", "nb"), ("bbt", "bb"),
+                       ("cm", "mb"), ("cn", "nb"), ("cb", "bb")):
+            r[f] = list(getattr(si, f))[:r[cnt]]
+        return r
+
     def node_info(self, node: int) -> dict:
         """Storage and schedule of one node (see mitnc_node_info)."""
         ni = _lib.mitnc_node_info()

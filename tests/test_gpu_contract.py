@@ -120,6 +120,14 @@ def test_auto(mb, nb, kb, bb):
     _run(mb, nb, kb, bb, -1, seed=11 + mb + 10 * nb + 100 * kb)
 
 
+# Skinny split-K (M N <= 16, K >= 2^8): batch indices, splits from many down
+# to none (direct store), every (M, N) register shape class.
+@pytest.mark.parametrize("mb,nb,kb,bb", [(2, 1, 17, 3), (2, 2, 12, 2), (0, 4, 10, 0), (4, 0, 9, 1), (1, 3, 8, 0),
+                                         (3, 1, 14, 5), (1, 1, 8, 10), (2, 1, 13, 8), (0, 0, 8, 0)])
+def test_splitk_skinny(mb, nb, kb, bb):
+    _run(mb, nb, kb, bb, SPLITK, seed=21 + mb + 10 * nb + 100 * kb + 1000 * bb)
+
+
 def test_splitk_long_k_accuracy():
     """K = 2^22: the blocked (split-K + FP64) summation keeps the error far
     below a single FP32 chain over K."""
