@@ -128,6 +128,13 @@ def test_splitk_skinny(mb, nb, kb, bb):
     _run(mb, nb, kb, bb, SPLITK, seed=21 + mb + 10 * nb + 100 * kb + 1000 * bb)
 
 
+# TALL steps with N <= 4 and long K (batch bits, split K).
+@pytest.mark.parametrize("mb,nb,kb,bb", [(9, 2, 10, 1), (12, 1, 8, 0), (7, 0, 13, 0), (6, 2, 12, 2), (8, 1, 9, 3),
+                                         (5, 0, 8, 0)])
+def test_tall_long_k(mb, nb, kb, bb):
+    _run(mb, nb, kb, bb, TALL, seed=31 + mb + 10 * nb + 100 * kb + 1000 * bb)
+
+
 def test_splitk_long_k_accuracy():
     """K = 2^22: the blocked (split-K + FP64) summation keeps the error far
     below a single FP32 chain over K."""
