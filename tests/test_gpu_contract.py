@@ -99,13 +99,14 @@ def test_splitk(mb, nb, kb, bb):
 
 
 # Every (k steps, column blocks) instantiation, K < 4 and N < 16 padding, and
-# runs long enough for several iterations per wave (m20 n2 k2, m18 n4 k6).
+# runs long enough for several iterations per wave (m20 n2 k2, m18 n4 k6,
+# m16 n5 k5, m15 n5 k5 b2).
 @pytest.mark.parametrize("mb,nb,kb,bb", [(12, 0, 0, 0), (12, 1, 1, 0), (13, 2, 2, 0), (14, 5, 5, 0),
                                          (12, 4, 6, 0), (12, 6, 4, 0), (15, 3, 3, 0), (12, 5, 3, 0),
                                          (16, 4, 5, 0), (12, 6, 2, 0), (12, 5, 4, 0), (12, 6, 3, 0),
                                          (20, 2, 2, 0), (18, 4, 6, 0), (8, 0, 0, 0), (8, 2, 2, 0), (9, 5, 5, 0),
                                          (10, 4, 6, 0), (8, 6, 4, 0), (11, 3, 3, 0), (10, 2, 2, 2), (12, 5, 5, 3),
-                                         (9, 4, 6, 1), (8, 3, 3, 4), (8, 1, 2, 8)])
+                                         (9, 4, 6, 1), (8, 3, 3, 4), (8, 1, 2, 8), (16, 5, 5, 0), (15, 5, 5, 2)])
 @pytest.mark.parametrize("in_place", [False, True])
 def test_stream(mb, nb, kb, bb, in_place):
     """Random C layouts (row indices past the lane bits in A's order, the lane
