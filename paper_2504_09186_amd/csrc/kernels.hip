@@ -53,6 +53,21 @@ __device__ __forceinline__ uint64_t scatter_bits(uint64_t x, const uint8_t* pos,
   return r;
 }
 
+// scatter_bits for n <= MAXN with no branches: every position byte is read
+// (index clamped to stay inside pos[0..n)), so the LDS reads issue back to
+// back and are waited for once (a per-bit branch on i < n serialises them).
+template <int MAXN>
+__device__ __forceinline__ uint64_t scatter_bits_n(uint64_t x, const uint8_t* pos, int n) {
+  uint64_t r = 0;
+#pragma unroll
+  for (int i = 0; i < MAXN; ++i) {
+    const bool on = i < n;
+    const uint32_t p = pos[on ? i : 0];
+    r |= (on ? ((x >> i) & 1ull) : 0ull) << p;
+  }
+  return r;
+}
+
 // Extracts the address bits pos[0..n) of a into the low n bits (n <= 32).
 __device__ __forceinline__ uint64_t gather_bits(uint64_t a, const uint8_t* pos, int n) {
   uint64_t r = 0;
@@ -495,40 +510,39 @@ struct StreamLut {
 // rl = log2 R; iters = 2^(hb + bb - rl - wl) fixes wl.
 __device__ __forceinline__ void stream_lut_init(const StepDesc& d, const uint8_t* tab, StreamLut& L, int rl,
                                                 uint32_t iters) {
+  __syncthreads();  // the position tables copied to tab by every thread
   const int t = threadIdx.x;
-  if (t == 0) {
-    L.mra = L.mja = L.mrc = L.mjc = 0;
-  }
-  __syncthreads();
   const int K = 1 << d.kb, N = 1 << d.nb, hb = d.mb - 4;
   const int wl = hb + d.bb - rl - (31 - __builtin_clz(iters));
   const int wlo = wl - d.bb;  // slot bits of the wave id
   if (t < 64) {
-    L.ak[t] = (uint32_t)scatter_bits(t & (K - 1), tab + T_AK, d.kb);
-    L.bk[t] = (uint32_t)scatter_bits(t & (K - 1), tab + T_BK, d.kb);
-    L.bn[t] = (uint32_t)scatter_bits(t & (N - 1), tab + T_BN, d.nb);
-    L.cn[t] = (uint32_t)scatter_bits(t & (N - 1), tab + T_CN, d.nb);
+    L.ak[t] = (uint32_t)scatter_bits_n<6>(t & (K - 1), tab + T_AK, d.kb);
+    L.bk[t] = (uint32_t)scatter_bits_n<6>(t & (K - 1), tab + T_BK, d.kb);
+    L.bn[t] = (uint32_t)scatter_bits_n<6>(t & (N - 1), tab + T_BN, d.nb);
+    L.cn[t] = (uint32_t)scatter_bits_n<6>(t & (N - 1), tab + T_CN, d.nb);
   } else if (t < 80) {
-    L.am[t - 64] = (uint32_t)scatter_bits(t - 64, tab + T_AM, 4);
-    L.cm[t - 64] = (uint32_t)scatter_bits(t - 64, tab + T_CM, 4);
+    L.am[t - 64] = (uint32_t)scatter_bits_n<4>(t - 64, tab + T_AM, 4);
+    L.cm[t - 64] = (uint32_t)scatter_bits_n<4>(t - 64, tab + T_CM, 4);
   } else if (t < 84) {
+    // the slot fills the row-block bits [0, rl + wlo); the batch bb <= 10 bits
     const uint64_t wid = (uint64_t)blockIdx.x * 4 + (t - 80);
     const uint64_t slot = (wid & ((1ull << wlo) - 1)) << rl;
     const uint64_t batch = wid >> wlo;
-    L.xa0[t - 80] = scatter_bits(slot, tab + T_AM + 4, hb);
-    L.xc0[t - 80] = scatter_bits(slot, tab + T_CM + 4, hb);
-    L.a_b[t - 80] = scatter_bits(batch, tab + T_AB, d.bb);
-    L.b_b[t - 80] = scatter_bits(batch, tab + T_BB, d.bb);
-    L.c_b[t - 80] = scatter_bits(batch, tab + T_CB, d.bb);
-  } else if (t >= 128 && t - 128 < hb) {
-    const int i = t - 128;
-    if (i < rl) {
-      atomicOr(&L.mra, 1ull << tab[T_AM + 4 + i]);
-      atomicOr(&L.mrc, 1ull << tab[T_CM + 4 + i]);
-    } else if (i >= rl + wlo) {
-      atomicOr(&L.mja, 1ull << tab[T_AM + 4 + i]);
-      atomicOr(&L.mjc, 1ull << tab[T_CM + 4 + i]);
-    }
+    L.xa0[t - 80] = scatter_bits_n<16>(slot, tab + T_AM + 4, rl + wlo);
+    L.xc0[t - 80] = scatter_bits_n<16>(slot, tab + T_CM + 4, rl + wlo);
+    L.a_b[t - 80] = scatter_bits_n<10>(batch, tab + T_AB, d.bb);
+    L.b_b[t - 80] = scatter_bits_n<10>(batch, tab + T_BB, d.bb);
+    L.c_b[t - 80] = scatter_bits_n<10>(batch, tab + T_CB, d.bb);
+  } else if (t < 88) {
+    // One mask per thread: row-block bits [0, rl) count blocks inside an
+    // iteration, bits [rl + wlo, hb) count iterations; in A (even t) and C.
+    const int j = t - 84;
+    const uint64_t rbits = (1ull << rl) - 1, jbits = ((1ull << hb) - 1) & ~((1ull << (rl + wlo)) - 1);
+    const uint64_t v = scatter_bits_n<28>(j < 2 ? rbits : jbits, tab + ((j & 1) ? T_CM : T_AM) + 4, hb);
+    if (j == 0) L.mra = v;
+    else if (j == 1) L.mrc = v;
+    else if (j == 2) L.mja = v;
+    else L.mjc = v;
   }
   __syncthreads();
 }
