@@ -503,46 +503,55 @@ __device__ __forceinline__ float stream_store(char* out, const StepDesc& d, uint
 struct StreamLut {
   uint32_t ak[64], bk[64], bn[64], cn[64];
   uint32_t am[16], cm[16];
-  unsigned long long mra, mja, mrc, mjc;
-  unsigned long long xa0[4], xc0[4], a_b[4], b_b[4], c_b[4];
+  // per wave w: slot offset in A and C, batch offset in A, B and C; then the
+  // r and j masks of A and C
+  unsigned long long wv[24];
 };
+enum { WV_XA = 0, WV_XC = 4, WV_AB = 8, WV_BB = 12, WV_CB = 16, WV_MRA = 20, WV_MRC = 21, WV_MJA = 22, WV_MJC = 23 };
 
 // rl = log2 R; iters = 2^(hb + bb - rl - wl) fixes wl.
 __device__ __forceinline__ void stream_lut_init(const StepDesc& d, const uint8_t* tab, StreamLut& L, int rl,
                                                 uint32_t iters) {
   __syncthreads();  // the position tables copied to tab by every thread
-  const int t = threadIdx.x;
+  // One branch-free job shape per wave (divergent branches inside a wave
+  // would run one after another): wave 0 the k offsets of A and B, wave 1 the
+  // n offsets of B and C, wave 2 the 16 lane rows of A and C, wave 3 the 24
+  // per-wave offsets and masks, one bounded scatter per lane.
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int K = 1 << d.kb, N = 1 << d.nb, hb = d.mb - 4;
   const int wl = hb + d.bb - rl - (31 - __builtin_clz(iters));
   const int wlo = wl - d.bb;  // slot bits of the wave id
-  if (t < 64) {
-    L.ak[t] = (uint32_t)scatter_bits_n<6>(t & (K - 1), tab + T_AK, d.kb);
-    L.bk[t] = (uint32_t)scatter_bits_n<6>(t & (K - 1), tab + T_BK, d.kb);
-    L.bn[t] = (uint32_t)scatter_bits_n<6>(t & (N - 1), tab + T_BN, d.nb);
-    L.cn[t] = (uint32_t)scatter_bits_n<6>(t & (N - 1), tab + T_CN, d.nb);
-  } else if (t < 80) {
-    L.am[t - 64] = (uint32_t)scatter_bits_n<4>(t - 64, tab + T_AM, 4);
-    L.cm[t - 64] = (uint32_t)scatter_bits_n<4>(t - 64, tab + T_CM, 4);
-  } else if (t < 84) {
-    // the slot fills the row-block bits [0, rl + wlo); the batch bb <= 10 bits
-    const uint64_t wid = (uint64_t)blockIdx.x * 4 + (t - 80);
-    const uint64_t slot = (wid & ((1ull << wlo) - 1)) << rl;
-    const uint64_t batch = wid >> wlo;
-    L.xa0[t - 80] = scatter_bits_n<16>(slot, tab + T_AM + 4, rl + wlo);
-    L.xc0[t - 80] = scatter_bits_n<16>(slot, tab + T_CM + 4, rl + wlo);
-    L.a_b[t - 80] = scatter_bits_n<10>(batch, tab + T_AB, d.bb);
-    L.b_b[t - 80] = scatter_bits_n<10>(batch, tab + T_BB, d.bb);
-    L.c_b[t - 80] = scatter_bits_n<10>(batch, tab + T_CB, d.bb);
-  } else if (t < 88) {
-    // One mask per thread: row-block bits [0, rl) count blocks inside an
-    // iteration, bits [rl + wlo, hb) count iterations; in A (even t) and C.
-    const int j = t - 84;
+  if (w == 0) {
+    L.ak[l] = (uint32_t)scatter_bits_n<6>(l & (K - 1), tab + T_AK, d.kb);
+    L.bk[l] = (uint32_t)scatter_bits_n<6>(l & (K - 1), tab + T_BK, d.kb);
+  } else if (w == 1) {
+    L.bn[l] = (uint32_t)scatter_bits_n<6>(l & (N - 1), tab + T_BN, d.nb);
+    L.cn[l] = (uint32_t)scatter_bits_n<6>(l & (N - 1), tab + T_CN, d.nb);
+  } else if (w == 2) {
+    if (l < 16) {
+      L.am[l] = (uint32_t)scatter_bits_n<4>(l, tab + T_AM, 4);
+      L.cm[l] = (uint32_t)scatter_bits_n<4>(l, tab + T_CM, 4);
+    }
+  } else if (l < 24) {
+    // jobs 0-19: (kind, wave) = (l >> 2, l & 3): slot in A, slot in C (the
+    // slot fills row-block bits [0, rl + wlo)), batch in A, B, C; jobs 20-23:
+    // r and j masks of A and C (row-block bits [0, rl) and [rl + wlo, hb))
+    const uint64_t wid = (uint64_t)blockIdx.x * 4 + (l & 3);
+    const uint64_t slot = (wid & ((1ull << wlo) - 1)) << rl, batch = wid >> wlo;
     const uint64_t rbits = (1ull << rl) - 1, jbits = ((1ull << hb) - 1) & ~((1ull << (rl + wlo)) - 1);
-    const uint64_t v = scatter_bits_n<28>(j < 2 ? rbits : jbits, tab + ((j & 1) ? T_CM : T_AM) + 4, hb);
-    if (j == 0) L.mra = v;
-    else if (j == 1) L.mrc = v;
-    else if (j == 2) L.mja = v;
-    else L.mjc = v;
+    const int kind = l >> 2;
+    uint64_t x;
+    int off, n;
+    if (l < 20) {
+      x = kind < 2 ? slot : batch;
+      off = kind == 0 ? T_AM + 4 : kind == 1 ? T_CM + 4 : kind == 2 ? T_AB : kind == 3 ? T_BB : T_CB;
+      n = kind < 2 ? rl + wlo : d.bb;
+    } else {
+      x = l < 22 ? rbits : jbits;
+      off = (l & 1) ? T_CM + 4 : T_AM + 4;
+      n = hb;
+    }
+    L.wv[l] = scatter_bits_n<28>(x, tab + off, n);
   }
   __syncthreads();
 }
@@ -578,7 +587,7 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
   const int K = 1 << d.kb, N = 1 << d.nb;
   if (((uint64_t)blockIdx.x * 4 + w) * iters * R >= (1ull << (d.mb - 4 + d.bb)))
     iters = 0;  // a wave past the last row block (grids of one workgroup)
-  const uint64_t b_b = L.b_b[w];
+  const uint64_t b_b = L.wv[WV_BB + w];
   // MFMA row r of a column block is column n = (r >> 2) + 4 (r & 3) of it, so
   // that output register i of lane group lq is column lq + 4 i: the lowest
   // two n bits sit on lanes and a store instruction covers them.
@@ -611,11 +620,12 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
 #pragma unroll
     for (int i = 0; i < 4; ++i) c_n[cb][i] = (c_lane + L.cn[(16 * cb + lq + 4 * i) & 63]) * ESC;
   // Row-block addresses are wave-uniform: keep them in scalar registers.
-  const uint64_t mra = uniform64(L.mra), mja = uniform64(L.mja), mrc = uniform64(L.mrc), mjc = uniform64(L.mjc);
+  const uint64_t mra = uniform64(L.wv[WV_MRA]), mja = uniform64(L.wv[WV_MJA]), mrc = uniform64(L.wv[WV_MRC]),
+                 mjc = uniform64(L.wv[WV_MJC]);
   uint64_t xra = 0, xja = 0, xrc = 0, xjc = 0;
-  const char* A = reinterpret_cast<const char*>(d.A) + (uniform64(L.a_b[w]) + uniform64(L.xa0[w])) * ESA;
+  const char* A = reinterpret_cast<const char*>(d.A) + (uniform64(L.wv[WV_AB + w]) + uniform64(L.wv[WV_XA + w])) * ESA;
   char* out = reinterpret_cast<char*>(EPI == 2 ? (void*)d.acc : d.C) +
-              (uniform64(L.c_b[w]) + uniform64(L.xc0[w])) * ESC;
+              (uniform64(L.wv[WV_CB + w]) + uniform64(L.wv[WV_XC + w])) * ESC;
   float mx = 0.f;
   Raw raw[R][KS], nxt[R][KS];
   auto load = [&](Raw (&dst)[R][KS]) {
@@ -715,7 +725,7 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
   const int K = 1 << d.kb, N = 1 << d.nb;
   if (((uint64_t)blockIdx.x * 4 + w) * iters * R >= (1ull << (d.mb - 4 + d.bb)))
     iters = 0;  // a wave past the last row block (grids of one workgroup)
-  const uint64_t b_b = L.b_b[w];
+  const uint64_t b_b = L.wv[WV_BB + w];
   // B''^T fragments: row lr of each 16-row block, k' = 4 lq + t
   v4h bf[NB8][KS8];
   {
@@ -757,11 +767,12 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
   for (int nb = 0; nb < NB8; ++nb)
 #pragma unroll
     for (int h = 0; h < 2; ++h) c_n[nb][h] = (c_lane + L.cn[(8 * nb + lq + 4 * h) & 63]) * ESC;
-  const uint64_t mra = uniform64(L.mra), mja = uniform64(L.mja), mrc = uniform64(L.mrc), mjc = uniform64(L.mjc);
+  const uint64_t mra = uniform64(L.wv[WV_MRA]), mja = uniform64(L.wv[WV_MJA]), mrc = uniform64(L.wv[WV_MRC]),
+                 mjc = uniform64(L.wv[WV_MJC]);
   uint64_t xra = 0, xja = 0, xrc = 0, xjc = 0;
-  const char* A = reinterpret_cast<const char*>(d.A) + (uniform64(L.a_b[w]) + uniform64(L.xa0[w])) * 4u;
+  const char* A = reinterpret_cast<const char*>(d.A) + (uniform64(L.wv[WV_AB + w]) + uniform64(L.wv[WV_XA + w])) * 4u;
   char* out = reinterpret_cast<char*>(EPI == 2 ? (void*)d.acc : d.C) +
-              (uniform64(L.c_b[w]) + uniform64(L.xc0[w])) * ESC;
+              (uniform64(L.wv[WV_CB + w]) + uniform64(L.wv[WV_XC + w])) * ESC;
   float mx = 0.f;
   for (uint32_t it = 0; it < iters; ++it) {
     uint32_t raw[R][KS8][2];
