@@ -412,7 +412,9 @@ int32_t mitnc_plan_reverse_info(const mitnc_plan* P, int32_t op, mitnc_step_info
     for (size_t lv = 0; lv < P->rev_levels.size(); ++lv) {
       for (int ri : P->rev_levels[lv].big) order.push_back({ri, (int)lv});
       for (size_t i = 0; i < P->rev.size(); ++i)
-        if (P->rev[i].kclass == MITNC_K_SMALL && P->rev_level_of[i] == (int)lv) order.push_back({(int)i, (int)lv});
+        if (P->rev[i].kclass == MITNC_K_SMALL && P->rev_level_of[i] == (int)lv &&
+            small_bounded(P->rev[i].d.mb, P->rev[i].d.nb, P->rev[i].d.kb, P->rev[i].d.bb))
+          order.push_back({(int)i, (int)lv});
     }
     *n_ops = (int32_t)order.size();
     if (!info) return;

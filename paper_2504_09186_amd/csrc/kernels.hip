@@ -68,6 +68,19 @@ __device__ __forceinline__ uint64_t scatter_bits_n(uint64_t x, const uint8_t* po
   return r;
 }
 
+// gather_bits for n <= MAXN with no branches (as scatter_bits_n).
+template <int MAXN>
+__device__ __forceinline__ uint64_t gather_bits_n(uint64_t a, const uint8_t* pos, int n) {
+  uint64_t r = 0;
+#pragma unroll
+  for (int i = 0; i < MAXN; ++i) {
+    const bool on = i < n;
+    const uint32_t p = pos[on ? i : 0];
+    r |= (on ? ((a >> p) & 1ull) : 0ull) << i;
+  }
+  return r;
+}
+
 // Extracts the address bits pos[0..n) of a into the low n bits (n <= 32).
 __device__ __forceinline__ uint64_t gather_bits(uint64_t a, const uint8_t* pos, int n) {
   uint64_t r = 0;
@@ -166,13 +179,27 @@ __device__ __forceinline__ void record_max(const StepDesc& d, float m) {
 // ---------------------------------------------------------------- small steps
 // One thread per output entry, direct loads; correct for any shape.  Output
 // entry c of C (address bits by the tables in LDS) from operands A, B.
-template <int P>
+// BOUNDED: small_bounded holds (the SMALL class limits), so the address
+// helpers run with compile-time bounds and no branches.
+
+template <bool BOUNDED>
+__device__ __forceinline__ uint64_t sc_s(uint64_t x, const uint8_t* pos, int n) {
+  if constexpr (BOUNDED) return scatter_bits_n<kSmallBits>(x, pos, n);
+  else return scatter_bits(x, pos, n);
+}
+template <bool BOUNDED>
+__device__ __forceinline__ uint64_t ga_s(uint64_t a, const uint8_t* pos, int n) {
+  if constexpr (BOUNDED) return gather_bits_n<kSmallBits>(a, pos, n);
+  else return gather_bits(a, pos, n);
+}
+
+template <int P, bool BOUNDED = false>
 __device__ __forceinline__ float2 small_entry(const void* A, const void* B, const uint8_t* tab, int mb, int nb,
                                               int kb, int bb, uint64_t c) {
-  const uint64_t m = gather_bits(c, tab + T_CM, mb), n = gather_bits(c, tab + T_CN, nb),
-                 b = gather_bits(c, tab + T_CB, bb);
-  const uint64_t ao = scatter_bits(m, tab + T_AM, mb) + scatter_bits(b, tab + T_AB, bb);
-  const uint64_t bo = scatter_bits(n, tab + T_BN, nb) + scatter_bits(b, tab + T_BB, bb);
+  const uint64_t m = ga_s<BOUNDED>(c, tab + T_CM, mb), n = ga_s<BOUNDED>(c, tab + T_CN, nb),
+                 b = ga_s<BOUNDED>(c, tab + T_CB, bb);
+  const uint64_t ao = sc_s<BOUNDED>(m, tab + T_AM, mb) + sc_s<BOUNDED>(b, tab + T_AB, bb);
+  const uint64_t bo = sc_s<BOUNDED>(n, tab + T_BN, nb) + sc_s<BOUNDED>(b, tab + T_BB, bb);
   // The k loop runs in groups of up to 8 independent loads so that memory
   // latency is paid once per group rather than once per term.
   const int kl = kb < 3 ? kb : 3;
@@ -180,14 +207,25 @@ __device__ __forceinline__ float2 small_entry(const void* A, const void* B, cons
   uint32_t ak_lo[8], bk_lo[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    ak_lo[j] = (uint32_t)scatter_bits(j, tab + T_AK, kl);
-    bk_lo[j] = (uint32_t)scatter_bits(j, tab + T_BK, kl);
+    if constexpr (BOUNDED) {
+      ak_lo[j] = (uint32_t)scatter_bits_n<3>(j, tab + T_AK, kl);
+      bk_lo[j] = (uint32_t)scatter_bits_n<3>(j, tab + T_BK, kl);
+    } else {
+      ak_lo[j] = (uint32_t)scatter_bits(j, tab + T_AK, kl);
+      bk_lo[j] = (uint32_t)scatter_bits(j, tab + T_BK, kl);
+    }
   }
   const uint64_t KH = 1ull << (kb - kl);
   float2 s = make_float2(0.f, 0.f);
   for (uint64_t kh = 0; kh < KH; ++kh) {
-    const uint64_t ah = ao + scatter_bits(kh, tab + T_AK + kl, kb - kl);
-    const uint64_t bh = bo + scatter_bits(kh, tab + T_BK + kl, kb - kl);
+    uint64_t ah, bh;
+    if constexpr (BOUNDED) {  // kb <= 6: at most 3 high k bits
+      ah = ao + scatter_bits_n<3>(kh, tab + T_AK + kl, kb - kl);
+      bh = bo + scatter_bits_n<3>(kh, tab + T_BK + kl, kb - kl);
+    } else {
+      ah = ao + scatter_bits(kh, tab + T_AK + kl, kb - kl);
+      bh = bo + scatter_bits(kh, tab + T_BK + kl, kb - kl);
+    }
     float2 a[8], bv[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j)
@@ -205,7 +243,7 @@ __device__ __forceinline__ float2 small_entry(const void* A, const void* B, cons
   return s;
 }
 
-template <int P>
+template <int P, bool BOUNDED>
 __global__ __launch_bounds__(256) void k_small(StepDesc d) {
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   load_tables(d, tab);
@@ -213,7 +251,8 @@ __global__ __launch_bounds__(256) void k_small(StepDesc d) {
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
   const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   float mx = 0.f;
-  if (c < c_elems) mx = epilogue_store<P>(d, c, small_entry<P>(d.A, d.B, tab, d.mb, d.nb, d.kb, d.bb, c), 0, c_elems);
+  if (c < c_elems)
+    mx = epilogue_store<P>(d, c, small_entry<P, BOUNDED>(d.A, d.B, tab, d.mb, d.nb, d.kb, d.bb, c), 0, c_elems);
   record_max(d, mx);
 }
 
@@ -240,9 +279,11 @@ __global__ __launch_bounds__(256) void k_small_multi(const SmallRevOp* ops, cons
   __syncthreads();
   const uint64_t c_elems = 1ull << (mb + nb + bb);
   const uint64_t c = (uint64_t)(gb - op.block0) * 256 + threadIdx.x;
-  if (c < c_elems) C[c] = small_entry<0>(A, B, tab, mb, nb, kb, bb, c);
+  if (c < c_elems) C[c] = small_entry<0, true>(A, B, tab, mb, nb, kb, bb, c);
 }
 
+// Every op of the table satisfies small_bounded (the planner puts the others
+// on single launches).
 hipError_t launch_small_multi(const SmallRevOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,
                               char* ws, uint64_t slice, hipStream_t s) {
   if (!blocks) return hipSuccess;
@@ -1780,7 +1821,8 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
   switch (kclass) {
     case MITNC_K_SMALL: {
       dim3 grid((unsigned)((c_elems + 255) / 256));
-      launch_k(k_small<P>, grid, dim3(256), 0, s, t, d);
+      if (small_bounded(d.mb, d.nb, d.kb, d.bb)) launch_k(k_small<P, true>, grid, dim3(256), 0, s, t, d);
+      else launch_k(k_small<P, false>, grid, dim3(256), 0, s, t, d);
       e = hipGetLastError();
       break;
     }

@@ -638,6 +638,12 @@ static void build_reverse(mitnc_plan* P, const mitnc_network* net, const mitnc_p
 // an op's level is one more than that of the op writing the adjoint it reads
 // (0 for the root's).  SMALL ops of a level go into the batched-launch
 // tables, one block-table entry per workgroup of 256 outputs.
+// A reverse op goes into the batched SMALL launch when it is SMALL and
+// within the class limits (a forced SMALL class on a larger shape runs alone).
+static bool batched_small(const RevOp& r) {
+  return r.kclass == MITNC_K_SMALL && small_bounded(r.d.mb, r.d.nb, r.d.kb, r.d.bb);
+}
+
 static void build_reverse_levels(mitnc_plan* P) {
   const int root = P->steps.back().out;
   std::vector<int> level_of(P->nodes.size(), -1);  // level of the op writing a node's adjoint
@@ -652,14 +658,14 @@ static void build_reverse_levels(mitnc_plan* P) {
     level_of[r.target] = lv;
     P->rev_level_of.push_back(lv);
     if ((int)P->rev_levels.size() <= lv) P->rev_levels.resize(lv + 1);
-    if (r.kclass != MITNC_K_SMALL) P->rev_levels[lv].big.push_back((int)i);
+    if (!batched_small(r)) P->rev_levels[lv].big.push_back((int)i);
   }
   for (size_t lv = 0; lv < P->rev_levels.size(); ++lv) {
     mitnc_plan::RevLevel& L = P->rev_levels[lv];
     L.small_first = (uint32_t)P->rblock.size();
     for (size_t i = 0; i < P->rev.size(); ++i) {
       const RevOp& r = P->rev[i];
-      if (r.kclass != MITNC_K_SMALL || P->rev_level_of[i] != (int)lv) continue;
+      if (!batched_small(r) || P->rev_level_of[i] != (int)lv) continue;
       SmallRevOp e;
       std::memset(&e, 0, sizeof(e));
       e.d = r.d;

@@ -73,6 +73,13 @@ inline constexpr bool skinny_fits(int mb, int nb, int kb, int bb, int ks_bits) {
          bb <= 16;
 }
 
+// SMALL steps within the class limits (at most 2^10 outputs, K <= 64) take
+// the small kernel's bounded, branch-free address code.
+inline constexpr int kSmallBits = 10;
+inline constexpr bool small_bounded(int mb, int nb, int kb, int bb) {
+  return mb <= kSmallBits && nb <= kSmallBits && bb <= kSmallBits && kb <= 6;
+}
+
 // One SMALL-class adjoint contraction of the reverse pass inside a batched
 // launch (device table in the workspace).  The descriptor gives the shape and
 // position tables; operands are workspace byte offsets, and the one operand
