@@ -68,6 +68,23 @@ __device__ __forceinline__ uint64_t scatter_bits_n(uint64_t x, const uint8_t* po
   return r;
 }
 
+// scatter_bits of a wave-uniform x, computed across the lanes: lane i
+// deposits bit i, an OR-reduction over the wave combines them (one LDS read
+// per lane instead of n dependent ones).  Every lane of the wave must call it
+// with the same arguments; every lane gets the result.  n <= 32.
+__device__ __forceinline__ uint64_t wave_scatter(uint64_t x, const uint8_t* pos, int n) {
+  const int l = threadIdx.x & 63;
+  const bool on = l < n;
+  const uint32_t p = pos[on ? l : 0];
+  uint64_t t = on ? (((x >> l) & 1ull) << p) : 0ull;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)t, o), hi = __shfl_xor((uint32_t)(t >> 32), o);
+    t |= ((uint64_t)hi << 32) | lo;
+  }
+  return t;
+}
+
 // gather_bits for n <= MAXN with no branches (as scatter_bits_n).
 template <int MAXN>
 __device__ __forceinline__ uint64_t gather_bits_n(uint64_t a, const uint8_t* pos, int n) {
@@ -1166,19 +1183,20 @@ struct TileSlot {
 // are independent of each other (two round trips instead of two per bit).
 __device__ __forceinline__ TileSlot decode_slot(int e, int nbits, const uint8_t* codes, const uint8_t* tab,
                                                 int first_cls, int off_first, int off_second) {
+  // Branch-free (index clamped, contribution masked): the LDS reads of all
+  // bits issue together instead of one dependent pair per bit.
   TileSlot r{0, 0, 0};
 #pragma unroll
   for (int b = 0; b < 16; ++b) {
-    if (b < nbits) {
-      const uint8_t code = codes[b];
-      const int idx = code & 31;
-      const bool first = (code >> 5) == first_cls;
-      const int pos = tab[(first ? off_first : off_second) + idx];
-      const int bit = (e >> b) & 1;
-      if (first) r.lo |= bit << idx;
-      else r.hi |= bit << idx;
-      r.off |= (uint32_t)bit << pos;
-    }
+    const bool on = b < nbits;
+    const uint8_t code = codes[on ? b : 0];
+    const int idx = code & 31;
+    const bool first = (code >> 5) == first_cls;
+    const int pos = tab[(first ? off_first : off_second) + idx];
+    const int bit = on ? (e >> b) & 1 : 0;
+    r.lo |= first ? bit << idx : 0;
+    r.hi |= first ? 0 : bit << idx;
+    r.off |= (uint32_t)bit << pos;
   }
   return r;
 }
@@ -1190,8 +1208,8 @@ __device__ __forceinline__ void store_c_tile(const StepDesc& d, const uint8_t* t
                                              uint64_t nt, uint64_t batch) {
   const int tid = threadIdx.x;
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
-  const uint64_t baseC = scatter_bits(mt, tab + T_CM + d.tm, d.mb - d.tm) +
-                         scatter_bits(nt, tab + T_CN + d.tn, d.nb - d.tn) + scatter_bits(batch, tab + T_CB, d.bb);
+  const uint64_t baseC = wave_scatter(mt, tab + T_CM + d.tm, d.mb - d.tm) +
+                         wave_scatter(nt, tab + T_CN + d.tn, d.nb - d.tn) + wave_scatter(batch, tab + T_CB, d.bb);
   const int nc = d.tm + d.tn;
   // Element e = tid + 256 j: the low 8 tile bits come from tid (decoded once
   // per thread), the others from j (uniform across the workgroup).
@@ -1275,9 +1293,9 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
   const uint64_t mt = blockIdx.x % n_mt, nt = blockIdx.x / n_mt;
   const uint64_t batch = blockIdx.z;
   const uint64_t baseA =
-      scatter_bits(mt, tab + T_AM + d.tm, d.mb - d.tm) + scatter_bits(batch, tab + T_AB, d.bb);
+      wave_scatter(mt, tab + T_AM + d.tm, d.mb - d.tm) + wave_scatter(batch, tab + T_AB, d.bb);
   const uint64_t baseB =
-      scatter_bits(nt, tab + T_BN + d.tn, d.nb - d.tn) + scatter_bits(batch, tab + T_BB, d.bb);
+      wave_scatter(nt, tab + T_BN + d.tn, d.nb - d.tn) + wave_scatter(batch, tab + T_BB, d.bb);
 
   // Per-thread load slots: global offset inside the tile and LDS index.
   // Slots outside a tile smaller than the template keep offset 0, so their
@@ -1327,8 +1345,8 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
     flip[0][tid] = fa;
     flip[1][tid] = fb;
   }
-  uint64_t ka = scatter_bits(kt0, tab + T_AK + d.tk, khb);
-  uint64_t kbo = scatter_bits(kt0, tab + T_BK + d.tk, khb);
+  uint64_t ka = wave_scatter(kt0, tab + T_AK + d.tk, khb);
+  uint64_t kbo = wave_scatter(kt0, tab + T_BK + d.tk, khb);
 
   float2 ra[A_LOADS], rb[B_LOADS];
   auto load = [&]() {
@@ -1453,9 +1471,9 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
   const uint64_t mt = blockIdx.x % n_mt, nt = blockIdx.x / n_mt;
   const uint64_t batch = blockIdx.z;
   const uint64_t baseA =
-      scatter_bits(mt, tab + T_AM + d.tm, d.mb - d.tm) + scatter_bits(batch, tab + T_AB, d.bb);
+      wave_scatter(mt, tab + T_AM + d.tm, d.mb - d.tm) + wave_scatter(batch, tab + T_AB, d.bb);
   const uint64_t baseB =
-      scatter_bits(nt, tab + T_BN + d.tn, d.nb - d.tn) + scatter_bits(batch, tab + T_BB, d.bb);
+      wave_scatter(nt, tab + T_BN + d.tn, d.nb - d.tn) + wave_scatter(batch, tab + T_BB, d.bb);
 
   uint32_t a_off[A_LOADS];
   int a_lds[A_LOADS];
@@ -1499,8 +1517,8 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
     flip[0][tid] = fa;
     flip[1][tid] = fb;
   }
-  uint64_t ka = scatter_bits(kt0, tab + T_AK + d.tk, khb);
-  uint64_t kbo = scatter_bits(kt0, tab + T_BK + d.tk, khb);
+  uint64_t ka = wave_scatter(kt0, tab + T_AK + d.tk, khb);
+  uint64_t kbo = wave_scatter(kt0, tab + T_BK + d.tk, khb);
 
   uint32_t ra[A_LOADS], rb[B_LOADS];
   auto load = [&]() {
