@@ -322,7 +322,11 @@ hipError_t launch_small_multi(const SmallRevOp* ops, const uint32_t* block_op, u
 // pos[2..]: step setting bit j (and clearing bits 2..j-1), modulo 2^64.
 __device__ __forceinline__ unsigned long long skinny_step_delta(const uint8_t* pos, int j) {
   unsigned long long v = 1ull << pos[j];
-  for (int i = 2; i < j; ++i) v -= 1ull << pos[i];
+#pragma unroll
+  for (int i = 2; i < 26; ++i) {  // branch-free: j <= 25 (k <= 32)
+    const bool on = i < j;
+    v -= on ? 1ull << pos[on ? i : 0] : 0ull;
+  }
   return v;
 }
 
@@ -336,10 +340,10 @@ __global__ __launch_bounds__(64) void k_skinny(StepDesc d) {
   const int KH = d.kb - LB;        // high k bits
   const int hl = KH - d.ks_bits;   // log2 of high k values per split (>= 2)
   const uint64_t split = blockIdx.x, b = blockIdx.y;
-  const float2* A = reinterpret_cast<const float2*>(d.A) + scatter_bits(b, tab + T_AB, d.bb) +
-                    scatter_bits(lane, tab + T_AK, LB);
-  const float2* B = reinterpret_cast<const float2*>(d.B) + scatter_bits(b, tab + T_BB, d.bb) +
-                    scatter_bits(lane, tab + T_BK, LB);
+  const float2* A = reinterpret_cast<const float2*>(d.A) + wave_scatter(b, tab + T_AB, d.bb) +
+                    scatter_bits_n<LB>(lane, tab + T_AK, LB);
+  const float2* B = reinterpret_cast<const float2*>(d.B) + wave_scatter(b, tab + T_BB, d.bb) +
+                    scatter_bits_n<LB>(lane, tab + T_BK, LB);
   // Offsets, one scatter per entry into LDS (wave-uniform values computed
   // in scalar registers would spill them): every m in A and n in B, the four
   // values of the two lowest high-k bits (one iteration) in A and B, this
@@ -351,17 +355,27 @@ __global__ __launch_bounds__(64) void k_skinny(StepDesc d) {
   // different k values).
   enum { E_AM = 0, E_BN = 16, E_OA = 32, E_OB = 36, E_XA = 40, E_XB = 41, E_DA = 64, E_DB = 96, E_N = 128 };
   __shared__ unsigned long long offs[E_N];
-  for (int e = lane; e < E_N; e += 64) {
-    unsigned long long v = 0;
-    if (e < E_AM + M) v = scatter_bits(e - E_AM, tab + T_AM, MB);
-    else if (e >= E_BN && e < E_BN + N) v = scatter_bits(e - E_BN, tab + T_BN, NB);
-    else if (e >= E_OA && e < E_OA + 4) v = scatter_bits(e - E_OA, tab + T_AK + LB, 2);
-    else if (e >= E_OB && e < E_OB + 4) v = scatter_bits(e - E_OB, tab + T_BK + LB, 2);
-    else if (e == E_XA) v = scatter_bits(split << hl, tab + T_AK + LB, KH);
-    else if (e == E_XB) v = scatter_bits(split << hl, tab + T_BK + LB, KH);
-    else if (e >= E_DA && e - E_DA < KH) v = skinny_step_delta(tab + T_AK + LB, e - E_DA);
-    else if (e >= E_DB && e - E_DB < KH) v = skinny_step_delta(tab + T_BK + LB, e - E_DB);
-    offs[e] = v;
+  // Pass 1 (entries 0-63): one bounded scatter per lane, its operands
+  // selected per entry; pass 2 (64-127): the counter-step deltas.  One job
+  // shape per pass, no divergent branches around the LDS reads.
+  {
+    uint64_t x = 0;
+    int off = T_AM, n = 0;
+    const int e = lane;
+    if (e < E_AM + M) {
+      x = e - E_AM; off = T_AM; n = MB;
+    } else if (e >= E_BN && e < E_BN + N) {
+      x = e - E_BN; off = T_BN; n = NB;
+    } else if (e >= E_OA && e < E_OA + 4) {
+      x = e - E_OA; off = T_AK + LB; n = 2;
+    } else if (e >= E_OB && e < E_OB + 4) {
+      x = e - E_OB; off = T_BK + LB; n = 2;
+    } else if (e == E_XA || e == E_XB) {
+      x = split << hl; off = (e == E_XA ? T_AK : T_BK) + LB; n = KH;
+    }
+    offs[e] = scatter_bits_n<26>(x, tab + off, n);  // KH <= 26 (k <= 32)
+    const int j = lane & 31;
+    offs[E_DA + lane] = j < KH ? skinny_step_delta(tab + (lane < 32 ? T_AK : T_BK) + LB, j) : 0ull;
   }
   __syncthreads();
   uint64_t a_m[M], b_n[N], oa[U], ob[U];
@@ -416,14 +430,14 @@ __global__ __launch_bounds__(64) void k_skinny(StepDesc d) {
       }
   // Every lane holds every sum; lane m N + n stores entry (m, n).
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
-  const uint64_t cb = scatter_bits(b, tab + T_CB, d.bb);
+  const uint64_t cb = wave_scatter(b, tab + T_CB, d.bb);
   float mx = 0.f;
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int n = 0; n < N; ++n)
       if (lane == m * N + n) {
-        const uint64_t c = cb + scatter_bits(m, tab + T_CM, MB) + scatter_bits(n, tab + T_CN, NB);
+        const uint64_t c = cb + scatter_bits_n<MB>(m, tab + T_CM, MB) + scatter_bits_n<NB>(n, tab + T_CN, NB);
         mx = epilogue_store<0>(d, c, acc[m][n], split, c_elems);
       }
   if (d.stats) {
@@ -450,22 +464,25 @@ __global__ __launch_bounds__(256) void k_stem(StepDesc d) {
   __syncthreads();
   const uint64_t batch = blockIdx.y;
   const int t = threadIdx.x;
+  // Batch offsets across the wave (uniform, every lane here), the rest with
+  // bounded branch-free scatters.
+  const uint64_t ab = wave_scatter(batch, tab + T_AB, d.bb), bbo = wave_scatter(batch, tab + T_BB, d.bb),
+                 cbo = wave_scatter(batch, tab + T_CB, d.bb);
   if (t < K * N) {
     const int k = t / N, n = t % N;
-    Bs[t] = load_c<P>(d.B, scatter_bits(batch, tab + T_BB, d.bb) + scatter_bits(k, tab + T_BK, KB) +
-                               scatter_bits(n, tab + T_BN, NB));
+    Bs[t] = load_c<P>(d.B, bbo + scatter_bits_n<KB>(k, tab + T_BK, KB) + scatter_bits_n<NB>(n, tab + T_BN, NB));
   }
-  if (t < K) ka[t] = (uint32_t)scatter_bits(t, tab + T_AK, KB);
-  if (t < N) nc[t] = (uint32_t)scatter_bits(t, tab + T_CN, NB);
+  if (t < K) ka[t] = (uint32_t)scatter_bits_n<KB>(t, tab + T_AK, KB);
+  if (t < N) nc[t] = (uint32_t)scatter_bits_n<NB>(t, tab + T_CN, NB);
   __syncthreads();
   const int lowb = d.mb < 8 ? d.mb : 8;
   const uint64_t n_mhi = 1ull << (d.mb - lowb);
+  const uint64_t a_lo = scatter_bits_n<8>(t, tab + T_AM, lowb), c_lo = scatter_bits_n<8>(t, tab + T_CM, lowb);
   float mx = 0.f;
   for (uint64_t mhi = blockIdx.x; t < (1 << lowb) && mhi < n_mhi; mhi += gridDim.x) {  // high m bits (uniform)
-    uint64_t aoff = scatter_bits(mhi, tab + T_AM + lowb, d.mb - lowb) + scatter_bits(batch, tab + T_AB, d.bb);
-    uint64_t coff = scatter_bits(mhi, tab + T_CM + lowb, d.mb - lowb) + scatter_bits(batch, tab + T_CB, d.bb);
-    aoff += scatter_bits(t, tab + T_AM, lowb);
-    coff += scatter_bits(t, tab + T_CM, lowb);
+    // at most 24 high m bits (m <= 32)
+    const uint64_t aoff = scatter_bits_n<24>(mhi, tab + T_AM + lowb, d.mb - lowb) + ab + a_lo;
+    const uint64_t coff = scatter_bits_n<24>(mhi, tab + T_CM + lowb, d.mb - lowb) + cbo + c_lo;
     float2 a[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) a[k] = load_c<P>(d.A, aoff + ka[k]);
