@@ -651,7 +651,7 @@ __device__ __forceinline__ uint32_t lane_offset(uint32_t x) {
   return x;
 }
 
-template <int P, int KS, int NBLK, int LD, bool PIPE, int EPI>
+template <int P, int KS, int NBLK, int LD, int EPI>
 __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* tab, const StreamLut& L,
                                              uint32_t iters) {
   constexpr int R = LD / KS > 0 ? LD / KS : 1;  // row blocks per iteration
@@ -702,7 +702,7 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
   char* out = reinterpret_cast<char*>(EPI == 2 ? (void*)d.acc : d.C) +
               (uniform64(L.wv[WV_CB + w]) + uniform64(L.wv[WV_XC + w])) * ESC;
   float mx = 0.f;
-  Raw raw[R][KS], nxt[R][KS];
+  Raw raw[R][KS];
   auto load = [&](Raw (&dst)[R][KS]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -712,15 +712,10 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
     }
     xja = ((xja | ~mja) + 1) & mja;
   };
-  if (PIPE) load(raw);
   for (uint32_t it = 0; it < iters; ++it) {
     // All loads of an iteration are issued before any of them is used, so a
     // wave waits for memory once per iteration.
-    if (PIPE) {
-      if (it + 1 < iters) load(nxt);
-    } else {
-      load(raw);
-    }
+    load(raw);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -755,17 +750,11 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
       xrc = ((xrc | ~mrc) + 1) & mrc;
     }
     xjc = ((xjc | ~mjc) + 1) & mjc;
-    if (PIPE) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) raw[r][ks] = nxt[r][ks];
-    }
   }
   return mx;
 }
 
-template <int P, int KS, int NBLK, int LD = stream_loads<P>(), bool PIPE = false>
+template <int P, int KS, int NBLK, int LD = stream_loads<P>()>
 __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   __shared__ StreamLut lut;
@@ -773,9 +762,9 @@ __global__ __launch_bounds__(256) void k_stream(StepDesc d, uint32_t iters) {
   constexpr int RL = LD / KS > 1 ? ilog2c(LD / KS) : 0;  // log2 R
   stream_lut_init(d, tab, lut, RL, iters);
   float mx;
-  if (d.mode == EPI_ACC64) mx = stream_body<P, KS, NBLK, LD, PIPE, 2>(d, tab, lut, iters);
-  else if (d.stats) mx = stream_body<P, KS, NBLK, LD, PIPE, 1>(d, tab, lut, iters);
-  else mx = stream_body<P, KS, NBLK, LD, PIPE, 0>(d, tab, lut, iters);
+  if (d.mode == EPI_ACC64) mx = stream_body<P, KS, NBLK, LD, 2>(d, tab, lut, iters);
+  else if (d.stats) mx = stream_body<P, KS, NBLK, LD, 1>(d, tab, lut, iters);
+  else mx = stream_body<P, KS, NBLK, LD, 0>(d, tab, lut, iters);
   record_max(d, mx);
 }
 
