@@ -254,3 +254,45 @@ def test_plan_replay_fused_sections(lib):
     for x in (fused, plain):
         assert np.linalg.norm(x - ref) <= 1e-5 * np.linalg.norm(ref)
     assert not _sections(tnc.Plan(net, fuse_sections=False))
+
+
+@pytest.mark.parametrize("rows,cols,cycles,nbits,nsl,seed", [(3, 3, 6, 16, 2, 41), (2, 4, 8, 4, 3, 42)])
+def test_reverse_schedule_levels(lib, rows, cols, cycles, nbits, nsl, seed):
+    """The backward runs level by level: execution order never goes back a
+    level, every adjoint is written once, and an op reads the root's adjoint
+    (the seed) or one written at an earlier level.  SMALL ops of a level
+    share one batched launch, so none of them may read an adjoint written at
+    its own level.  Every step with a single-qubit gate below it contributes
+    its adjoint ops (pruning removes only gradient-free subtrees)."""
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(rows, cols, cycles, seed=seed)
+    n = c.n_qubits
+    bits = synth.random_bitstrings(n, nbits, seed=seed + 1)
+    spec = np.full(n, -2, dtype=np.int8)
+    net = tnc.Network(c, spec, bits)
+    net.path_search(seed=seed + 2, trials=8, max_log2=30, min_sliced=nsl)
+    plan = tnc.Plan(net, differentiable=True)
+    n_ops = plan.reverse_info()
+    assert n_ops > 0
+    ops = [plan.reverse_info(i) for i in range(n_ops)]
+    steps = [plan.step_info(i) for i in range(plan.stats.n_steps)]
+    root = max(s["out"] for s in steps)
+    written = {}
+    last_level = 0
+    for op in ops:
+        assert op["level"] >= last_level
+        last_level = op["level"]
+        assert op["out"] not in written, "adjoint written twice"
+        if op["a"] != root:
+            assert op["a"] in written, "adjoint read before it is written"
+            assert written[op["a"]] < op["level"]
+        else:
+            assert op["level"] == 0
+        written[op["out"]] = op["level"]
+    # every single-qubit gate leaf gets its adjoint
+    assert n_ops == plan.stats.n_reverse_ops
+    n_1q = sum(1 for g in c.gates if len(g.qubits) == 1)
+    assert n_1q == plan.stats.n_grad_gates
+    assert sum(1 for x in written if x < net.n_leaves) == n_1q
+    with pytest.raises(Exception):
+        plan.reverse_info(n_ops)
