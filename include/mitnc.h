@@ -276,7 +276,9 @@ int32_t mitnc_step_maxima(mitnc_plan* plan, void* ws, size_t ws_bytes, float* ou
  * of the slice (nodes whose sliced indices did not change are reused) and
  * runs the reverse pass: for every step C = A (x) B with a single-qubit gate
  * leaf below, adj(A) = adj(C) contracted with B onto A's indices (and the same
- * for B), subtrees without such leaves pruned.  Adds the holomorphic VJP
+ * for B), subtrees without such leaves pruned.  The adjoint contractions run
+ * level by level of the reverse tree (mitnc_plan_reverse_info); the SMALL
+ * ones of a level share one launch.  Adds the holomorphic VJP
  *   grad[g][i][j] += sum_r w[r] * d result[r] / d U_g[i][j]
  * to grad_accum (device complex128, n_grad_gates x 4 entries, U[out][in]
  * row-major, gates in circuit order of the single-qubit gates).  w: device
@@ -331,7 +333,10 @@ enum {
   MITNC_K_STEM = 1,   /* big tensor times small matrix: vector FMA, one thread per row */
   MITNC_K_TILE = 2,   /* LDS-staged, bit-permuted tiles, complex GEMM on FP32 MFMA */
   MITNC_K_TALL = 3,   /* as TILE with a 128 x 16 tile for narrow N */
-  MITNC_K_SPLITK = 4, /* small M, N, long K: K split over workgroups, FP64 reduction */
+  MITNC_K_SPLITK = 4, /* small M, N, long K: K split over workgroups, FP64 reduction;
+                         complex64 steps with M N <= 16 per batch index and
+                         K >= 2^8 run on a register-only kernel (one wave per
+                         k split and batch index), the others on LDS tiles */
   MITNC_K_STREAM = 5  /* big tensor times small matrix on MFMA, streamed with no LDS staging:
                          needs at most 2^10 batch indices, M >= 2^8, K <= 64, N <= 64,
                          max(K/4, 1) * max(N/16, 1) <= 16, and the row indices
