@@ -54,16 +54,11 @@ def golden_amplitudes():
 
 
 def amp_error(got, ref):
-    import numpy as np
+    import oracle
     if ref is None:
         return None
-    p = np.abs(ref) ** 2
-    p /= p.sum()
-    q = np.abs(got) ** 2
-    q /= q.sum()
-    xeb = (ref.size * np.sum(p * q) - 1.0) / (ref.size * np.sum(p * p) - 1.0)
-    return {"rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), "xeb_loss": float(abs(1.0 - xeb)),
-            "against": "FP64 oracle, all 64 amplitudes"}
+    return {"rel_l2": oracle.rel_l2(got, ref), "overlap": oracle.overlap_fidelity(got, ref),
+            "xeb_loss": abs(1.0 - oracle.xeb_ratio(got, ref)), "against": "FP64 oracle, all 64 amplitudes"}
 
 
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")

@@ -202,11 +202,7 @@ def test_fused_sections(prec):
         assert np.linalg.norm(a.cpu().numpy() - ref) <= TOL * np.linalg.norm(ref)
     else:
         assert oracle.rel_l2(got, ref) < 2e-2
-        p = np.abs(ref) ** 2
-        q = np.abs(got) ** 2
-        p, q = p / p.sum(), q / q.sum()
-        xeb = (ref.size * np.sum(p * q) - 1.0) / (ref.size * np.sum(p * p) - 1.0)
-        assert abs(1.0 - xeb) < 1e-3
+        assert abs(1.0 - oracle.xeb_ratio(got, ref)) < 1e-3
 
 
 def _run_opts(net, **kw):

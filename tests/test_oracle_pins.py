@@ -292,3 +292,51 @@ def test_metrics_closed_forms():
     assert oracle.xeb_ratio(a * 3.0, a) == pytest.approx(1.0, abs=1e-12)
     b = a + 1e-3 * synth.complex_normal(64, seed=72)
     assert 0 < oracle.rel_l2(b, a) < 2e-3
+
+
+def _from_probs(p, scale, seed):
+    """Amplitudes with |x|^2 proportional to p, arbitrary norm and phases."""
+    rng = np.random.default_rng(seed)
+    ph = np.exp(2j * np.pi * rng.random(len(p)))
+    return scale * np.sqrt(np.asarray(p, dtype=np.float64)) * ph
+
+
+def test_xeb_ratio_hand_values():
+    """Linear XEB ratio (|B| sum p q - 1) / (|B| sum p^2 - 1) worked by hand on
+    non-identical distributions; p (reference) and q (approximation) enter
+    asymmetrically, so exchanging them in the denominator, dropping the
+    normalisation or the -1 terms fails one of the cases."""
+    p = [0.4, 0.3, 0.2, 0.1]          # sum p^2 = 0.30
+    # q = (0.5, 0.5, 0, 0): sum p q = 0.35 -> (1.4 - 1) / (1.2 - 1) = 2
+    # (with q in the denominator: sum q^2 = 0.5 -> 0.4 / 1.0 = 0.4)
+    ref = _from_probs(p, 3e-5, 1)
+    got = _from_probs([0.5, 0.5, 0.0, 0.0], 7.0, 2)
+    assert oracle.xeb_ratio(got, ref) == pytest.approx(2.0, rel=1e-12)
+    # q uniform: sum p q = 1/4 -> (1 - 1) / 0.2 = 0
+    assert abs(oracle.xeb_ratio(_from_probs([1, 1, 1, 1], 0.1, 3), ref)) < 1e-12
+    # q reversed: sum p q = 0.2 -> (0.8 - 1) / 0.2 = -1
+    assert oracle.xeb_ratio(_from_probs(p[::-1], 2.0, 4), ref) == pytest.approx(-1.0, rel=1e-12)
+    # |B| = 2: p = (1/4, 3/4), q = (1/2, 1/2): sum p q = 1/2 -> (1 - 1) / (2 * 5/8 - 1) = 0
+    assert abs(oracle.xeb_ratio(np.array([1.0, 1j]), np.array([1.0, np.sqrt(3.0)]))) < 1e-12
+    # |B| = 2: p = (1/4, 3/4), q = (3/4, 1/4): (2 * 3/8 - 1) / (2 * 5/8 - 1) = -1
+    assert oracle.xeb_ratio(np.array([np.sqrt(3.0), 1.0]), np.array([1.0, 1j * np.sqrt(3.0)])) == \
+        pytest.approx(-1.0, rel=1e-12)
+
+
+def test_overlap_fidelity_hand_values():
+    """|<a, b>|^2 / (|a|^2 |b|^2) with the conjugate on the reference."""
+    # <(1, i), (1, -i)> = 1 + (-i)(-i) = 0; without the conjugate it would be 2 -> 1
+    assert oracle.overlap_fidelity(np.array([1.0, -1j]), np.array([1.0, 1j])) == pytest.approx(0.0, abs=1e-15)
+    # <(1, 0), (1, 1)> = 1, norms 1 and 2 -> 1/2
+    assert oracle.overlap_fidelity(np.array([1.0, 1.0]), np.array([1.0, 0.0])) == pytest.approx(0.5, rel=1e-14)
+    # <(1, i, 0), (2, 0, 2i)> = 2, norms 2 and 8 -> 4 / 16
+    assert oracle.overlap_fidelity(np.array([2.0, 0.0, 2j]), np.array([1.0, 1j, 0.0])) == \
+        pytest.approx(0.25, rel=1e-14)
+
+
+def test_rel_l2_hand_values():
+    """||b - a|| / ||a|| with the reference norm in the denominator."""
+    # a = (3, 4), b = (3, 4 + 5i): ||b - a|| = 5, ||a|| = 5 (||b|| = sqrt 50)
+    assert oracle.rel_l2(np.array([3.0, 4.0 + 5j]), np.array([3.0, 4.0])) == pytest.approx(1.0, rel=1e-15)
+    # a = (1, 1, 1, 1), b = (1, 1, 1, 2i - 1): ||b - a|| = |2i - 2| = sqrt 8, ||a|| = 2
+    assert oracle.rel_l2(np.array([1, 1, 1, 2j - 1]), np.ones(4)) == pytest.approx(np.sqrt(2.0), rel=1e-15)
