@@ -78,7 +78,10 @@ int32_t mitnc_network_from_circuit(int32_t n_qubits, int32_t n_gates, const mitn
 int32_t mitnc_network_set_output(mitnc_network* net, const int8_t* per_qubit, int32_t n_batch,
                                  const uint8_t* batch_bits);
 
-/* Number of leaves (tensors) and of contraction steps (n_leaves - 1). */
+/* Sizes of the network of Sec. II-A: n_leaves receives the number of
+ * tensors (a contraction path has n_leaves - 1 steps), n_labels (may be
+ * NULL) the number of distinct indices.  Errors: INVALID_ARG for a null
+ * network. */
 int32_t mitnc_network_info(const mitnc_network* net, int32_t* n_leaves, int32_t* n_labels);
 
 /* Contraction order and slicing search.  Runs `trials` randomised greedy
@@ -100,26 +103,42 @@ typedef struct mitnc_search_opts {
   int32_t max_sliced;
   int32_t keep_slicing; /* 1: keep the current sliced indices (outermost, in
                            their order) and only add more if the cap needs it */
+  int32_t method;       /* 0: randomised greedy trials; 1: recursive-bisection
+                           trials (parts sharing few indices, refined by
+                           Fiduccia-Mattheyses moves, random balance and
+                           leaf-size parameters per trial); 2: both, `trials`
+                           of each */
 } mitnc_search_opts;
 int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* opts);
 
-/* Path as SSA pairs: step t contracts ids pairs[2t], pairs[2t+1] into id
- * n_leaves + t.  get: pairs_out has room for 2*(n_leaves-1) int32.
+/* Contraction path (Sec. II-A: the order of the pairwise contractions;
+ * Evaluation: the paper takes it from an external search) as SSA pairs:
+ * step t contracts ids pairs[2t], pairs[2t+1] into id n_leaves + t.
+ * Errors: INVALID_ARG for null pointers, PATH_INVALID for a path that
+ * reuses or skips a tensor.  get: pairs_out has room for 2*(n_leaves-1) int32.
  * set: validates (every id used once, ids exist when used).  Setting a path
  * keeps the slicing. */
 int32_t mitnc_get_path(const mitnc_network* net, int32_t* pairs_out);
 int32_t mitnc_set_path(mitnc_network* net, int32_t n_steps, const int32_t* pairs);
 
-/* Sliced indices, outer -> inner (the last is the least significant bit of
- * the slice id).  get: n_out receives the count; ids_out (may be NULL) has
+/* Sliced indices (Sec. III-A: fixing an index splits the contraction into
+ * independent subtasks whose results are summed), outer -> inner (the last
+ * is the least significant bit of the slice id; slices run in increasing id
+ * order, so inner indices change most often, Sec. III-B).  get: n_out receives the count; ids_out (may be NULL) has
  * room for 64 labels.  set: every label must be a closed binary edge (shared
  * by exactly two leaves, not an output). */
 int32_t mitnc_get_slicing(const mitnc_network* net, int32_t* n_out, int64_t* ids_out);
 int32_t mitnc_set_slicing(mitnc_network* net, int32_t n, const int64_t* ids);
 
-/* Greedy slicing for the current path (see mitnc_path_search). */
+/* Greedy slicing for the current path (Sec. III-A; the same rule as
+ * mitnc_path_search): slices indices until the largest intermediate has at
+ * most 2^max_log2_elems entries and at least min_sliced indices are sliced
+ * (at most max_sliced <= 64), replacing the current slicing.  n_out and
+ * ids_out (room for 64 labels) receive the chosen labels, outer -> inner;
+ * either may be NULL.  Errors: UNSUPPORTED if the cap cannot be met within
+ * max_sliced (the slicing is then unchanged). */
 int32_t mitnc_slice_greedy(mitnc_network* net, int32_t max_log2_elems, int32_t min_sliced,
-                           int32_t max_sliced);
+                           int32_t max_sliced, int32_t* n_out, int64_t* ids_out);
 
 /* Eq. (1) of the paper for label `a` on the current path and slicing:
  * O(a) = 2 C_a / C_ori, C = real flops of one subtask (8 per complex
@@ -153,9 +172,32 @@ typedef struct mitnc_plan_opts {
                              ignored with force_kernel >= 0 or differentiable.
                              0 (recommended on MI355X): one stream launch per
                              step, which measured faster */
+  int32_t no_rerun;       /* FP16/BF16 plans: 1 = an exponent miss or overflow
+                             makes mitnc_execute return MITNC_NUMERIC at once;
+                             0 = it re-derives the exponents and re-runs */
+  int32_t splitk_max_mn_bits; /* split-K GEPDOT (Sec. V-B) takes steps whose m
+                                 and n index counts are both at most this
+                                 (0 = 4, i.e. M, N <= 16; at most 8) */
+  int32_t splitk_target_bits; /* log2 of the workgroups (waves for the
+                                 register-only form) a split-K step is spread
+                                 over, K split until the grid reaches it
+                                 (0 = 12 register-only, 11 LDS-tiled, 8 for
+                                 large tiles; at most 16) */
 } mitnc_plan_opts;
 
+/* Execution plan of the sliced contraction tree for the network's current
+ * path and slicing (Sec. II-A, III-A, III-B): per step the kernel class,
+ * operand address maps (the permutation of TTGT as an address map, Sec.
+ * V-A), output layout, split-K factor (Sec. V-B), per-node recompute level
+ * and the workspace layout.  Host only; the plan copies what it needs from
+ * the network.  Errors: INVALID_ARG (null, bad option), UNSUPPORTED (a
+ * step outside every kernel class, or more than 64 sliced indices). */
 int32_t mitnc_plan_create(const mitnc_network* net, const mitnc_plan_opts* opts, mitnc_plan** out);
+
+/* Sizes and algorithmic work of a plan (host only).  Flops count 8 real
+ * flops per complex multiply-add (the 4M convention, whatever split runs);
+ * bytes count every operand read once and every output written once.
+ * Errors: INVALID_ARG for null pointers. */
 
 typedef struct mitnc_plan_stats {
   uint64_t workspace_bytes;   /* device bytes the caller must provide */
@@ -177,7 +219,8 @@ typedef struct mitnc_plan_stats {
 } mitnc_plan_stats;
 int32_t mitnc_plan_query(const mitnc_plan* plan, mitnc_plan_stats* stats);
 
-/* Per-step description for reports (host only).  info has 12 doubles per
+/* Per-step description for reports (host only; the per-step costs behind
+ * Eq. (1) and the kernel classes of Sec. V).  info has 12 doubles per
  * step: kernel class, m bits, n bits, k bits, batch bits, recompute level
  * (-1 = slice invariant), flops, algorithmic bytes, k-split count, swapped,
  * output log2 size, is-root. */
@@ -217,7 +260,8 @@ int32_t mitnc_plan_step_info(const mitnc_plan* plan, int32_t step, mitnc_step_in
  * range; n_ops = 0 for plans that are not differentiable.  Host only. */
 int32_t mitnc_plan_reverse_info(const mitnc_plan* plan, int32_t op, mitnc_step_info* info, int32_t* n_ops);
 
-/* ws_offset: byte offset of the node's tensor in the workspace of a
+/* Storage and schedule of one node (host only; Sec. III-B reuse levels).
+ * ws_offset: byte offset of the node's tensor in the workspace of a
  * complex64 run (UINT64_MAX for the root, which is the caller's result);
  * level: -1 = computed once per slice range, else recomputed for slice s
  * when ctz(s) >= level (Sec. III-B); a slice reads the sub-tensor at
@@ -238,64 +282,112 @@ typedef struct mitnc_node_info {
 int32_t mitnc_plan_node_info(const mitnc_plan* plan, int32_t node, mitnc_node_info* info);
 
 /* The complex64 entries (re, im interleaved) a plan uploads for leaf
- * `leaf`: 2^full_rank entries; out may be null to query n_floats. */
+ * `leaf` (a gate tensor of Sec. II-A in its address layout; sliced leaves
+ * hold every value of their sliced indices): 2^full_rank entries; out may
+ * be null to query n_floats.  Host only.  Errors: INVALID_ARG (null, leaf
+ * out of range, capacity too small). */
 int32_t mitnc_plan_leaf_data(const mitnc_plan* plan, int32_t leaf, float* out, uint64_t capacity_floats,
                              uint64_t* n_floats);
 
-/* Copies leaves into the caller-owned device workspace (ws, ws_bytes) and
- * resets the cross-slice cache.  Errors: WORKSPACE_TOO_SMALL, HIP_ERROR. */
+/* Copies leaves and tables into the caller-owned device workspace (ws,
+ * ws_bytes >= workspace_bytes; the workspace stays the caller's and must
+ * outlive every later call on this plan) and resets the cross-slice cache
+ * (Sec. III-B) and, for FP16/BF16 plans, the calibration.  Synchronises
+ * the stream.  Errors: INVALID_ARG (null), WORKSPACE_TOO_SMALL, HIP_ERROR. */
 int32_t mitnc_plan_upload(mitnc_plan* plan, void* ws, size_t ws_bytes, void* stream);
 
 /* Contracts slices slice_begin .. slice_end-1 in order and ADDS their sum to
  * result_accum (device, complex128 interleaved, result_elems entries; FP64
- * cross-slice sum, Sec. VI: the single reduction of the method).  Must
- * follow mitnc_plan_upload on the same workspace (and, for FP16/BF16 plans,
- * mitnc_calibrate).  Errors: INVALID_ARG for an empty or out-of-range slice
- * range or an uncalibrated FP16/BF16 plan, WORKSPACE_TOO_SMALL, HIP_ERROR. */
+ * cross-slice sum, Sec. VI: the single reduction of the method; slices are
+ * independent subtasks, Sec. III-A, and a node is recomputed only when a
+ * sliced index below it changes, Sec. III-B).  Must follow
+ * mitnc_plan_upload on the same workspace (and, for FP16/BF16 plans,
+ * mitnc_calibrate).  Complex64 plans: asynchronous on `stream`.
+ * FP16/BF16 plans (value = mantissa * 2^e per tensor): the slices are
+ * summed in a workspace buffer first; the call then synchronises the stream
+ * and checks every stored step's largest |Re|, |Im|: a non-finite value, a
+ * value >= 65504 with FP16 storage, or a largest value outside
+ * [2^9, 2^18) (more than 2^4 away from the target [2^13, 2^14)) is an
+ * overflow or exponent miss.  On a miss the exponents are re-derived from
+ * complex64 maxima over this slice range (as mitnc_calibrate) and the range
+ * runs once more; only a clean run is added to result_accum.  Errors:
+ * INVALID_ARG for an empty or out-of-range slice range or an uncalibrated
+ * FP16/BF16 plan, WORKSPACE_TOO_SMALL, HIP_ERROR, NUMERIC when the re-run
+ * misses again or the plan was created with no_rerun (result_accum is then
+ * unchanged). */
 int32_t mitnc_execute(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t slice_begin,
                       uint64_t slice_end, double* result_accum, void* stream);
 
-/* FP16/BF16 plans: chooses every tensor's power-of-two exponent.  Runs
- * slices slice_begin .. slice_end-1 in complex64 inside the workspace,
- * records each step's largest |Re|, |Im| and sets the exponent so that this
- * maximum maps into [2^13, 2^14) (two bits of headroom below the FP16
- * maximum); slices are statistically alike, so one or a few slices suffice.
- * Synchronises the stream.  No effect on complex64 plans. */
+/* FP16/BF16 plans (not in the paper; the precision form): chooses every
+ * stored tensor's power-of-two exponent.  Runs slices slice_begin ..
+ * slice_end-1 in complex64 inside the workspace, records each step's
+ * largest |Re|, |Im| and sets the exponent so that this maximum maps into
+ * [2^13, 2^14) (two bits of headroom below the FP16 maximum); a step that
+ * was all zero gets the worst-case exponent e_A + e_B + 14 + (contracted
+ * bits).  Slices are statistically alike, so one or a few slices suffice;
+ * mitnc_execute corrects a miss.  Synchronises the stream.  No effect on
+ * complex64 plans.  Errors: INVALID_ARG (range), WORKSPACE_TOO_SMALL,
+ * HIP_ERROR. */
 int32_t mitnc_calibrate(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t slice_begin,
                         uint64_t slice_end, void* stream);
 
-/* FP16/BF16 plans record, per step, the largest stored |Re|, |Im| (after
- * scaling; +inf for a non-finite value) over all executed slices.  Copies
- * n_steps floats to host memory `out` (synchronises the stream) and clears
- * them if reset != 0.  A value >= 65504 means FP16 overflow. */
+/* FP16/BF16 plans: per step, the largest stored |Re|, |Im| (after scaling,
+ * before rounding to 16 bits; +inf for a non-finite value) of the last
+ * mitnc_execute call (of its final run).  Copies n_steps floats to host
+ * memory `out` (synchronises the stream) and clears them if reset != 0.
+ * Errors: INVALID_ARG, WORKSPACE_TOO_SMALL, HIP_ERROR. */
 int32_t mitnc_step_maxima(mitnc_plan* plan, void* ws, size_t ws_bytes, float* out, int32_t reset,
                           void* stream);
 
-/* Differentiation form (not in the paper; see the oracle's definition):
- * for slices slice_begin .. slice_end-1, recomputes the forward contraction
- * of the slice (nodes whose sliced indices did not change are reused) and
- * runs the reverse pass: for every step C = A (x) B with a single-qubit gate
- * leaf below, adj(A) = adj(C) contracted with B onto A's indices (and the same
- * for B), subtrees without such leaves pruned.  The adjoint contractions run
- * level by level of the reverse tree (mitnc_plan_reverse_info); the SMALL
- * ones of a level share one launch.  Adds the holomorphic VJP
+/* FP16/BF16 plans: per-node exponents (node ids as in mitnc_plan_node_info:
+ * leaves, then step outputs; value = stored mantissa * 2^exp) and the
+ * number of exponent re-runs mitnc_execute has made.  exps_out (n_leaves +
+ * n_steps int32, may be NULL) receives the current exponents; exps_in (may
+ * be NULL) replaces those of the step outputs (leaf entries are ignored,
+ * their mantissas were fixed at plan creation) and the scale factors of the
+ * steps follow.  A testing and inspection aid: a wrong exponent is caught
+ * and corrected by mitnc_execute.  Host only.  Errors: INVALID_ARG. */
+int32_t mitnc_plan_exponents(mitnc_plan* plan, int32_t* exps_out, const int32_t* exps_in, int32_t* reruns_out);
+
+/* Differentiation form (not in the paper; the problem is: loss
+ * L = sum_b log|a_b|^2 over a batch of amplitudes, gradients with respect to
+ * every single-qubit gate instance, each an independent complex 2x2
+ * parameter).  This call computes the holomorphic vector-Jacobian product
  *   grad[g][i][j] += sum_r w[r] * d result[r] / d U_g[i][j]
- * to grad_accum (device complex128, n_grad_gates x 4 entries, U[out][in]
- * row-major, gates in circuit order of the single-qubit gates).  w: device
- * complex128, result_elems entries in result order; no conjugation is
- * applied.  Needs a plan created with differentiable = 1 and uploaded. */
+ * summed over slices slice_begin .. slice_end-1, where result[r] is the
+ * (partial) amplitude sum mitnc_execute would give for those slices and
+ * U_g[i][j] (U[out][in]) enters linearly; no conjugation is applied (for L,
+ * w = 1 / a, and dL/dRe U + i dL/dIm U = 2 conj(grad)).  Method, per slice:
+ * recompute the forward contraction (nodes whose sliced indices did not
+ * change are reused, Sec. III-B), seed the root's adjoint with w, and for
+ * every step C = A (x) B with a single-qubit gate leaf below, adj(A) +=
+ * adj(C) contracted with B onto A's indices (the same kind of pairwise
+ * contraction, batch indices kept; likewise for B); subtrees without such
+ * leaves are pruned.  The adjoint contractions run level by level of the
+ * reverse tree (mitnc_plan_reverse_info); the SMALL ones of a level share
+ * one launch.  A sliced gate leaf's adjoint goes to the entries of its
+ * sliced values.  grad_accum: device complex128, n_grad_gates x 4 entries,
+ * gates in circuit order of the single-qubit gates.  w: device complex128,
+ * result_elems entries in result order.  Needs a plan created with
+ * differentiable = 1 and uploaded.  Asynchronous on `stream`.  Errors:
+ * INVALID_ARG (not differentiable, range, null), WORKSPACE_TOO_SMALL,
+ * HIP_ERROR. */
 int32_t mitnc_backward(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t slice_begin,
                        uint64_t slice_end, const double* w, double* grad_accum, void* stream);
 
-/* Replaces the matrices of all single-qubit gates of an uploaded plan
- * (host complex128, n_grad_gates x 4 entries U[out][in], circuit order) and
- * re-uploads those leaves; the cross-slice cache restarts at the next
- * execute.  Complex64 plans only. */
+/* Differentiation form: replaces the matrices of all single-qubit gates of
+ * an uploaded plan (the parameters of mitnc_backward; host complex128,
+ * n_grad_gates x 4 entries U[out][in], circuit order) and re-uploads those
+ * leaves (a sliced leaf keeps every value of its sliced indices); the
+ * cross-slice cache restarts at the next execute.  Complex64 plans only.
+ * Synchronises the stream.  Errors: INVALID_ARG (null, not uploaded,
+ * precision), HIP_ERROR. */
 int32_t mitnc_plan_set_gates(mitnc_plan* plan, void* ws, size_t ws_bytes, const double* mats,
                              void* stream);
 
 /* Single pairwise contraction on the GPU (the TTGT step of Sec. II-A /
- * Sec. V with the permutation fused into the loads).  A, B, C: device
+ * Sec. V with the permutation fused into the loads; split-K for long
+ * common indices, Sec. V-B).  A, B, C: device
  * tensors of 2^ra, 2^rb, 2^rc complex entries (precision MITNC_C64:
  * interleaved float; MITNC_CF16 / MITNC_CBF16: interleaved 16-bit halves)
  * whose address bit i carries label la[i] / lb[i] / lc[i].  Labels shared by
@@ -311,7 +403,8 @@ int32_t mitnc_contract(const void* A, int32_t ra, const int64_t* la, const void*
                        float out_scale, int32_t kernel, void* work, size_t work_bytes,
                        size_t* work_bytes_needed, void* stream);
 
-/* Launch timing for measurement.  mitnc_plan_timing(plan, 1) starts
+/* Launch timing for measurement (the per-kernel figures of the paper's
+ * performance analysis, Sec. VII).  mitnc_plan_timing(plan, 1) starts
  * recording a hipEvent pair around the main kernel of every step launched by
  * mitnc_execute (events are created on first use and reused after a reset);
  * calling it again (enable 0 or 1) discards the recorded pairs.
@@ -323,8 +416,12 @@ int32_t mitnc_plan_timing(mitnc_plan* plan, int32_t enable);
 int32_t mitnc_plan_timing_read(mitnc_plan* plan, double* ms, double* launches, double* flops,
                                double* bytes);
 
+/* Frees a plan or network (host memory only; NULL is ignored).  A plan does
+ * not reference its network after mitnc_plan_create. */
 void mitnc_plan_destroy(mitnc_plan* plan);
 void mitnc_network_destroy(mitnc_network* net);
+/* Message of the last failing call on this thread ("" if none); valid until
+ * the next failing call on the same thread. */
 const char* mitnc_last_error(void);
 
 /* Kernel class ids (mitnc_plan_stats.steps_by_class index, force_kernel). */

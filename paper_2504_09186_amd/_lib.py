@@ -32,13 +32,15 @@ class mitnc_gate(C.Structure):
 
 class mitnc_search_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("trials", C.c_int32), ("max_log2_elems", C.c_int32),
-                ("min_sliced", C.c_int32), ("max_sliced", C.c_int32), ("keep_slicing", C.c_int32)]
+                ("min_sliced", C.c_int32), ("max_sliced", C.c_int32), ("keep_slicing", C.c_int32),
+                ("method", C.c_int32)]
 
 
 class mitnc_plan_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("reuse", C.c_int32),
                 ("cache_budget_bytes", C.c_uint64), ("force_kernel", C.c_int32),
-                ("differentiable", C.c_int32), ("fuse_sections", C.c_int32)]
+                ("differentiable", C.c_int32), ("fuse_sections", C.c_int32), ("no_rerun", C.c_int32),
+                ("splitk_max_mn_bits", C.c_int32), ("splitk_target_bits", C.c_int32)]
 
 
 class mitnc_plan_stats(C.Structure):
@@ -77,7 +79,7 @@ _SIGS = {
     "mitnc_set_path": [_VP, _I32, C.POINTER(_I32)],
     "mitnc_get_slicing": [_VP, C.POINTER(_I32), C.POINTER(C.c_int64)],
     "mitnc_set_slicing": [_VP, _I32, C.POINTER(C.c_int64)],
-    "mitnc_slice_greedy": [_VP, _I32, _I32, _I32],
+    "mitnc_slice_greedy": [_VP, _I32, _I32, _I32, C.POINTER(_I32), C.POINTER(C.c_int64)],
     "mitnc_index_overhead": [_VP, C.c_int64, C.POINTER(C.c_double)],
     "mitnc_plan_create": [_VP, C.POINTER(mitnc_plan_opts), C.POINTER(_VP)],
     "mitnc_plan_query": [_VP, C.POINTER(mitnc_plan_stats)],
@@ -93,6 +95,7 @@ _SIGS = {
                                C.POINTER(C.c_double)],
     "mitnc_calibrate": [_VP, _VP, C.c_size_t, C.c_uint64, C.c_uint64, _VP],
     "mitnc_step_maxima": [_VP, _VP, C.c_size_t, C.POINTER(C.c_float), _I32, _VP],
+    "mitnc_plan_exponents": [_VP, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32)],
     "mitnc_backward": [_VP, _VP, C.c_size_t, C.c_uint64, C.c_uint64, _VP, _VP, _VP],
     "mitnc_plan_set_gates": [_VP, _VP, C.c_size_t, C.POINTER(C.c_double), _VP],
     "mitnc_contract": [_VP, _I32, C.POINTER(C.c_int64), _VP, _I32, C.POINTER(C.c_int64), _VP, _I32,

@@ -175,14 +175,32 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
     double best = -1;
     Path best_path;
     std::vector<int> best_sl;
-    for (int t = 0; t < trials; ++t) {
-      double a = t == 0 ? 1.0 : alphas[rng() % 4];
-      double tau = t == 0 ? 0.0 : temps[rng() % 4];
-      Path p = greedy_path(sn, a, tau, rng(), o->keep_slicing ? &fixed : nullptr);
+    const int method = o->method;
+    if (method < 0 || method > 2) fail(MITNC_INVALID_ARG, "unknown search method");
+    const double imbs[] = {0.05, 0.1, 0.2, 0.3, 0.5};
+    const int cutoffs[] = {4, 6, 8, 10, 12};
+    const double exts[] = {0.0, 0.25, 0.5, 1.0};
+    std::vector<char> none(sn.n_labels, 0);
+    const std::vector<char>& rm = o->keep_slicing ? fixed : none;
+    const int n_runs = method == 2 ? 2 * trials : trials;
+    for (int r = 0; r < n_runs; ++r) {
+      const bool bisect = method == 1 || (method == 2 && r >= trials);
+      const int t = method == 2 ? r % trials : r;
+      Path p;
+      if (bisect) {
+        PartitionParams prm;
+        prm.imbalance = imbs[rng() % 5];
+        prm.cutoff = cutoffs[rng() % 5];
+        prm.ext_weight = exts[rng() % 4];
+        prm.starts = 4;
+        p = partition_path(sn, rm, prm, rng());
+      } else {
+        double a = t == 0 ? 1.0 : alphas[rng() % 4];
+        double tau = t == 0 ? 0.0 : temps[rng() % 4];
+        p = greedy_path(sn, a, tau, rng(), o->keep_slicing ? &fixed : nullptr);
+      }
       {
         // local refinement before slicing: no intermediate may grow
-        std::vector<char> none(sn.n_labels, 0);
-        const std::vector<char>& rm = o->keep_slicing ? fixed : none;
         const int width = sym_max_bits(sn, sym_run(sn, p, rm), rm);
         p = optimize_path(sn, p, &rm, width, 4);
       }
@@ -278,16 +296,21 @@ int32_t mitnc_set_slicing(mitnc_network* net, int32_t n, const int64_t* ids) {
   });
 }
 
-int32_t mitnc_slice_greedy(mitnc_network* net, int32_t max_log2_elems, int32_t min_sliced, int32_t max_sliced) {
+int32_t mitnc_slice_greedy(mitnc_network* net, int32_t max_log2_elems, int32_t min_sliced, int32_t max_sliced,
+                           int32_t* n_out, int64_t* ids_out) {
   return guarded([&] {
     if (!net) fail(MITNC_INVALID_ARG, "null network");
     if (net->path.empty()) fail(MITNC_PATH_INVALID, "no path");
+    if (max_sliced > 64) fail(MITNC_INVALID_ARG, "at most 64 sliced indices");
     SymNet sn = make_symnet(net->leaves, net->output_lsb);
     bool ok;
     auto sl = greedy_slices(sn, net->path, max_log2_elems, min_sliced, max_sliced, &ok);
     if (!ok) fail(MITNC_UNSUPPORTED, "cap not met within max_sliced");
     net->sliced.clear();
     for (int x : order_slices(sn, net->path, sl)) net->sliced.push_back(sn.label_id[x]);
+    if (n_out) *n_out = (int32_t)net->sliced.size();
+    if (ids_out)
+      for (size_t i = 0; i < net->sliced.size(); ++i) ids_out[i] = net->sliced[i];
   });
 }
 
@@ -644,6 +667,60 @@ static void check_ws(mitnc_plan* P, void* ws, size_t ws_bytes) {
   if (ws_bytes < P->ws_bytes) fail(MITNC_WORKSPACE_TOO_SMALL, "workspace too small");
 }
 
+// Exponents of an FP16/BF16 plan from complex64 maxima: runs slices s0 .. s1-1
+// in complex64 (result into the calibration buffer), records each step's
+// largest |Re|, |Im| and derives every tensor's exponent in path order;
+// leaves the per-step maxima cleared.
+static void calibrate_range(mitnc_plan* P, char* base, uint64_t s0, uint64_t s1, hipStream_t s) {
+  const size_t nst = P->steps.size();
+  hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * nst, s), "stats reset");
+  hip_check(hipMemsetAsync(base + P->off_calib, 0, 16 * P->result_elems, s), "calibration result reset");
+  run_slices(P, base, s0, s1, (double*)(base + P->off_calib), s, MITNC_C64, true);
+  std::vector<float> mx(nst);
+  hip_check(hipMemcpyAsync(mx.data(), base + P->off_stats, 4 * nst, hipMemcpyDeviceToHost, s), "stats read");
+  hip_check(hipStreamSynchronize(s), "calibration sync");
+  // Exponents in path order: stored C = true C * 2^-eC, and the kernel
+  // result is (true A B) * 2^-(eA + eB).
+  for (size_t i = 0; i < nst; ++i) {
+    PlanStep& st = P->steps[i];
+    const int ea = P->nodes[st.a].exp, eb = P->nodes[st.b].exp;
+    if (st.root) {
+      st.d.acc_scale = std::ldexp(1.0, ea + eb);
+      st.d.out_scale = 1.f;
+      continue;
+    }
+    // A step that was all zero in the calibration slices gets the exponent
+    // of the worst case: |mantissa products| <= 2^14 * 2^14 per term, 2^kb
+    // terms, so 2^(ea + eb + 14 + kb) keeps any later value below 2^14.
+    const int ec = mx[i] > 0 ? mantissa_exponent((double)mx[i]) : ea + eb + 14 + st.d.kb;
+    P->nodes[st.out].exp = ec;
+    st.d.out_scale = (float)std::ldexp(1.0, ea + eb - ec);
+    st.d.acc_scale = 1.0;
+  }
+  hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * nst, s), "stats reset");
+  P->calibrated = true;
+}
+
+// Checks the per-step maxima of the stored mantissas of one FP16/BF16 run:
+// a value that is not finite or reaches the FP16 maximum (FP16 storage)
+// overflowed; a largest value more than 2^4 away from the target range
+// [2^13, 2^14) (below 2^9 or at or above 2^18) is an exponent miss.  Steps
+// whose stored values were all zero carry no information and pass.
+static bool maxima_ok(const mitnc_plan* P, const std::vector<float>& mx, int prec, std::string* why) {
+  for (size_t i = 0; i < P->steps.size(); ++i) {
+    if (P->steps[i].root) continue;
+    const float m = mx[i];
+    const bool over = !std::isfinite(m) || (prec == MITNC_CF16 && m >= 65504.f);
+    const bool miss = m > 0.f && (m < 512.f || m >= 262144.f);
+    if (over || miss) {
+      if (why) *why = "step " + std::to_string(i) + (over ? ": overflow" : ": exponent miss") + " (largest stored " +
+                      std::to_string(m) + ")";
+      return false;
+    }
+  }
+  return true;
+}
+
 int32_t mitnc_execute(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, uint64_t s1, double* acc,
                       void* stream) {
   return guarded([&] {
@@ -652,8 +729,61 @@ int32_t mitnc_execute(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, uin
     if (!P->calibrated) fail(MITNC_INVALID_ARG, "FP16/BF16 plan: call mitnc_calibrate first");
     uint64_t n_slices = 1ull << P->S;
     if (s0 >= s1 || s1 > n_slices) fail(MITNC_INVALID_ARG, "slice range out of bounds");
-    const bool half = P->opts.precision != MITNC_C64;
-    run_slices(P, (char*)ws, s0, s1, acc, (hipStream_t)stream, P->opts.precision, half);
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    const int prec = P->opts.precision;
+    if (prec == MITNC_C64) {
+      run_slices(P, base, s0, s1, acc, s, prec, false);
+      return;
+    }
+    // Precision form: the slices are summed into the calibration buffer and
+    // added to the caller's result only once the stored maxima show no
+    // overflow and no exponent miss; otherwise the exponents are re-derived
+    // from complex64 maxima over this very slice range and the range runs
+    // again (at most once; then MITNC_NUMERIC).
+    const size_t nst = P->steps.size();
+    double* stage = (double*)(base + P->off_calib);
+    std::vector<float> mx(nst);
+    std::string why;
+    for (int attempt = 0;; ++attempt) {
+      hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * nst, s), "stats reset");
+      hip_check(hipMemsetAsync(stage, 0, 16 * P->result_elems, s), "staging reset");
+      run_slices(P, base, s0, s1, stage, s, prec, true);
+      hip_check(hipMemcpyAsync(mx.data(), base + P->off_stats, 4 * nst, hipMemcpyDeviceToHost, s), "stats read");
+      hip_check(hipStreamSynchronize(s), "exponent check sync");
+      if (maxima_ok(P, mx, prec, &why)) break;
+      P->reruns++;
+      if (attempt == 1 || P->opts.no_rerun)
+        fail(MITNC_NUMERIC, "FP16/BF16 exponents: " + why + (P->opts.no_rerun ? " (re-run disabled)" : " after a re-run"));
+      calibrate_range(P, base, s0, s1, s);
+    }
+    hip_check(launch_accumulate(acc, stage, P->result_elems, s), "result accumulate");
+  });
+}
+
+int32_t mitnc_plan_exponents(mitnc_plan* P, int32_t* exps_out, const int32_t* exps_in, int32_t* reruns_out) {
+  return guarded([&] {
+    if (!P) fail(MITNC_INVALID_ARG, "null plan");
+    if (exps_out)
+      for (size_t i = 0; i < P->nodes.size(); ++i) exps_out[i] = P->nodes[i].exp;
+    if (reruns_out) *reruns_out = P->reruns;
+    if (!exps_in) return;
+    if (P->opts.precision == MITNC_C64) fail(MITNC_INVALID_ARG, "complex64 plans have no exponents");
+    for (size_t i = 0; i < P->steps.size(); ++i) {
+      PlanStep& st = P->steps[i];
+      if (!st.root) P->nodes[st.out].exp = exps_in[st.out];
+    }
+    for (size_t i = 0; i < P->steps.size(); ++i) {
+      PlanStep& st = P->steps[i];
+      const int ea = P->nodes[st.a].exp, eb = P->nodes[st.b].exp;
+      if (st.root) {
+        st.d.acc_scale = std::ldexp(1.0, ea + eb);
+        st.d.out_scale = 1.f;
+      } else {
+        st.d.out_scale = (float)std::ldexp(1.0, ea + eb - P->nodes[st.out].exp);
+        st.d.acc_scale = 1.0;
+      }
+    }
   });
 }
 
@@ -663,32 +793,7 @@ int32_t mitnc_calibrate(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, u
     if (P->opts.precision == MITNC_C64) return;  // nothing to calibrate
     uint64_t n_slices = 1ull << P->S;
     if (s0 >= s1 || s1 > n_slices) fail(MITNC_INVALID_ARG, "slice range out of bounds");
-    hipStream_t s = (hipStream_t)stream;
-    char* base = (char*)ws;
-    const size_t nst = P->steps.size();
-    hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * nst, s), "stats reset");
-    hip_check(hipMemsetAsync(base + P->off_calib, 0, 16 * P->result_elems, s), "calibration result reset");
-    run_slices(P, base, s0, s1, (double*)(base + P->off_calib), s, MITNC_C64, true);
-    std::vector<float> mx(nst);
-    hip_check(hipMemcpyAsync(mx.data(), base + P->off_stats, 4 * nst, hipMemcpyDeviceToHost, s), "stats read");
-    hip_check(hipStreamSynchronize(s), "calibration sync");
-    // Exponents in path order: stored C = true C * 2^-eC, and the kernel
-    // result is (true A B) * 2^-(eA + eB).
-    for (size_t i = 0; i < nst; ++i) {
-      PlanStep& st = P->steps[i];
-      const int ea = P->nodes[st.a].exp, eb = P->nodes[st.b].exp;
-      if (st.root) {
-        st.d.acc_scale = std::ldexp(1.0, ea + eb);
-        st.d.out_scale = 1.f;
-        continue;
-      }
-      const int ec = mx[i] > 0 ? mantissa_exponent((double)mx[i]) : ea + eb;
-      P->nodes[st.out].exp = ec;
-      st.d.out_scale = (float)std::ldexp(1.0, ea + eb - ec);
-      st.d.acc_scale = 1.0;
-    }
-    hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * nst, s), "stats reset");
-    P->calibrated = true;
+    calibrate_range(P, (char*)ws, s0, s1, (hipStream_t)stream);
   });
 }
 
@@ -788,58 +893,71 @@ int32_t mitnc_plan_set_gates(mitnc_plan* P, void* ws, size_t ws_bytes, const dou
   });
 }
 
+}  // extern "C"
+
+// One pairwise contraction (mitnc_contract).
+static void contract_impl(const void* A, int32_t ra, const int64_t* la, const void* B, int32_t rb,
+                          const int64_t* lb, void* C, int32_t rc, const int64_t* lc, int32_t precision,
+                          float out_scale, int32_t kernel, void* work, size_t work_bytes, size_t* work_bytes_needed,
+                          void* stream) {
+  if (ra < 0 || rb < 0 || rc < 0 || ra > 32 || rb > 32 || rc > 32) fail(MITNC_INVALID_ARG, "bad rank");
+  if ((ra && !la) || (rb && !lb) || (rc && !lc)) fail(MITNC_INVALID_ARG, "null labels");
+  if (precision != MITNC_C64 && precision != MITNC_CF16 && precision != MITNC_CBF16)
+    fail(MITNC_INVALID_ARG, "unknown precision");
+  // Reuse the plan step builder on a two-leaf pseudo-plan.
+  mitnc_plan P;
+  P.nodes.resize(3);
+  auto setn = [](PlanNode& nd, int r, const int64_t* l) {
+    for (int i = 0; i < r; ++i) {
+      nd.labels.push_back(l[i]);
+      nd.pos.push_back(i);
+    }
+    nd.rank = r;
+  };
+  setn(P.nodes[0], ra, la);
+  setn(P.nodes[1], rb, lb);
+  std::map<int64_t, int> cnt;
+  for (int i = 0; i < ra; ++i) cnt[la[i]] |= 1;
+  for (int i = 0; i < rb; ++i) cnt[lb[i]] |= 2;
+  std::vector<int64_t> cl(lc, lc + rc);
+  for (auto x : cl)
+    if (!cnt.count(x)) fail(MITNC_INVALID_ARG, "output label not in any operand");
+  for (size_t i = 0; i < cl.size(); ++i)
+    for (size_t j = i + 1; j < cl.size(); ++j)
+      if (cl[i] == cl[j]) fail(MITNC_INVALID_ARG, "duplicate output label");
+  PlanStep st;
+  st.a = 0;
+  st.b = 1;
+  st.out = 2;
+  st.root = false;
+  build_step_for(&P, st, cl, &cl, kernel, precision);
+  if (work_bytes_needed) *work_bytes_needed = st.part_bytes;
+  if (!A && !B && !C) return;  // size query
+  if (!A || !B || !C) fail(MITNC_INVALID_ARG, "null tensor");
+  if (st.part_bytes > 0 && (!work || work_bytes < st.part_bytes))
+    fail(MITNC_WORKSPACE_TOO_SMALL, "split-K work buffer too small");
+  StepDesc d = st.d;
+  d.A = st.swapped ? B : A;
+  d.B = st.swapped ? A : B;
+  d.C = C;
+  d.acc = nullptr;
+  d.part = (float*)work;
+  d.stats = nullptr;
+  d.mode = EPI_STORE;
+  d.prec = precision;
+  d.out_scale = out_scale;
+  d.acc_scale = 1.0;
+  hip_check(launch_step(st.kclass, d, (hipStream_t)stream), "kernel launch");
+}
+
+extern "C" {
+
 int32_t mitnc_contract(const void* A, int32_t ra, const int64_t* la, const void* B, int32_t rb, const int64_t* lb,
                        void* C, int32_t rc, const int64_t* lc, int32_t precision, float out_scale, int32_t kernel,
                        void* work, size_t work_bytes, size_t* work_bytes_needed, void* stream) {
   return guarded([&] {
-    if (ra < 0 || rb < 0 || rc < 0 || ra > 32 || rb > 32 || rc > 32) fail(MITNC_INVALID_ARG, "bad rank");
-    if ((ra && !la) || (rb && !lb) || (rc && !lc)) fail(MITNC_INVALID_ARG, "null labels");
-    if (precision != MITNC_C64 && precision != MITNC_CF16 && precision != MITNC_CBF16)
-      fail(MITNC_INVALID_ARG, "unknown precision");
-    // Reuse the plan step builder on a two-leaf pseudo-plan.
-    mitnc_plan P;
-    P.nodes.resize(3);
-    auto setn = [](PlanNode& nd, int r, const int64_t* l) {
-      for (int i = 0; i < r; ++i) {
-        nd.labels.push_back(l[i]);
-        nd.pos.push_back(i);
-      }
-      nd.rank = r;
-    };
-    setn(P.nodes[0], ra, la);
-    setn(P.nodes[1], rb, lb);
-    std::map<int64_t, int> cnt;
-    for (int i = 0; i < ra; ++i) cnt[la[i]] |= 1;
-    for (int i = 0; i < rb; ++i) cnt[lb[i]] |= 2;
-    std::vector<int64_t> cl(lc, lc + rc);
-    for (auto x : cl)
-      if (!cnt.count(x)) fail(MITNC_INVALID_ARG, "output label not in any operand");
-    for (size_t i = 0; i < cl.size(); ++i)
-      for (size_t j = i + 1; j < cl.size(); ++j)
-        if (cl[i] == cl[j]) fail(MITNC_INVALID_ARG, "duplicate output label");
-    PlanStep st;
-    st.a = 0;
-    st.b = 1;
-    st.out = 2;
-    st.root = false;
-    build_step_for(&P, st, cl, &cl, kernel, precision);
-    if (work_bytes_needed) *work_bytes_needed = st.part_bytes;
-    if (!A && !B && !C) return;  // size query
-    if (!A || !B || !C) fail(MITNC_INVALID_ARG, "null tensor");
-    if (st.part_bytes > 0 && (!work || work_bytes < st.part_bytes))
-      fail(MITNC_WORKSPACE_TOO_SMALL, "split-K work buffer too small");
-    StepDesc d = st.d;
-    d.A = st.swapped ? B : A;
-    d.B = st.swapped ? A : B;
-    d.C = C;
-    d.acc = nullptr;
-    d.part = (float*)work;
-    d.stats = nullptr;
-    d.mode = EPI_STORE;
-    d.prec = precision;
-    d.out_scale = out_scale;
-    d.acc_scale = 1.0;
-    hip_check(launch_step(st.kclass, d, (hipStream_t)stream), "kernel launch");
+    contract_impl(A, ra, la, B, rb, lb, C, rc, lc, precision, out_scale, kernel, work, work_bytes,
+                  work_bytes_needed, stream);
   });
 }
 

@@ -69,6 +69,14 @@ std::vector<int> order_slices(const SymNet& sn, const Path& path, const std::vec
 // kept at most 2^cap_bits entries.
 Path optimize_path(const SymNet& sn, const Path& path, const std::vector<char>* removed, int cap_bits, int passes);
 void validate_path(int n_leaves, const Path& path);
+// Recursive-bisection path search (partition.cpp).
+struct PartitionParams {
+  double imbalance = 0.1;   // part sizes within (1 +- imbalance) / 2 of the tensors split
+  int cutoff = 8;           // parts of at most this many tensors are contracted greedily
+  int starts = 4;           // initial cuts refined per bisection
+  double ext_weight = 0.5;  // weight of cut indices also held outside the part
+};
+Path partition_path(const SymNet& sn, const std::vector<char>& removed, const PartitionParams& prm, uint64_t seed);
 
 }  // namespace mitnc
 

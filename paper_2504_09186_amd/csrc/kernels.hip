@@ -1702,6 +1702,26 @@ __global__ __launch_bounds__(256) void k_grad(const GradEntry* tab, int n_entrie
   }
 }
 
+// acc[i] += src[i] (complex128): adds a verified partial sum of slices into
+// the caller's result.
+__global__ __launch_bounds__(256) void k_accumulate(double2* acc, const double2* src, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    double2 o = acc[i];
+    const double2 v = src[i];
+    o.x += v.x;
+    o.y += v.y;
+    acc[i] = o;
+  }
+}
+
+hipError_t launch_accumulate(double* acc, const double* src, uint64_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<double2*>(acc), reinterpret_cast<const double2*>(src), n);
+  return hipGetLastError();
+}
+
 hipError_t launch_seed(const double* w, float* adj, uint64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_seed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                      reinterpret_cast<const double2*>(w), reinterpret_cast<float2*>(adj), n);

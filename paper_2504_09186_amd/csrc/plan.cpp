@@ -73,20 +73,27 @@ int mantissa_exponent(double max_abs) {
   return (e2 - 1) - 13;
 }
 
-static int choose_class_no_stream(int mb, int nb, int kb, int bb) {
+// Split-K takes steps whose m and n bit counts are both at most `smn`
+// (plan option; 4 by default: M, N <= 16, Sec. V-B's narrow GEPDOTs).
+static int splitk_mn_bits(const mitnc_plan* P) {
+  const int v = P->opts.splitk_max_mn_bits;
+  return v > 0 ? std::min(v, 8) : 4;
+}
+
+static int choose_class_no_stream(int mb, int nb, int kb, int bb, int smn) {
   if (mb + nb + bb <= 10 && kb <= 6) return MITNC_K_SMALL;
   if (nb <= 2 && kb <= 4) return MITNC_K_STEM;
-  if (mb <= 4 && nb <= 4) return MITNC_K_SPLITK;
+  if (mb <= smn && nb <= smn) return MITNC_K_SPLITK;
   if (nb <= 4) return MITNC_K_TALL;
   return MITNC_K_TILE;
 }
 
-static int choose_class(int mb, int nb, int kb, int bb) {
+static int choose_class(int mb, int nb, int kb, int bb, int smn) {
   int out_bits = mb + nb + bb;
   if (out_bits <= 10 && kb <= 6) return MITNC_K_SMALL;
   if (stream_fits(mb, nb, kb, bb)) return MITNC_K_STREAM;
   if (nb <= 2 && kb <= 4) return MITNC_K_STEM;
-  if (mb <= 4 && nb <= 4) return MITNC_K_SPLITK;
+  if (mb <= smn && nb <= smn) return MITNC_K_SPLITK;
   if (nb <= 4) return MITNC_K_TALL;
   return MITNC_K_TILE;
 }
@@ -135,9 +142,9 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   std::sort(N.begin(), N.end(), by(pb));
   std::sort(Bt.begin(), Bt.end(), by(pa));
   int kclass = force_kernel >= 0 ? force_kernel
-                                 : choose_class((int)M.size(), (int)N.size(), (int)K.size(), (int)Bt.size());
+                                 : choose_class((int)M.size(), (int)N.size(), (int)K.size(), (int)Bt.size(), splitk_mn_bits(P));
   if (force_kernel < 0 && kclass == MITNC_K_STREAM && root_layout && !rows_in_order(M, *root_layout))
-    kclass = choose_class_no_stream((int)M.size(), (int)N.size(), (int)K.size(), (int)Bt.size());
+    kclass = choose_class_no_stream((int)M.size(), (int)N.size(), (int)K.size(), (int)Bt.size(), splitk_mn_bits(P));
   if (kclass == MITNC_K_STREAM) {
     // Stream kernel: the two lowest k bits ride on lanes next to the four
     // lowest m bits, so K goes by A position (B is small and cached).
@@ -214,7 +221,8 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
   // the FP64 result, the largest entry an output may get).
   const uint64_t stream_a_bytes = precision == MITNC_C64 ? 8 : 4;
   if (st.kclass == MITNC_K_STREAM && force_kernel < 0 && !stream_offsets_fit(d, stream_a_bytes, 16))
-    return build_step(P, st, c_labels_set, root_layout, choose_class_no_stream(d.mb, d.nb, d.kb, d.bb), precision);
+    return build_step(P, st, c_labels_set, root_layout, choose_class_no_stream(d.mb, d.nb, d.kb, d.bb, splitk_mn_bits(P)),
+                      precision);
   if (st.kclass == MITNC_K_STREAM &&
       (!stream_fits(d.mb, d.nb, d.kb, d.bb) || !stream_rows_sorted(d) || !stream_offsets_fit(d, stream_a_bytes, 16)))
     fail(MITNC_UNSUPPORTED,
@@ -250,7 +258,10 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     // wave per split, 2^12 waves.
     const bool skinny = st.kclass == MITNC_K_SPLITK && precision == MITNC_C64 && d.mb + d.nb <= 4 &&
                         d.kb >= kSkinnyLaneBits + 2 && d.bb <= 16;
-    int target_bits = st.kclass == MITNC_K_TILE ? 8 : skinny ? 12 : 11;
+    int target_bits = P->opts.splitk_target_bits > 0 ? std::min(P->opts.splitk_target_bits, 16)
+                      : st.kclass == MITNC_K_TILE                 ? 8
+                      : skinny                                    ? 12
+                                                                  : 11;
     int ks = 0;
     while (tiles_bits + ks < target_bits && ks + 2 < khigh) ++ks;
     uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);

@@ -83,6 +83,7 @@ struct mitnc_plan {
   uint64_t off_leaf_half = 0, off_persist = 0, off_arena = 0, off_part = 0, off_stats = 0, off_calib = 0;
   uint64_t ws_bytes = 0;
   bool calibrated = false;
+  int32_t reruns = 0;  // FP16/BF16 executes that re-ran after an exponent miss
   // Differentiation form (opts.differentiable): every node keeps its own
   // buffer, adjoints live in [off_adj, off_adj + adj_bytes).
   std::vector<char> has_grad;          // per node: a single-qubit gate leaf below

@@ -61,8 +61,9 @@ class Network:
             self.h = None
 
     def path_search(self, seed: int = 0, trials: int = 32, max_log2: int = 30, min_sliced: int = 0,
-                    max_sliced: int = 40, keep_slicing: bool = False) -> None:
-        o = mitnc_search_opts(seed, trials, max_log2, min_sliced, max_sliced, 1 if keep_slicing else 0)
+                    max_sliced: int = 40, keep_slicing: bool = False, method: int = 0) -> None:
+        """Path and slicing search (method 0 greedy, 1 recursive bisection, 2 both)."""
+        o = mitnc_search_opts(seed, trials, max_log2, min_sliced, max_sliced, 1 if keep_slicing else 0, method)
         call("mitnc_path_search", self.h, C.byref(o))
 
     def path(self) -> List[Tuple[int, int]]:
@@ -84,8 +85,12 @@ class Network:
         buf = (C.c_int64 * max(1, len(labels)))(*[int(x) for x in labels])
         call("mitnc_set_slicing", self.h, len(labels), buf)
 
-    def slice_greedy(self, max_log2: int, min_sliced: int = 0, max_sliced: int = 40) -> None:
-        call("mitnc_slice_greedy", self.h, max_log2, min_sliced, max_sliced)
+    def slice_greedy(self, max_log2: int, min_sliced: int = 0, max_sliced: int = 40) -> List[int]:
+        """Greedy slicing of the current path; returns the sliced labels, outer -> inner."""
+        n = C.c_int32()
+        buf = (C.c_int64 * 64)()
+        call("mitnc_slice_greedy", self.h, max_log2, min_sliced, max_sliced, C.byref(n), buf)
+        return [int(buf[i]) for i in range(n.value)]
 
     def index_overhead(self, label: int) -> float:
         v = C.c_double()
@@ -98,9 +103,11 @@ class Plan:
 
     def __init__(self, net: Network, precision: int = _lib.MITNC_C64, reuse: bool = True,
                  cache_budget_bytes: int = 0, force_kernel: int = -1, differentiable: bool = False,
-                 fuse_sections: bool = False):
+                 fuse_sections: bool = False, no_rerun: bool = False, splitk_max_mn_bits: int = 0,
+                 splitk_target_bits: int = 0):
         o = mitnc_plan_opts(precision, 1 if reuse else 0, cache_budget_bytes, force_kernel,
-                            1 if differentiable else 0, 1 if fuse_sections else 0)
+                            1 if differentiable else 0, 1 if fuse_sections else 0, 1 if no_rerun else 0,
+                            splitk_max_mn_bits, splitk_target_bits)
         h = C.c_void_p()
         call("mitnc_plan_create", net.h, C.byref(o), C.byref(h))
         self.h = h
@@ -108,6 +115,7 @@ class Plan:
         st = mitnc_plan_stats()
         call("mitnc_plan_query", h, C.byref(st))
         self.stats = st
+        self._n_leaves = net.n_leaves
         self.n_slices = 1 << st.n_sliced
         self.workspace = None
 
@@ -202,6 +210,22 @@ class Plan:
              out.ctypes.data_as(C.POINTER(C.c_float)), 1 if reset else 0, _stream_handle(stream))
         return out
 
+    def exponents(self, new: Optional[Sequence[int]] = None):
+        """(per-node exponents, exponent re-runs so far); with ``new`` the
+        step outputs' exponents are replaced first (FP16/BF16 plans)."""
+        nn = self.stats.n_steps + self._n_leaves
+        out = np.zeros(nn, dtype=np.int32)
+        rr = C.c_int32()
+        inp = None
+        if new is not None:
+            arr = np.ascontiguousarray(np.asarray(new, dtype=np.int32))
+            if arr.size != nn:
+                raise ValueError("one exponent per node expected")
+            inp = arr.ctypes.data_as(C.POINTER(C.c_int32))
+        call("mitnc_plan_exponents", self.h, None, inp, None)
+        call("mitnc_plan_exponents", self.h, out.ctypes.data_as(C.POINTER(C.c_int32)), None, C.byref(rr))
+        return out, rr.value
+
     def set_gates(self, mats, stream=None) -> None:
         """Replace all single-qubit gate matrices (n_grad_gates x 2 x 2, U[out, in])."""
         m = np.ascontiguousarray(np.asarray(mats, dtype=np.complex128).reshape(-1)).view(np.float64)
@@ -242,14 +266,28 @@ class Plan:
 _ELEM_BYTES = {_lib.MITNC_C64: 8, _lib.MITNC_CF16: 4, _lib.MITNC_CBF16: 4}
 
 
+def contract_work_bytes(la: Sequence[int], lb: Sequence[int], lc: Sequence[int], kernel: int = -1,
+                        precision: int = _lib.MITNC_C64) -> int:
+    """Device bytes of split-K partials a contraction with these layouts
+    needs (host-only size query)."""
+    la_ = (C.c_int64 * max(1, len(la)))(*la)
+    lb_ = (C.c_int64 * max(1, len(lb)))(*lb)
+    lc_ = (C.c_int64 * max(1, len(lc)))(*lc)
+    need = C.c_size_t()
+    call("mitnc_contract", None, len(la), la_, None, len(lb), lb_, None, len(lc), lc_, precision,
+         C.c_float(1.0), kernel, None, 0, C.byref(need), None)
+    return int(need.value)
+
+
 def contract(a, la: Sequence[int], b, lb: Sequence[int], lc: Sequence[int], kernel: int = -1,
-             precision: int = _lib.MITNC_C64, out_scale: float = 1.0, stream=None):
+             precision: int = _lib.MITNC_C64, out_scale: float = 1.0, stream=None, out=None):
     """One pairwise contraction on the GPU.  a, b: contiguous device tensors
     holding 2^len(la) / 2^len(lb) complex entries in the storage of
     `precision` (complex64, or interleaved FP16/BF16 halves in any 4-byte-per-
     entry dtype); address bit i carries label la[i] (LSB first).  Returns C
     with address bits lc (complex64 tensor, or int32 words of 16-bit pairs),
-    scaled by out_scale."""
+    scaled by out_scale.  ``out`` (optional) is a preallocated result of the
+    right size."""
     import torch
     eb = _ELEM_BYTES[precision]
     la_ = (C.c_int64 * max(1, len(la)))(*la)
@@ -261,10 +299,11 @@ def contract(a, la: Sequence[int], b, lb: Sequence[int], lc: Sequence[int], kern
     for t, r in ((a, len(la)), (b, len(lb))):
         if not t.is_contiguous() or t.numel() * t.element_size() != (1 << r) * eb:
             raise ValueError("operand size does not match its labels and precision")
-    if precision == _lib.MITNC_C64:
-        out = torch.empty(1 << len(lc), dtype=torch.complex64, device=a.device)
-    else:
-        out = torch.empty(1 << len(lc), dtype=torch.int32, device=a.device)
+    dt = torch.complex64 if precision == _lib.MITNC_C64 else torch.int32
+    if out is None:
+        out = torch.empty(1 << len(lc), dtype=dt, device=a.device)
+    elif out.dtype != dt or not out.is_contiguous() or out.numel() != (1 << len(lc)):
+        raise ValueError("out does not match the output labels and precision")
     work = torch.empty(max(256, need.value), dtype=torch.uint8, device=a.device) if need.value else None
     call("mitnc_contract", C.c_void_p(a.data_ptr()), len(la), la_, C.c_void_p(b.data_ptr()), len(lb), lb_,
          C.c_void_p(out.data_ptr()), len(lc), lc_, precision, C.c_float(out_scale), kernel,
@@ -303,16 +342,21 @@ def _amplitude_fn():
 
         @staticmethod
         def forward(ctx, gates, plan):
-            plan.set_gates(gates.detach().cpu().numpy())
+            mats = gates.detach().cpu().numpy().copy()
+            plan.set_gates(mats)
             acc = plan.new_result(plan.workspace.device)
             plan.execute(acc)
             ctx.plan = plan
+            # the plan's gate leaves may be replaced by another forward before
+            # this backward runs: keep this call's matrices and restore them
+            ctx.mats = mats
             ctx.gates_device = gates.device
             return acc
 
         @staticmethod
         def backward(ctx, grad_out):
             plan = ctx.plan
+            plan.set_gates(ctx.mats)
             # conj_physical: a lazy conj() view would hand the library the
             # unconjugated bytes
             w = torch.conj_physical(grad_out.to(torch.complex128)).contiguous()

@@ -9,4 +9,4 @@ from .circuits import (  # noqa: F401
     Gate, Circuit, gate_matrix, lattice_circuit, sqrt_x, sqrt_y, sqrt_w, fsim,
     random_fixed_bits, random_bitstrings, output_spec,
 )
-from .tensors import complex_normal  # noqa: F401
+from .tensors import complex_normal, complex_normal_c64  # noqa: F401

@@ -143,6 +143,50 @@ def test_splitk_long_k_accuracy():
     assert rel < 2e-6
 
 
+
+def test_splitk_k27_elementwise():
+    """The narrow-factor GEPDOT of the split-common evaluation: two rank-29 /
+    rank-28 operands sharing 27 indices (M = 4, N = 2, K = 2^27; 4 GiB and
+    2 GiB of complex64), elementwise against FP64 sums.  K is split over
+    2^12 waves; a wave's lanes run FP32 chains of K / (2^12 * 64) = 512
+    products (4-multiply complex form), a 64-lane shuffle tree adds them, and
+    the splits are summed in FP64 in a fixed order (Eq. 3 with blocked
+    summation).  Bound per entry: 6 gamma_{2^10} sum_k |a_k||b_k| (covers the
+    chain, the tree and FP64) plus the final complex64 rounding 2^-23 |C|.
+    An unblocked FP32 chain over 2^27 terms has an expected error of about
+    u sqrt(K) sum_k |a_k||b_k| ~ 7e-4 of it, above this bound."""
+    require_gpu()
+    import torch
+    from paper_2504_09186_amd import tnc
+    kb, mb, nb = 27, 2, 1
+    K = [3000 + i for i in range(kb)]
+    la = K + [1000, 1001]        # A[m][k]: k on the low 27 address bits
+    lb = K + [2000]              # B[n][k]
+    lc = [1000, 1001, 2000]      # C[n][m]
+    print("split-K case m2 n1 k27 (seed 4270)", flush=True)
+    a = synth.complex_normal_c64(1 << (kb + mb), seed=4270)
+    b = synth.complex_normal_c64(1 << (kb + nb), seed=4271)
+    ta = torch.from_numpy(a).cuda()
+    tb = torch.from_numpy(b).cuda()
+    c = tnc.contract(ta, la, tb, lb, lc, kernel=SPLITK)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy().astype(np.complex128)
+    del ta, tb
+    A2, B2 = a.reshape(1 << mb, 1 << kb), b.reshape(1 << nb, 1 << kb)
+    ref = np.zeros((1 << nb, 1 << mb), dtype=np.complex128)
+    absab = np.zeros((1 << nb, 1 << mb))
+    step = 1 << 23
+    for k0 in range(0, 1 << kb, step):
+        ac = A2[:, k0:k0 + step].astype(np.complex128)
+        bc = B2[:, k0:k0 + step].astype(np.complex128)
+        ref += bc @ ac.T
+        absab += np.abs(bc) @ np.abs(ac).T
+    ref, absab = ref.reshape(-1), absab.reshape(-1)
+    bound = 6.0 * gamma(1 << 10) * absab + 2.0 ** -23 * np.abs(ref)
+    err = np.abs(got - ref)
+    print(f"max err / bound {np.max(err / bound):.3e}, max err / sum|a||b| {np.max(err / absab):.3e}")
+    assert np.all(err <= bound)
+
 # ---------------------------------------------------------------- FP16 / BF16 storage
 def _to_half_words(x, prec):
     """complex entries -> int32 words of two 16-bit halves (re low)."""
@@ -168,25 +212,39 @@ def _from_half_words(w, prec):
     (7, 6, 9, 1, TILE), (0, 0, 9, 0, SPLITK), (5, 5, 0, 0, TILE), (13, 5, 5, 0, STREAM), (12, 2, 1, 0, STREAM),
     (12, 4, 6, 0, STREAM), (8, 3, 2, 0, STREAM), (9, 6, 4, 0, STREAM), (10, 5, 5, 2, STREAM)])
 def test_half_storage(prec, mb, nb, kb, bb, kernel):
-    """16-bit storage, FP32 accumulate.  Inputs are mantissas of values around
-    2^-30 (scaled by 2^30 into range); the output is rescaled by out_scale.
-    Bound: FP32 accumulation error 6 gamma_{K+4} |A||B| plus one rounding of
-    the output (2^-11 FP16, 2^-8 BF16 relative)."""
+    """16-bit storage, FP32 accumulate, values far below the 16-bit range.
+    The true operands are x = X 2^-30 and y = Y 2^-20 (X, Y complex normal
+    rounded to 16 bits: |x| ~ 2^-30 is below FP16's smallest subnormal, so
+    only the mantissa plus exponent form can carry it).  The kernel gets the
+    mantissas X, Y and out_scale = 2^-s_C with s_C chosen so that the largest
+    stored |Re|, |Im| falls in [2^13, 2^14); the value is read back as
+    stored * 2^(e_A + e_B + s_C) and compared elementwise with the FP64
+    contraction of the true tiny operands.  Bound: FP32 accumulation error
+    6 gamma_{K+4} |x||y| plus one rounding of the output (2^-11 FP16, 2^-8
+    BF16 relative)."""
     require_gpu()
     import torch
     from paper_2504_09186_amd import tnc
     la, lb, lc, a, b = _case(mb, nb, kb, bb, 77 + mb + 10 * nb + 100 * kb + prec, rows_ordered=kernel == STREAM)
-    a = a.astype(np.complex128) * 2.0 ** -30 * 2.0 ** 30  # mantissas of 2^-30-sized values
-    wa, ar = _to_half_words(a, prec)
-    wb, br = _to_half_words(b.astype(np.complex128), prec)
-    scale = 2.0 ** -3
-    print(f"half contract m{mb} n{nb} k{kb} b{bb} kernel {kernel} prec {prec}", flush=True)
+    ea, eb = -30, -20
+    wa, xr = _to_half_words(a.astype(np.complex128), prec)  # mantissas X
+    wb, yr = _to_half_words(b.astype(np.complex128), prec)
+    x_true, y_true = np.ldexp(xr.real, ea) + 1j * np.ldexp(xr.imag, ea), np.ldexp(yr.real, eb) + 1j * np.ldexp(yr.imag, eb)
+    ref = ref_contract(x_true, la, y_true, lb, lc)
+    absab = ref_contract(x_true, la, y_true, lb, lc, absval=True).real
+    # output exponent from the true result's largest component
+    mx = max(np.max(np.abs(ref.real)), np.max(np.abs(ref.imag)))
+    s_c = int(np.frexp(mx)[1] - 1) - 13 - (ea + eb)
+    scale = 2.0 ** -s_c
+    print(f"half contract m{mb} n{nb} k{kb} b{bb} kernel {kernel} prec {prec} s_C {s_c}", flush=True)
     c = tnc.contract(wa.cuda(), la, wb.cuda(), lb, lc, kernel=kernel, precision=prec, out_scale=scale)
     torch.cuda.synchronize()
-    got = _from_half_words(c, prec) / scale
-    ref = ref_contract(ar, la, br, lb, lc)
-    absab = ref_contract(ar, la, br, lb, lc, absval=True).real
+    stored = _from_half_words(c, prec)
+    smax = max(np.max(np.abs(stored.real)), np.max(np.abs(stored.imag)))
+    assert 2.0 ** 13 * (1 - 2 ** -8) <= smax < 2.0 ** 14 * (1 + 2 ** -8)
+    e_c = ea + eb + s_c
+    got = np.ldexp(stored.real, e_c) + 1j * np.ldexp(stored.imag, e_c)
     u_out = 2.0 ** -11 if prec == 1 else 2.0 ** -8
-    bound = absab * gamma((1 << kb) + 4) * 6.0 + np.abs(ref) * u_out * 1.01 + 1e-30
+    bound = absab * gamma((1 << kb) + 4) * 6.0 + np.abs(ref) * u_out * 1.01 + 1e-300
     err = np.abs(got - ref)
     assert np.all(err <= bound), f"max err/bound {np.max(err / bound)}"

@@ -84,3 +84,40 @@ def test_config2_oracle_slicing_first_16_slices():
         got = acc.cpu().numpy()
         ref = to_c(g["slice_results"][str(s)])
         assert np.linalg.norm(got - ref) <= 1e-5 * max(np.linalg.norm(ref), 1e-30), f"slice {s}"
+
+
+@pytest.mark.parametrize("prec,xeb_bound,rel_bound", [(1, 1e-3, 2e-2), (2, 1e-2, 1.5e-1)])
+def test_config2_all_slices_half_precision(prec, xeb_bound, rel_bound):
+    """Precision form at full size: all 256 slices of the benchmark plan with
+    complex FP16 (prec 1) or BF16 (prec 2) storage, FP32 accumulation and
+    per-tensor exponents calibrated on slices 0-1, FP64 cross-slice sum.  The
+    result is an approximation, pinned only by the error metrics against the
+    FP64 oracle's amplitudes: linear-XEB fidelity loss <= 1e-3 (FP16) or
+    <= 1e-2 (BF16, 8-bit significand) and relative L2 <= 2e-2 (FP16) or
+    <= 1.5e-1 (BF16); no stored value may overflow."""
+    require_gpu()
+    import torch
+
+    import oracle
+    from paper_2504_09186_amd import tnc
+    g, to_c = _golden()
+    c, spec = _workload()
+    net = tnc.Network(c, spec)
+    net.path_search(seed=3001, trials=64, max_log2=26, min_sliced=8, max_sliced=8)
+    plan = tnc.Plan(net, precision=prec)
+    plan.upload()
+    plan.calibrate(0, 2)
+    acc = plan.new_result()
+    print(f"config 2: all 256 slices, precision {prec}", flush=True)
+    plan.execute(acc)
+    torch.cuda.synchronize()
+    got = acc.cpu().numpy()
+    ref = to_c(g["amplitudes"])
+    rel = oracle.rel_l2(got, ref)
+    loss = abs(1.0 - oracle.xeb_ratio(got, ref))
+    mx = float(plan.step_maxima().max())
+    print(f"rel-L2 {rel:.3e}, XEB loss {loss:.3e}, largest stored {mx:.1f}")
+    assert np.all(np.isfinite(got))
+    assert mx < 65504.0
+    assert loss <= xeb_bound
+    assert rel <= rel_bound

@@ -123,3 +123,52 @@ def test_gradient_finite_differences_gpu():
             gv.append(grad[g, i, j].real if part == 0 else grad[g, i, j].imag)
     fd, gv = np.array(fd), np.array(gv)
     assert np.linalg.norm(fd - gv) <= 1e-3 * np.linalg.norm(gv)
+
+
+def test_gradient_20_qubits_sliced():
+    """A 4x5 lattice (20 qubits), 10 cycles, 16 random bitstrings as a batch
+    index, 4 sliced indices (16 slices, each recomputed by the backward):
+    GPU gradient of L = sum log|a|^2 against the oracle's reverse-mode
+    gradient on the same slicing, relative L2 <= 1e-4."""
+    require_gpu()
+    c, spec, bits, net, onet, sliced = _setup(4, 5, 10, 16, 4, 31)
+    print(f"gradient case 4x5x10, 16 bitstrings, sliced {sliced}", flush=True)
+    amps, grad, plan, _ = _gpu_grad(net, c)
+    assert plan.n_slices == 16
+    opath = oracle.greedy_path(onet)
+    ref_amps = oracle.contract_sliced(onet, opath, sliced).reshape(-1)
+    assert oracle.rel_l2(amps, ref_amps) < 1e-5
+    j = oracle.tn_gate_gradients(onet, opath, 1.0 / ref_amps, sliced=sliced)
+    ref = np.stack([oracle.torch_convention_grad(j[g]) for g in c.one_qubit_gate_ids()])
+    assert np.linalg.norm(grad - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+def test_two_forwards_before_backward():
+    """loss = f(G1) + f(G2) with two forwards on one plan before the backward:
+    each backward differentiates at its own forward's gate matrices (the
+    plan's gate leaves were replaced by the second forward)."""
+    require_gpu()
+    import torch
+    from paper_2504_09186_amd import tnc
+    c, spec, bits, net, onet, sliced = _setup(3, 3, 6, 8, 2, 41)
+    plan = tnc.Plan(net, differentiable=True)
+    plan.upload()
+    m1 = np.stack([g.matrix for g in c.gates if g.arity == 1])
+    rng = np.random.default_rng(42)
+    m2 = m1 + 0.05 * (rng.standard_normal(m1.shape) + 1j * rng.standard_normal(m1.shape))
+    g1 = torch.tensor(m1, dtype=torch.complex128, requires_grad=True)
+    g2 = torch.tensor(m2, dtype=torch.complex128, requires_grad=True)
+    f = tnc.AmplitudeFn()
+    loss = torch.sum(torch.log(torch.abs(f.apply(g1, plan)) ** 2)) + \
+        torch.sum(torch.log(torch.abs(f.apply(g2, plan)) ** 2))
+    loss.backward()
+    opath = oracle.greedy_path(onet)
+    ids = c.one_qubit_gate_ids()
+    for g, m in ((g1, m1), (g2, m2)):
+        c2 = synth.Circuit(c.n_qubits, [synth.Gate(gt.name, gt.qubits, m[ids.index(i)] if gt.arity == 1
+                                                   else gt.matrix) for i, gt in enumerate(c.gates)])
+        on2 = oracle.build_network(c2, spec, bits)
+        a = oracle.contract_network(on2, opath).reshape(-1)
+        j = oracle.tn_gate_gradients(on2, opath, 1.0 / a)
+        ref = np.stack([oracle.torch_convention_grad(j[k]) for k in ids])
+        assert np.linalg.norm(g.grad.numpy() - ref) <= 1e-4 * np.linalg.norm(ref)
