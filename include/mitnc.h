@@ -403,6 +403,24 @@ int32_t mitnc_contract(const void* A, int32_t ra, const int64_t* la, const void*
                        float out_scale, int32_t kernel, void* work, size_t work_bytes,
                        size_t* work_bytes_needed, void* stream);
 
+/* Allocation-free form of mitnc_contract, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the split-K partial sums live in a
+ * fixed device array of MITNC_NOALLOC_SCRATCH_BYTES inside the library, one
+ * per GPU, held until the process ends (its device address is looked up on
+ * the first call on each device).  The caller passes inputs and output only;
+ * the call allocates and frees nothing.  A step whose partials would need
+ * more than the array fails with WORKSPACE_TOO_SMALL (use mitnc_contract
+ * with a work buffer).  Every call on one GPU shares the array and leaves its
+ * partials there: calls that overlap on one GPU (other streams or threads)
+ * race and must be serialised by the caller.  Nothing needs clearing: every
+ * partial a call reads, it has written first.  Same arguments, results and
+ * other errors as mitnc_contract. */
+#define MITNC_NOALLOC_SCRATCH_BYTES (32u << 20)
+int32_t mitnc_contract_noalloc(const void* A, int32_t ra, const int64_t* la, const void* B, int32_t rb,
+                               const int64_t* lb, void* C, int32_t rc, const int64_t* lc, int32_t precision,
+                               float out_scale, int32_t kernel, void* stream);
+
 /* Launch timing for measurement (the per-kernel figures of the paper's
  * performance analysis, Sec. VII).  mitnc_plan_timing(plan, 1) starts
  * recording a hipEvent pair around the main kernel of every step launched by

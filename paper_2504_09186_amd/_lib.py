@@ -101,6 +101,8 @@ _SIGS = {
     "mitnc_contract": [_VP, _I32, C.POINTER(C.c_int64), _VP, _I32, C.POINTER(C.c_int64), _VP, _I32,
                        C.POINTER(C.c_int64), _I32, C.c_float, _I32, _VP, C.c_size_t, C.POINTER(C.c_size_t),
                        _VP],
+    "mitnc_contract_noalloc": [_VP, _I32, C.POINTER(C.c_int64), _VP, _I32, C.POINTER(C.c_int64), _VP, _I32,
+                               C.POINTER(C.c_int64), _I32, C.c_float, _I32, _VP],
 }
 _VOID = {"mitnc_plan_destroy": [_VP], "mitnc_network_destroy": [_VP]}
 

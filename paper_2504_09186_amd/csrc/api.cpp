@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <random>
 
 #include "kernels.hpp"
@@ -895,7 +896,7 @@ int32_t mitnc_plan_set_gates(mitnc_plan* P, void* ws, size_t ws_bytes, const dou
 
 }  // extern "C"
 
-// One pairwise contraction (mitnc_contract).
+// One pairwise contraction (mitnc_contract and its allocation-free form).
 static void contract_impl(const void* A, int32_t ra, const int64_t* la, const void* B, int32_t rb,
                           const int64_t* lb, void* C, int32_t rc, const int64_t* lc, int32_t precision,
                           float out_scale, int32_t kernel, void* work, size_t work_bytes, size_t* work_bytes_needed,
@@ -950,6 +951,30 @@ static void contract_impl(const void* A, int32_t ra, const int64_t* la, const vo
   hip_check(launch_step(st.kclass, d, (hipStream_t)stream), "kernel launch");
 }
 
+// Device scratch of the allocation-free entry point: the split-K partial
+// sums (one FP32 complex per split and output entry).  Each GPU the library
+// runs on holds its own copy until the process ends.  Host code must not
+// pass `scratch` itself to a kernel (on the host it is only a stand-in):
+// the device address comes from hipGetSymbolAddress, once per device.
+static constexpr size_t kScratchBytes = 32ull << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[256];
+
+static void* scratch_for_current_device() {
+  int dev = -1;
+  hip_check(hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= 256) fail(MITNC_UNSUPPORTED, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch symbol address");
+    if (!ptr) fail(MITNC_HIP_ERROR, "scratch symbol address is null");
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
 extern "C" {
 
 int32_t mitnc_contract(const void* A, int32_t ra, const int64_t* la, const void* B, int32_t rb, const int64_t* lb,
@@ -958,6 +983,24 @@ int32_t mitnc_contract(const void* A, int32_t ra, const int64_t* la, const void*
   return guarded([&] {
     contract_impl(A, ra, la, B, rb, lb, C, rc, lc, precision, out_scale, kernel, work, work_bytes,
                   work_bytes_needed, stream);
+  });
+}
+
+int32_t mitnc_contract_noalloc(const void* A, int32_t ra, const int64_t* la, const void* B, int32_t rb,
+                               const int64_t* lb, void* C, int32_t rc, const int64_t* lc, int32_t precision,
+                               float out_scale, int32_t kernel, void* stream) {
+  return guarded([&] {
+    if (!A || !B || !C) fail(MITNC_INVALID_ARG, "null tensor");
+    size_t need = 0;
+    contract_impl(nullptr, ra, la, nullptr, rb, lb, nullptr, rc, lc, precision, out_scale, kernel, nullptr, 0,
+                  &need, stream);
+    if (need > kScratchBytes)
+      fail(MITNC_WORKSPACE_TOO_SMALL, "split-K partials need " + std::to_string(need) +
+                                          " bytes, more than the fixed scratch of " + std::to_string(kScratchBytes) +
+                                          " bytes; use mitnc_contract with a work buffer");
+    void* work = need ? scratch_for_current_device() : nullptr;
+    contract_impl(A, ra, la, B, rb, lb, C, rc, lc, precision, out_scale, kernel, work, kScratchBytes, nullptr,
+                  stream);
   });
 }
 

@@ -280,14 +280,16 @@ def contract_work_bytes(la: Sequence[int], lb: Sequence[int], lc: Sequence[int],
 
 
 def contract(a, la: Sequence[int], b, lb: Sequence[int], lc: Sequence[int], kernel: int = -1,
-             precision: int = _lib.MITNC_C64, out_scale: float = 1.0, stream=None, out=None):
+             precision: int = _lib.MITNC_C64, out_scale: float = 1.0, stream=None, out=None,
+             noalloc: bool = False):
     """One pairwise contraction on the GPU.  a, b: contiguous device tensors
     holding 2^len(la) / 2^len(lb) complex entries in the storage of
     `precision` (complex64, or interleaved FP16/BF16 halves in any 4-byte-per-
     entry dtype); address bit i carries label la[i] (LSB first).  Returns C
     with address bits lc (complex64 tensor, or int32 words of 16-bit pairs),
     scaled by out_scale.  ``out`` (optional) is a preallocated result of the
-    right size."""
+    right size; with ``noalloc`` the library's allocation-free entry point
+    runs the contraction (split-K partials in its fixed device scratch)."""
     import torch
     eb = _ELEM_BYTES[precision]
     la_ = (C.c_int64 * max(1, len(la)))(*la)
@@ -304,6 +306,11 @@ def contract(a, la: Sequence[int], b, lb: Sequence[int], lc: Sequence[int], kern
         out = torch.empty(1 << len(lc), dtype=dt, device=a.device)
     elif out.dtype != dt or not out.is_contiguous() or out.numel() != (1 << len(lc)):
         raise ValueError("out does not match the output labels and precision")
+    if noalloc:
+        call("mitnc_contract_noalloc", C.c_void_p(a.data_ptr()), len(la), la_, C.c_void_p(b.data_ptr()), len(lb),
+             lb_, C.c_void_p(out.data_ptr()), len(lc), lc_, precision, C.c_float(out_scale), kernel,
+             _stream_handle(stream))
+        return out
     work = torch.empty(max(256, need.value), dtype=torch.uint8, device=a.device) if need.value else None
     call("mitnc_contract", C.c_void_p(a.data_ptr()), len(la), la_, C.c_void_p(b.data_ptr()), len(lb), lb_,
          C.c_void_p(out.data_ptr()), len(lc), lc_, precision, C.c_float(out_scale), kernel,
