@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the sliced contraction hot path on one MI355X.
 
-Workload: the 5x6-qubit (30 qubits), 14-cycle random lattice circuit
-(sqrt-X/Y/W + fSim(pi/2, pi/6), ABCD couplers, seed 1001), 64 amplitudes
-(qubits 24-29 open, the other 24 output bits fixed at random, seed 2001),
-randomised-greedy path with the largest intermediate <= 2^26 entries and 8
-sliced indices (256 slices).  One step = all 256 slices (the whole sliced
-tree, FP64 cross-slice sum), inputs resident in HBM.
+Headline workload (the metric's configuration): a 7x8-qubit (56 qubits),
+20-cycle random lattice circuit (sqrt-X/Y/W + fSim(pi/2, pi/6), ABCD couplers,
+seed 1004), qubits 44-55 open (2^12 amplitudes), the other 44 output bits
+fixed at random (seed 2004); the library's recursive-bisection path search
+(seed 3004) with every intermediate <= 2^30 entries; one GPU's share of 256
+slices (the 8 innermost sliced indices vary, the outer ones are 0).  One step
+= those 256 slices (shared-prefix reuse across them, FP64 cross-slice sum),
+inputs resident in HBM.
 
-Two forms are timed on the same plan: complex64 (FP32 MFMA; the headline
-`value`) and scaled complex FP16 (FP16 MFMA, FP32 accumulate, per-tensor
-power-of-two exponents calibrated on slices 0-1), each with its amplitude
-error against the oracle's values stored in tests/golden.  Prints one JSON
-line.
+Two forms run on the same path and slicing: complex64 (FP32 MFMA; the
+headline `value`) and scaled complex FP16 (FP16 MFMA, FP32 accumulate,
+per-tensor power-of-two exponents calibrated on slices 0-1, re-run on an
+exponent miss).  Errors are reported against the FP64 oracle's stored
+sub-slice results (the oracle's own 60-index slicing of the same network,
+computed by tests/golden/make_golden_config4.py) and, for the FP16 form,
+against the complex64 result of the 256 slices.  Also reported: the 5x6-qubit
+14-cycle workload (64 amplitudes, 256 slices) and the differentiation form
+(forward vs backward time).  Prints one JSON line.
 """
 import argparse
 import json
@@ -34,93 +40,107 @@ def class_peak(label, cls):
     """Compute peak of the units a kernel class runs on: the FP16 form's tile
     and stream kernels use FP16 MFMA; everything else computes in FP32."""
     return PEAK_FP16 if label == "cf16" and cls in (2, 3, 4, 5) else PEAK_FP32
-GOLDEN = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.json")
 
 
-def workload():
+def executed_fraction(label, cls):
+    """Real flops the MFMA executes per flop of the 4M count (8 M K N): the
+    complex64 tile, tall and stream kernels run the 3M split (three real
+    products instead of four); the FP16/BF16 kernels run the 4M split as one
+    real GEMM."""
+    return 0.75 if label == "c64" and cls in (2, 3, 5) else 1.0
+GOLDEN2 = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.json")
+GOLDEN4 = os.path.join(ROOT, "tests", "golden", "config4_subslices.json")
+WORKLOAD4 = "rqc-7x8-20cyc-4096amp-256slice-share"
+WORKLOAD2 = "rqc-5x6-14cyc-64amp-256slices"
+
+
+def workload4():
+    import synth
+    c = synth.lattice_circuit(7, 8, 20, seed=1004)
+    spec = synth.output_spec(56, list(range(44, 56)), seed=2004)
+    return c, spec
+
+
+def workload2():
     import synth
     c = synth.lattice_circuit(5, 6, 14, seed=1001)
     spec = synth.output_spec(30, list(range(24, 30)), seed=2001)
     return c, spec
 
 
-def golden_amplitudes():
+def load_json(path):
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def to_complex(v):
     import numpy as np
-    if not os.path.exists(GOLDEN):
-        return None
-    with open(GOLDEN) as f:
-        g = json.load(f)
-    return np.array([a + 1j * b for a, b in g["amplitudes"]])
+    return np.array([a + 1j * b for a, b in v])
 
 
-def amp_error(got, ref):
+def error_metrics(got, ref, against):
     import oracle
-    if ref is None:
-        return None
     return {"rel_l2": oracle.rel_l2(got, ref), "overlap": oracle.overlap_fidelity(got, ref),
-            "xeb_loss": abs(1.0 - oracle.xeb_ratio(got, ref)), "against": "FP64 oracle, all 64 amplitudes"}
+            "xeb_loss": abs(1.0 - oracle.xeb_ratio(got, ref)), "against": against}
 
 
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def measured_traffic(label, kernel):
+def measured_traffic(workload, label, kernel):
     """HBM bytes per launch of the dominant kernel from the committed
     FETCH_SIZE/WRITE_SIZE counters, or None when they do not apply: another
-    kernel or form, or kernel sources changed since the counters were taken."""
+    workload, kernel or form, or kernel sources changed since the counters
+    were taken."""
     import hashlib
-    if kernel != "stream" or not os.path.exists(TRAFFIC):
+    rec = load_json(TRAFFIC)
+    if rec is None:
         return None
-    with open(TRAFFIC) as f:
-        rec = json.load(f)
     h = hashlib.sha256()
     for rel in ("paper_2504_09186_amd/csrc/kernels.hip", "paper_2504_09186_amd/csrc/step.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     if h.hexdigest() != rec.get("kernels_sha256"):
         return None
-    return rec.get(f"stream_{label}_bytes_per_launch")
+    return rec.get(f"{workload}:{kernel}:{label}")
 
 
-def run_form(net, precision, steps, warmup, label):
+def run_form(plan, steps, warmup, label, workload, s0=0, s1=None):
+    """Times `steps` executions of slices [s0, s1) after `warmup` untimed
+    ones, then repeats them with per-launch event timing for the kernel
+    classes.  Returns the throughput record and the last result."""
     import torch
-
-    from paper_2504_09186_amd import tnc
-    plan = tnc.Plan(net, precision=precision)
     st = plan.stats
-    n_slices = plan.n_slices
-    plan.upload()
-    if precision != 0:
-        plan.calibrate(0, 2)
+    s1 = plan.n_slices if s1 is None else s1
+    n_slices = s1 - s0
     acc = plan.new_result()
     for _ in range(warmup):
         acc.zero_()
-        plan.execute(acc)
+        plan.execute(acc, s0, s1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         acc.zero_()
-        plan.execute(acc)
+        plan.execute(acc, s0, s1)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     result = acc.cpu().numpy()
     # Kernel durations: the same steps again with a hipEvent pair around every
-    # launch (the events add host-side launch cost, so `value` above is taken
+    # launch (the events add host-side launch cost, so `value` is taken
     # without them).
     plan.timing(True)
     acc.zero_()
-    plan.execute(acc)  # allocates the event pool
+    plan.execute(acc, s0, s1)  # allocates the event pool
     torch.cuda.synchronize()
     plan.timing(True)
     for _ in range(steps):
         acc.zero_()
-        plan.execute(acc)
+        plan.execute(acc, s0, s1)
     torch.cuda.synchronize()
     ms, launches, flops, nbytes = plan.timing_read()
     plan.timing(False)
-    overflow = None
-    if precision != 0:
-        overflow = bool(float(plan.step_maxima().max()) >= 65504.0)
     nc = len(CLASS_NAMES)
     dom = int(max(range(nc), key=lambda k: ms[k]))
     # Bound of the dominant kernel: its arithmetic intensity against the
@@ -128,9 +148,10 @@ def run_form(net, precision, steps, warmup, label):
     peak = class_peak(label, dom)
     ai = flops[dom] / max(nbytes[dom], 1.0)
     if ai >= peak * 1e12 / (PEAK_HBM_GBS * 1e9):
-        achieved = flops[dom] / (ms[dom] * 1e-3) / 1e12
+        # executed MFMA flops against the dense peak of their type
+        achieved = flops[dom] * executed_fraction(label, dom) / (ms[dom] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None}
+                "traffic": None, "achieved_4m_count": flops[dom] / (ms[dom] * 1e-3) / 1e12}
     else:
         achieved = nbytes[dom] / (ms[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -138,18 +159,62 @@ def run_form(net, precision, steps, warmup, label):
     roof["flop_per_byte"] = ai
     roof["kernel"] = CLASS_NAMES[dom]
     roof["algorithmic_bytes_per_launch"] = nbytes[dom] / max(1.0, launches[dom])
-    roof["traffic"] = measured_traffic(label, CLASS_NAMES[dom])
+    roof["algorithmic_flops_per_launch"] = flops[dom] / max(1.0, launches[dom])
+    roof["traffic"] = measured_traffic(workload, label, CLASS_NAMES[dom])
     roof["launches"] = int(launches[dom])
     roof["avg_launch_ms"] = ms[dom] / max(1.0, launches[dom])
-    total_flops = st.flops_reused_slice * n_slices * steps
+    step_flops = float(sum(flops[:nc])) / steps  # algorithmic flops of one step's launches
     total_bytes = sum(nbytes[:nc])
-    return {
+    overflow = None
+    if plan.stats is not None and label != "c64":
+        overflow = bool(float(plan.step_maxima().max()) >= 65504.0)
+    rec = {
         "value": n_slices * steps / el, "unit": "slices/s", "ms_per_step": el / steps * 1e3,
-        "tflops": total_flops / el / 1e12, "hbm_gbs": total_bytes / el / 1e9,
-        "mfma_frac": total_flops / el / 1e12 / (PEAK_FP16 if label == "cf16" else PEAK_FP32),
+        "tflops": step_flops * steps / el / 1e12, "hbm_gbs": total_bytes / el / 1e9,
+        "flops_per_step": step_flops,
         "kernel_ms_by_class": {CLASS_NAMES[k]: ms[k] / steps for k in range(nc)},
-        "roofline": roof, "n_slices": n_slices, "stats": st, "result": result, "fp16_overflow": overflow,
+        "kernel_tflops_by_class": {CLASS_NAMES[k]: (flops[k] / (ms[k] * 1e-3) / 1e12 if ms[k] > 0 else 0.0)
+                                   for k in range(nc)},
+        "roofline": roof, "n_slices": n_slices, "fp16_overflow": overflow,
+        "exponent_reruns": plan.exponents()[1] if label != "c64" else None,
     }
+    return rec, result
+
+
+def subslice_check(c, spec, g, precision):
+    """The oracle's stored sub-slices (its own slicing of the same network),
+    recomputed with the library's path for that slicing."""
+    import numpy as np
+    import torch
+
+    from paper_2504_09186_amd import tnc
+    net = tnc.Network(c, spec)
+    lab = g["oracle_sliced_labels"]
+    net.set_slicing(lab)
+    net.path_search(seed=3004, trials=8, max_log2=30, min_sliced=len(lab), max_sliced=62, keep_slicing=True,
+                    method=1)
+    extra = len(net.slicing()) - len(lab)
+    plan = tnc.Plan(net, precision=precision)
+    plan.upload()
+    gots, refs = [], []
+    for sid in g["sub_slice_ids"]:
+        s0, s1 = sid << extra, (sid + 1) << extra
+        if precision:
+            plan.calibrate(s0, min(s1, s0 + 2))
+        acc = plan.new_result()
+        plan.execute(acc, s0, s1)
+        torch.cuda.synchronize()
+        gots.append(acc.cpu().numpy())
+        refs.append(to_complex(g["sub_slice_results"][str(sid)]))
+    del plan
+    torch.cuda.empty_cache()
+    # metrics per sub-slice (each its own result set of 2^12 amplitudes); the worst is reported
+    per = [error_metrics(a, b, "") for a, b in zip(gots, refs)]
+    worst = {k: max(p[k] for p in per) for k in ("rel_l2", "xeb_loss")}
+    worst["overlap"] = min(p["overlap"] for p in per)
+    worst["against"] = (f"FP64 oracle, worst of {len(gots)} sub-slices of its own {len(lab)}-index slicing "
+                        f"(2^12 amplitudes each)")
+    return worst
 
 
 def grad_timing(steps):
@@ -196,6 +261,26 @@ def grad_timing(steps):
             "finite": bool(torch.isfinite(torch.view_as_real(grad)).all())}
 
 
+def cpu_baseline_subslice(c, spec, g, gpu_flops_per_slice):
+    """The FP64 oracle, as it stands, on a bounded sample of the same
+    network: one sub-slice of its own 62-index slicing (stored path), timed
+    on the host's cores; its flop rate is converted to slices/s of the GPU
+    plan's executed flops per slice."""
+    import oracle
+    onet = oracle.build_network(c, spec)
+    path = [tuple(p) for p in g["oracle_path"]]
+    sl = g["cpu_sample_sliced_labels"]
+    t0 = time.perf_counter()
+    oracle.contract_sliced(onet, path, sl, slice_ids=[0])
+    el = time.perf_counter() - t0
+    rate = g["cpu_sample_flops"] / el
+    return {"value": rate / gpu_flops_per_slice, "unit": "slices/s", "cores": _host_threads(), "kind": "oracle",
+            "sample": f"one sub-slice of the oracle's own {len(sl)}-index slicing of the same 56-qubit network "
+                      f"({g['cpu_sample_flops']:.3e} flops in {el:.1f} s = {rate / 1e9:.1f} GFLOP/s, numpy "
+                      f"complex128), converted at the GPU plan's {gpu_flops_per_slice:.3e} executed flops per "
+                      f"slice", "host": _host_info()}
+
+
 def cpu_baseline(c, spec, path, sliced, seconds: float):
     """The FP64 oracle, as it stands, on the same path and slicing: slices
     0, 1, 2, ... until about `seconds` of host time are spent."""
@@ -209,15 +294,58 @@ def cpu_baseline(c, spec, path, sliced, seconds: float):
         if time.perf_counter() - t0 >= seconds:
             break
     el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "slices/s", "cores": _host_threads(), "kind": "oracle",
+            "sample": f"slices 0..{done - 1} of the same 256-slice workload, same path and sliced "
+                      f"indices, numpy complex128 ({el:.1f} s)", "host": _host_info()}
+
+
+def _host_threads():
     try:
         from threadpoolctl import threadpool_info
         info = threadpool_info()
-        cores = max(int(i.get("num_threads", 1)) for i in info) if info else 1
+        return max(int(i.get("num_threads", 1)) for i in info) if info else 1
     except Exception:
-        cores = os.cpu_count() or 1
-    return {"value": done / el, "unit": "slices/s", "cores": cores, "kind": "oracle",
-            "sample": f"slices 0..{done - 1} of the same 256-slice workload, same path and sliced "
-                      f"indices, numpy complex128 ({el:.1f} s)"}
+        return os.cpu_count() or 1
+
+
+def _host_info():
+    model, mem = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            mem = int(f.readline().split()[1]) / 2 ** 20
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu": model, "ram_gib": mem}
+
+
+def run_config2(steps, warmup, trials):
+    """The 5x6-qubit workload: both forms on the greedy-search plan, errors
+    against all 64 oracle amplitudes."""
+    import torch
+
+    from paper_2504_09186_amd import tnc
+    c, spec = workload2()
+    net = tnc.Network(c, spec)
+    net.path_search(seed=3001, trials=trials, max_log2=26, min_sliced=8, max_sliced=8)
+    g = load_json(GOLDEN2)
+    ref = to_complex(g["amplitudes"]) if g else None
+    out = {"workload": WORKLOAD2}
+    for prec, label in ((0, "c64"), (1, "cf16")):
+        plan = tnc.Plan(net, precision=prec)
+        plan.upload()
+        if prec:
+            plan.calibrate(0, 2)
+        rec, res = run_form(plan, steps, warmup, label, WORKLOAD2)
+        rec["amp_error"] = error_metrics(res, ref, "FP64 oracle, all 64 amplitudes") if ref is not None else None
+        out[label] = rec
+        del plan
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -225,10 +353,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--trials", type=int, default=64, help="path-search trials")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--trials", type=int, default=8, help="path-search trials (headline workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only (no 5x6 workload, no differentiation form)")
+    ap.add_argument("--workload", choices=["rqc7x8", "rqc5x6"], default="rqc7x8")
     ap.add_argument("--grad", action="store_true",
                     help="only time the differentiation form (forward vs backward over all slices) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -256,37 +385,65 @@ def main():
     if args.grad:
         print(json.dumps(grad_timing(args.steps)), flush=True)
         return
-    c, spec = workload()
-    net = tnc.Network(c, spec)
-    net.path_search(seed=3001, trials=args.trials, max_log2=26, min_sliced=8, max_sliced=8)
-    ref = golden_amplitudes()
+    if args.workload == "rqc5x6":
+        r = run_config2(args.steps, args.warmup, 64)
+        c64 = r["c64"]
+        out = {"metric": METRIC, "value": c64["value"], "unit": "slices/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": c64["ms_per_step"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+               "config": {"workload": WORKLOAD2}, "roofline": c64["roofline"], "detail": r}
+        print(json.dumps(out), flush=True)
+        return
 
-    r64 = run_form(net, 0, args.steps, args.warmup, "c64")
-    st = r64["stats"]
+    c, spec = workload4()
+    net = tnc.Network(c, spec)
+    t0 = time.perf_counter()
+    net.path_search(seed=3004, trials=args.trials, max_log2=30, min_sliced=8, max_sliced=62, method=1)
+    search_s = time.perf_counter() - t0
+    print(f"path search {search_s:.1f} s, {len(net.slicing())} sliced indices", file=sys.stderr, flush=True)
+    g4 = load_json(GOLDEN4)
+    share = (0, 256)
+
+    plan = tnc.Plan(net, precision=0)
+    st = plan.stats
+    plan.upload()
+    r64, res64 = run_form(plan, args.steps, args.warmup, "c64", WORKLOAD4, *share)
+    del plan
+    torch.cuda.empty_cache()
+    print(f"complex64: {r64['value']:.1f} slices/s", file=sys.stderr, flush=True)
+    plan = tnc.Plan(net, precision=1)
+    plan.upload()
+    plan.calibrate(0, 2)
+    r16, res16 = run_form(plan, args.steps, args.warmup, "cf16", WORKLOAD4, *share)
+    del plan
+    torch.cuda.empty_cache()
+    print(f"complex FP16: {r16['value']:.1f} slices/s", file=sys.stderr, flush=True)
+    r16["vs_complex64"] = error_metrics(res16, res64, "complex64 GPU result of the same 256 slices")
+    if g4 is not None:
+        r64["amp_error"] = subslice_check(c, spec, g4, 0)
+        r16["amp_error"] = subslice_check(c, spec, g4, 1)
     out = {
         "metric": METRIC, "value": r64["value"], "unit": "slices/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": "rqc-5x6-14cyc-64amp-256slices", "qubits": 30, "cycles": 14,
-                   "open_qubits": 6, "slices_per_step": r64["n_slices"], "max_log2_elems": st.max_log2_elems,
-                   "steps_per_slice": st.n_steps, "flops_per_slice": st.flops_reused_slice,
+        "config": {"workload": WORKLOAD4, "qubits": 56, "cycles": 20, "open_qubits": 12,
+                   "slices_per_step": 256, "n_sliced": st.n_sliced, "max_log2_elems": st.max_log2_elems,
+                   "steps_per_slice": st.n_steps, "flops_full_slice": st.flops_full_slice,
+                   "path_search_s": search_s,
                    "precision": "complex64, FP32 MFMA (3M), FP64 cross-slice sum"},
-        "tflops": r64["tflops"], "mfma_frac": r64["mfma_frac"], "hbm_gbs": r64["hbm_gbs"],
-        "amp_error": amp_error(r64["result"], ref),
-        "kernel_ms_by_class": r64["kernel_ms_by_class"],
+        "tflops": r64["tflops"],
+        "hbm_gbs": r64["hbm_gbs"], "amp_error": r64.get("amp_error"),
+        "kernel_ms_by_class": r64["kernel_ms_by_class"], "kernel_tflops_by_class": r64["kernel_tflops_by_class"],
         "roofline": r64["roofline"],
+        "cf16": dict(r16, precision="complex FP16 storage, FP16 MFMA (4M) with FP32 accumulate, per-tensor 2^e "
+                                    "scaling, FP64 cross-slice sum"),
     }
-    if not args.no_fp16:
-        r16 = run_form(net, 1, args.steps, args.warmup, "cf16")
-        out["cf16"] = {"value": r16["value"], "unit": "slices/s", "ms_per_step": r16["ms_per_step"],
-                       "tflops": r16["tflops"], "mfma_frac": r16["mfma_frac"], "hbm_gbs": r16["hbm_gbs"],
-                       "amp_error": amp_error(r16["result"], ref), "fp16_overflow": r16["fp16_overflow"],
-                       "kernel_ms_by_class": r16["kernel_ms_by_class"], "roofline": r16["roofline"],
-                       "precision": "complex FP16 storage, FP16 MFMA (4M) with FP32 accumulate, "
-                                    "per-tensor 2^e scaling, FP64 cross-slice sum"}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(c, spec, net.path(), net.slicing(), args.cpu_seconds)
+    if not args.no_extras:
+        out["config2"] = run_config2(args.steps, args.warmup, 64)
+        out["grad"] = grad_timing(args.steps)
+    if not args.no_cpu_baseline and g4 is not None:
+        out["cpu_baseline"] = cpu_baseline_subslice(c, spec, g4, r64["flops_per_step"] / 256)
     print(json.dumps(out), flush=True)
 
 

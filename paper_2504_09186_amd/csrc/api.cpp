@@ -3,12 +3,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <random>
+#include <thread>
 
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -184,22 +186,39 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
     std::vector<char> none(sn.n_labels, 0);
     const std::vector<char>& rm = o->keep_slicing ? fixed : none;
     const int n_runs = method == 2 ? 2 * trials : trials;
+    // Parameters of every run are drawn first, in run order, so that the
+    // runs can go in parallel and the result does not depend on the thread
+    // count; ties keep the earliest run.
+    struct Run {
+      bool bisect;
+      double alpha, tau;
+      PartitionParams prm;
+      uint64_t seed;
+      double f = -1;
+      Path path;
+      std::vector<int> sl;
+    };
+    std::vector<Run> runs(n_runs);
     for (int r = 0; r < n_runs; ++r) {
-      const bool bisect = method == 1 || (method == 2 && r >= trials);
+      Run& R = runs[r];
+      R.bisect = method == 1 || (method == 2 && r >= trials);
       const int t = method == 2 ? r % trials : r;
-      Path p;
-      if (bisect) {
-        PartitionParams prm;
-        prm.imbalance = imbs[rng() % 5];
-        prm.cutoff = cutoffs[rng() % 5];
-        prm.ext_weight = exts[rng() % 4];
-        prm.starts = 4;
-        p = partition_path(sn, rm, prm, rng());
+      if (R.bisect) {
+        R.prm.imbalance = imbs[rng() % 5];
+        R.prm.cutoff = cutoffs[rng() % 5];
+        R.prm.ext_weight = exts[rng() % 4];
+        R.prm.starts = 4;
+        R.seed = rng();
       } else {
-        double a = t == 0 ? 1.0 : alphas[rng() % 4];
-        double tau = t == 0 ? 0.0 : temps[rng() % 4];
-        p = greedy_path(sn, a, tau, rng(), o->keep_slicing ? &fixed : nullptr);
+        R.alpha = t == 0 ? 1.0 : alphas[rng() % 4];
+        R.tau = t == 0 ? 0.0 : temps[rng() % 4];
+        R.seed = rng();
       }
+    }
+    auto run_one = [&](Run& R) {
+      const bool bisect = R.bisect;
+      Path p = bisect ? partition_path(sn, rm, R.prm, R.seed)
+                      : greedy_path(sn, R.alpha, R.tau, R.seed, o->keep_slicing ? &fixed : nullptr);
       {
         // local refinement before slicing: no intermediate may grow
         const int width = sym_max_bits(sn, sym_run(sn, p, rm), rm);
@@ -207,7 +226,12 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
       }
       bool ok;
       std::vector<int> sl;
-      if (o->keep_slicing) {
+      if (bisect) {
+        // slicing interleaved with re-optimisation of the tree
+        std::vector<int> extra = slice_reconf(sn, p, fixed_list, o->max_log2_elems, o->min_sliced, o->max_sliced, 2, &ok);
+        sl = fixed_list;
+        sl.insert(sl.end(), extra.begin(), extra.end());
+      } else if (o->keep_slicing) {
         SymNet sub = sn;
         for (auto& v : sub.leaf) {
           std::vector<int> w;
@@ -224,16 +248,52 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
       } else {
         sl = greedy_slices(sn, p, o->max_log2_elems, o->min_sliced, o->max_sliced, &ok);
       }
-      if (!ok) continue;
+      if (!ok) return;
       std::vector<char> m(sn.n_labels, 0);
       for (int x : sl) m[x] = 1;
       // refine again for the per-slice network, keeping the size cap
       p = optimize_path(sn, p, &m, std::max(o->max_log2_elems, sym_max_bits(sn, sym_run(sn, p, m), m)), 4);
-      double f = sym_total_flops(sym_run(sn, p, m)) * std::ldexp(1.0, (int)sl.size());
-      if (best < 0 || f < best) {
-        best = f;
-        best_path = p;
-        best_sl = sl;
+      // Greedy trials are ranked by the flops of all slices; bisection trials
+      // by the flops all slices execute with shared-prefix reuse (Sec. III-B),
+      // sliced indices in the order the plan will use.
+      double f;
+      if (bisect) {
+        std::vector<int> extra(sl.begin() + fixed_list.size(), sl.end());
+        std::vector<int> ord = fixed_list;
+        for (int x : order_slices(sn, p, extra)) ord.push_back(x);
+        f = reuse_total_flops(sn, p, ord);
+      } else {
+        f = sym_total_flops(sym_run(sn, p, m)) * std::ldexp(1.0, (int)sl.size());
+      }
+      R.f = f;
+      R.path = std::move(p);
+      R.sl = std::move(sl);
+    };
+    {
+      const int nth = std::max(1, std::min<int>(n_runs, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+      std::atomic<int> next{0};
+      std::vector<std::thread> pool;
+      std::vector<std::string> errs(nth);
+      for (int i = 0; i < nth; ++i)
+        pool.emplace_back([&, i] {
+          try {
+            for (int r; (r = next.fetch_add(1)) < n_runs;) run_one(runs[r]);
+          } catch (const Error& e) {
+            errs[i] = e.msg;
+          } catch (const std::exception& e) {
+            errs[i] = e.what();
+          }
+        });
+      for (auto& th : pool) th.join();
+      for (auto& e : errs)
+        if (!e.empty()) fail(MITNC_INVALID_ARG, "path search: " + e);
+    }
+    for (Run& R : runs) {
+      if (R.f < 0) continue;
+      if (best < 0 || R.f < best) {
+        best = R.f;
+        best_path = R.path;
+        best_sl = R.sl;
       }
     }
     if (best < 0) fail(MITNC_UNSUPPORTED, "no path met the size cap within max_sliced");

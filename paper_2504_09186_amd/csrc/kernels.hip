@@ -681,19 +681,22 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
   // Only K < 4 (one k step) pads inside a k step; the padded lanes read an
   // aliased in-bounds entry and are zeroed.
   const bool kvalid = KS > 1 || lq < K;
-  const uint32_t a_lane = L.am[lr];
-  const uint32_t c_lane = L.cm[lr];
-  // Lane offsets in bytes, 32 bits (the launcher checks they fit): the
-  // loads and stores take a scalar 64-bit base plus one vector register.
+  // Lane offsets in bytes, 32 bits (the launcher checks they fit): the four
+  // lowest row bits and k = lq (A), n = lq (C).  The rest of k = 4 ks + lq
+  // and n = 16 cb + 4 i + lq is the same on every lane: 64-bit scalar
+  // offsets added to the scalar base (the offsets of disjoint bits add).
   constexpr uint32_t ESA = sizeof(Raw), ESC = stream_out_bytes<P, EPI>();
-  uint32_t a_k[KS];
+  const uint32_t a_lo = (L.am[lr] + L.ak[lq]) * ESA;
+  const uint32_t c_lo = (L.cm[lr] + L.cn[lq]) * ESC;
+  // (element offsets of at most 2^32-entry tensors: 32-bit scalars)
+  uint32_t a_hi[KS];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) a_k[ks] = (a_lane + L.ak[(4 * ks + lq) & 63]) * ESA;
-  uint32_t c_n[NBLK][4];
+  for (int ks = 0; ks < KS; ++ks) a_hi[ks] = __builtin_amdgcn_readfirstlane(L.ak[(4 * ks) & 63]);
+  uint32_t c_hb[NBLK], c_hi[4];  // n bits 4-5 (column block) and 2-3
 #pragma unroll
-  for (int cb = 0; cb < NBLK; ++cb)
+  for (int cb = 0; cb < NBLK; ++cb) c_hb[cb] = __builtin_amdgcn_readfirstlane(L.cn[(16 * cb) & 63]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) c_n[cb][i] = (c_lane + L.cn[(16 * cb + lq + 4 * i) & 63]) * ESC;
+  for (int i = 0; i < 4; ++i) c_hi[i] = __builtin_amdgcn_readfirstlane(L.cn[4 * i]);
   // Row-block addresses are wave-uniform: keep them in scalar registers.
   const uint64_t mra = uniform64(L.wv[WV_MRA]), mja = uniform64(L.wv[WV_MJA]), mrc = uniform64(L.wv[WV_MRC]),
                  mjc = uniform64(L.wv[WV_MJC]);
@@ -707,7 +710,8 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) dst[r][ks] = *reinterpret_cast<const Raw*>(A + (xra | xja) * ESA + lane_offset(a_k[ks]));
+      for (int ks = 0; ks < KS; ++ks)
+        dst[r][ks] = *reinterpret_cast<const Raw*>(A + ((xra | xja) + (uint64_t)a_hi[ks]) * ESA + lane_offset(a_lo));
       xra = ((xra | ~mra) + 1) & mra;
     }
     xja = ((xja | ~mja) + 1) & mja;
@@ -745,7 +749,9 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
         for (int i = 0; i < 4; ++i)
           if (16 * cb + lq + 4 * i < N) {
             const float t1 = acc[0][cb][i], t2 = acc[1][cb][i], t3 = acc[2][cb][i];
-            mx = fmaxf(mx, stream_store<P, EPI>(out + (xrc | xjc) * ESC, d, lane_offset(c_n[cb][i]), make_float2(t1 - t2, t3 - t1 - t2)));
+            mx = fmaxf(mx, stream_store<P, EPI>(out + ((xrc | xjc) + (uint64_t)(c_hb[cb] + c_hi[i])) * ESC, d,
+                                                lane_offset(c_lo),
+                                                make_float2(t1 - t2, t3 - t1 - t2)));
           }
       xrc = ((xrc | ~mrc) + 1) & mrc;
     }
@@ -813,24 +819,26 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
         }
       }
   }
-  const uint32_t a_lane = L.am[lr];
-  const uint32_t c_lane = L.cm[lr];
-  uint32_t a_k[KS8][2];
+  // 32-bit lane offsets hold the four lowest row bits and k = 2 lq + h (A),
+  // n = lq (C); the rest of k = 8 ks + 2 lq + h and n = 8 nb + 4 h + lq is
+  // wave-uniform and goes to the scalar base, as in stream_body.
+  uint32_t a_lo[2];
   bool kv[KS8][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) a_lo[h] = (L.am[lr] + L.ak[2 * lq + h]) * 4u;
 #pragma unroll
   for (int ks = 0; ks < KS8; ++ks)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = 8 * ks + 2 * lq + h;
-      kv[ks][h] = k < K;
-      a_k[ks][h] = (a_lane + L.ak[k & 63]) * 4u;
-    }
-  constexpr uint32_t ESC = stream_out_bytes<P, EPI>();  // 32-bit byte offsets, as in stream_body
-  uint32_t c_n[NB8][2];
+    for (int h = 0; h < 2; ++h) kv[ks][h] = 8 * ks + 2 * lq + h < K;
+  uint32_t a_hi[KS8];
 #pragma unroll
-  for (int nb = 0; nb < NB8; ++nb)
+  for (int ks = 0; ks < KS8; ++ks) a_hi[ks] = __builtin_amdgcn_readfirstlane(L.ak[(8 * ks) & 63]);
+  constexpr uint32_t ESC = stream_out_bytes<P, EPI>();
+  const uint32_t c_lo = (L.cm[lr] + L.cn[lq]) * ESC;
+  uint32_t c_hb[NB8];  // n bits 3-5 (column block); bit 2 is h
 #pragma unroll
-    for (int h = 0; h < 2; ++h) c_n[nb][h] = (c_lane + L.cn[(8 * nb + lq + 4 * h) & 63]) * ESC;
+  for (int nb = 0; nb < NB8; ++nb) c_hb[nb] = __builtin_amdgcn_readfirstlane(L.cn[(8 * nb) & 63]);
+  const uint32_t c_h4 = __builtin_amdgcn_readfirstlane(L.cn[4]);
   const uint64_t mra = uniform64(L.wv[WV_MRA]), mja = uniform64(L.wv[WV_MJA]), mrc = uniform64(L.wv[WV_MRC]),
                  mjc = uniform64(L.wv[WV_MJC]);
   uint64_t xra = 0, xja = 0, xrc = 0, xjc = 0;
@@ -845,7 +853,9 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
 #pragma unroll
       for (int ks = 0; ks < KS8; ++ks)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) raw[r][ks][h] = *reinterpret_cast<const uint32_t*>(A + (xra | xja) * 4u + lane_offset(a_k[ks][h]));
+        for (int h = 0; h < 2; ++h)
+          raw[r][ks][h] =
+              *reinterpret_cast<const uint32_t*>(A + ((xra | xja) + (uint64_t)a_hi[ks]) * 4u + lane_offset(a_lo[h]));
       xra = ((xra | ~mra) + 1) & mra;
     }
     xja = ((xja | ~mja) + 1) & mja;
@@ -872,7 +882,8 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
 #pragma unroll
         for (int h = 0; h < 2; ++h)
           if (8 * nb + lq + 4 * h < N)
-            mx = fmaxf(mx, stream_store<P, EPI>(out + (xrc | xjc) * ESC, d, lane_offset(c_n[nb][h]),
+            mx = fmaxf(mx, stream_store<P, EPI>(out + ((xrc | xjc) + (uint64_t)(c_hb[nb] + (h ? c_h4 : 0u))) * ESC, d,
+                                                lane_offset(c_lo),
                                                 make_float2(acc[nb][2 * h], acc[nb][2 * h + 1])));
       xrc = ((xrc | ~mrc) + 1) & mrc;
     }

@@ -272,6 +272,87 @@ std::vector<int> greedy_slices(const SymNet& sn, const Path& path, int cap, int 
   return chosen;
 }
 
+// Slicing interleaved with subtree reconfiguration: slices greedily (the
+// rule of greedy_slices) one index at a time, and after every `every`
+// indices re-optimises the tree for the sliced network under the current
+// largest intermediate, so later choices see the improved tree.  Returns the
+// sliced indices; `path` is updated in place.
+std::vector<int> slice_reconf(const SymNet& sn, Path& path, const std::vector<int>& fixed, int cap, int min_sliced,
+                              int max_sliced, int every, bool* ok) {
+  std::vector<char> sl(sn.n_labels, 0);
+  for (int x : fixed) sl[x] = 1;
+  std::vector<int> chosen;
+  *ok = false;
+  SymNet sub = sn;
+  for (int x : fixed) sub.closed[x] = 0;
+  while (true) {
+    auto st = sym_run(sn, path, sl);
+    int mx = sym_max_bits(sn, st, sl);
+    if (mx <= cap && (int)(chosen.size() + fixed.size()) >= min_sliced) {
+      *ok = true;
+      break;
+    }
+    if ((int)(chosen.size() + fixed.size()) >= max_sliced) break;
+    std::vector<char> cand(sn.n_labels, 0);
+    for (auto& s : st)
+      if (s.c_bits == mx)
+        for (int x : s.c)
+          if (sub.closed[x] && !sl[x]) cand[x] = 1;
+    bool any = false;
+    for (int x = 0; x < sn.n_labels; ++x) any |= cand[x];
+    if (!any)
+      for (int x = 0; x < sn.n_labels; ++x) cand[x] = sub.closed[x] && !sl[x];
+    int best = -1;
+    std::pair<int, double> bkey{1 << 30, 0.0};
+    for (int x = 0; x < sn.n_labels; ++x) {
+      if (!cand[x]) continue;
+      sl[x] = 1;
+      auto s2 = sym_run(sn, path, sl);
+      std::pair<int, double> key{sym_max_bits(sn, s2, sl), sym_total_flops(s2)};
+      sl[x] = 0;
+      if (best < 0 || key < bkey || (key == bkey && sn.label_id[x] < sn.label_id[best])) {
+        best = x;
+        bkey = key;
+      }
+    }
+    if (best < 0) break;
+    sl[best] = 1;
+    chosen.push_back(best);
+    if (every > 0 && chosen.size() % every == 0) {
+      const int width = sym_max_bits(sn, sym_run(sn, path, sl), sl);
+      path = optimize_path(sn, path, &sl, std::max(width, cap), 2);
+    }
+  }
+  return chosen;
+}
+
+// Flops of all 2^S slices, run in slice-id order with shared-prefix reuse
+// (Sec. III-B): a step whose subtree holds sliced indices with lowest
+// slice-id bit b is recomputed 2^(S - b) times, a step with none once.
+// `ordered` lists the sliced indices outer -> inner (the last is bit 0).
+double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered) {
+  const int S = (int)ordered.size();
+  std::vector<char> sl(sn.n_labels, 0);
+  std::vector<int> bit(sn.n_labels, -1);
+  for (int i = 0; i < S; ++i) {
+    sl[ordered[i]] = 1;
+    bit[ordered[i]] = S - 1 - i;
+  }
+  const auto st = sym_run(sn, path, sl);
+  const size_t n = sn.leaf.size();
+  std::vector<uint64_t> dep(n + path.size(), 0);
+  for (size_t i = 0; i < n; ++i)
+    for (int x : sn.leaf[i])
+      if (bit[x] >= 0) dep[i] |= 1ull << bit[x];
+  double f = 0;
+  for (size_t s = 0; s < path.size(); ++s) {
+    const uint64_t d = dep[path[s].first] | dep[path[s].second];
+    dep[n + s] = d;
+    f += st[s].flops * (d ? std::ldexp(1.0, S - __builtin_ctzll(d)) : 1.0);
+  }
+  return f;
+}
+
 // Outer -> inner order: decreasing recomputation cost, i.e. the flops of all
 // steps whose subtree holds a leaf carrying the index.  Inner (fast-varying)
 // indices then force the least recomputation between consecutive slices.

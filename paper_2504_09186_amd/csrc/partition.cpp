@@ -171,187 +171,267 @@ int greedy_part(State& S, std::vector<int> V) {
   return V[0];
 }
 
-// Bisection of the live ids V.  side[i] in {0, 1} for V[i].
-struct Bisector {
-  const State& S;
-  const std::vector<int>& V;
-  double ext_weight;
-  double imbalance;
-  std::mt19937_64& rng;
+// Hypergraph of one bisection: vertices with weights (tensors merged by
+// coarsening), nets with weights (indices).
+struct Graph {
   int m = 0;
-  // local hypergraph
-  std::vector<std::vector<int>> vedges;  // per vertex: local edge ids
-  std::vector<std::vector<int>> epins;   // per edge: local vertices
-  std::vector<double> ew;                // per edge weight
+  std::vector<int> vw;                   // vertex weights
+  std::vector<std::vector<int>> vedges;  // per vertex: incident nets
+  std::vector<std::vector<int>> epins;   // per net: vertices (distinct)
+  std::vector<double> ew;                // net weights
+  int total_weight() const { return std::accumulate(vw.begin(), vw.end(), 0); }
+};
 
-  Bisector(const State& s, const std::vector<int>& v, double ext, double imb, std::mt19937_64& r)
-      : S(s), V(v), ext_weight(ext), imbalance(imb), rng(r) {
-    m = (int)V.size();
-    std::vector<std::vector<int>> in_v;  // label -> local holders
-    std::vector<int> lab_edge(S.sn.n_labels, -1);
-    vedges.assign(m, {});
-    std::vector<int> seen;
-    for (int i = 0; i < m; ++i)
-      for (int x : S.t[V[i]]) {
-        if (lab_edge[x] < 0) {
-          lab_edge[x] = (int)epins.size();
-          epins.push_back({});
-          seen.push_back(x);
-        }
-        epins[lab_edge[x]].push_back(i);
+Graph local_graph(const State& S, const std::vector<int>& V, double ext_weight) {
+  Graph g;
+  g.m = (int)V.size();
+  g.vw.assign(g.m, 1);
+  g.vedges.assign(g.m, {});
+  std::vector<int> lab_net(S.sn.n_labels, -1), net_lab;
+  std::vector<std::vector<int>> pins;
+  for (int i = 0; i < g.m; ++i)
+    for (int x : S.t[V[i]]) {
+      if (lab_net[x] < 0) {
+        lab_net[x] = (int)pins.size();
+        pins.push_back({});
+        net_lab.push_back(x);
       }
-    // keep edges with >= 2 pins in V
-    std::vector<int> remap(epins.size(), -1);
-    std::vector<std::vector<int>> pins2;
-    for (size_t e = 0; e < epins.size(); ++e) {
-      if (epins[e].size() < 2) continue;
-      const int x = seen[e];
-      const bool internal = !S.sn.is_out[x] && S.count[x] == (int)epins[e].size();
-      remap[e] = (int)pins2.size();
-      pins2.push_back(epins[e]);
-      ew.push_back(internal ? 1.0 : ext_weight);
+      pins[lab_net[x]].push_back(i);
     }
-    epins.swap(pins2);
-    for (size_t e = 0; e < epins.size(); ++e)
-      for (int v : epins[e]) vedges[v].push_back((int)e);
+  for (size_t e = 0; e < pins.size(); ++e) {
+    if (pins[e].size() < 2) continue;  // a net on one vertex is never cut
+    const int x = net_lab[e];
+    const bool internal = !S.sn.is_out[x] && S.count[x] == (int)pins[e].size();
+    g.epins.push_back(pins[e]);
+    g.ew.push_back(internal ? 1.0 : ext_weight);
   }
+  for (size_t e = 0; e < g.epins.size(); ++e)
+    for (int v : g.epins[e]) g.vedges[v].push_back((int)e);
+  return g;
+}
 
-  double cut_of(const std::vector<int>& side) const {
-    double c = 0;
-    for (size_t e = 0; e < epins.size(); ++e) {
-      int n1 = 0;
-      for (int v : epins[e]) n1 += side[v];
-      if (n1 > 0 && n1 < (int)epins[e].size()) c += ew[e];
+// Heavy-net matching: each vertex pairs with the unmatched neighbour it
+// shares the most net weight with (per unit of combined vertex weight).
+// map[v] = coarse vertex.  Returns the coarse graph.
+Graph coarsen(const Graph& g, std::vector<int>& map, std::mt19937_64& rng, int max_vw) {
+  std::vector<int> order(g.m);
+  std::iota(order.begin(), order.end(), 0);
+  std::shuffle(order.begin(), order.end(), rng);
+  std::vector<int> match(g.m, -1);
+  std::vector<double> conn(g.m, 0.0);
+  std::vector<int> touched;
+  for (int v : order) {
+    if (match[v] >= 0) continue;
+    touched.clear();
+    for (int e : g.vedges[v]) {
+      const double w = g.ew[e] / (double)(g.epins[e].size() - 1);
+      for (int u : g.epins[e])
+        if (u != v && match[u] < 0) {
+          if (conn[u] == 0.0) touched.push_back(u);
+          conn[u] += w;
+        }
     }
-    return c;
+    int best = -1;
+    double bv = 0;
+    for (int u : touched) {
+      if (g.vw[u] + g.vw[v] <= max_vw) {
+        const double sc = conn[u] / (double)(g.vw[u] + g.vw[v]);
+        if (sc > bv) {
+          bv = sc;
+          best = u;
+        }
+      }
+      conn[u] = 0.0;
+    }
+    match[v] = best >= 0 ? best : v;
+    if (best >= 0) match[best] = v;
   }
+  Graph c;
+  map.assign(g.m, -1);
+  for (int v = 0; v < g.m; ++v) {
+    if (map[v] >= 0) continue;
+    map[v] = c.m;
+    if (match[v] != v) map[match[v]] = c.m;
+    c.vw.push_back(g.vw[v] + (match[v] != v ? g.vw[match[v]] : 0));
+    ++c.m;
+  }
+  c.vedges.assign(c.m, {});
+  std::vector<int> stamp(c.m, -1);
+  for (size_t e = 0; e < g.epins.size(); ++e) {
+    std::vector<int> p;
+    for (int v : g.epins[e]) {
+      const int cv = map[v];
+      if (stamp[cv] != (int)e) {
+        stamp[cv] = (int)e;
+        p.push_back(cv);
+      }
+    }
+    if (p.size() < 2) continue;
+    c.epins.push_back(std::move(p));
+    c.ew.push_back(g.ew[e]);
+  }
+  for (size_t e = 0; e < c.epins.size(); ++e)
+    for (int v : c.epins[e]) c.vedges[v].push_back((int)e);
+  return c;
+}
 
-  // Greedy growth of side 1 from a random vertex up to `target` vertices.
-  void grow(std::vector<int>& side, int target) {
-    side.assign(m, 0);
-    std::vector<double> conn(m, 0.0);  // weight of edges into the grown part
-    std::uniform_int_distribution<int> pick(0, m - 1);
-    int seed = pick(rng);
-    int size = 0;
-    std::uniform_real_distribution<double> jit(0.0, 1e-3);
-    auto add = [&](int v) {
-      side[v] = 1;
-      ++size;
-      for (int e : vedges[v])
-        for (int u : epins[e])
-          if (!side[u]) conn[u] += ew[e];
-    };
-    add(seed);
-    while (size < target) {
-      int best = -1;
-      double bv = -1e300;
+double cut_of(const Graph& g, const std::vector<int>& side) {
+  double c = 0;
+  for (size_t e = 0; e < g.epins.size(); ++e) {
+    int n1 = 0;
+    for (int v : g.epins[e]) n1 += side[v];
+    if (n1 > 0 && n1 < (int)g.epins[e].size()) c += g.ew[e];
+  }
+  return c;
+}
+
+// Fiduccia-Mattheyses passes; the weight of side 1 stays within [lo, hi].
+void fm_refine(const Graph& g, std::vector<int>& side, int lo, int hi, int max_passes) {
+  const int m = g.m;
+  std::vector<std::array<int, 2>> cnt(g.epins.size());
+  auto gain = [&](int v) {
+    const int s = side[v];
+    double r = 0;
+    for (int e : g.vedges[v]) {
+      if (cnt[e][s] == 1 && cnt[e][1 - s] > 0) r += g.ew[e];
+      else if (cnt[e][1 - s] == 0 && cnt[e][s] > 1) r -= g.ew[e];
+    }
+    return r;
+  };
+  for (int pass = 0; pass < max_passes; ++pass) {
+    for (size_t e = 0; e < g.epins.size(); ++e) {
+      cnt[e] = {0, 0};
+      for (int v : g.epins[e]) cnt[e][side[v]]++;
+    }
+    int w1 = 0;
+    for (int v = 0; v < m; ++v) w1 += side[v] * g.vw[v];
+    std::vector<double> gv(m);
+    for (int v = 0; v < m; ++v) gv[v] = gain(v);
+    std::vector<char> locked(m, 0);
+    std::vector<int> moves;
+    double cum = 0, best_cum = 0;
+    size_t best_len = 0;
+    for (int step = 0; step < m; ++step) {
+      int bv = -1;
+      double bg = -1e300;
       for (int v = 0; v < m; ++v) {
-        if (side[v]) continue;
-        // prefer vertices tied to the part, with few ties elsewhere
-        double other = 0;
-        for (int e : vedges[v]) other += ew[e];
-        const double g = 2 * conn[v] - other + jit(rng);
-        if (g > bv) {
-          bv = g;
-          best = v;
+        if (locked[v]) continue;
+        const int w_after = w1 + (side[v] ? -g.vw[v] : g.vw[v]);
+        if (w_after < lo || w_after > hi) continue;
+        if (gv[v] > bg) {
+          bg = gv[v];
+          bv = v;
         }
       }
-      add(best);
+      if (bv < 0) break;
+      const int s = side[bv];
+      for (int e : g.vedges[bv]) {
+        cnt[e][s]--;
+        cnt[e][1 - s]++;
+      }
+      side[bv] = 1 - s;
+      w1 += s ? -g.vw[bv] : g.vw[bv];
+      locked[bv] = 1;
+      cum += bg;
+      moves.push_back(bv);
+      for (int e : g.vedges[bv])
+        for (int u : g.epins[e])
+          if (!locked[u]) gv[u] = gain(u);
+      if (cum > best_cum + 1e-12) {
+        best_cum = cum;
+        best_len = moves.size();
+      }
+    }
+    for (size_t k = moves.size(); k > best_len; --k) side[moves[k - 1]] ^= 1;
+    if (best_len == 0) break;
+  }
+}
+
+// Greedy growth of side 1 from a random vertex up to weight `target`.
+void grow(const Graph& g, std::vector<int>& side, int target, std::mt19937_64& rng) {
+  side.assign(g.m, 0);
+  std::vector<double> conn(g.m, 0.0), deg(g.m, 0.0);
+  for (int v = 0; v < g.m; ++v)
+    for (int e : g.vedges[v]) deg[v] += g.ew[e];
+  std::uniform_real_distribution<double> jit(0.0, 1e-3);
+  int w = 0;
+  auto add = [&](int v) {
+    side[v] = 1;
+    w += g.vw[v];
+    for (int e : g.vedges[v])
+      for (int u : g.epins[e])
+        if (!side[u]) conn[u] += g.ew[e];
+  };
+  add(std::uniform_int_distribution<int>(0, g.m - 1)(rng));
+  while (w < target) {
+    int best = -1;
+    double bv = -1e300;
+    for (int v = 0; v < g.m; ++v) {
+      if (side[v]) continue;
+      const double sc = 2 * conn[v] - deg[v] + jit(rng);
+      if (sc > bv) {
+        bv = sc;
+        best = v;
+      }
+    }
+    if (best < 0) break;
+    add(best);
+  }
+}
+
+// Multilevel bisection: coarsen to at most `coarse_m` vertices, several
+// grown and refined starts there, then project back refining each level.
+std::vector<int> bisect(const Graph& g0, double imbalance, int starts, std::mt19937_64& rng) {
+  const int W = g0.total_weight();
+  const double half = W / 2.0;
+  const int lo = std::max(1, (int)std::floor(half * (1.0 - imbalance)));
+  const int hi = std::min(W - 1, (int)std::ceil(half * (1.0 + imbalance)));
+  std::vector<Graph> levels{g0};
+  std::vector<std::vector<int>> maps;
+  const int coarse_m = 40;
+  while (levels.back().m > coarse_m) {
+    std::vector<int> map;
+    Graph c = coarsen(levels.back(), map, rng, std::max(2, W / 8));
+    if (c.m > 0.9 * levels.back().m) break;  // matching stalled
+    maps.push_back(std::move(map));
+    levels.push_back(std::move(c));
+  }
+  const Graph& gc = levels.back();
+  std::vector<int> best;
+  double best_cut = 0;
+  std::uniform_int_distribution<int> tg(lo, hi);
+  for (int st = 0; st < starts; ++st) {
+    std::vector<int> side;
+    grow(gc, side, tg(rng), rng);
+    fm_refine(gc, side, lo, hi, 8);
+    int w1 = 0;
+    for (int v = 0; v < gc.m; ++v) w1 += side[v] * gc.vw[v];
+    if (w1 < lo || w1 > hi) continue;
+    const double c = cut_of(gc, side);
+    if (best.empty() || c < best_cut) {
+      best = side;
+      best_cut = c;
     }
   }
-
-  // Fiduccia-Mattheyses passes; side sizes kept within [lo, hi].
-  void refine(std::vector<int>& side, int lo, int hi) {
-    std::vector<std::array<int, 2>> cnt(epins.size());
-    auto recount = [&]() {
-      for (size_t e = 0; e < epins.size(); ++e) {
-        cnt[e] = {0, 0};
-        for (int v : epins[e]) cnt[e][side[v]]++;
-      }
-    };
-    auto gain = [&](int v) {
-      const int s = side[v];
-      double g = 0;
-      for (int e : vedges[v]) {
-        if (cnt[e][s] == 1 && cnt[e][1 - s] > 0) g += ew[e];
-        else if (cnt[e][1 - s] == 0 && cnt[e][s] > 1) g -= ew[e];
-      }
-      return g;
-    };
-    for (int pass = 0; pass < 8; ++pass) {
-      recount();
-      int n1 = 0;
-      for (int v = 0; v < m; ++v) n1 += side[v];
-      std::vector<double> g(m);
-      for (int v = 0; v < m; ++v) g[v] = gain(v);
-      std::vector<char> locked(m, 0);
-      std::vector<int> moves;
-      double cum = 0, best_cum = 0;
-      size_t best_len = 0;
-      for (int step = 0; step < m; ++step) {
-        int bv = -1;
-        double bg = -1e300;
-        for (int v = 0; v < m; ++v) {
-          if (locked[v]) continue;
-          const int n1_after = n1 + (side[v] ? -1 : 1);
-          if (n1_after < lo || n1_after > hi) continue;
-          if (g[v] > bg) {
-            bg = g[v];
-            bv = v;
-          }
-        }
-        if (bv < 0) break;
-        // move bv
-        const int s = side[bv];
-        for (int e : vedges[bv]) {
-          cnt[e][s]--;
-          cnt[e][1 - s]++;
-        }
-        side[bv] = 1 - s;
-        n1 += s ? -1 : 1;
-        locked[bv] = 1;
-        cum += bg;
-        moves.push_back(bv);
-        for (int e : vedges[bv])
-          for (int u : epins[e])
-            if (!locked[u]) g[u] = gain(u);
-        if (cum > best_cum + 1e-12) {
-          best_cum = cum;
-          best_len = moves.size();
-        }
-      }
-      // roll back past the best prefix
-      for (size_t k = moves.size(); k > best_len; --k) side[moves[k - 1]] ^= 1;
-      if (best_len == 0) break;
-    }
-  }
-
-  std::vector<int> run(int starts) {
-    std::vector<int> best;
-    double best_cut = 0;
-    const double half = m / 2.0;
-    const int lo = std::max(1, (int)std::floor(half * (1.0 - imbalance)));
-    const int hi = std::min(m - 1, (int)std::ceil(half * (1.0 + imbalance)));
-    std::uniform_int_distribution<int> tg(lo, hi);
-    for (int st = 0; st < starts; ++st) {
-      std::vector<int> side;
-      grow(side, tg(rng));
-      refine(side, lo, hi);
-      const double c = cut_of(side);
-      if (best.empty() || c < best_cut) {
-        best = side;
-        best_cut = c;
-      }
-    }
+  if (best.empty()) {  // no balanced start at the coarsest level: grow on the finest
+    grow(g0, best, (lo + hi) / 2, rng);
+    fm_refine(g0, best, lo, hi, 8);
     return best;
   }
-};
+  for (int L = (int)levels.size() - 2; L >= 0; --L) {
+    std::vector<int> fine(levels[L].m);
+    for (int v = 0; v < levels[L].m; ++v) fine[v] = best[maps[L][v]];
+    best.swap(fine);
+    fm_refine(levels[L], best, lo, hi, 8);
+  }
+  return best;
+}
 
 int build(State& S, const std::vector<int>& V, const PartitionParams& prm, std::mt19937_64& rng) {
   if (V.size() == 1) return V[0];
   if ((int)V.size() <= prm.cutoff) return greedy_part(S, V);
-  Bisector bs(S, V, prm.ext_weight, prm.imbalance, rng);
-  std::vector<int> side = bs.run(prm.starts);
+  const Graph g = local_graph(S, V, prm.ext_weight);
+  std::vector<int> side = bisect(g, prm.imbalance, prm.starts, rng);
   std::vector<int> V0, V1;
   for (size_t i = 0; i < V.size(); ++i) (side[i] ? V1 : V0).push_back(V[i]);
   if (V0.empty() || V1.empty()) return greedy_part(S, V);

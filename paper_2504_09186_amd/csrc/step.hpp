@@ -159,10 +159,13 @@ inline constexpr bool stream_fits(int mb, int nb, int kb, int bb) {
   return bb <= 10 && mb >= kStreamMinM && kb <= 6 && nb <= 6 && (kb > 2 ? kb - 2 : 0) + (nb > 4 ? nb - 4 : 0) <= 4;
 }
 
-// The stream kernels address a lane's entries as a scalar 64-bit base plus a
-// 32-bit byte offset that holds the lane-row and k (A) or lane-row and n (C)
-// address bits: those bits' largest offset must stay below 4 GiB at the
-// entry sizes (A, C or the FP64 result) the launch uses.
+// The stream kernels address a lane's entries as a scalar 64-bit base (row
+// block, batch, and the k or n bits that are the same on every lane of a
+// wave) plus a 32-bit byte offset that holds only the lane-varying bits: the
+// four lowest row bits and the lowest k bits (two for complex64 entries,
+// three for 16-bit ones) in A, the four lowest row bits and the two lowest n
+// bits in C.  Those bits' largest offset must stay below 4 GiB at the entry
+// sizes (A, C or the FP64 result) the launch uses.
 inline bool stream_offsets_fit(const StepDesc& d, uint64_t a_bytes, uint64_t c_bytes) {
   uint64_t a = 0, c = 0;
   auto add = [](uint64_t& m, const uint8_t* pos, int n) {
@@ -173,7 +176,10 @@ inline bool stream_offsets_fit(const StepDesc& d, uint64_t a_bytes, uint64_t c_b
     return true;
   };
   const int lanes = d.mb < 4 ? d.mb : 4;
-  if (!add(a, d.am, lanes) || !add(a, d.ak, d.kb) || !add(c, d.cm, lanes) || !add(c, d.cn, d.nb)) return false;
+  const int k_lane = a_bytes == 8 ? 2 : 3;
+  if (!add(a, d.am, lanes) || !add(a, d.ak, d.kb < k_lane ? d.kb : k_lane) || !add(c, d.cm, lanes) ||
+      !add(c, d.cn, d.nb < 2 ? d.nb : 2))
+    return false;
   return a * a_bytes < (1ull << 32) && c * c_bytes < (1ull << 32);
 }
 

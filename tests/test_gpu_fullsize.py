@@ -121,3 +121,62 @@ def test_config2_all_slices_half_precision(prec, xeb_bound, rel_bound):
     assert mx < 65504.0
     assert loss <= xeb_bound
     assert rel <= rel_bound
+
+
+GOLDEN4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config4_subslices.json")
+
+
+def _config4_subslice_plan(prec):
+    """The 7x8-qubit, 20-cycle network (qubits 44-55 open) with the oracle's
+    sliced indices kept (outermost, in its order) and the library's own
+    path; extra inner indices only if its path needs them for 2^30."""
+    from paper_2504_09186_amd import tnc
+    if not os.path.exists(GOLDEN4):
+        pytest.skip("golden file not generated")
+    with open(GOLDEN4) as f:
+        g = json.load(f)
+    c = synth.lattice_circuit(7, 8, 20, seed=1004)
+    spec = synth.output_spec(56, list(range(44, 56)), seed=2004)
+    net = tnc.Network(c, spec)
+    lab = g["oracle_sliced_labels"]
+    net.set_slicing(lab)
+    net.path_search(seed=3004, trials=8, max_log2=30, min_sliced=len(lab), max_sliced=62, keep_slicing=True,
+                    method=1)
+    assert net.slicing()[:len(lab)] == lab
+    extra = len(net.slicing()) - len(lab)
+    plan = tnc.Plan(net, precision=prec)
+    return g, plan, extra
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_config4_oracle_subslices(prec):
+    """Full-size 56-qubit network, sub-slices of the oracle's 60-index slicing
+    (each a partial sum over the sliced indices' other values, about 4e12
+    flops for the oracle): complex64 within 1e-5 relative L2 of the FP64
+    oracle; complex FP16 (exponents calibrated on the first checked
+    sub-slice) within 2e-2 relative L2 and an XEB fidelity loss <= 1e-3 over
+    the 2^12 open amplitudes of each sub-slice."""
+    require_gpu()
+    import torch
+
+    import oracle
+    g, plan, extra = _config4_subslice_plan(prec)
+    to_c = lambda v: np.array([a + 1j * b for a, b in v])  # noqa: E731
+    plan.upload()
+    for sid in g["sub_slice_ids"]:
+        s0, s1 = sid << extra, (sid + 1) << extra
+        if prec:
+            plan.calibrate(s0, min(s1, s0 + 2))
+        acc = plan.new_result()
+        print(f"config 4: sub-slice {sid} (library slices {s0}..{s1 - 1}), precision {prec}", flush=True)
+        plan.execute(acc, s0, s1)
+        torch.cuda.synchronize()
+        got = acc.cpu().numpy()
+        ref = to_c(g["sub_slice_results"][str(sid)])
+        rel = oracle.rel_l2(got, ref)
+        print(f"rel-L2 {rel:.3e}")
+        if prec == 0:
+            assert rel <= 1e-5
+        else:
+            assert rel <= 2e-2
+            assert abs(1.0 - oracle.xeb_ratio(got, ref)) <= 1e-3
