@@ -340,3 +340,78 @@ def test_rel_l2_hand_values():
     assert oracle.rel_l2(np.array([3.0, 4.0 + 5j]), np.array([3.0, 4.0])) == pytest.approx(1.0, rel=1e-15)
     # a = (1, 1, 1, 1), b = (1, 1, 1, 2i - 1): ||b - a|| = |2i - 2| = sqrt 8, ||a|| = 2
     assert oracle.rel_l2(np.array([1, 1, 1, 2j - 1]), np.ones(4)) == pytest.approx(np.sqrt(2.0), rel=1e-15)
+
+
+# ---------------------------------------------------------------- oracle planning for large networks
+def _is_valid_path(n, path):
+    alive = set(range(n))
+    for t, (i, j) in enumerate(path):
+        if i == j or i not in alive or j not in alive:
+            return False
+        alive -= {i, j}
+        alive.add(n + t)
+    return len(path) == n - 1
+
+
+@pytest.mark.parametrize("seed,imb", [(0, 0.1), (1, 0.5), (2, 0.7)])
+def test_bisection_path_valid_and_same_amplitudes(seed, imb):
+    """The recursive-bisection path is a valid SSA path (every tensor used
+    once) and contracts to the state-vector amplitudes, sliced or not."""
+    from oracle import planning
+    c = synth.lattice_circuit(3, 4, 8, seed=70 + seed)
+    spec = synth.output_spec(12, [9, 10, 11], seed=71)
+    net = oracle.build_network(c, spec)
+    path = planning.bisection_path(net, imbalance=imb, seed=seed, cutoff=4)
+    assert _is_valid_path(net.n_leaves, path)
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    got = oracle.contract_network(net, path).reshape(-1)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-14)
+    sl = net.closed_labels()[5:8]
+    assert np.allclose(oracle.contract_sliced(net, path, sl).reshape(-1), ref, rtol=1e-12, atol=1e-14)
+
+
+def test_bitset_stats_match_path_stats():
+    """The bitset statistics (C = A xor B plus shared outputs) give the same
+    largest intermediate and flops as the set-based path_stats, with and
+    without sliced labels."""
+    from oracle import planning
+    c = synth.lattice_circuit(4, 4, 10, seed=80)
+    spec = synth.output_spec(16, [13, 14, 15], seed=81)
+    net = oracle.build_network(c, spec)
+    path = planning.bisection_path(net, seed=3)
+    masks, out, labels = planning._bitsets(net)
+    for sl in ([], net.closed_labels()[::17]):
+        cut = sum(1 << labels.index(x) for x in sl)
+        big, flops = planning._bit_stats(masks, out, path, cut)
+        st = planning.path_stats(net, path, sl)
+        assert big == max(s[0] for s in st)
+        assert np.isclose(flops, sum(s[1] for s in st), rtol=1e-12)
+
+
+def test_choose_slices_eval_follows_the_rule():
+    """Slicing with evaluations reaches the cap, and each chosen label is
+    the best (largest intermediate, then flops, then label) among the closed
+    labels of the largest intermediates at that point: checked by brute
+    force with path_stats."""
+    from oracle import planning
+    c = synth.lattice_circuit(3, 4, 10, seed=90)
+    spec = synth.output_spec(12, [10, 11], seed=91)
+    net = oracle.build_network(c, spec)
+    path = planning.bisection_path(net, seed=1)
+    cap = max(s[0] for s in planning.path_stats(net, path)) - 3
+    chosen = planning.choose_slices_eval(net, path, cap)
+    assert max(s[0] for s in planning.path_stats(net, path, chosen)) <= cap
+    closed = net.closed_labels()
+    for i, x in enumerate(chosen):
+        before = chosen[:i]
+        st = planning.path_stats(net, path, before)
+        big = max(s[0] for s in st)
+        keys = []
+        for y in closed:
+            if y in before:
+                continue
+            s2 = planning.path_stats(net, path, before + [y])
+            keys.append((max(s[0] for s in s2), sum(s[1] for s in s2), y))
+        best = min(keys)
+        mine = [k for k in keys if k[2] == x][0]
+        assert mine[:2] == best[:2]
