@@ -348,6 +348,68 @@ def run_config2(steps, warmup, trials):
     return out
 
 
+MICRO = {
+    # name: (m, n, k bits, kernel class or -1, description)
+    "square": (15, 15, 13, -1, "MB-square: rank-28 x rank-28 tensors, 13 common indices (M = N = 2^15, K = 2^13)"),
+    "stem": (25, 5, 5, -1, "MB-stem: rank-30 tensor x rank-10 tensor, 5 common (M = 2^25, K = N = 2^5)"),
+    "gepdot": (3, 3, 27, -1, "MB-GEPDOT: rank-30 x rank-30, 27 common (M = N = 2^3, K = 2^27)"),
+}
+
+
+def micro(name, precision, reps):
+    """Per-class microbenchmark: one pairwise contraction through the
+    library's one-step entry point, seeded complex normal operands with
+    random bit layouts (the permutation is part of the load), timed with
+    events on the launching stream."""
+    import numpy as np
+    import torch
+
+    from paper_2504_09186_amd import tnc
+    mb, nb, kb, kern, desc = MICRO[name]
+    rng = np.random.default_rng(5000 + len(name))
+    M = [1000 + i for i in range(mb)]
+    N = [2000 + i for i in range(nb)]
+    K = [3000 + i for i in range(kb)]
+    la = [int(x) for x in rng.permutation(M + K)]
+    lb = [int(x) for x in rng.permutation(K + N)]
+    lc = [int(x) for x in rng.permutation(M + N)]
+    if name == "stem":
+        # the planner's layout for a stem step: the new indices take the
+        # address bits the contracted ones free ("in place")
+        it = iter(N)
+        lc = [next(it) if x in K else x for x in la]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5001)
+    if precision == 0:
+        a = torch.randn(1 << len(la), dtype=torch.complex64, device="cuda", generator=gen)
+        b = torch.randn(1 << len(lb), dtype=torch.complex64, device="cuda", generator=gen)
+        esz = 8
+    else:
+        a = torch.randn(2 << len(la), dtype=torch.float16, device="cuda", generator=gen).view(torch.int32)
+        b = torch.randn(2 << len(lb), dtype=torch.float16, device="cuda", generator=gen).view(torch.int32)
+        esz = 4
+    out = torch.empty(1 << len(lc), dtype=torch.complex64 if precision == 0 else torch.int32, device="cuda")
+    tnc.contract(a, la, b, lb, lc, kernel=kern, precision=precision, out=out)  # warmup
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        tnc.contract(a, la, b, lb, lc, kernel=kern, precision=precision, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = 8.0 * 2.0 ** (mb + nb + kb)
+    nbytes = esz * (2.0 ** len(la) + 2.0 ** len(lb) + 2.0 ** len(lc))
+    # the complex64 tile and stream kernels run the 3M split; the split-K
+    # kernels and the 16-bit forms run all four real products
+    ex = 0.75 if precision == 0 and name in ("square", "stem") else 1.0
+    peak = PEAK_FP32 if precision == 0 else PEAK_FP16
+    return {"micro": name, "what": desc, "precision": "c64" if precision == 0 else "cf16", "ms": ms,
+            "tflops_4m_count": flops / ms / 1e9, "tflops_executed": flops * ex / ms / 1e9,
+            "mfma_frac": flops * ex / ms / 1e9 / peak, "gbs": nbytes / ms / 1e6, "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBS,
+            "algorithmic_bytes": nbytes, "algorithmic_flops": flops, "reps": reps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,6 +422,8 @@ def main():
     ap.add_argument("--workload", choices=["rqc7x8", "rqc5x6"], default="rqc7x8")
     ap.add_argument("--grad", action="store_true",
                     help="only time the differentiation form (forward vs backward over all slices) and exit")
+    ap.add_argument("--micro", choices=sorted(MICRO), help="only run one per-class microbenchmark and exit")
+    ap.add_argument("--micro-precision", type=int, default=0, help="0 complex64, 1 complex FP16")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -384,6 +448,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.grad:
         print(json.dumps(grad_timing(args.steps)), flush=True)
+        return
+    if args.micro:
+        print(json.dumps(micro(args.micro, args.micro_precision, max(1, args.steps))), flush=True)
         return
     if args.workload == "rqc5x6":
         r = run_config2(args.steps, args.warmup, 64)

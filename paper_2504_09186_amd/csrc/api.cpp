@@ -253,11 +253,11 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
       for (int x : sl) m[x] = 1;
       // refine again for the per-slice network, keeping the size cap
       p = optimize_path(sn, p, &m, std::max(o->max_log2_elems, sym_max_bits(sn, sym_run(sn, p, m), m)), 4);
-      // Greedy trials are ranked by the flops of all slices; bisection trials
-      // by the flops all slices execute with shared-prefix reuse (Sec. III-B),
-      // sliced indices in the order the plan will use.
+      // Method 0 ranks by the flops of all slices; methods 1 and 2 rank every
+      // trial by the flops all slices execute with shared-prefix reuse
+      // (Sec. III-B), sliced indices in the order the plan will use.
       double f;
-      if (bisect) {
+      if (method != 0) {
         std::vector<int> extra(sl.begin() + fixed_list.size(), sl.end());
         std::vector<int> ord = fixed_list;
         for (int x : order_slices(sn, p, extra)) ord.push_back(x);

@@ -1908,7 +1908,8 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
                 (unsigned)(1ull << d.bb));
       if constexpr (P == 0) {
         if (kclass == MITNC_K_TILE)
-          launch_k(k_tile<4, 1, 1, 2, 4, 8>, grid, dim3(256), 0, s, t, d);
+          launch_k(k_tile<MITNC_TILE_WM, MITNC_TILE_WN, MITNC_TILE_WK, MITNC_TILE_BM, MITNC_TILE_BN, MITNC_TILE_TK>,
+                   grid, dim3(256), 0, s, t, d);
         else if (kclass == MITNC_K_TALL)
           launch_k(k_tile<4, 1, 1, 2, 1, 16>, grid, dim3(256), 0, s, t, d);
         else if (skinny_fits(d.mb, d.nb, d.kb, d.bb, d.ks_bits))
@@ -1917,7 +1918,9 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
           launch_k(k_tile<1, 1, 4, 1, 1, 64>, grid, dim3(256), 0, s, t, d);
       } else {
         if (kclass == MITNC_K_TILE)
-          launch_k(k_tile_h<P, 2, 2, 1, 4, 4, 32>, grid, dim3(256), 0, s, t, d);
+          launch_k(k_tile_h<P, MITNC_TILEH_WM, MITNC_TILEH_WN, MITNC_TILEH_WK, MITNC_TILEH_BM, MITNC_TILEH_BN,
+                            MITNC_TILEH_TK>,
+                   grid, dim3(256), 0, s, t, d);
         else if (kclass == MITNC_K_TALL)
           launch_k(k_tile_h<P, 4, 1, 1, 2, 2, 32>, grid, dim3(256), 0, s, t, d);
         else

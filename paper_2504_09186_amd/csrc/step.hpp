@@ -99,12 +99,39 @@ struct SmallRevOp {
 struct TileGeom {
   int tm_bits, tn_bits, tk_bits;
 };
-// complex64 (3M split on FP32 MFMA)
-inline constexpr TileGeom geom_tile() { return {7, 6, 3}; }    // 128 x 64 complex, k 8
+// Wave layout of the square-tile kernels (TILE class): WM x WN x WK waves,
+// BM x BN MFMA blocks per wave, TK complex k per k tile.  Compile-time
+// constants (overridable with -D for tuning builds); the plan's tile bits
+// follow from them.
+#ifndef MITNC_TILE_WM
+#define MITNC_TILE_WM 4
+#define MITNC_TILE_WN 1
+#define MITNC_TILE_WK 1
+#define MITNC_TILE_BM 2
+#define MITNC_TILE_BN 4
+#define MITNC_TILE_TK 8
+#endif
+#ifndef MITNC_TILEH_WM
+#define MITNC_TILEH_WM 2
+#define MITNC_TILEH_WN 2
+#define MITNC_TILEH_WK 1
+#define MITNC_TILEH_BM 4
+#define MITNC_TILEH_BN 4
+#define MITNC_TILEH_TK 32
+#endif
+inline constexpr int ilog2_exact(int x) { return x <= 1 ? 0 : 1 + ilog2_exact(x >> 1); }
+// complex64 (3M split on FP32 MFMA): 16 x 16 MFMA blocks
+inline constexpr TileGeom geom_tile() {
+  return {ilog2_exact(MITNC_TILE_WM * MITNC_TILE_BM * 16), ilog2_exact(MITNC_TILE_WN * MITNC_TILE_BN * 16),
+          ilog2_exact(MITNC_TILE_TK)};
+}
 inline constexpr TileGeom geom_tall() { return {7, 4, 4}; }    // 128 x 16, k 16
 inline constexpr TileGeom geom_splitk() { return {4, 4, 6}; }  // 16 x 16, k 64 (4 waves split k)
 // complex FP16 / BF16 (4M split on 16x16x32 MFMA)
-inline constexpr TileGeom geom_tile_h() { return {7, 6, 5}; }    // 128 x 64, k 32
+inline constexpr TileGeom geom_tile_h() {  // 16 rows x 8 complex columns per MFMA block
+  return {ilog2_exact(MITNC_TILEH_WM * MITNC_TILEH_BM * 16), ilog2_exact(MITNC_TILEH_WN * MITNC_TILEH_BN * 8),
+          ilog2_exact(MITNC_TILEH_TK)};
+}
 inline constexpr TileGeom geom_tall_h() { return {7, 4, 5}; }    // 128 x 16, k 32
 inline constexpr TileGeom geom_splitk_h() { return {4, 4, 7}; }  // 16 x 16, k 128 (4 waves split k)
 
