@@ -217,11 +217,13 @@ def subslice_check(c, spec, g, precision):
     return worst
 
 
-def grad_timing(steps):
+def grad_timing(steps, cap=28):
     """Differentiation form: 6x6 lattice, 8 cycles, 256 random bitstrings as a
-    batch index (seeds 1003 / 2003 / 3003), intermediates <= 2^32 entries with
-    the batch bits.  Times the forward over all slices and the backward (per
-    slice: forward recompute, reverse pass, gate-gradient accumulation) with
+    batch index (seeds 1003 / 2003 / 3003), intermediates <= 2^28 entries with
+    the batch bits (greedy and bisection search; the path found needs no
+    sliced index at this cap).  Times the forward over all slices and the
+    backward (per slice: forward recompute unless the workspace still holds
+    that slice's values, reverse pass, gate-gradient accumulation) with
     w = 1 / a, the holomorphic seed of L = sum log|a|^2."""
     import numpy as np
     import torch
@@ -232,7 +234,7 @@ def grad_timing(steps):
     bits = synth.random_bitstrings(36, 256, seed=2003)
     spec = np.full(36, -2, dtype=np.int8)
     net = tnc.Network(c, spec, bits)
-    net.path_search(seed=3003, trials=32, max_log2=32)
+    net.path_search(seed=3003, trials=16, max_log2=cap, method=2)
     plan = tnc.Plan(net, differentiable=True)
     plan.upload()
     acc = plan.new_result()
@@ -254,7 +256,8 @@ def grad_timing(steps):
     torch.cuda.synchronize()
     bwd = (time.perf_counter() - t0) / steps
     st = plan.stats
-    return {"workload": "rqc-6x6-8cyc-256bitstrings-grad", "slices": plan.n_slices,
+    return {"workload": f"rqc-6x6-8cyc-256bitstrings-grad-cap{cap}", "slices": plan.n_slices,
+            "max_log2_elems": st.max_log2_elems,
             "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "backward_over_forward": bwd / fwd,
             "forward_flops": st.flops_full_slice * plan.n_slices,
             "reverse_flops": st.flops_reverse_slice * plan.n_slices, "n_grad_gates": st.n_grad_gates,
@@ -447,7 +450,8 @@ def main():
     from paper_2504_09186_amd import tnc
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.grad:
-        print(json.dumps(grad_timing(args.steps)), flush=True)
+        print(json.dumps({"grad": grad_timing(args.steps), "grad_sliced": grad_timing(args.steps, cap=22)}),
+              flush=True)
         return
     if args.micro:
         print(json.dumps(micro(args.micro, args.micro_precision, max(1, args.steps))), flush=True)
@@ -509,6 +513,9 @@ def main():
     if not args.no_extras:
         out["config2"] = run_config2(args.steps, args.warmup, 64)
         out["grad"] = grad_timing(args.steps)
+        # the same with intermediates capped at 2^22 entries: 16 slices, each
+        # recomputed per slice by the backward
+        out["grad_sliced"] = grad_timing(args.steps, cap=22)
     if not args.no_cpu_baseline and g4 is not None:
         out["cpu_baseline"] = cpu_baseline_subslice(c, spec, g4, r64["flops_per_step"] / 256)
     print(json.dumps(out), flush=True)

@@ -601,6 +601,7 @@ int32_t mitnc_plan_upload(mitnc_plan* P, void* ws, size_t ws_bytes, void* stream
     }
     hip_check(hipStreamSynchronize(s), "leaf upload sync");
     P->uploaded = true;
+    P->valid_slice = -1;
     P->uploaded_ws = ws;
   });
 }
@@ -795,6 +796,8 @@ int32_t mitnc_execute(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, uin
     const int prec = P->opts.precision;
     if (prec == MITNC_C64) {
       run_slices(P, base, s0, s1, acc, s, prec, false);
+      // every node of a differentiable plan now holds its value for s1 - 1
+      P->valid_slice = P->opts.differentiable ? (int64_t)(s1 - 1) : -1;
       return;
     }
     // Precision form: the slices are summed into the calibration buffer and
@@ -892,14 +895,22 @@ int32_t mitnc_backward(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, ui
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)ws;
     const int root = P->steps.back().out;
-    for (uint64_t sl = s0; sl < s1; ++sl) {
+    // Slices run from the last to the first: when the workspace still holds
+    // the values of the last slice (the forward pass that produced the
+    // amplitudes ended there), its recomputation is skipped.  Going from
+    // slice s + 1 down to s changes the slice-id bits 0 .. ctz(s + 1), so a
+    // node is recomputed when its lowest sliced bit is at most that.
+    for (uint64_t sl = s1; sl-- > s0;) {
       // forward: recompute the nodes whose sliced indices changed (the root's
       // value itself is not needed)
-      int level = (sl == s0) ? kLevelFirst : __builtin_ctzll(sl);
+      int level;
+      if (sl == s1 - 1) level = P->valid_slice == (int64_t)sl ? -1 : kLevelFirst;
+      else level = __builtin_ctzll(sl + 1);
       for (auto& st : P->steps) {
         if (st.root || P->nodes[st.out].lo > level) continue;
         launch_plan_step(P, st, base, sl, nullptr, s, MITNC_C64, false);
       }
+      P->valid_slice = (int64_t)sl;
       // reverse
       hip_check(launch_seed(w, (float*)(base + P->off_adj + P->adj_offset[root]), P->result_elems, s), "seed");
       for (const mitnc_plan::RevLevel& L : P->rev_levels) {
@@ -950,6 +961,7 @@ int32_t mitnc_plan_set_gates(mitnc_plan* P, void* ws, size_t ws_bytes, const dou
                 "gate upload");
       ++g;
     }
+    P->valid_slice = -1;
     hip_check(hipStreamSynchronize(s), "gate upload sync");
   });
 }

@@ -109,6 +109,9 @@ struct mitnc_plan {
   uint64_t result_elems = 0;
   int max_log2 = 0;
   bool uploaded = false;
+  // Differentiable plans keep every node's value: the slice whose values the
+  // workspace holds after the last forward pass (-1: none).
+  int64_t valid_slice = -1;
   void* uploaded_ws = nullptr;
   // Optional per-launch timing (hipEvent pairs around each step's main kernel).
   bool timing = false;

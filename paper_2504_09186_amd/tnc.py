@@ -233,6 +233,13 @@ class Plan:
             raise ValueError("expected n_grad_gates x 2 x 2 matrices")
         call("mitnc_plan_set_gates", self.h, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
              m.ctypes.data_as(C.POINTER(C.c_double)), _stream_handle(stream))
+        self._gates = m.copy()
+
+    def gates_equal(self, mats) -> bool:
+        """True when the plan's single-qubit gate leaves were last set to mats."""
+        cur = getattr(self, "_gates", None)
+        m = np.ascontiguousarray(np.asarray(mats, dtype=np.complex128).reshape(-1)).view(np.float64)
+        return cur is not None and cur.shape == m.shape and bool(np.array_equal(cur, m))
 
     def backward(self, w, grad, slice_begin: int = 0, slice_end: Optional[int] = None, stream=None):
         """grad += sum_r w[r] d result[r] / d U_g (holomorphic VJP; complex128
@@ -363,7 +370,8 @@ def _amplitude_fn():
         @staticmethod
         def backward(ctx, grad_out):
             plan = ctx.plan
-            plan.set_gates(ctx.mats)
+            if not plan.gates_equal(ctx.mats):
+                plan.set_gates(ctx.mats)
             # conj_physical: a lazy conj() view would hand the library the
             # unconjugated bytes
             w = torch.conj_physical(grad_out.to(torch.complex128)).contiguous()
