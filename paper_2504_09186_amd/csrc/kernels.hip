@@ -1454,7 +1454,7 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
 // odd columns.  One MFMA covers 16 rows, 8 complex columns and 16 complex k.
 // LDS rows are k-contiguous: A row m holds A[m][k] as 32-bit words, B' row
 // 2n + c holds the words (br, -bi) (c = 0) or (bi, br) (c = 1) of B[k][n].
-template <int P, int WM, int WN, int WK, int BM, int BN, int TK>
+template <int P, int WM, int WN, int WK, int BM, int BN, int TK, int VEC>
 __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
   constexpr int TM = WM * BM * 16;              // complex rows
   constexpr int TN = WN * BN * 8;               // complex columns
@@ -1463,13 +1463,22 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
   constexpr int SW = TK + 4;                    // 32-bit words per LDS row (k contiguous)
   constexpr int STAGE = TM * SW + 2 * TN * SW;  // words per stage
   constexpr int SC = TN + 2;                    // float2 per LDS row of the C tile
+  // VEC words per global load: 4 (one 16-byte load) when the two lowest
+  // tile bits of A and of B are their address bits 0 and 1 (the launcher
+  // checks), else 1.  A thread's elements of a load are consecutive in
+  // address order; their LDS slots differ by the uniform slot offsets of
+  // tile elements 0 .. VEC-1 (decoding is additive over disjoint bits).
   constexpr int A_LOADS = TM * TK / 256;
   constexpr int B_LOADS = (TK * TN + 255) / 256;
+  constexpr int AV = A_LOADS / VEC, BV = (B_LOADS + VEC - 1) / VEC;
+  static_assert(VEC == 1 || VEC == 4, "1- or 4-word loads");
+  static_assert(AV * VEC == A_LOADS, "A loads split into whole vectors");
   constexpr int C_ITEMS = TM * TN / 256;
   constexpr int SMEM_AB = 2 * STAGE;
   constexpr int SMEM_C = WK * TM * SC * 2;
   constexpr int SMEM = SMEM_AB > SMEM_C ? SMEM_AB : SMEM_C;
   static_assert(A_LOADS >= 1 && C_ITEMS >= 1, "tile too small");
+  using Vec = typename std::conditional<VEC == 4, uint4, uint32_t>::type;
   __shared__ __align__(16) uint32_t smem[SMEM];
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   __shared__ uint64_t flip[2][32];
@@ -1492,12 +1501,17 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
   const uint64_t baseB =
       wave_scatter(nt, tab + T_BN + d.tn, d.nb - d.tn) + wave_scatter(batch, tab + T_BB, d.bb);
 
-  uint32_t a_off[A_LOADS];
-  int a_lds[A_LOADS];
+  uint32_t a_off[AV];
+  int a_lds[AV], a_du[VEC];
   const int na = d.tm + d.tk;
 #pragma unroll
-  for (int j = 0; j < A_LOADS; ++j) {
-    const int e = tid + 256 * j;
+  for (int u = 0; u < VEC; ++u) {
+    const TileSlot s = decode_slot(u, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK);
+    a_du[u] = s.lo * SW + s.hi;
+  }
+#pragma unroll
+  for (int j = 0; j < AV; ++j) {
+    const int e = (tid + 256 * j) * VEC;
     a_lds[j] = -1;
     a_off[j] = 0;
     if (e < (1 << na)) {
@@ -1506,12 +1520,17 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
       a_lds[j] = s.lo * SW + s.hi;
     }
   }
-  uint32_t b_off[B_LOADS];
-  int b_lds[B_LOADS];
+  uint32_t b_off[BV];
+  int b_lds[BV], b_du[VEC];
   const int nbt = d.tk + d.tn;
 #pragma unroll
-  for (int j = 0; j < B_LOADS; ++j) {
-    const int e = tid + 256 * j;
+  for (int u = 0; u < VEC; ++u) {
+    const TileSlot s = decode_slot(u, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN);
+    b_du[u] = (2 * s.hi) * SW + s.lo;
+  }
+#pragma unroll
+  for (int j = 0; j < BV; ++j) {
+    const int e = (tid + 256 * j) * VEC;
     b_lds[j] = -1;
     b_off[j] = 0;
     if (e < (1 << nbt)) {
@@ -1537,25 +1556,33 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
   uint64_t ka = wave_scatter(kt0, tab + T_AK + d.tk, khb);
   uint64_t kbo = wave_scatter(kt0, tab + T_BK + d.tk, khb);
 
-  uint32_t ra[A_LOADS], rb[B_LOADS];
+  Vec ra[AV], rb[BV];
   auto load = [&]() {
 #pragma unroll
-    for (int j = 0; j < A_LOADS; ++j) ra[j] = A[baseA + ka + a_off[j]];
+    for (int j = 0; j < AV; ++j) ra[j] = *reinterpret_cast<const Vec*>(A + (baseA + ka + a_off[j]));
 #pragma unroll
-    for (int j = 0; j < B_LOADS; ++j) rb[j] = B[baseB + kbo + b_off[j]];
+    for (int j = 0; j < BV; ++j) rb[j] = *reinterpret_cast<const Vec*>(B + (baseB + kbo + b_off[j]));
+  };
+  auto word = [](const Vec& v, int u) -> uint32_t {
+    if constexpr (VEC == 4) return u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w;
+    else return v;
   };
   auto store = [&](int stage) {
     uint32_t* S = smem + stage * STAGE;
 #pragma unroll
-    for (int j = 0; j < A_LOADS; ++j)
-      if (a_lds[j] >= 0) S[a_lds[j]] = ra[j];
+    for (int j = 0; j < AV; ++j)
+      if (a_lds[j] >= 0)
 #pragma unroll
-    for (int j = 0; j < B_LOADS; ++j)
-      if (b_lds[j] >= 0) {
-        const uint32_t w = rb[j];                  // (br, bi)
-        S[b_lds[j]] = w ^ 0x80000000u;             // (br, -bi)
-        S[b_lds[j] + SW] = (w >> 16) | (w << 16);  // (bi, br)
-      }
+        for (int u = 0; u < VEC; ++u) S[a_lds[j] + a_du[u]] = word(ra[j], u);
+#pragma unroll
+    for (int j = 0; j < BV; ++j)
+      if (b_lds[j] >= 0)
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) {
+          const uint32_t w = word(rb[j], u);                   // (br, bi)
+          S[b_lds[j] + b_du[u]] = w ^ 0x80000000u;             // (br, -bi)
+          S[b_lds[j] + b_du[u] + SW] = (w >> 16) | (w << 16);  // (bi, br)
+        }
   };
 
   v4f acc[BM][BN];
@@ -1869,6 +1896,23 @@ static hipError_t launch_skinny(const StepDesc& d, hipStream_t s, Timing t) {
   return hipErrorInvalidValue;
 }
 
+// Address bit of tile bit `code` in A (is_a) or B.
+static int tile_bit_pos(const StepDesc& d, uint8_t code, bool is_a) {
+  const int cls = code >> 5, idx = code & 31;
+  if (is_a) return cls == TB_M ? d.am[idx] : d.ak[idx];
+  return cls == TB_K ? d.bk[idx] : d.bn[idx];
+}
+
+// 16-byte tile loads apply when the two lowest tile bits of A and of B are
+// their address bits 0 and 1 (four consecutive words of a tile are then
+// consecutive in memory) and both operands are 16-byte aligned.
+static bool tile_vec4(const StepDesc& d) {
+  if (d.tm + d.tk < 2 || d.tk + d.tn < 2) return false;
+  if (tile_bit_pos(d, d.a_tile[0], true) != 0 || tile_bit_pos(d, d.a_tile[1], true) != 1) return false;
+  if (tile_bit_pos(d, d.b_tile[0], false) != 0 || tile_bit_pos(d, d.b_tile[1], false) != 1) return false;
+  return (reinterpret_cast<uintptr_t>(d.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
+}
+
 template <int P>
 static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
@@ -1917,14 +1961,23 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
         else
           launch_k(k_tile<1, 1, 4, 1, 1, 64>, grid, dim3(256), 0, s, t, d);
       } else {
-        if (kclass == MITNC_K_TILE)
-          launch_k(k_tile_h<P, MITNC_TILEH_WM, MITNC_TILEH_WN, MITNC_TILEH_WK, MITNC_TILEH_BM, MITNC_TILEH_BN,
-                            MITNC_TILEH_TK>,
-                   grid, dim3(256), 0, s, t, d);
-        else if (kclass == MITNC_K_TALL)
-          launch_k(k_tile_h<P, 4, 1, 1, 2, 2, 32>, grid, dim3(256), 0, s, t, d);
-        else
-          launch_k(k_tile_h<P, 1, 1, 4, 1, 2, 128>, grid, dim3(256), 0, s, t, d);
+        const bool v4 = tile_vec4(d);
+        if (kclass == MITNC_K_TILE) {
+          if (v4)
+            launch_k(k_tile_h<P, MITNC_TILEH_WM, MITNC_TILEH_WN, MITNC_TILEH_WK, MITNC_TILEH_BM, MITNC_TILEH_BN,
+                              MITNC_TILEH_TK, 4>,
+                     grid, dim3(256), 0, s, t, d);
+          else
+            launch_k(k_tile_h<P, MITNC_TILEH_WM, MITNC_TILEH_WN, MITNC_TILEH_WK, MITNC_TILEH_BM, MITNC_TILEH_BN,
+                              MITNC_TILEH_TK, 1>,
+                     grid, dim3(256), 0, s, t, d);
+        } else if (kclass == MITNC_K_TALL) {
+          if (v4) launch_k(k_tile_h<P, 4, 1, 1, 2, 2, 32, 4>, grid, dim3(256), 0, s, t, d);
+          else launch_k(k_tile_h<P, 4, 1, 1, 2, 2, 32, 1>, grid, dim3(256), 0, s, t, d);
+        } else {
+          if (v4) launch_k(k_tile_h<P, 1, 1, 4, 1, 2, 128, 4>, grid, dim3(256), 0, s, t, d);
+          else launch_k(k_tile_h<P, 1, 1, 4, 1, 2, 128, 1>, grid, dim3(256), 0, s, t, d);
+        }
       }
       if (e == hipSuccess) e = hipGetLastError();
       if (e != hipSuccess || d.ks_bits == 0) return e;
