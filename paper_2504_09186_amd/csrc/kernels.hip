@@ -177,9 +177,18 @@ __device__ __forceinline__ float epilogue_store(const StepDesc& d, uint64_t addr
   }
 }
 
-// Per-step maximum of stored magnitudes: wave and workgroup reduction, one
-// atomic per workgroup (grids are capped so that one address sees few of
-// them).  Every thread of the workgroup must call it.
+// Raises the recorded maximum *slot to m (the bit pattern of a non-negative
+// float orders like the float).  The recorded value only grows, so a plain
+// read that already shows m or more makes the atomic unnecessary: with
+// thousands of workgroups per launch, most skip it instead of queueing on
+// one address.
+__device__ __forceinline__ void raise_max(unsigned int* slot, float m) {
+  const unsigned int v = __float_as_uint(m);
+  if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) atomicMax(slot, v);
+}
+
+// Per-step maximum of stored magnitudes: wave and workgroup reduction, at
+// most one atomic per workgroup.  Every thread of the workgroup must call it.
 __device__ __forceinline__ void record_max(const StepDesc& d, float m) {
   if (!d.stats) return;
   __shared__ float red[4];
@@ -189,7 +198,7 @@ __device__ __forceinline__ void record_max(const StepDesc& d, float m) {
   __syncthreads();
   if (threadIdx.x == 0) {
     m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    if (m > 0.f) atomicMax(reinterpret_cast<unsigned int*>(d.stats) + d.step_index, __float_as_uint(m));
+    if (m > 0.f) raise_max(reinterpret_cast<unsigned int*>(d.stats) + d.step_index, m);
   }
 }
 
@@ -444,7 +453,7 @@ __global__ __launch_bounds__(64) void k_skinny(StepDesc d) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
     if (lane == 0 && mx > 0.f)
-      atomicMax(reinterpret_cast<unsigned int*>(d.stats) + d.step_index, __float_as_uint(mx));
+      raise_max(reinterpret_cast<unsigned int*>(d.stats) + d.step_index, mx);
   }
 }
 
@@ -950,7 +959,7 @@ __device__ __forceinline__ void record_max_at(float* stats, int idx, float m) {
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
-    if (m > 0.f) atomicMax(reinterpret_cast<unsigned int*>(stats) + idx, __float_as_uint(m));
+    if (m > 0.f) raise_max(reinterpret_cast<unsigned int*>(stats) + idx, m);
   }
 }
 
