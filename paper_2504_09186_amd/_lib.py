@@ -118,6 +118,13 @@ def load() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2504_09186_amd.build")
+    # torch brings its own HIP runtime; loading it first makes the library
+    # bind to that same runtime (with two runtimes in one process the second
+    # one finds no device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, args in _SIGS.items():
         f = getattr(lib, name)

@@ -1281,14 +1281,25 @@ __device__ __forceinline__ void store_c_tile(const StepDesc& d, const uint8_t* t
 // T3 = (Ar + Ai)(Br + Bi), Re C = T1 - T2, Im C = T3 - T1 - T2: three real
 // 16 x 16 x 4 FP32 MFMAs per 16 x 16 complex block and 4 complex k, instead of
 // the four of the 4M split.
+// Column XOR of LDS row k of a complex64 tile operand: the XOR of swz[j]
+// over the set bits j of k, kept inside the row (mask = columns - 1).
+__device__ __forceinline__ int row_xor(const uint8_t* swz, int k, int mask) {
+  int h = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) h ^= ((k >> j) & 1) ? (int)swz[j] : 0;
+  return h & mask;
+}
+
 template <int WM, int WN, int WK, int BM, int BN, int TK>
 __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
   constexpr int TM = WM * BM * 16;
   constexpr int TN = WN * BN * 16;
   constexpr int KW = TK / WK;                   // complex k per wave and k tile
   static_assert(KW % 4 == 0, "k per wave must be a multiple of 4");
-  constexpr int SA = TM + (TM >= 64 ? 16 : 0);  // float2 per LDS row of A (row = k)
-  constexpr int SB = TN + (TN >= 64 ? 16 : 0);  // float2 per LDS row of B (row = k)
+  // LDS rows of A and B are the k of the tile, unpadded: row k stores column
+  // c at c ^ H(k), with the step's row masks (StepDesc::a_swz, b_swz).
+  constexpr int SA = TM;                        // float2 per LDS row of A (row = k)
+  constexpr int SB = TN;                        // float2 per LDS row of B (row = k)
   constexpr int STAGE = TK * SA + TK * SB;      // float2 per stage
   constexpr int SC = TN + 4;                    // float2 per LDS row of the C tile
   constexpr int A_LOADS = TM * TK / 256;
@@ -1337,7 +1348,7 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
     if (e < (1 << na)) {
       const TileSlot s = decode_slot(e, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK);
       a_off[j] = s.off;
-      a_lds[j] = s.hi * SA + s.lo;
+      a_lds[j] = s.hi * SA + (s.lo ^ row_xor(d.a_swz, s.hi, TM - 1));
     }
   }
   uint32_t b_off[B_LOADS];
@@ -1351,7 +1362,7 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
     if (e < (1 << nbt)) {
       const TileSlot s = decode_slot(e, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN);
       b_off[j] = s.off;
-      b_lds[j] = TK * SA + s.lo * SB + s.hi;
+      b_lds[j] = TK * SA + s.lo * SB + (s.hi ^ row_xor(d.b_swz, s.lo, TN - 1));
     }
   }
 
@@ -1418,10 +1429,11 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
 #pragma unroll
     for (int ks = 0; ks < KW / 4; ++ks) {
       const int k = wk * KW + ks * 4 + kq;
+      const int ha = row_xor(d.a_swz, k, TM - 1), hb = row_xor(d.b_swz, k, TN - 1);
 #pragma unroll
-      for (int bm = 0; bm < BM; ++bm) av[ks][bm] = As[k * SA + (wm * BM + bm) * 16 + row];
+      for (int bm = 0; bm < BM; ++bm) av[ks][bm] = As[k * SA + (((wm * BM + bm) * 16 + row) ^ ha)];
 #pragma unroll
-      for (int bn = 0; bn < BN; ++bn) bv[ks][bn] = Bs[k * SB + (wn * BN + bn) * 16 + row];
+      for (int bn = 0; bn < BN; ++bn) bv[ks][bn] = Bs[k * SB + (((wn * BN + bn) * 16 + row) ^ hb)];
     }
 #pragma unroll
     for (int ks = 0; ks < KW / 4; ++ks)

@@ -45,6 +45,93 @@ static void tile_order(uint8_t* dst, std::vector<std::pair<int, uint8_t>> v) {
   for (size_t i = 0; i < v.size(); ++i) dst[i] = v[i].second;
 }
 
+namespace {
+// Span of a set of vectors over GF(2) (bit b of piv[b] is its leading bit).
+struct XorSpan {
+  uint32_t piv[32] = {};
+  bool contains(uint32_t v) const {  // true for v == 0
+    for (int b = 31; b >= 0; --b)
+      if ((v >> b) & 1) {
+        if (!piv[b]) return false;
+        v ^= piv[b];
+      }
+    return true;
+  }
+  void add(uint32_t v) {
+    for (int b = 31; b >= 0; --b)
+      if ((v >> b) & 1) {
+        if (!piv[b]) {
+          piv[b] = v;
+          return;
+        }
+        v ^= piv[b];
+      }
+  }
+};
+}  // namespace
+
+// Row XOR masks of a complex64 tile operand in LDS: rows are the k bits,
+// 2^col_bits float2 columns per row, no padding; row k stores column c at
+// c ^ H(k), H(k) the XOR of g[j] over the set bits j of k (g[j] < 2^col_bits).
+// A float2 slot covers two 4-byte banks, so a wave access is served 16 lanes
+// (32 banks) or 32 lanes (64 banks) at a time and is conflict-free when those
+// lanes' slots differ mod 16 (mod 32).  Staging writes: lanes take
+// consecutive tile elements in address order, so lanes 0-15 (0-31) differ in
+// the tile bits codes[0..3] (codes[0..4]); the slot moves by 2^i for column
+// bit i and by 2^(col_bits + j) ^ g[j] for row bit j, and the writes are
+// conflict-free when those moves are linearly independent (GF(2)) mod 16 and
+// mod 32.  The g of the row bits among the lowest tile bits are chosen in
+// that order to keep both sets independent.  Fragment reads take 16
+// consecutive columns of one row per 16 lanes (a permutation of 16
+// consecutive slots) and rows k, k + 1 in lanes 0-31: g[0] gets bit 4 where
+// free, so those two rows use the two halves of 64 banks.
+static void lds_row_swizzle(const uint8_t* codes, int ncodes, int row_cls, int col_bits, uint8_t* g) {
+  std::fill(g, g + 8, (uint8_t)0);
+  const uint32_t cols = 1u << col_bits;
+  const uint32_t gmax = cols < 32 ? cols : 32;
+  auto colvec = [](int i) -> uint32_t { return i < 5 ? 1u << i : 0u; };
+  const int nl = ncodes < 5 ? ncodes : 5;
+  XorSpan s16, s32;
+  for (int t = 0; t < nl; ++t) {
+    if ((codes[t] >> 5) == row_cls) continue;
+    const uint32_t v = colvec(codes[t] & 31);
+    if (t < 4) s16.add(v & 15);
+    s32.add(v);
+  }
+  bool row0_lane = false;
+  for (int t = 0; t < nl; ++t) {
+    if ((codes[t] >> 5) != row_cls) continue;
+    const int j = codes[t] & 31;
+    if (j >= 8) continue;
+    const uint32_t stride = (cols << j) & 31;
+    if (j == 0) row0_lane = true;
+    std::vector<uint32_t> cand;
+    for (uint32_t v = 0; v < gmax; ++v) cand.push_back(v);
+    auto key = [&](uint32_t v) {
+      const int hi = (j == 0 && ((stride ^ v) & 16)) ? 0 : 1;
+      return std::make_tuple(hi, __builtin_popcount(v), v);
+    };
+    std::sort(cand.begin(), cand.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
+    int pick = -1;
+    for (int pass = 0; pass < 2 && pick < 0; ++pass)
+      for (uint32_t v : cand) {
+        const uint32_t vec = stride ^ v;
+        const bool ok16 = t > 3 || !s16.contains(vec & 15);
+        const bool ok32 = !s32.contains(vec);
+        if (ok16 && (ok32 || pass == 1)) {
+          pick = (int)v;
+          break;
+        }
+      }
+    if (pick < 0) pick = 0;
+    g[j] = (uint8_t)pick;
+    const uint32_t vec = stride ^ (uint32_t)pick;
+    if (t < 4) s16.add(vec & 15);
+    s32.add(vec);
+  }
+  if (!row0_lane && gmax == 32 && !(cols & 16)) g[0] = 16;
+}
+
 static TileGeom geom_of(int kclass, int precision) {
   const bool h = precision != MITNC_C64;
   switch (kclass) {
@@ -246,6 +333,10 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     tile_order(d.a_tile, ta);
     tile_order(d.b_tile, tb);
     tile_order(d.c_tile, tc);
+    if (precision == MITNC_C64) {
+      lds_row_swizzle(d.a_tile, d.tm + d.tk, TB_K, g.tm_bits, d.a_swz);
+      lds_row_swizzle(d.b_tile, d.tk + d.tn, TB_K, g.tn_bits, d.b_swz);
+    }
     // Split K over workgroups when there are too few output tiles to fill the
     // chip (Sec. V-B: partition along the common indices); keep at least 4 k
     // tiles per workgroup.

@@ -42,6 +42,11 @@ struct StepDesc {
   uint8_t bk[32], bn[32], bbt[32];
   uint8_t cm[32], cn[32], cb[32];
   uint8_t a_tile[16], b_tile[16], c_tile[16];  // tile bits sorted by address position
+  // Complex64 tile kernels: LDS row k of the A (B) stage stores column m (n)
+  // at m ^ H(k), H(k) the XOR of a_swz[j] (b_swz[j]) over the set bits j of
+  // k.  Chosen per step so that the scattered staging writes and the
+  // fragment reads hit distinct LDS banks (all zero: plain rows).
+  uint8_t a_swz[8], b_swz[8];
 };
 
 // Byte offsets of the tables relative to StepDesc::am.
