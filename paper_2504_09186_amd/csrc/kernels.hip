@@ -1291,7 +1291,7 @@ __device__ __forceinline__ int row_xor(const uint8_t* swz, int k, int mask) {
 }
 
 template <int WM, int WN, int WK, int BM, int BN, int TK>
-__global__ __launch_bounds__(256) void k_tile(StepDesc d) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tile(StepDesc d) {
   constexpr int TM = WM * BM * 16;
   constexpr int TN = WN * BN * 16;
   constexpr int KW = TK / WK;                   // complex k per wave and k tile
@@ -1385,21 +1385,30 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
   uint64_t ka = wave_scatter(kt0, tab + T_AK + d.tk, khb);
   uint64_t kbo = wave_scatter(kt0, tab + T_BK + d.tk, khb);
 
-  float2 ra[A_LOADS], rb[B_LOADS];
-  auto load = [&]() {
+  // Two register sets of staged loads: k tile t + 2 is requested while
+  // tile t is computed and tile t + 1 (requested one tile earlier) goes to
+  // the other LDS stage, so every load has two tiles of MFMA work to land.
+  float2 ra[2][A_LOADS], rb[2][B_LOADS];
+  auto load = [&](int r) {
 #pragma unroll
-    for (int j = 0; j < A_LOADS; ++j) ra[j] = A[baseA + ka + a_off[j]];
+    for (int j = 0; j < A_LOADS; ++j) ra[r][j] = A[baseA + ka + a_off[j]];
 #pragma unroll
-    for (int j = 0; j < B_LOADS; ++j) rb[j] = B[baseB + kbo + b_off[j]];
+    for (int j = 0; j < B_LOADS; ++j) rb[r][j] = B[baseB + kbo + b_off[j]];
   };
-  auto store = [&](int stage) {
+  auto store = [&](int r, int stage) {
     float2* S = smem + stage * STAGE;
 #pragma unroll
     for (int j = 0; j < A_LOADS; ++j)
-      if (a_lds[j] >= 0) S[a_lds[j]] = ra[j];
+      if (a_lds[j] >= 0) S[a_lds[j]] = ra[r][j];
 #pragma unroll
     for (int j = 0; j < B_LOADS; ++j)
-      if (b_lds[j] >= 0) S[b_lds[j]] = rb[j];
+      if (b_lds[j] >= 0) S[b_lds[j]] = rb[r][j];
+  };
+  // Moves the load offsets from k tile kt0 + t - 1 to kt0 + t (t >= 1).
+  auto advance = [&](uint64_t t) {
+    const int fl = __builtin_ctzll(kt0 + t);
+    ka ^= flip[0][fl];
+    kbo ^= flip[1][fl];
   };
 
   v4f acc[3][BM][BN];
@@ -1410,19 +1419,8 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
 #pragma unroll
       for (int j = 0; j < BN; ++j) acc[p][i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  load();
-  store(0);
-  __syncthreads();
   const int row = lane & 15, kq = lane >> 4;
-  for (uint64_t it = 0; it < per; ++it) {
-    const int cur = (int)(it & 1);
-    const bool more = it + 1 < per;
-    if (more) {
-      const int fl = __builtin_ctzll(kt0 + it + 1);
-      ka ^= flip[0][fl];
-      kbo ^= flip[1][fl];
-      load();
-    }
+  auto compute = [&](int cur) {
     const float2* As = smem + cur * STAGE;
     const float2* Bs = As + TK * SA;
     float2 av[KW / 4][BM], bv[KW / 4][BN];
@@ -1446,8 +1444,29 @@ __global__ __launch_bounds__(256) void k_tile(StepDesc d) {
           acc[1][bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[1][bm][bn], 0, 0, 0);
           acc[2][bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, acc[2][bm][bn], 0, 0, 0);
         }
-    if (more) store(cur ^ 1);
+  };
+  // One k tile: stage it & 1 holds tile it, register set x holds tile it + 1.
+  auto step = [&](uint64_t it, int x) {
+    if (it + 2 < per) {
+      advance(it + 2);
+      load(x ^ 1);
+    }
+    compute((int)(it & 1));
+    if (it + 1 < per) store(x, (int)(it & 1) ^ 1);
     __syncthreads();
+  };
+
+  __syncthreads();  // flip[][] (written above by threads tid < khb) is read from here on
+  load(0);
+  if (per > 1) {
+    advance(1);
+    load(1);
+  }
+  store(0, 0);
+  __syncthreads();
+  for (uint64_t it = 0; it < per; it += 2) {
+    step(it, 1);
+    if (it + 1 < per) step(it + 1, 0);
   }
   // Accumulators -> LDS tile: Re = T1 - T2, Im = T3 - T1 - T2.
   float2* Cs = smem;
