@@ -247,6 +247,21 @@ typedef struct mitnc_step_info {
   uint8_t am[32], ak[32], ab[32];  /* A address bit of each m, k, batch bit */
   uint8_t bk[32], bn[32], bbt[32]; /* B address bit of each k, n, batch bit */
   uint8_t cm[32], cn[32], cb[32];  /* C address bit of each m, n, batch bit */
+  /* MFMA-class steps (kernel class TILE, TALL, SPLITK; zero otherwise): */
+  int32_t tm, tn, tk;              /* tile bits of m, n, k */
+  uint8_t a_tile[16], b_tile[16];  /* tile bits of A / B in address order:
+                                      class << 5 | index, class 0 m, 1 k, 2 n */
+  uint8_t lds_a_swz[8], lds_b_swz[8]; /* complex64: LDS row k of the A (B) stage
+                                      stores column c at c ^ XOR of swz[j]
+                                      over the set bits j of k */
+  uint16_t lds_a_row[8], lds_b_row[8]; /* FP16/BF16: LDS word address vector
+                                      of A row bit i (m bit i) and of the
+                                      expanded B row bit r (r = 0 re/im row,
+                                      r = i + 1 n bit i) */
+  uint8_t lds_k_col[8];            /* FP16/BF16: LDS column bit of tile k bit j;
+                                      a tile entry's word address is the XOR
+                                      of its bits' vectors */
+  int32_t vec_a, vec_b;            /* FP16/BF16: 16-byte loads planned (4) or not (1) */
 } mitnc_step_info;
 int32_t mitnc_plan_step_info(const mitnc_plan* plan, int32_t step, mitnc_step_info* info);
 

@@ -59,7 +59,11 @@ class mitnc_step_info(C.Structure):
                 ("kernel_class", C.c_int32), ("section", C.c_int32), ("section_pos", C.c_int32),
                 ("section_len", C.c_int32), ("mb", C.c_int32), ("nb", C.c_int32), ("kb", C.c_int32),
                 ("bb", C.c_int32)] + [(f, C.c_uint8 * 32) for f in ("am", "ak", "ab", "bk", "bn", "bbt",
-                                                                     "cm", "cn", "cb")]
+                                                                     "cm", "cn", "cb")] + [
+        ("tm", C.c_int32), ("tn", C.c_int32), ("tk", C.c_int32), ("a_tile", C.c_uint8 * 16),
+        ("b_tile", C.c_uint8 * 16), ("lds_a_swz", C.c_uint8 * 8), ("lds_b_swz", C.c_uint8 * 8),
+        ("lds_a_row", C.c_uint16 * 8), ("lds_b_row", C.c_uint16 * 8), ("lds_k_col", C.c_uint8 * 8),
+        ("vec_a", C.c_int32), ("vec_b", C.c_int32)]
 
 
 class mitnc_node_info(C.Structure):

@@ -484,6 +484,20 @@ int32_t mitnc_plan_step_info(const mitnc_plan* P, int32_t step, mitnc_step_info*
     std::memcpy(info->cm, d.cm, 32);
     std::memcpy(info->cn, d.cn, 32);
     std::memcpy(info->cb, d.cb, 32);
+    if (s.kclass == MITNC_K_TILE || s.kclass == MITNC_K_TALL || s.kclass == MITNC_K_SPLITK) {
+      info->tm = d.tm;
+      info->tn = d.tn;
+      info->tk = d.tk;
+      std::memcpy(info->a_tile, d.a_tile, 16);
+      std::memcpy(info->b_tile, d.b_tile, 16);
+      std::memcpy(info->lds_a_swz, d.a_swz, 8);
+      std::memcpy(info->lds_b_swz, d.b_swz, 8);
+      std::memcpy(info->lds_a_row, d.ha_row, sizeof d.ha_row);
+      std::memcpy(info->lds_b_row, d.hb_row, sizeof d.hb_row);
+      std::memcpy(info->lds_k_col, d.hk, 8);
+      info->vec_a = d.vec_a;
+      info->vec_b = d.vec_b;
+    }
   });
 }
 

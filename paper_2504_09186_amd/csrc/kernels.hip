@@ -36,7 +36,11 @@ typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 
 static_assert(offsetof(StepDesc, am) % 4 == 0, "tables must be dword aligned");
-static_assert(offsetof(StepDesc, c_tile) + 16 - offsetof(StepDesc, am) == TAB_BYTES, "table layout");
+static_assert(offsetof(StepDesc, hk) + 8 - offsetof(StepDesc, am) == TAB_BYTES, "table layout");
+static_assert(offsetof(StepDesc, ha_row) - offsetof(StepDesc, am) == T_HAROW &&
+                  offsetof(StepDesc, hb_row) - offsetof(StepDesc, am) == T_HBROW &&
+                  offsetof(StepDesc, hk) - offsetof(StepDesc, am) == T_HK,
+              "table offsets");
 
 __device__ __forceinline__ void load_tables(const StepDesc& d, uint8_t* tab) {
   const uint32_t* src = reinterpret_cast<const uint32_t*>(d.am);
@@ -1210,18 +1214,20 @@ struct TileSlot {
 __device__ __forceinline__ TileSlot decode_slot(int e, int nbits, const uint8_t* codes, const uint8_t* tab,
                                                 int first_cls, int off_first, int off_second) {
   // Branch-free (index clamped, contribution masked): the LDS reads of all
-  // bits issue together instead of one dependent pair per bit.
+  // bits issue together instead of one dependent pair per bit.  Both
+  // position tables are read and the one of the bit's class kept by masks,
+  // so no control flow or scalar select depends on the class.
   TileSlot r{0, 0, 0};
 #pragma unroll
   for (int b = 0; b < 16; ++b) {
-    const bool on = b < nbits;
-    const uint8_t code = codes[on ? b : 0];
+    const int on = b < nbits ? 1 : 0;
+    const int code = codes[on ? b : 0];
     const int idx = code & 31;
-    const bool first = (code >> 5) == first_cls;
-    const int pos = tab[(first ? off_first : off_second) + idx];
-    const int bit = on ? (e >> b) & 1 : 0;
-    r.lo |= first ? bit << idx : 0;
-    r.hi |= first ? 0 : bit << idx;
+    const int m = (((code >> 5) ^ first_cls) - 1) >> 31;  // all ones for the first class
+    const int pos = (tab[off_first + idx] & m) | (tab[off_second + idx] & ~m);
+    const int bit = (e >> b) & on;
+    r.lo |= (bit << idx) & m;
+    r.hi |= (bit << idx) & ~m;
     r.off |= (uint32_t)bit << pos;
   }
   return r;
@@ -1335,35 +1341,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       wave_scatter(nt, tab + T_BN + d.tn, d.nb - d.tn) + wave_scatter(batch, tab + T_BB, d.bb);
 
   // Per-thread load slots: global offset inside the tile and LDS index.
-  // Slots outside a tile smaller than the template keep offset 0, so their
-  // (unused) loads stay in bounds and the loads need no branches.
+  // Decoding ignores bits at or above the operand's tile bits, so a slot
+  // past a tile smaller than the template repeats a valid one (same load,
+  // same value to the same LDS slot): loads and stores need no branches.
   uint32_t a_off[A_LOADS];
   int a_lds[A_LOADS];
   const int na = d.tm + d.tk;
 #pragma unroll
   for (int j = 0; j < A_LOADS; ++j) {
-    const int e = tid + 256 * j;
-    a_lds[j] = -1;
-    a_off[j] = 0;
-    if (e < (1 << na)) {
-      const TileSlot s = decode_slot(e, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK);
-      a_off[j] = s.off;
-      a_lds[j] = s.hi * SA + (s.lo ^ row_xor(d.a_swz, s.hi, TM - 1));
-    }
+    const TileSlot s = decode_slot(tid + 256 * j, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK);
+    a_off[j] = s.off;
+    a_lds[j] = s.hi * SA + (s.lo ^ row_xor(d.a_swz, s.hi, TM - 1));
   }
   uint32_t b_off[B_LOADS];
   int b_lds[B_LOADS];
   const int nbt = d.tk + d.tn;
 #pragma unroll
   for (int j = 0; j < B_LOADS; ++j) {
-    const int e = tid + 256 * j;
-    b_lds[j] = -1;
-    b_off[j] = 0;
-    if (e < (1 << nbt)) {
-      const TileSlot s = decode_slot(e, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN);
-      b_off[j] = s.off;
-      b_lds[j] = TK * SA + s.lo * SB + (s.hi ^ row_xor(d.b_swz, s.lo, TN - 1));
-    }
+    const TileSlot s = decode_slot(tid + 256 * j, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN);
+    b_off[j] = s.off;
+    b_lds[j] = TK * SA + s.lo * SB + (s.hi ^ row_xor(d.b_swz, s.lo, TN - 1));
   }
 
   const uint64_t k_tiles = 1ull << (d.kb - d.tk);
@@ -1398,11 +1395,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   auto store = [&](int r, int stage) {
     float2* S = smem + stage * STAGE;
 #pragma unroll
-    for (int j = 0; j < A_LOADS; ++j)
-      if (a_lds[j] >= 0) S[a_lds[j]] = ra[r][j];
+    for (int j = 0; j < A_LOADS; ++j) S[a_lds[j]] = ra[r][j];
 #pragma unroll
-    for (int j = 0; j < B_LOADS; ++j)
-      if (b_lds[j] >= 0) S[b_lds[j]] = rb[r][j];
+    for (int j = 0; j < B_LOADS; ++j) S[b_lds[j]] = rb[r][j];
   };
   // Moves the load offsets from k tile kt0 + t - 1 to kt0 + t (t >= 1).
   auto advance = [&](uint64_t t) {
@@ -1492,36 +1487,81 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // and B is expanded in LDS into 2 x 2 real blocks [[br, bi], [-bi, br]]
 // (rows 2k, 2k+1; columns 2n, 2n+1), so A' B' holds Re C in even and Im C in
 // odd columns.  One MFMA covers 16 rows, 8 complex columns and 16 complex k.
-// LDS rows are k-contiguous: A row m holds A[m][k] as 32-bit words, B' row
-// 2n + c holds the words (br, -bi) (c = 0) or (bi, br) (c = 1) of B[k][n].
-template <int P, int WM, int WN, int WK, int BM, int BN, int TK, int VEC>
-__global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
+// LDS rows hold one complex k per 32-bit word: A row m holds A[m][k], B'
+// row 2n + c holds the words (br, -bi) (c = 0) or (bi, br) (c = 1) of
+// B[k][n].  Word addresses follow the step's GF(2)-linear map (StepDesc::
+// ha_row, hb_row, hk): the order of the k inside a row is the same for A and
+// B (the sum over k does not depend on it) and 4-word groups are permuted
+// per row so that staging writes and fragment reads spread over the banks.
+
+// XOR of rows[i] over the set bits i of r (a row's word address).
+__device__ __forceinline__ uint32_t row_addr_h(const uint16_t* rows, int r) {
+  uint32_t a = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a ^= ((r >> i) & 1) ? (uint32_t)rows[i] : 0u;
+  return a;
+}
+
+// Address mask and LDS word vector of tile bit b of one operand (b < nbits;
+// zero beyond): row bits of class row_cls use rows[idx + row_off], k bits
+// 1 << hk[idx].  Branch-free: both table entries are read and the one of the
+// bit's class is kept by masks.
+__device__ __forceinline__ void tile_bit_h(int b, int nbits, const uint8_t* codes, const uint8_t* tab, int row_cls,
+                                           int off_row, int off_k, const uint16_t* rows, int row_off, uint32_t& off,
+                                           uint32_t& lds) {
+  const uint32_t on = 0u - (uint32_t)(b < nbits ? 1 : 0);
+  const int code = codes[b & 15];
+  const int idx = code & 31;
+  const uint32_t m = (uint32_t)((((code >> 5) ^ row_cls) - 1) >> 31);  // all ones for a row bit
+  const uint32_t pos = ((uint32_t)tab[off_row + idx] & m) | ((uint32_t)tab[off_k + idx] & ~m);
+  off = (1u << (pos & 31)) & on;
+  lds = (((uint32_t)rows[(idx + row_off) & 7] & m) | ((1u << (tab[T_HK + (idx & 7)] & 31)) & ~m)) & on;
+}
+
+// Address (OR of masks) and LDS word (XOR of vectors) of tile entry e.
+__device__ __forceinline__ void decode_h(uint32_t e, const uint32_t* boff, const uint32_t* blds, uint32_t& off,
+                                         uint32_t& lds) {
+  off = 0;
+  lds = 0;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    const uint32_t m = 0u - ((e >> b) & 1u);
+    off |= boff[b] & m;
+    lds ^= blds[b] & m;
+  }
+}
+
+template <int P, int WM, int WN, int WK, int BM, int BN, int TK, int VA, int VB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tile_h(StepDesc d) {
   constexpr int TM = WM * BM * 16;              // complex rows
   constexpr int TN = WN * BN * 8;               // complex columns
   constexpr int KW = TK / WK;                   // complex k per wave and k tile
   static_assert(KW % 16 == 0, "k per wave must be a multiple of 16");
-  constexpr int SW = TK + 4;                    // 32-bit words per LDS row (k contiguous)
-  constexpr int STAGE = TM * SW + 2 * TN * SW;  // words per stage
+  constexpr int A_WORDS = TM * TK;              // A stage: TM rows of TK words
+  constexpr int STAGE = A_WORDS + 2 * TN * TK;  // + expanded B: 2 TN rows
   constexpr int SC = TN + 2;                    // float2 per LDS row of the C tile
-  // VEC words per global load: 4 (one 16-byte load) when the two lowest
-  // tile bits of A and of B are their address bits 0 and 1 (the launcher
-  // checks), else 1.  A thread's elements of a load are consecutive in
-  // address order; their LDS slots differ by the uniform slot offsets of
-  // tile elements 0 .. VEC-1 (decoding is additive over disjoint bits).
+  // VA (VB) words per global load of A (B): 4 (one 16-byte load) when the
+  // two lowest tile bits are address bits 0 and 1 (the launcher checks),
+  // else 1.  A thread's words of one load differ in those two bits only, so
+  // their LDS words are the thread's slot XOR the uniform vectors du[u]; when
+  // du = {0, 1, 2, 3} they are one aligned 16-byte LDS store.
   constexpr int A_LOADS = TM * TK / 256;
   constexpr int B_LOADS = (TK * TN + 255) / 256;
-  constexpr int AV = A_LOADS / VEC, BV = (B_LOADS + VEC - 1) / VEC;
-  static_assert(VEC == 1 || VEC == 4, "1- or 4-word loads");
-  static_assert(AV * VEC == A_LOADS, "A loads split into whole vectors");
+  constexpr int AV = A_LOADS / VA, BV = (B_LOADS + VB - 1) / VB;
+  static_assert((VA == 1 || VA == 4) && (VB == 1 || VB == 4), "1- or 4-word loads");
+  static_assert(AV * VA == A_LOADS && AV <= 16 && BV <= 16, "A loads split into whole vectors");
+  constexpr int LVA = VA == 4 ? 2 : 0, LVB = VB == 4 ? 2 : 0;
   constexpr int C_ITEMS = TM * TN / 256;
   constexpr int SMEM_AB = 2 * STAGE;
   constexpr int SMEM_C = WK * TM * SC * 2;
   constexpr int SMEM = SMEM_AB > SMEM_C ? SMEM_AB : SMEM_C;
   static_assert(A_LOADS >= 1 && C_ITEMS >= 1, "tile too small");
-  using Vec = typename std::conditional<VEC == 4, uint4, uint32_t>::type;
+  using VecA = typename std::conditional<VA == 4, uint4, uint32_t>::type;
+  using VecB = typename std::conditional<VB == 4, uint4, uint32_t>::type;
   __shared__ __align__(16) uint32_t smem[SMEM];
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   __shared__ uint64_t flip[2][32];
+  __shared__ __align__(16) uint32_t bit_off[2][16], bit_lds[2][16];  // per tile bit of A (0) and B (1)
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -1530,8 +1570,22 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
   const uint32_t* B = reinterpret_cast<const uint32_t*>(d.B);
 
   load_tables(d, tab);
+  // Zero both stages once: entries outside the valid tile stay zero, so
+  // padded k never contributes and padded rows only feed outputs that are
+  // never stored.
   for (int i = tid; i < SMEM_AB; i += 256) smem[i] = 0u;
   __syncthreads();
+  const uint16_t* arow = reinterpret_cast<const uint16_t*>(tab + T_HAROW);
+  const uint16_t* brow = reinterpret_cast<const uint16_t*>(tab + T_HBROW);
+  const int na = d.tm + d.tk, nbt = d.tk + d.tn;
+  if (tid < 32) {
+    const int o = tid >> 4, b = tid & 15;
+    uint32_t off, lv;
+    if (o == 0) tile_bit_h(b, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK, arow, 0, off, lv);
+    else tile_bit_h(b, nbt, tab + T_BTILE, tab, TB_N, T_BN, T_BK, brow, 1, off, lv);
+    bit_off[o][b] = off;
+    bit_lds[o][b] = lv;
+  }
 
   const uint64_t n_mt = 1ull << (d.mb - d.tm);
   const uint64_t mt = blockIdx.x % n_mt, nt = blockIdx.x / n_mt;
@@ -1541,49 +1595,12 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
   const uint64_t baseB =
       wave_scatter(nt, tab + T_BN + d.tn, d.nb - d.tn) + wave_scatter(batch, tab + T_BB, d.bb);
 
-  uint32_t a_off[AV];
-  int a_lds[AV], a_du[VEC];
-  const int na = d.tm + d.tk;
-#pragma unroll
-  for (int u = 0; u < VEC; ++u) {
-    const TileSlot s = decode_slot(u, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK);
-    a_du[u] = s.lo * SW + s.hi;
-  }
-#pragma unroll
-  for (int j = 0; j < AV; ++j) {
-    const int e = (tid + 256 * j) * VEC;
-    a_lds[j] = -1;
-    a_off[j] = 0;
-    if (e < (1 << na)) {
-      const TileSlot s = decode_slot(e, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK);
-      a_off[j] = s.off;
-      a_lds[j] = s.lo * SW + s.hi;
-    }
-  }
-  uint32_t b_off[BV];
-  int b_lds[BV], b_du[VEC];
-  const int nbt = d.tk + d.tn;
-#pragma unroll
-  for (int u = 0; u < VEC; ++u) {
-    const TileSlot s = decode_slot(u, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN);
-    b_du[u] = (2 * s.hi) * SW + s.lo;
-  }
-#pragma unroll
-  for (int j = 0; j < BV; ++j) {
-    const int e = (tid + 256 * j) * VEC;
-    b_lds[j] = -1;
-    b_off[j] = 0;
-    if (e < (1 << nbt)) {
-      const TileSlot s = decode_slot(e, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN);
-      b_off[j] = s.off;
-      b_lds[j] = TM * SW + (2 * s.hi) * SW + s.lo;  // row 2n; row 2n + 1 is SW further
-    }
-  }
-
   const uint64_t k_tiles = 1ull << (d.kb - d.tk);
   const uint64_t per = k_tiles >> d.ks_bits;
   const uint64_t kt0 = (uint64_t)blockIdx.y * per;
   const int khb = d.kb - d.tk;
+  // Going from k tile t to t + 1 flips the logical high-k bits 0 .. ctz(t +
+  // 1); flip[.][j] holds the address bits of logical bits 0 .. j.
   if (tid < khb) {
     uint64_t fa = 0, fb = 0;
     for (int i = 0; i <= tid; ++i) {
@@ -1593,36 +1610,105 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
     flip[0][tid] = fa;
     flip[1][tid] = fb;
   }
+  __syncthreads();  // bit_off, bit_lds and flip are read from here on
+
+  // Load slots: entry e = (tid + 256 j) * V of an operand splits into the
+  // lane part tid * V (decoded once) and the uniform part 256 V j, whose
+  // address mask and LDS vector combine by OR / XOR (disjoint bits).  Bits
+  // at or above the operand's tile bits decode to zero, so a slot past a
+  // small tile repeats a valid one (same load, same word to the same LDS
+  // address): loads and stores need no bounds branches.
+  uint32_t a_off_t, a_lds_t, b_off_t, b_lds_t;
+  decode_h((uint32_t)tid * VA, bit_off[0], bit_lds[0], a_off_t, a_lds_t);
+  decode_h((uint32_t)tid * VB, bit_off[1], bit_lds[1], b_off_t, b_lds_t);
+  uint32_t ua_off[4], ua_lds[4], ub_off[4], ub_lds[4];  // tile bits 8 + log2 V + i
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ua_off[i] = __builtin_amdgcn_readfirstlane(bit_off[0][(8 + LVA + i) & 15]) * (8 + LVA + i < 16);
+    ua_lds[i] = __builtin_amdgcn_readfirstlane(bit_lds[0][(8 + LVA + i) & 15]) * (8 + LVA + i < 16);
+    ub_off[i] = __builtin_amdgcn_readfirstlane(bit_off[1][(8 + LVB + i) & 15]) * (8 + LVB + i < 16);
+    ub_lds[i] = __builtin_amdgcn_readfirstlane(bit_lds[1][(8 + LVB + i) & 15]) * (8 + LVB + i < 16);
+  }
+  auto uni = [](const uint32_t* v, int j) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r ^= ((j >> i) & 1) ? v[i] : 0u;
+    return r;
+  };
+  uint32_t a_du[VA], b_du[VB];  // LDS vectors of a load's words 0 .. V-1
+#pragma unroll
+  for (int u = 0; u < VA; ++u) a_du[u] = (u & 1 ? bit_lds[0][0] : 0u) ^ (u & 2 ? bit_lds[0][1] : 0u);
+#pragma unroll
+  for (int u = 0; u < VB; ++u) b_du[u] = (u & 1 ? bit_lds[1][0] : 0u) ^ (u & 2 ? bit_lds[1][1] : 0u);
+  bool a_vec = false, b_vec = false;
+  if constexpr (VA == 4) a_vec = a_du[1] == 1 && a_du[2] == 2 && a_du[3] == 3;
+  if constexpr (VB == 4) b_vec = b_du[1] == 1 && b_du[2] == 2 && b_du[3] == 3;
+  const uint32_t b_c = brow[0];
+
   uint64_t ka = wave_scatter(kt0, tab + T_AK + d.tk, khb);
   uint64_t kbo = wave_scatter(kt0, tab + T_BK + d.tk, khb);
-
-  Vec ra[AV], rb[BV];
-  auto load = [&]() {
+  // Two register sets of staged loads: k tile t + 2 is requested while tile
+  // t is computed and tile t + 1 (requested one tile earlier) goes to the
+  // other LDS stage.
+  VecA ra[2][AV];
+  VecB rb[2][BV];
+  auto load = [&](int r) {
+    const uint32_t* pa = A + (baseA + ka + a_off_t);
+    const uint32_t* pb = B + (baseB + kbo + b_off_t);
 #pragma unroll
-    for (int j = 0; j < AV; ++j) ra[j] = *reinterpret_cast<const Vec*>(A + (baseA + ka + a_off[j]));
+    for (int j = 0; j < AV; ++j) ra[r][j] = *reinterpret_cast<const VecA*>(pa + uni(ua_off, j));
 #pragma unroll
-    for (int j = 0; j < BV; ++j) rb[j] = *reinterpret_cast<const Vec*>(B + (baseB + kbo + b_off[j]));
+    for (int j = 0; j < BV; ++j) rb[r][j] = *reinterpret_cast<const VecB*>(pb + uni(ub_off, j));
   };
-  auto word = [](const Vec& v, int u) -> uint32_t {
-    if constexpr (VEC == 4) return u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w;
-    else return v;
-  };
-  auto store = [&](int stage) {
+  auto swap_halves = [](uint32_t w) { return (w >> 16) | (w << 16); };
+  auto store = [&](int r, int stage) {
     uint32_t* S = smem + stage * STAGE;
+    uint32_t* SB = S + A_WORDS;
 #pragma unroll
-    for (int j = 0; j < AV; ++j)
-      if (a_lds[j] >= 0)
-#pragma unroll
-        for (int u = 0; u < VEC; ++u) S[a_lds[j] + a_du[u]] = word(ra[j], u);
-#pragma unroll
-    for (int j = 0; j < BV; ++j)
-      if (b_lds[j] >= 0)
-#pragma unroll
-        for (int u = 0; u < VEC; ++u) {
-          const uint32_t w = word(rb[j], u);                   // (br, bi)
-          S[b_lds[j] + b_du[u]] = w ^ 0x80000000u;             // (br, -bi)
-          S[b_lds[j] + b_du[u] + SW] = (w >> 16) | (w << 16);  // (bi, br)
+    for (int j = 0; j < AV; ++j) {
+      const uint32_t l = a_lds_t ^ uni(ua_lds, j);
+      if constexpr (VA == 4) {
+        if (a_vec) {
+          *reinterpret_cast<uint4*>(S + l) = ra[r][j];
+        } else {
+          S[l ^ a_du[0]] = ra[r][j].x;
+          S[l ^ a_du[1]] = ra[r][j].y;
+          S[l ^ a_du[2]] = ra[r][j].z;
+          S[l ^ a_du[3]] = ra[r][j].w;
         }
+      } else {
+        S[l] = ra[r][j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BV; ++j) {
+      const uint32_t l = b_lds_t ^ uni(ub_lds, j);  // row 2n; row 2n + 1 is this XOR brow[0]
+      if constexpr (VB == 4) {
+        const uint4 w = rb[r][j];
+        if (b_vec) {
+          *reinterpret_cast<uint4*>(SB + l) =
+              uint4{w.x ^ 0x80000000u, w.y ^ 0x80000000u, w.z ^ 0x80000000u, w.w ^ 0x80000000u};
+          *reinterpret_cast<uint4*>(SB + (l ^ b_c)) =
+              uint4{swap_halves(w.x), swap_halves(w.y), swap_halves(w.z), swap_halves(w.w)};
+        } else {
+          const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t x = l ^ b_du[u];
+            SB[x] = ws[u] ^ 0x80000000u;       // (br, -bi)
+            SB[x ^ b_c] = swap_halves(ws[u]);  // (bi, br)
+          }
+        }
+      } else {
+        SB[l] = rb[r][j] ^ 0x80000000u;
+        SB[l ^ b_c] = swap_halves(rb[r][j]);
+      }
+    }
+  };
+  auto advance = [&](uint64_t t) {  // load offsets from k tile kt0 + t - 1 to kt0 + t
+    const int fl = __builtin_ctzll(kt0 + t);
+    ka ^= flip[0][fl];
+    kbo ^= flip[1][fl];
   };
 
   v4f acc[BM][BN];
@@ -1631,31 +1717,28 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
 #pragma unroll
     for (int j = 0; j < BN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  load();
-  store(0);
-  __syncthreads();
+  // Fragment word addresses: row part (lane rows 0-15 and the block rows,
+  // both XORs of row vectors) and the lane's 4-word k group; each MFMA step
+  // ks adds 16 words (XOR: the bits are disjoint).
   const int row = lane & 15, kg = lane >> 4;
-  for (uint64_t it = 0; it < per; ++it) {
-    const int cur = (int)(it & 1);
-    const bool more = it + 1 < per;
-    if (more) {
-      const int fl = __builtin_ctzll(kt0 + it + 1);
-      ka ^= flip[0][fl];
-      kbo ^= flip[1][fl];
-      load();
-    }
+  const uint32_t a_lane = row_addr_h(arow, row) ^ (uint32_t)(wk * KW + 4 * kg);
+  const uint32_t b_lane = row_addr_h(brow, row) ^ (uint32_t)(wk * KW + 4 * kg);
+  uint32_t a_frag[BM], b_frag[BN];
+#pragma unroll
+  for (int bm = 0; bm < BM; ++bm) a_frag[bm] = a_lane ^ row_addr_h(arow, (wm * BM + bm) * 16);
+#pragma unroll
+  for (int bn = 0; bn < BN; ++bn) b_frag[bn] = b_lane ^ row_addr_h(brow, (wn * BN + bn) * 16);
+
+  auto compute = [&](int cur) {
     const uint32_t* As = smem + cur * STAGE;
-    const uint32_t* Bs = As + TM * SW;
+    const uint32_t* Bs = As + A_WORDS;
 #pragma unroll
     for (int ks = 0; ks < KW / 16; ++ks) {
-      const int kw = wk * KW + ks * 16 + 4 * kg;  // first of this lane's 4 complex k
       uint4 av[BM], bv[BN];
 #pragma unroll
-      for (int bm = 0; bm < BM; ++bm)
-        av[bm] = *reinterpret_cast<const uint4*>(As + ((wm * BM + bm) * 16 + row) * SW + kw);
+      for (int bm = 0; bm < BM; ++bm) av[bm] = *reinterpret_cast<const uint4*>(As + (a_frag[bm] ^ (uint32_t)(16 * ks)));
 #pragma unroll
-      for (int bn = 0; bn < BN; ++bn)
-        bv[bn] = *reinterpret_cast<const uint4*>(Bs + ((wn * BN + bn) * 16 + row) * SW + kw);
+      for (int bn = 0; bn < BN; ++bn) bv[bn] = *reinterpret_cast<const uint4*>(Bs + (b_frag[bn] ^ (uint32_t)(16 * ks)));
 #pragma unroll
       for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
@@ -1668,8 +1751,28 @@ __global__ __launch_bounds__(256) void k_tile_h(StepDesc d) {
                 __builtin_bit_cast(v8bf, av[bm]), __builtin_bit_cast(v8bf, bv[bn]), acc[bm][bn], 0, 0, 0);
         }
     }
-    if (more) store(cur ^ 1);
+  };
+  // One k tile: stage it & 1 holds tile it, register set x holds tile it + 1.
+  auto step = [&](uint64_t it, int x) {
+    if (it + 2 < per) {
+      advance(it + 2);
+      load(x ^ 1);
+    }
+    compute((int)(it & 1));
+    if (it + 1 < per) store(x, (int)(it & 1) ^ 1);
     __syncthreads();
+  };
+
+  load(0);
+  if (per > 1) {
+    advance(1);
+    load(1);
+  }
+  store(0, 0);
+  __syncthreads();
+  for (uint64_t it = 0; it < per; it += 2) {
+    step(it, 1);
+    if (it + 1 < per) step(it + 1, 0);
   }
   // Accumulators -> LDS tile (rows m, interleaved re/im columns).
   float* Cf = reinterpret_cast<float*>(smem);
@@ -1943,14 +2046,26 @@ static int tile_bit_pos(const StepDesc& d, uint8_t code, bool is_a) {
   return cls == TB_K ? d.bk[idx] : d.bn[idx];
 }
 
-// 16-byte tile loads apply when the two lowest tile bits of A and of B are
-// their address bits 0 and 1 (four consecutive words of a tile are then
-// consecutive in memory) and both operands are 16-byte aligned.
-static bool tile_vec4(const StepDesc& d) {
-  if (d.tm + d.tk < 2 || d.tk + d.tn < 2) return false;
-  if (tile_bit_pos(d, d.a_tile[0], true) != 0 || tile_bit_pos(d, d.a_tile[1], true) != 1) return false;
-  if (tile_bit_pos(d, d.b_tile[0], false) != 0 || tile_bit_pos(d, d.b_tile[1], false) != 1) return false;
-  return (reinterpret_cast<uintptr_t>(d.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
+// 16-byte loads of A (B) apply when the plan chose them (StepDesc::vec_a,
+// vec_b), the two lowest tile bits are the operand's address bits 0 and 1
+// (four consecutive words of a tile are then consecutive in memory) and the
+// operand is 16-byte aligned.
+static bool tile_vec_a(const StepDesc& d) {
+  return d.vec_a == 4 && d.tm + d.tk >= 2 && tile_bit_pos(d, d.a_tile[0], true) == 0 &&
+         tile_bit_pos(d, d.a_tile[1], true) == 1 && (reinterpret_cast<uintptr_t>(d.A) & 15) == 0;
+}
+static bool tile_vec_b(const StepDesc& d) {
+  return d.vec_b == 4 && d.tk + d.tn >= 2 && tile_bit_pos(d, d.b_tile[0], false) == 0 &&
+         tile_bit_pos(d, d.b_tile[1], false) == 1 && (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
+}
+
+template <int P, int WM, int WN, int WK, int BM, int BN, int TK>
+static void launch_tile_h(const StepDesc& d, dim3 grid, hipStream_t s, Timing t) {
+  const bool va = tile_vec_a(d), vb = tile_vec_b(d);
+  if (va && vb) launch_k(k_tile_h<P, WM, WN, WK, BM, BN, TK, 4, 4>, grid, dim3(256), 0, s, t, d);
+  else if (va) launch_k(k_tile_h<P, WM, WN, WK, BM, BN, TK, 4, 1>, grid, dim3(256), 0, s, t, d);
+  else if (vb) launch_k(k_tile_h<P, WM, WN, WK, BM, BN, TK, 1, 4>, grid, dim3(256), 0, s, t, d);
+  else launch_k(k_tile_h<P, WM, WN, WK, BM, BN, TK, 1, 1>, grid, dim3(256), 0, s, t, d);
 }
 
 template <int P>
@@ -2001,23 +2116,13 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
         else
           launch_k(k_tile<1, 1, 4, 1, 1, 64>, grid, dim3(256), 0, s, t, d);
       } else {
-        const bool v4 = tile_vec4(d);
-        if (kclass == MITNC_K_TILE) {
-          if (v4)
-            launch_k(k_tile_h<P, MITNC_TILEH_WM, MITNC_TILEH_WN, MITNC_TILEH_WK, MITNC_TILEH_BM, MITNC_TILEH_BN,
-                              MITNC_TILEH_TK, 4>,
-                     grid, dim3(256), 0, s, t, d);
-          else
-            launch_k(k_tile_h<P, MITNC_TILEH_WM, MITNC_TILEH_WN, MITNC_TILEH_WK, MITNC_TILEH_BM, MITNC_TILEH_BN,
-                              MITNC_TILEH_TK, 1>,
-                     grid, dim3(256), 0, s, t, d);
-        } else if (kclass == MITNC_K_TALL) {
-          if (v4) launch_k(k_tile_h<P, 4, 1, 1, 2, 2, 32, 4>, grid, dim3(256), 0, s, t, d);
-          else launch_k(k_tile_h<P, 4, 1, 1, 2, 2, 32, 1>, grid, dim3(256), 0, s, t, d);
-        } else {
-          if (v4) launch_k(k_tile_h<P, 1, 1, 4, 1, 2, 128, 4>, grid, dim3(256), 0, s, t, d);
-          else launch_k(k_tile_h<P, 1, 1, 4, 1, 2, 128, 1>, grid, dim3(256), 0, s, t, d);
-        }
+        if (kclass == MITNC_K_TILE)
+          launch_tile_h<P, MITNC_TILEH_WM, MITNC_TILEH_WN, MITNC_TILEH_WK, MITNC_TILEH_BM, MITNC_TILEH_BN,
+                        MITNC_TILEH_TK>(d, grid, s, t);
+        else if (kclass == MITNC_K_TALL)
+          launch_tile_h<P, 4, 1, 1, 2, 2, 32>(d, grid, s, t);
+        else
+          launch_tile_h<P, 1, 1, 4, 1, 2, 128>(d, grid, s, t);
       }
       if (e == hipSuccess) e = hipGetLastError();
       if (e != hipSuccess || d.ks_bits == 0) return e;

@@ -20,10 +20,12 @@
 //    batched or short ones), square-ish GEMM tiles on MFMA, narrow tiles, and
 //    split-K for K >> M, N (Sec. V-B, split-common TTGT).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <set>
 #include <tuple>
@@ -130,6 +132,191 @@ static void lds_row_swizzle(const uint8_t* codes, int ncodes, int row_cls, int c
     s32.add(vec);
   }
   if (!row0_lane && gmax == 32 && !(cols & 16)) g[0] = 16;
+}
+
+// ---------------------------------------------------------------- FP16/BF16 tile LDS layout
+// The FP16/BF16 tile kernels keep A as TM rows (m) and the expanded B as
+// 2 TN rows (2n + re/im) of 2^tkb 32-bit words (one complex k per word).
+// The word address of a tile entry is the XOR of one vector per set bit:
+// m bit i -> ha_row[i], B row bit r -> hb_row[r], k bit j -> 1 << hk[j].
+// Row vectors are the row stride plus a swizzle c << 2 (c permutes the
+// 4-word groups of a row), so the map is a bijection and 4-word groups stay
+// contiguous for the 16-byte fragment reads.
+//
+// Bank model: 4-byte banks, 32 (128 B per clock) or 64 (256 B per clock);
+// a wave access is served in groups of lanes that together fill the banks
+// once (32 lanes for 4-byte, 8 for 16-byte accesses with 32 banks; twice as
+// many with 64), and a group whose lanes differ in d address bits that are
+// linearly dependent over GF(2) in the bank index takes 2^d times as long.
+namespace {
+struct HDesign {
+  uint16_t arow[8] = {}, brow[8] = {};
+  uint8_t hk[8] = {};
+  int va = 1, vb = 1;
+  double cost = 1e30;
+};
+
+int gf2_rank(const uint32_t* v, int n) {
+  XorSpan s;
+  int r = 0;
+  for (int i = 0; i < n; ++i)
+    if (!s.contains(v[i])) {
+      s.add(v[i]);
+      ++r;
+    }
+  return r;
+}
+
+// Modeled cycles of one 64-lane LDS access whose lane bits 0..5 move the
+// word address by lane_vec[0..5], width 1 or 4 words, summed over the
+// 32- and 64-bank models.
+double access_cost(const uint32_t* lane_vec, int width) {
+  double c = 0;
+  for (int nb : {32, 64}) {
+    const int per = nb / width;  // lanes per group
+    const int L = __builtin_ctz(per);
+    const int sh = width == 4 ? 2 : 0;
+    uint32_t v[6];
+    for (int i = 0; i < L; ++i) v[i] = (lane_vec[i] >> sh) & (uint32_t)(per - 1);
+    const int deg = 1 << (L - gf2_rank(v, L));
+    c += (64.0 / per) * deg;  // groups per instruction x conflict degree
+  }
+  return c;
+}
+
+// Row swizzles c0..c3 (of row bits 0..3) for which 16-byte fragment reads
+// of 8 (16) consecutive rows hit distinct 4-word blocks mod 32 (64) banks.
+const std::vector<std::array<uint8_t, 4>>& read_feasible(int tkb) {
+  static std::vector<std::array<uint8_t, 4>> cache[16];
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  auto& f = cache[tkb];
+  if (!f.empty()) return f;
+  const int ng = std::min(tkb - 2, 4);
+  const int G = 1 << ng;
+  for (int c0 = 0; c0 < G; ++c0)
+    for (int c1 = 0; c1 < G; ++c1)
+      for (int c2 = 0; c2 < G; ++c2)
+        for (int c3 = 0; c3 < G; ++c3) {
+          const int cs[4] = {c0, c1, c2, c3};
+          uint32_t r32[3], r64[4];
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t rv = (1u << (i + tkb)) ^ ((uint32_t)cs[i] << 2);
+            if (i < 3) r32[i] = (rv >> 2) & 7;
+            r64[i] = (rv >> 2) & 15;
+          }
+          if (gf2_rank(r32, 3) == 3 && gf2_rank(r64, 4) == 4)
+            f.push_back({(uint8_t)c0, (uint8_t)c1, (uint8_t)c2, (uint8_t)c3});
+        }
+  return f;
+}
+
+// Best row vectors for one operand: codes = tile bits in address order,
+// row_cls = class of the row bits, row_off = row bit of row index 0 of that
+// class (1 for the expanded B), nrows = template row bits.  Returns the cost
+// of the operand's staging writes per k tile and thread.
+double choose_rows(const uint8_t* codes, int ncodes, int row_cls, int row_off, int nrows, int tkb,
+                   const uint8_t* hk, int vec, int words_per_thread, int copies, uint16_t* rows_out) {
+  const auto& feas = read_feasible(tkb);
+  const int ub = vec == 4 ? 2 : 0;
+  double best = 1e30;
+  for (const auto& cs : feas) {
+    uint32_t rv[8];
+    for (int i = 0; i < nrows; ++i) rv[i] = (1u << (i + tkb)) ^ (i < 4 ? (uint32_t)cs[i] << 2 : 0u);
+    auto vec_of = [&](uint8_t code) -> uint32_t {
+      const int cls = code >> 5, idx = code & 31;
+      if (cls == row_cls) return rv[idx + row_off];
+      return 1u << hk[idx];
+    };
+    uint32_t lane[6] = {};
+    for (int i = 0; i < 6; ++i) lane[i] = ub + i < ncodes ? vec_of(codes[ub + i]) : 0u;
+    const bool contig = vec == 4 && ncodes >= 2 && vec_of(codes[0]) == 1 && vec_of(codes[1]) == 2;
+    const double per_instr = contig ? access_cost(lane, 4) : access_cost(lane, 1);
+    const int instr = contig ? std::max(1, words_per_thread / 4) : std::max(1, words_per_thread);
+    const double cost = per_instr * instr * copies;
+    if (cost < best) {
+      best = cost;
+      for (int i = 0; i < nrows; ++i) rows_out[i] = (uint16_t)rv[i];
+    }
+  }
+  return best;
+}
+}  // namespace
+
+// Chooses the FP16/BF16 tile LDS layout of a step (see above): 16-byte
+// loads for each operand whose layout allows them, and among k-bit orders
+// that put the lowest k bits of A or B at columns 0 and 1, the one with the
+// fewest modeled staging-write cycles (reads are conflict-free by
+// construction).
+static void lds_design_h(StepDesc& d, const TileGeom& g) {
+  const int tkb = g.tk_bits;
+  auto pos_a = [&](uint8_t c) { return (c >> 5) == TB_M ? d.am[c & 31] : d.ak[c & 31]; };
+  auto pos_b = [&](uint8_t c) { return (c >> 5) == TB_K ? d.bk[c & 31] : d.bn[c & 31]; };
+  const int na = d.tm + d.tk, nb = d.tk + d.tn;
+  const bool va_ok = na >= 2 && pos_a(d.a_tile[0]) == 0 && pos_a(d.a_tile[1]) == 1;
+  const bool vb_ok = nb >= 2 && pos_b(d.b_tile[0]) == 0 && pos_b(d.b_tile[1]) == 1;
+  std::vector<int> ka, kb;  // tile k bits in address order
+  for (int i = 0; i < na; ++i)
+    if ((d.a_tile[i] >> 5) == TB_K) ka.push_back(d.a_tile[i] & 31);
+  for (int i = 0; i < nb; ++i)
+    if ((d.b_tile[i] >> 5) == TB_K) kb.push_back(d.b_tile[i] & 31);
+  std::vector<std::vector<int>> firsts;
+  auto two = [](const std::vector<int>& v) { return std::vector<int>(v.begin(), v.begin() + std::min<size_t>(2, v.size())); };
+  firsts.push_back(two(ka));
+  firsts.push_back(two(kb));
+  if (!ka.empty() && !kb.empty()) {
+    for (int x : kb)
+      if (x != ka[0]) {
+        firsts.push_back({ka[0], x});
+        break;
+      }
+    for (int x : ka)
+      if (x != kb[0]) {
+        firsts.push_back({kb[0], x});
+        break;
+      }
+  }
+  firsts.push_back({});
+  const int wa = std::max(1, (1 << na) / 256), wb = std::max(1, (1 << nb) / 256);
+  const int nrow_a = g.tm_bits, nrow_b = g.tn_bits + 1;
+  HDesign best;
+  std::set<std::vector<int>> seen;
+  for (const auto& f : firsts) {
+    if (!seen.insert(f).second) continue;
+    uint8_t hk[8] = {};
+    std::vector<char> used(8, 0);
+    int col = 0;
+    for (int j : f) {
+      hk[j] = (uint8_t)col++;
+      used[j] = 1;
+    }
+    for (int j = 0; j < d.tk; ++j)
+      if (!used[j]) hk[j] = (uint8_t)col++;
+    for (int va : {4, 1}) {
+      if (va == 4 ? !va_ok : va_ok) continue;  // 16-byte loads whenever the layout has them
+      uint16_t ra[8] = {};
+      const double ca = choose_rows(d.a_tile, na, TB_M, 0, nrow_a, tkb, hk, va, wa, 1, ra);
+      for (int vb : {4, 1}) {
+        if (vb == 4 ? !vb_ok : vb_ok) continue;
+        uint16_t rb[8] = {};
+        const double cb = choose_rows(d.b_tile, nb, TB_N, 1, nrow_b, tkb, hk, vb, wb, 2, rb);
+        const double cost = ca + cb - 1e-3 * (va + vb);  // ties: wider loads
+        if (cost < best.cost) {
+          best.cost = cost;
+          best.va = va;
+          best.vb = vb;
+          std::memcpy(best.arow, ra, sizeof ra);
+          std::memcpy(best.brow, rb, sizeof rb);
+          std::memcpy(best.hk, hk, sizeof hk);
+        }
+      }
+    }
+  }
+  std::memcpy(d.ha_row, best.arow, sizeof d.ha_row);
+  std::memcpy(d.hb_row, best.brow, sizeof d.hb_row);
+  std::memcpy(d.hk, best.hk, sizeof d.hk);
+  d.vec_a = (uint8_t)best.va;
+  d.vec_b = (uint8_t)best.vb;
 }
 
 static TileGeom geom_of(int kclass, int precision) {
@@ -336,6 +523,8 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     if (precision == MITNC_C64) {
       lds_row_swizzle(d.a_tile, d.tm + d.tk, TB_K, g.tm_bits, d.a_swz);
       lds_row_swizzle(d.b_tile, d.tk + d.tn, TB_K, g.tn_bits, d.b_swz);
+    } else {
+      lds_design_h(d, g);
     }
     // Split K over workgroups when there are too few output tiles to fill the
     // chip (Sec. V-B: partition along the common indices); keep at least 4 k

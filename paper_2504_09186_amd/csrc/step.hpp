@@ -42,18 +42,29 @@ struct StepDesc {
   uint8_t bk[32], bn[32], bbt[32];
   uint8_t cm[32], cn[32], cb[32];
   uint8_t a_tile[16], b_tile[16], c_tile[16];  // tile bits sorted by address position
+  // FP16/BF16 tile kernels: the LDS word address of a tile entry is the XOR
+  // of one vector per set tile bit (a GF(2)-linear map chosen per step for
+  // conflict-free LDS access): row bit i of the A stage (m bit i) gives
+  // ha_row[i], row bit r of the expanded B stage (r = 0: the re/im row of
+  // the 2 x 2 block, r = i + 1: n bit i) gives hb_row[r], and tile k bit j
+  // gives 1 << hk[j] (its column bit in the row).
+  uint16_t ha_row[8], hb_row[8];
+  uint8_t hk[8];
   // Complex64 tile kernels: LDS row k of the A (B) stage stores column m (n)
   // at m ^ H(k), H(k) the XOR of a_swz[j] (b_swz[j]) over the set bits j of
   // k.  Chosen per step so that the scattered staging writes and the
   // fragment reads hit distinct LDS banks (all zero: plain rows).
   uint8_t a_swz[8], b_swz[8];
+  // FP16/BF16 tile kernels: 16-byte global loads wanted for A / B (the two
+  // lowest tile bits are address bits 0 and 1); 4 or 1.
+  uint8_t vec_a, vec_b;
 };
 
 // Byte offsets of the tables relative to StepDesc::am.
 enum TabOff : int {
   T_AM = 0, T_AK = 32, T_AB = 64, T_BK = 96, T_BN = 128, T_BB = 160,
   T_CM = 192, T_CN = 224, T_CB = 256, T_ATILE = 288, T_BTILE = 304, T_CTILE = 320,
-  TAB_BYTES = 336
+  T_HAROW = 336, T_HBROW = 352, T_HK = 368, TAB_BYTES = 376
 };
 
 // Device table entry mapping a single-qubit gate leaf's adjoint into the

@@ -138,6 +138,10 @@ class Plan:
         for f, cnt in (("am", "mb"), ("ak", "kb"), ("ab", "bb"), ("bk", "kb"), ("bn", "nb"), ("bbt", "bb"),
                        ("cm", "mb"), ("cn", "nb"), ("cb", "bb")):
             r[f] = list(getattr(si, f))[:r[cnt]]
+        for f in ("tm", "tn", "tk", "vec_a", "vec_b"):
+            r[f] = int(getattr(si, f))
+        for f in ("a_tile", "b_tile", "lds_a_swz", "lds_b_swz", "lds_a_row", "lds_b_row", "lds_k_col"):
+            r[f] = [int(x) for x in getattr(si, f)]
         return r
 
     def reverse_info(self, op: Optional[int] = None):

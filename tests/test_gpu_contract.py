@@ -222,10 +222,18 @@ def test_half_storage(prec, mb, nb, kb, bb, kernel):
     contraction of the true tiny operands.  Bound: FP32 accumulation error
     6 gamma_{K+4} |x||y| plus one rounding of the output (2^-11 FP16, 2^-8
     BF16 relative)."""
+    la, lb, lc, a, b = _case(mb, nb, kb, bb, 77 + mb + 10 * nb + 100 * kb + prec, rows_ordered=kernel == STREAM)
+    _half_check(prec, la, lb, lc, a, b, kernel)
+
+
+def _half_check(prec, la, lb, lc, a, b, kernel):
     require_gpu()
     import torch
     from paper_2504_09186_amd import tnc
-    la, lb, lc, a, b = _case(mb, nb, kb, bb, 77 + mb + 10 * nb + 100 * kb + prec, rows_ordered=kernel == STREAM)
+    kb = len(set(la) & set(lb)) - len([x for x in la if x < 0])
+    mb, nb, bb = len(la) - kb, len(lb) - kb, len([x for x in la if x < 0])
+    mb -= bb
+    nb -= bb
     ea, eb = -30, -20
     wa, xr = _to_half_words(a.astype(np.complex128), prec)  # mantissas X
     wb, yr = _to_half_words(b.astype(np.complex128), prec)
@@ -248,3 +256,42 @@ def test_half_storage(prec, mb, nb, kb, bb, kernel):
     bound = absab * gamma((1 << kb) + 4) * 6.0 + np.abs(ref) * u_out * 1.01 + 1e-300
     err = np.abs(got - ref)
     assert np.all(err <= bound), f"max err/bound {np.max(err / bound)}"
+
+
+def _case_low_bits(mb, nb, kb, a_low, b_low, seed):
+    """Layouts whose lowest address bits are chosen: a_low / b_low list the
+    classes ('m', 'k', 'n') of A's / B's lowest bits (in order); the other
+    bits are random.  This steers the FP16/BF16 tile kernels onto their
+    16-byte load paths (the two lowest tile bits at address bits 0 and 1),
+    with the four words of a load landing on one LDS row (k bits) or on
+    different rows (m or n bits)."""
+    rng = np.random.default_rng(seed)
+    M = [1000 + i for i in range(mb)]
+    N = [2000 + i for i in range(nb)]
+    K = [3000 + i for i in range(kb)]
+    def layout(low, pools):
+        pools = {c: list(rng.permutation(v)) for c, v in pools.items()}
+        head = [int(pools[c].pop()) for c in low]
+        rest = [int(x) for v in pools.values() for x in v]
+        return head + [int(x) for x in rng.permutation(rest)] if rest else head
+    la = layout(a_low, {"m": M, "k": K})
+    lb = layout(b_low, {"k": K, "n": N})
+    lc = [int(x) for x in rng.permutation(M + N)]
+    a = synth.complex_normal(1 << len(la), seed=seed + 1).astype(np.complex64)
+    b = synth.complex_normal(1 << len(lb), seed=seed + 2).astype(np.complex64)
+    return la, lb, lc, a, b
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("mb,nb,kb,a_low,b_low,kernel", [
+    (9, 7, 8, "kk", "kk", TILE), (9, 7, 8, "kk", "kn", TILE), (9, 7, 8, "mk", "kk", TILE),
+    (8, 8, 7, "mm", "nn", TILE), (9, 4, 7, "kk", "kk", TALL), (9, 4, 7, "mm", "kn", TALL),
+    (4, 4, 10, "kk", "kk", SPLITK), (3, 3, 11, "km", "nk", SPLITK)])
+def test_half_tile_load_paths(prec, mb, nb, kb, a_low, b_low, kernel):
+    """FP16/BF16 tile kernels on layouts that take the 16-byte load paths of
+    A and B (the lowest two bits of an operand are both tile bits); same
+    bound as test_half_storage."""
+    la, lb, lc, a, b = _case_low_bits(mb, nb, kb, a_low, b_low, 500 + mb + 10 * nb + 100 * kb + prec)
+    print(f"half tile load paths m{mb} n{nb} k{kb} A low {a_low} B low {b_low} kernel {kernel} prec {prec}",
+          flush=True)
+    _half_check(prec, la, lb, lc, a, b, kernel)
