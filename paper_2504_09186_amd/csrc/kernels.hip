@@ -1296,6 +1296,23 @@ __device__ __forceinline__ int row_xor(const uint8_t* swz, int k, int mask) {
   return h & mask;
 }
 
+// Output tile (mt, nt) of workgroup x among n_mt x n_nt tiles.  Workgroups
+// are dealt round-robin over the 8 XCDs, each with its own L2.  With few n
+// tiles (2 to 8) the tiles of one m block go to one XCD next to each other in
+// dispatch order, so the A block is read from HBM once and the other n tiles
+// find it in that XCD's L2; otherwise m is the fastest index (the tiles of
+// one m block still share an XCD when n_mt is a multiple of 8).
+__device__ __forceinline__ void tile_of(uint64_t x, uint64_t n_mt, uint64_t n_nt, uint64_t& mt, uint64_t& nt) {
+  if (n_nt > 1 && n_nt <= 8 && (n_mt & 7) == 0) {
+    const uint64_t i = x >> 3;
+    nt = i % n_nt;
+    mt = (i / n_nt) * 8 + (x & 7);
+  } else {
+    mt = x % n_mt;
+    nt = x / n_mt;
+  }
+}
+
 template <int WM, int WN, int WK, int BM, int BN, int TK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tile(StepDesc d) {
   constexpr int TM = WM * BM * 16;
@@ -1326,19 +1343,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const float2* B = reinterpret_cast<const float2*>(d.B);
 
   load_tables(d, tab);
-  // Zero both stages once: entries outside the valid tile stay zero, so
-  // padded k never contributes and padded rows/columns only feed outputs that
-  // are never stored.
-  for (int i = tid; i < SMEM_AB; i += 256) smem[i] = make_float2(0.f, 0.f);
   __syncthreads();
-
-  const uint64_t n_mt = 1ull << (d.mb - d.tm);
-  const uint64_t mt = blockIdx.x % n_mt, nt = blockIdx.x / n_mt;
-  const uint64_t batch = blockIdx.z;
-  const uint64_t baseA =
-      wave_scatter(mt, tab + T_AM + d.tm, d.mb - d.tm) + wave_scatter(batch, tab + T_AB, d.bb);
-  const uint64_t baseB =
-      wave_scatter(nt, tab + T_BN + d.tn, d.nb - d.tn) + wave_scatter(batch, tab + T_BB, d.bb);
+  // Padded k (fewer k bits than the stage) must read as zero in both
+  // operands; other entries outside the valid tile only feed outputs that
+  // are never stored.  A tile's C staging overwrites the stages, so with
+  // padded k the stages are zeroed again for every tile.
+  const bool pad_k = d.tk < __builtin_ctz(TK);
+  uint64_t baseA = 0, baseB = 0;  // tile origins in A and B (set per output tile)
 
   // Per-thread load slots: global offset inside the tile and LDS index.
   // Decoding ignores bits at or above the operand's tile bits, so a slot
@@ -1379,8 +1390,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     flip[0][tid] = fa;
     flip[1][tid] = fb;
   }
-  uint64_t ka = wave_scatter(kt0, tab + T_AK + d.tk, khb);
-  uint64_t kbo = wave_scatter(kt0, tab + T_BK + d.tk, khb);
+  const uint64_t ka0 = wave_scatter(kt0, tab + T_AK + d.tk, khb);
+  const uint64_t kbo0 = wave_scatter(kt0, tab + T_BK + d.tk, khb);
+  uint64_t ka = ka0, kbo = kbo0;
 
   // Two register sets of staged loads: k tile t + 2 is requested while
   // tile t is computed and tile t + 1 (requested one tile earlier) goes to
@@ -1407,13 +1419,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   };
 
   v4f acc[3][BM][BN];
-#pragma unroll
-  for (int p = 0; p < 3; ++p)
-#pragma unroll
-    for (int i = 0; i < BM; ++i)
-#pragma unroll
-      for (int j = 0; j < BN; ++j) acc[p][i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-
   const int row = lane & 15, kq = lane >> 4;
   auto compute = [&](int cur) {
     const float2* As = smem + cur * STAGE;
@@ -1452,32 +1457,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   };
 
   __syncthreads();  // flip[][] (written above by threads tid < khb) is read from here on
-  load(0);
-  if (per > 1) {
-    advance(1);
-    load(1);
+  // Output tiles are dealt grid-stride (the launch holds about as many
+  // workgroups as are resident), so the set-up above is paid once per
+  // workgroup and a tile's stores drain while the next tile loads.
+  const uint64_t n_mt = 1ull << (d.mb - d.tm), n_nt = 1ull << (d.nb - d.tn);
+  const uint64_t batch = blockIdx.z;
+  for (uint64_t tx = blockIdx.x; tx < n_mt * n_nt; tx += gridDim.x) {
+    uint64_t mt, nt;
+    tile_of(tx, n_mt, n_nt, mt, nt);
+    baseA = wave_scatter(mt, tab + T_AM + d.tm, d.mb - d.tm) + wave_scatter(batch, tab + T_AB, d.bb);
+    baseB = wave_scatter(nt, tab + T_BN + d.tn, d.nb - d.tn) + wave_scatter(batch, tab + T_BB, d.bb);
+    ka = ka0;
+    kbo = kbo0;
+    if (pad_k) {
+      for (int i = tid; i < SMEM_AB; i += 256) smem[i] = make_float2(0.f, 0.f);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) acc[p][i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    load(0);
+    if (per > 1) {
+      advance(1);
+      load(1);
+    }
+    store(0, 0);
+    __syncthreads();
+    for (uint64_t it = 0; it < per; it += 2) {
+      step(it, 1);
+      if (it + 1 < per) step(it + 1, 0);
+    }
+    // Accumulators -> LDS tile: Re = T1 - T2, Im = T3 - T1 - T2.
+    float2* Cs = smem;
+#pragma unroll
+    for (int bm = 0; bm < BM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < BN; ++bn)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = (wm * BM + bm) * 16 + 4 * kq + i;
+          const int n = (wn * BN + bn) * 16 + row;
+          const float t1 = acc[0][bm][bn][i], t2 = acc[1][bm][bn][i], t3 = acc[2][bm][bn][i];
+          Cs[(wk * TM + m) * SC + n] = make_float2(t1 - t2, t3 - t1 - t2);
+        }
+    __syncthreads();
+    store_c_tile<0, TM, WK, SC, C_ITEMS>(d, tab, Cs, mt, nt, batch);
+    __syncthreads();  // the next tile's staging overwrites the C tile
   }
-  store(0, 0);
-  __syncthreads();
-  for (uint64_t it = 0; it < per; it += 2) {
-    step(it, 1);
-    if (it + 1 < per) step(it + 1, 0);
-  }
-  // Accumulators -> LDS tile: Re = T1 - T2, Im = T3 - T1 - T2.
-  float2* Cs = smem;
-#pragma unroll
-  for (int bm = 0; bm < BM; ++bm)
-#pragma unroll
-    for (int bn = 0; bn < BN; ++bn)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int m = (wm * BM + bm) * 16 + 4 * kq + i;
-        const int n = (wn * BN + bn) * 16 + row;
-        const float t1 = acc[0][bm][bn][i], t2 = acc[1][bm][bn][i], t3 = acc[2][bm][bn][i];
-        Cs[(wk * TM + m) * SC + n] = make_float2(t1 - t2, t3 - t1 - t2);
-      }
-  __syncthreads();
-  store_c_tile<0, TM, WK, SC, C_ITEMS>(d, tab, Cs, mt, nt, batch);
 }
 
 // ---------------------------------------------------------------- FP16 / BF16 MFMA tiles
@@ -1570,11 +1599,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const uint32_t* B = reinterpret_cast<const uint32_t*>(d.B);
 
   load_tables(d, tab);
-  // Zero both stages once: entries outside the valid tile stay zero, so
-  // padded k never contributes and padded rows only feed outputs that are
-  // never stored.
-  for (int i = tid; i < SMEM_AB; i += 256) smem[i] = 0u;
   __syncthreads();
+  // Padded k (fewer k bits than the stage) must read as zero in both
+  // operands; other entries outside the valid tile only feed outputs that
+  // are never stored.  A tile's C staging overwrites the stages, so with
+  // padded k the stages are zeroed again for every tile.
+  const bool pad_k = d.tk < __builtin_ctz(TK);
   const uint16_t* arow = reinterpret_cast<const uint16_t*>(tab + T_HAROW);
   const uint16_t* brow = reinterpret_cast<const uint16_t*>(tab + T_HBROW);
   const int na = d.tm + d.tk, nbt = d.tk + d.tn;
@@ -1587,13 +1617,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     bit_lds[o][b] = lv;
   }
 
-  const uint64_t n_mt = 1ull << (d.mb - d.tm);
-  const uint64_t mt = blockIdx.x % n_mt, nt = blockIdx.x / n_mt;
-  const uint64_t batch = blockIdx.z;
-  const uint64_t baseA =
-      wave_scatter(mt, tab + T_AM + d.tm, d.mb - d.tm) + wave_scatter(batch, tab + T_AB, d.bb);
-  const uint64_t baseB =
-      wave_scatter(nt, tab + T_BN + d.tn, d.nb - d.tn) + wave_scatter(batch, tab + T_BB, d.bb);
+  uint64_t baseA = 0, baseB = 0;  // tile origins in A and B (set per output tile)
 
   const uint64_t k_tiles = 1ull << (d.kb - d.tk);
   const uint64_t per = k_tiles >> d.ks_bits;
@@ -1645,8 +1669,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if constexpr (VB == 4) b_vec = b_du[1] == 1 && b_du[2] == 2 && b_du[3] == 3;
   const uint32_t b_c = brow[0];
 
-  uint64_t ka = wave_scatter(kt0, tab + T_AK + d.tk, khb);
-  uint64_t kbo = wave_scatter(kt0, tab + T_BK + d.tk, khb);
+  const uint64_t ka0 = wave_scatter(kt0, tab + T_AK + d.tk, khb);
+  const uint64_t kbo0 = wave_scatter(kt0, tab + T_BK + d.tk, khb);
+  uint64_t ka = ka0, kbo = kbo0;
   // Two register sets of staged loads: k tile t + 2 is requested while tile
   // t is computed and tile t + 1 (requested one tile earlier) goes to the
   // other LDS stage.
@@ -1712,10 +1737,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   };
 
   v4f acc[BM][BN];
-#pragma unroll
-  for (int i = 0; i < BM; ++i)
-#pragma unroll
-    for (int j = 0; j < BN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
   // Fragment word addresses: row part (lane rows 0-15 and the block rows,
   // both XORs of row vectors) and the lane's 4-word k group; each MFMA step
@@ -1729,28 +1750,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
   for (int bn = 0; bn < BN; ++bn) b_frag[bn] = b_lane ^ row_addr_h(brow, (wn * BN + bn) * 16);
 
+  // All fragment reads of a k tile are issued before its MFMAs, so the
+  // MFMAs of step ks wait only for that step's reads.
   auto compute = [&](int cur) {
     const uint32_t* As = smem + cur * STAGE;
     const uint32_t* Bs = As + A_WORDS;
+    uint4 av[KW / 16][BM], bv[KW / 16][BN];
 #pragma unroll
     for (int ks = 0; ks < KW / 16; ++ks) {
-      uint4 av[BM], bv[BN];
 #pragma unroll
-      for (int bm = 0; bm < BM; ++bm) av[bm] = *reinterpret_cast<const uint4*>(As + (a_frag[bm] ^ (uint32_t)(16 * ks)));
+      for (int bm = 0; bm < BM; ++bm)
+        av[ks][bm] = *reinterpret_cast<const uint4*>(As + (a_frag[bm] ^ (uint32_t)(16 * ks)));
 #pragma unroll
-      for (int bn = 0; bn < BN; ++bn) bv[bn] = *reinterpret_cast<const uint4*>(Bs + (b_frag[bn] ^ (uint32_t)(16 * ks)));
+      for (int bn = 0; bn < BN; ++bn)
+        bv[ks][bn] = *reinterpret_cast<const uint4*>(Bs + (b_frag[bn] ^ (uint32_t)(16 * ks)));
+    }
+#pragma unroll
+    for (int ks = 0; ks < KW / 16; ++ks)
 #pragma unroll
       for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
         for (int bn = 0; bn < BN; ++bn) {
           if constexpr (P == 1)
-            acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av[bm]),
-                                                                 __builtin_bit_cast(v8h, bv[bn]), acc[bm][bn], 0, 0, 0);
+            acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                __builtin_bit_cast(v8h, av[ks][bm]), __builtin_bit_cast(v8h, bv[ks][bn]), acc[bm][bn], 0, 0, 0);
           else
             acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                __builtin_bit_cast(v8bf, av[bm]), __builtin_bit_cast(v8bf, bv[bn]), acc[bm][bn], 0, 0, 0);
+                __builtin_bit_cast(v8bf, av[ks][bm]), __builtin_bit_cast(v8bf, bv[ks][bn]), acc[bm][bn], 0, 0, 0);
         }
-    }
   };
   // One k tile: stage it & 1 holds tile it, register set x holds tile it + 1.
   auto step = [&](uint64_t it, int x) {
@@ -1763,31 +1790,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     __syncthreads();
   };
 
-  load(0);
-  if (per > 1) {
-    advance(1);
-    load(1);
+  // Output tiles are dealt grid-stride (the launch holds about as many
+  // workgroups as are resident), so the set-up above is paid once per
+  // workgroup and a tile's stores drain while the next tile loads.
+  const uint64_t n_mt = 1ull << (d.mb - d.tm), n_nt = 1ull << (d.nb - d.tn);
+  const uint64_t batch = blockIdx.z;
+  for (uint64_t tx = blockIdx.x; tx < n_mt * n_nt; tx += gridDim.x) {
+    uint64_t mt, nt;
+    tile_of(tx, n_mt, n_nt, mt, nt);
+    baseA = wave_scatter(mt, tab + T_AM + d.tm, d.mb - d.tm) + wave_scatter(batch, tab + T_AB, d.bb);
+    baseB = wave_scatter(nt, tab + T_BN + d.tn, d.nb - d.tn) + wave_scatter(batch, tab + T_BB, d.bb);
+    ka = ka0;
+    kbo = kbo0;
+    if (pad_k) {
+      for (int i = tid; i < SMEM_AB; i += 256) smem[i] = 0u;
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    load(0);
+    if (per > 1) {
+      advance(1);
+      load(1);
+    }
+    store(0, 0);
+    __syncthreads();
+    for (uint64_t it = 0; it < per; it += 2) {
+      step(it, 1);
+      if (it + 1 < per) step(it + 1, 0);
+    }
+    // Accumulators -> LDS tile (rows m, interleaved re/im columns).
+    float* Cf = reinterpret_cast<float*>(smem);
+#pragma unroll
+    for (int bm = 0; bm < BM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < BN; ++bn)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = (wm * BM + bm) * 16 + 4 * kg + i;
+          const int col = (wn * BN + bn) * 16 + row;  // 2n + part
+          Cf[(wk * TM + m) * (2 * SC) + col] = acc[bm][bn][i];
+        }
+    __syncthreads();
+    store_c_tile<P, TM, WK, SC, C_ITEMS>(d, tab, reinterpret_cast<const float2*>(smem), mt, nt, batch);
+    __syncthreads();  // the next tile's staging overwrites the C tile
   }
-  store(0, 0);
-  __syncthreads();
-  for (uint64_t it = 0; it < per; it += 2) {
-    step(it, 1);
-    if (it + 1 < per) step(it + 1, 0);
-  }
-  // Accumulators -> LDS tile (rows m, interleaved re/im columns).
-  float* Cf = reinterpret_cast<float*>(smem);
-#pragma unroll
-  for (int bm = 0; bm < BM; ++bm)
-#pragma unroll
-    for (int bn = 0; bn < BN; ++bn)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int m = (wm * BM + bm) * 16 + 4 * kg + i;
-        const int col = (wn * BN + bn) * 16 + row;  // 2n + part
-        Cf[(wk * TM + m) * (2 * SC) + col] = acc[bm][bn][i];
-      }
-  __syncthreads();
-  store_c_tile<P, TM, WK, SC, C_ITEMS>(d, tab, reinterpret_cast<const float2*>(smem), mt, nt, batch);
 }
 
 // Deterministic FP64 sum of split-K partials (blocked summation, Sec. V-B /
@@ -2103,8 +2152,15 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
         return hipErrorInvalidValue;
       const int final_mode = d.mode;
       if (d.ks_bits > 0) d.mode = EPI_PARTIAL;
-      dim3 grid((unsigned)(1ull << ((d.mb - d.tm) + (d.nb - d.tn))), (unsigned)(1ull << d.ks_bits),
-                (unsigned)(1ull << d.bb));
+      // Output tiles per split and batch index are dealt grid-stride by the
+      // kernels: the launch holds about the resident workgroup count (2 per
+      // CU), in multiples of 8 (one per XCD), or every tile when there are
+      // fewer.
+      const uint64_t n_tiles = 1ull << ((d.mb - d.tm) + (d.nb - d.tn));
+      const uint64_t yz = (1ull << d.ks_bits) << d.bb;
+      const uint64_t slots = 2ull * 256;
+      const uint64_t cap = yz * 8 >= slots ? 8 : (slots / yz) & ~7ull;
+      dim3 grid((unsigned)(n_tiles < cap ? n_tiles : cap), (unsigned)(1ull << d.ks_bits), (unsigned)(1ull << d.bb));
       if constexpr (P == 0) {
         if (kclass == MITNC_K_TILE)
           launch_k(k_tile<MITNC_TILE_WM, MITNC_TILE_WN, MITNC_TILE_WK, MITNC_TILE_BM, MITNC_TILE_BN, MITNC_TILE_TK>,

@@ -28,6 +28,7 @@
 #include <mutex>
 #include <numeric>
 #include <set>
+#include <string>
 #include <tuple>
 
 #include "plan.hpp"
@@ -255,6 +256,29 @@ static void lds_design_h(StepDesc& d, const TileGeom& g) {
   const int na = d.tm + d.tk, nb = d.tk + d.tn;
   const bool va_ok = na >= 2 && pos_a(d.a_tile[0]) == 0 && pos_a(d.a_tile[1]) == 1;
   const bool vb_ok = nb >= 2 && pos_b(d.b_tile[0]) == 0 && pos_b(d.b_tile[1]) == 1;
+  // The choice depends only on the tile codes, the load-width conditions
+  // and the geometry: repeated shapes (one-step contractions, plans built
+  // again) take it from a cache.
+  std::string key(reinterpret_cast<const char*>(d.a_tile), (size_t)na);
+  key.append(reinterpret_cast<const char*>(d.b_tile), (size_t)nb);
+  key += {(char)na, (char)nb, (char)va_ok, (char)vb_ok, (char)g.tm_bits, (char)g.tn_bits, (char)tkb};
+  static std::mutex cache_mu;
+  static std::map<std::string, HDesign> cache;
+  auto apply = [&](const HDesign& h) {
+    std::memcpy(d.ha_row, h.arow, sizeof d.ha_row);
+    std::memcpy(d.hb_row, h.brow, sizeof d.hb_row);
+    std::memcpy(d.hk, h.hk, sizeof d.hk);
+    d.vec_a = (uint8_t)h.va;
+    d.vec_b = (uint8_t)h.vb;
+  };
+  {
+    std::lock_guard<std::mutex> lk(cache_mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      apply(it->second);
+      return;
+    }
+  }
   std::vector<int> ka, kb;  // tile k bits in address order
   for (int i = 0; i < na; ++i)
     if ((d.a_tile[i] >> 5) == TB_K) ka.push_back(d.a_tile[i] & 31);
@@ -312,11 +336,10 @@ static void lds_design_h(StepDesc& d, const TileGeom& g) {
       }
     }
   }
-  std::memcpy(d.ha_row, best.arow, sizeof d.ha_row);
-  std::memcpy(d.hb_row, best.brow, sizeof d.hb_row);
-  std::memcpy(d.hk, best.hk, sizeof d.hk);
-  d.vec_a = (uint8_t)best.va;
-  d.vec_b = (uint8_t)best.vb;
+  apply(best);
+  std::lock_guard<std::mutex> lk(cache_mu);
+  if (cache.size() > 4096) cache.clear();
+  cache.emplace(key, best);
 }
 
 static TileGeom geom_of(int kclass, int precision) {
@@ -529,9 +552,11 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     // Split K over workgroups when there are too few output tiles to fill the
     // chip (Sec. V-B: partition along the common indices); keep at least 4 k
     // tiles per workgroup.
-    // Workgroup target: one 128 x 64 tile per CU (256) for TILE (measured
-    // better than two: half the partials to write and reduce); the smaller
-    // tiles of TALL / SPLITK fit four to five per CU.
+    // Workgroup target: the resident count of the TILE kernels (2 per CU,
+    // 512) for complex64, one per CU (256) for FP16/BF16 (measured on the
+    // 56-qubit share: complex64 gains 2 % from the extra loads in flight,
+    // FP16 loses more to the larger partials); the smaller tiles of TALL /
+    // SPLITK fit four to five per CU.
     int tiles_bits = (d.mb - d.tm) + (d.nb - d.tn) + d.bb;
     int khigh = d.kb - d.tk;
     // Skinny split-K (complex64 SPLITK steps the skinny kernel takes): one
@@ -539,7 +564,7 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     const bool skinny = st.kclass == MITNC_K_SPLITK && precision == MITNC_C64 && d.mb + d.nb <= 4 &&
                         d.kb >= kSkinnyLaneBits + 2 && d.bb <= 16;
     int target_bits = P->opts.splitk_target_bits > 0 ? std::min(P->opts.splitk_target_bits, 16)
-                      : st.kclass == MITNC_K_TILE                 ? 8
+                      : st.kclass == MITNC_K_TILE                 ? (precision == MITNC_C64 ? 9 : 8)
                       : skinny                                    ? 12
                                                                   : 11;
     int ks = 0;

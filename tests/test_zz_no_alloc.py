@@ -60,7 +60,8 @@ def test_split_rule_fits_scratch():
     """Host-side check: with the library's split rule (the K split stops once
     output tiles x splits reach the class's workgroup target), no single
     contraction needs more partials than the fixed 32 MiB scratch; the
-    largest, an LDS-tiled split with 128 x 64 output tiles, needs 16 MiB."""
+    largest, a complex64 LDS-tiled split with 128 x 64 output tiles (2^9
+    workgroups), needs exactly 32 MiB."""
     from paper_2504_09186_amd import tnc
     worst = 0
     for mb, nb, kb, kernel in [(7, 6, 15, TILE), (9, 8, 20, TILE), (12, 10, 16, TILE), (4, 4, 24, SPLITK),
