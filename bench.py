@@ -50,6 +50,10 @@ def executed_fraction(label, cls):
     return 0.75 if label == "c64" and cls in (2, 3, 5) else 1.0
 GOLDEN2 = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.json")
 GOLDEN4 = os.path.join(ROOT, "tests", "golden", "config4_subslices.json")
+# Stored path and slicing of the headline network (written by
+# paper_2504_09186_amd/paths/make_paths.py: recursive-bisection search, 256
+# trials, ranked by the flops of all slices dealt in 256-slice shares).
+PATH4 = os.path.join(ROOT, "paper_2504_09186_amd", "paths", "rqc_7x8_20.json")
 WORKLOAD4 = "rqc-7x8-20cyc-4096amp-256slice-share"
 WORKLOAD2 = "rqc-5x6-14cyc-64amp-256slices"
 
@@ -418,7 +422,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--trials", type=int, default=8, help="path-search trials (headline workload)")
+    ap.add_argument("--trials", type=int, default=8, help="path-search trials (headline workload, with --search)")
+    ap.add_argument("--search", action="store_true", help="search the headline path instead of loading the stored one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline workload only (no 5x6 workload, no differentiation form)")
@@ -468,10 +473,21 @@ def main():
 
     c, spec = workload4()
     net = tnc.Network(c, spec)
-    t0 = time.perf_counter()
-    net.path_search(seed=3004, trials=args.trials, max_log2=30, min_sliced=8, max_sliced=62, method=1)
-    search_s = time.perf_counter() - t0
-    print(f"path search {search_s:.1f} s, {len(net.slicing())} sliced indices", file=sys.stderr, flush=True)
+    stored = load_json(PATH4) if not args.search else None
+    if stored is not None and stored["n_leaves"] == net.n_leaves:
+        net.set_path([tuple(x) for x in stored["path"]])
+        net.set_slicing(stored["slicing"])
+        search_s = stored["search"]["seconds"]
+        path_source = (f"stored: recursive bisection, {stored['search']['trials']} trials, ranked by job flops "
+                       f"in 256-slice shares")
+    else:
+        t0 = time.perf_counter()
+        net.path_search(seed=3004, trials=args.trials, max_log2=30, min_sliced=8, max_sliced=62, method=1,
+                        window_bits=8)
+        search_s = time.perf_counter() - t0
+        path_source = f"searched here: recursive bisection, {args.trials} trials"
+    print(f"path {path_source} ({search_s:.1f} s), {len(net.slicing())} sliced indices", file=sys.stderr,
+          flush=True)
     g4 = load_json(GOLDEN4)
     share = (0, 256)
 
@@ -501,7 +517,8 @@ def main():
         "config": {"workload": WORKLOAD4, "qubits": 56, "cycles": 20, "open_qubits": 12,
                    "slices_per_step": 256, "n_sliced": st.n_sliced, "max_log2_elems": st.max_log2_elems,
                    "steps_per_slice": st.n_steps, "flops_full_slice": st.flops_full_slice,
-                   "path_search_s": search_s,
+                   "path_search_s": search_s, "path": path_source,
+                   "job_flops": r64["flops_per_step"] * 2.0 ** (st.n_sliced - 8),
                    "precision": "complex64, FP32 MFMA (3M), FP64 cross-slice sum"},
         "tflops": r64["tflops"],
         "hbm_gbs": r64["hbm_gbs"], "amp_error": r64.get("amp_error"),

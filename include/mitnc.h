@@ -108,6 +108,11 @@ typedef struct mitnc_search_opts {
                            Fiduccia-Mattheyses moves, random balance and
                            leaf-size parameters per trial); 2: both, `trials`
                            of each */
+  int32_t window_bits;  /* methods 1 and 2 rank trials by the flops all
+                           slices execute with shared-prefix reuse (Sec.
+                           III-B): run in one sequence (0), or dealt in
+                           aligned ranges of 2^window_bits slices (one per
+                           device or stream), each range starting cold */
 } mitnc_search_opts;
 int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* opts);
 

@@ -33,7 +33,7 @@ class mitnc_gate(C.Structure):
 class mitnc_search_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("trials", C.c_int32), ("max_log2_elems", C.c_int32),
                 ("min_sliced", C.c_int32), ("max_sliced", C.c_int32), ("keep_slicing", C.c_int32),
-                ("method", C.c_int32)]
+                ("method", C.c_int32), ("window_bits", C.c_int32)]
 
 
 class mitnc_plan_opts(C.Structure):

@@ -180,6 +180,7 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
     std::vector<int> best_sl;
     const int method = o->method;
     if (method < 0 || method > 2) fail(MITNC_INVALID_ARG, "unknown search method");
+    if (o->window_bits < 0 || o->window_bits > 62) fail(MITNC_INVALID_ARG, "window_bits out of range");
     const double imbs[] = {0.05, 0.1, 0.2, 0.3, 0.5};
     const int cutoffs[] = {4, 6, 8, 10, 12};
     const double exts[] = {0.0, 0.25, 0.5, 1.0};
@@ -254,14 +255,15 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
       // refine again for the per-slice network, keeping the size cap
       p = optimize_path(sn, p, &m, std::max(o->max_log2_elems, sym_max_bits(sn, sym_run(sn, p, m), m)), 4);
       // Method 0 ranks by the flops of all slices; methods 1 and 2 rank every
-      // trial by the flops all slices execute with shared-prefix reuse
-      // (Sec. III-B), sliced indices in the order the plan will use.
+      // trial by the flops executed with shared-prefix reuse (Sec. III-B),
+      // sliced indices in the order the plan will use, over all slices or
+      // over one aligned window of 2^window_bits slices.
       double f;
       if (method != 0) {
         std::vector<int> extra(sl.begin() + fixed_list.size(), sl.end());
         std::vector<int> ord = fixed_list;
         for (int x : order_slices(sn, p, extra)) ord.push_back(x);
-        f = reuse_total_flops(sn, p, ord);
+        f = reuse_total_flops(sn, p, ord, o->window_bits);
       } else {
         f = sym_total_flops(sym_run(sn, p, m)) * std::ldexp(1.0, (int)sl.size());
       }

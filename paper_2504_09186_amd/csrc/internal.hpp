@@ -65,7 +65,7 @@ std::vector<int> greedy_slices(const SymNet& sn, const Path& path, int cap, int 
                                int max_sliced, bool* ok);
 std::vector<int> slice_reconf(const SymNet& sn, Path& path, const std::vector<int>& fixed, int cap, int min_sliced,
                               int max_sliced, int every, bool* ok);
-double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered);
+double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered, int window_bits = 0);
 std::vector<int> order_slices(const SymNet& sn, const Path& path, const std::vector<int>& sl);
 // Subtree reconfiguration (reconf.cpp): locally optimal re-ordering of the
 // tree, flops measured with `removed` labels (sliced) absent, intermediates

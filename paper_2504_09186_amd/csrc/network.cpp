@@ -330,7 +330,7 @@ std::vector<int> slice_reconf(const SymNet& sn, Path& path, const std::vector<in
 // (Sec. III-B): a step whose subtree holds sliced indices with lowest
 // slice-id bit b is recomputed 2^(S - b) times, a step with none once.
 // `ordered` lists the sliced indices outer -> inner (the last is bit 0).
-double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered) {
+double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered, int window_bits) {
   const int S = (int)ordered.size();
   std::vector<char> sl(sn.n_labels, 0);
   std::vector<int> bit(sn.n_labels, -1);
@@ -348,7 +348,18 @@ double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<i
   for (size_t s = 0; s < path.size(); ++s) {
     const uint64_t d = dep[path[s].first] | dep[path[s].second];
     dep[n + s] = d;
-    f += st[s].flops * (d ? std::ldexp(1.0, S - __builtin_ctzll(d)) : 1.0);
+    // Runs of the step over all 2^S slices: in one sequence (the step reruns
+    // whenever slice-id bit ctz(d) or a lower one changes), or dealt in
+    // aligned windows of 2^w slices, each starting with everything computed
+    // (2^(S-w) windows; a step independent of the window's bits runs once
+    // per window).
+    const int lo = d ? __builtin_ctzll(d) : 64;
+    double runs;
+    if (window_bits > 0 && window_bits < S)
+      runs = std::ldexp(lo >= window_bits ? 1.0 : std::ldexp(1.0, window_bits - lo), S - window_bits);
+    else
+      runs = d ? std::ldexp(1.0, S - lo) : 1.0;
+    f += st[s].flops * runs;
   }
   return f;
 }

@@ -1,0 +1,74 @@
+"""Writes the stored contraction paths of the benchmark workloads.
+
+A path search is not part of the contraction itself (the paper takes its
+path from a separate search); the benchmark loads the stored result so that
+its run does not repeat a minutes-long search.  Each file holds the SSA path
+pairs and the sliced labels (outer to inner) of one network, with the search
+parameters and the resulting costs.
+
+Usage: python -m paper_2504_09186_amd.paths.make_paths [--trials N]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+
+# 7x8 lattice, 20 cycles, last 12 qubits open: the headline workload.
+RQC_7X8_20 = dict(rows=7, cols=8, cycles=20, circuit_seed=1004, open_qubits=list(range(44, 56)), spec_seed=2004,
+                  max_log2=30, min_sliced=8, max_sliced=62, window_bits=8)
+
+
+def share_flops(plan, window_bits):
+    """Flops of the first 2^window_bits slices with shared-prefix reuse."""
+    n = 1 << window_bits
+    tot = 0.0
+    for r in plan.steps():
+        lvl = int(r[5])
+        runs = 1 if lvl < 0 else 1 + (n - 1) // (1 << lvl)
+        tot += r[6] * runs
+    return tot
+
+
+def make_rqc_7x8_20(trials: int, seed: int) -> dict:
+    sys.path.insert(0, ROOT)
+    import synth
+    from paper_2504_09186_amd import tnc
+    w = RQC_7X8_20
+    c = synth.lattice_circuit(w["rows"], w["cols"], w["cycles"], seed=w["circuit_seed"])
+    spec = synth.output_spec(w["rows"] * w["cols"], w["open_qubits"], seed=w["spec_seed"])
+    net = tnc.Network(c, spec)
+    t0 = time.perf_counter()
+    net.path_search(seed=seed, trials=trials, max_log2=w["max_log2"], min_sliced=w["min_sliced"],
+                    max_sliced=w["max_sliced"], method=1, window_bits=w["window_bits"])
+    search_s = time.perf_counter() - t0
+    plan = tnc.Plan(net, precision=0)
+    sl = [int(x) for x in net.slicing()]
+    sf = share_flops(plan, w["window_bits"])
+    return dict(workload=w, n_leaves=net.n_leaves, search=dict(method=1, trials=trials, seed=seed,
+                                                               seconds=round(search_s, 1)),
+                path=[[int(a), int(b)] for a, b in net.path()], slicing=sl, n_sliced=len(sl),
+                max_log2_elems=int(plan.stats.max_log2_elems), share_flops=sf,
+                job_flops=sf * 2.0 ** (len(sl) - w["window_bits"]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trials", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=3004)
+    args = ap.parse_args()
+    out = make_rqc_7x8_20(args.trials, args.seed)
+    path = os.path.join(HERE, "rqc_7x8_20.json")
+    with open(path, "w") as f:
+        json.dump(out, f, separators=(",", ":"))
+    print(f"wrote {path}: {out['n_sliced']} sliced, share flops {out['share_flops']:.3e}, "
+          f"job flops {out['job_flops']:.3e} ({out['search']['seconds']} s search)")
+
+
+if __name__ == "__main__":
+    main()

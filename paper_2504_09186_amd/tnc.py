@@ -61,9 +61,14 @@ class Network:
             self.h = None
 
     def path_search(self, seed: int = 0, trials: int = 32, max_log2: int = 30, min_sliced: int = 0,
-                    max_sliced: int = 40, keep_slicing: bool = False, method: int = 0) -> None:
-        """Path and slicing search (method 0 greedy, 1 recursive bisection, 2 both)."""
-        o = mitnc_search_opts(seed, trials, max_log2, min_sliced, max_sliced, 1 if keep_slicing else 0, method)
+                    max_sliced: int = 40, keep_slicing: bool = False, method: int = 0,
+                    window_bits: int = 0) -> None:
+        """Path and slicing search (method 0 greedy, 1 recursive bisection, 2
+        both).  Methods 1 and 2 rank trials by the reuse-aware flops of all
+        slices, run in one sequence (window_bits 0) or dealt in aligned
+        ranges of 2^window_bits slices that each start cold."""
+        o = mitnc_search_opts(seed, trials, max_log2, min_sliced, max_sliced, 1 if keep_slicing else 0, method,
+                              window_bits)
         call("mitnc_path_search", self.h, C.byref(o))
 
     def path(self) -> List[Tuple[int, int]]:

@@ -92,6 +92,22 @@ def test_path_search_structure(lib):
     assert info[-1, 11] == 1 and info[:-1, 11].sum() == 0
 
 
+def test_path_search_window_ranking(lib):
+    """Ranking trials by the reuse-aware flops of aligned slice windows
+    (window_bits) returns a valid path and slicing under the cap; a negative
+    window is refused."""
+    from paper_2504_09186_amd import _lib
+    c, spec, onet, net = _nets(4, 4, 8, seed=62, nopen=3)
+    net.path_search(seed=5, trials=6, max_log2=9, min_sliced=3, method=1, window_bits=2)
+    p = net.path()
+    assert len(p) == net.n_leaves - 1
+    assert len(net.slicing()) >= 3
+    from paper_2504_09186_amd import tnc
+    assert tnc.Plan(net).stats.max_log2_elems <= 9
+    with pytest.raises(_lib.MitncError):
+        net.path_search(seed=5, trials=2, max_log2=9, min_sliced=3, method=1, window_bits=-1)
+
+
 def test_validation_errors(lib):
     from paper_2504_09186_amd import _lib
     c, spec, onet, net = _nets()
