@@ -552,11 +552,10 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     // Split K over workgroups when there are too few output tiles to fill the
     // chip (Sec. V-B: partition along the common indices); keep at least 4 k
     // tiles per workgroup.
-    // Workgroup target: the resident count of the TILE kernels (2 per CU,
-    // 512) for complex64, one per CU (256) for FP16/BF16 (measured on the
-    // 56-qubit share: complex64 gains 2 % from the extra loads in flight,
-    // FP16 loses more to the larger partials); the smaller tiles of TALL /
-    // SPLITK fit four to five per CU.
+    // Workgroup target: the resident count of the TILE and TALL kernels (2
+    // per CU, 512; measured on the 56-qubit share against 256 and 2048: the
+    // split GEPDOT steps stream longer k ranges per workgroup with loads in
+    // flight on every CU); SPLITK tiles are smaller and take 2^11.
     int tiles_bits = (d.mb - d.tm) + (d.nb - d.tn) + d.bb;
     int khigh = d.kb - d.tk;
     // Skinny split-K (complex64 SPLITK steps the skinny kernel takes): one
@@ -564,7 +563,7 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     const bool skinny = st.kclass == MITNC_K_SPLITK && precision == MITNC_C64 && d.mb + d.nb <= 4 &&
                         d.kb >= kSkinnyLaneBits + 2 && d.bb <= 16;
     int target_bits = P->opts.splitk_target_bits > 0 ? std::min(P->opts.splitk_target_bits, 16)
-                      : st.kclass == MITNC_K_TILE                 ? (precision == MITNC_C64 ? 9 : 8)
+                      : st.kclass == MITNC_K_TILE || st.kclass == MITNC_K_TALL ? 9
                       : skinny                                    ? 12
                                                                   : 11;
     int ks = 0;
