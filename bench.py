@@ -424,6 +424,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--trials", type=int, default=8, help="path-search trials (headline workload, with --search)")
     ap.add_argument("--search", action="store_true", help="search the headline path instead of loading the stored one")
+    ap.add_argument("--only", choices=["c64", "cf16"], help="profiling runs: time one form only (no JSON line)")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle sub-slice error check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline workload only (no 5x6 workload, no differentiation form)")
@@ -491,6 +493,18 @@ def main():
     g4 = load_json(GOLDEN4)
     share = (0, 256)
 
+    if args.only:
+        # A profiling run: one form's share passes and nothing else, so that
+        # kernel statistics of the run are those of the timed passes.
+        prec = 0 if args.only == "c64" else 1
+        plan = tnc.Plan(net, precision=prec)
+        plan.upload()
+        if prec:
+            plan.calibrate(0, 2)
+        r, _ = run_form(plan, args.steps, args.warmup, args.only, WORKLOAD4, *share)
+        print(json.dumps({"only": args.only, "value": r["value"], "ms_per_step": r["ms_per_step"],
+                          "roofline": r["roofline"], "kernel_ms_by_class": r["kernel_ms_by_class"]}), flush=True)
+        return
     plan = tnc.Plan(net, precision=0)
     st = plan.stats
     plan.upload()
@@ -506,7 +520,7 @@ def main():
     torch.cuda.empty_cache()
     print(f"complex FP16: {r16['value']:.1f} slices/s", file=sys.stderr, flush=True)
     r16["vs_complex64"] = error_metrics(res16, res64, "complex64 GPU result of the same 256 slices")
-    if g4 is not None:
+    if g4 is not None and not args.no_check:
         r64["amp_error"] = subslice_check(c, spec, g4, 0)
         r16["amp_error"] = subslice_check(c, spec, g4, 1)
     out = {

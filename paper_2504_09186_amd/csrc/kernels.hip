@@ -1296,17 +1296,22 @@ __device__ __forceinline__ int row_xor(const uint8_t* swz, int k, int mask) {
   return h & mask;
 }
 
-// Output tile (mt, nt) of workgroup x among n_mt x n_nt tiles.  Workgroups
-// are dealt round-robin over the 8 XCDs, each with its own L2.  With few n
-// tiles (2 to 8) the tiles of one m block go to one XCD next to each other in
-// dispatch order, so the A block is read from HBM once and the other n tiles
-// find it in that XCD's L2; otherwise m is the fastest index (the tiles of
-// one m block still share an XCD when n_mt is a multiple of 8).
+// Output tile (mt, nt) of tile index x among n_mt x n_nt tiles.  Workgroups
+// are dealt round-robin over the 8 XCDs, each with its own L2, and the
+// kernels take tile indices x = workgroup + i * (multiple of 8), so x & 7 is
+// the XCD.  An XCD owns the m blocks mt = 8 r + xcd and walks its (r, nt)
+// tiles in groups of up to 8 consecutive r: inside a group r is the fastest
+// index, so the ~64 tiles an XCD holds at once span about 8 m blocks by 8 n
+// blocks.  At each k stage they then read about 8 A and 8 B stage tiles
+// instead of 64 A tiles and one B tile (m fastest over the whole grid), so
+// far fewer operand tiles miss in L2.
 __device__ __forceinline__ void tile_of(uint64_t x, uint64_t n_mt, uint64_t n_nt, uint64_t& mt, uint64_t& nt) {
-  if (n_nt > 1 && n_nt <= 8 && (n_mt & 7) == 0) {
-    const uint64_t i = x >> 3;
-    nt = i % n_nt;
-    mt = (i / n_nt) * 8 + (x & 7);
+  if ((n_mt & 7) == 0 && n_nt > 1) {
+    const uint64_t i = x >> 3, nm = n_mt >> 3;
+    const uint64_t gm = nm < 8 ? nm : 8;
+    const uint64_t grp = i / (gm * n_nt), within = i % (gm * n_nt);
+    mt = ((grp * gm + within % gm) << 3) | (x & 7);
+    nt = within / gm;
   } else {
     mt = x % n_mt;
     nt = x / n_mt;
