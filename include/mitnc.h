@@ -113,6 +113,11 @@ typedef struct mitnc_search_opts {
                            III-B): run in one sequence (0), or dealt in
                            aligned ranges of 2^window_bits slices (one per
                            device or stream), each range starting cold */
+  int32_t merge_bits;   /* methods 1 and 2: the ranking also counts the
+                           post-lifetime merge of the innermost merge_bits
+                           slice-id bits (mitnc_plan_opts.merge_bits; 0..12) */
+  int32_t branch_exchange; /* 1: after the search, reorder absorptions
+                              (mitnc_branch_exchange) with the same ranking */
 } mitnc_search_opts;
 int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* opts);
 
@@ -149,6 +154,20 @@ int32_t mitnc_slice_greedy(mitnc_network* net, int32_t max_log2_elems, int32_t m
  * O(a) = 2 C_a / C_ori, C = real flops of one subtask (8 per complex
  * multiply-add).  Host only. */
 int32_t mitnc_index_overhead(const mitnc_network* net, int64_t label, double* overhead);
+
+/* Branch exchange (Sec. III-B, last paragraph): where one tensor absorbs two
+ * others in consecutive steps, swapping the two absorptions leaves the
+ * result unchanged but moves where lifetimes of sliced indices start and
+ * end.  Local search over such adjacent pairs of the current path (up to
+ * `passes` sweeps), keeping each swap that lowers the flops of all slices
+ * with pre-lifetime reuse and the post-lifetime merge of the innermost
+ * merge_bits bits (ranges of 2^window_bits slices as in mitnc_search_opts)
+ * and keeps every intermediate within 2^max_log2_elems entries; replaces
+ * the path, keeps the slicing.  flops_before / flops_after (either may be
+ * NULL) receive that count for the old and new path.  Host only.  Errors:
+ * INVALID_ARG (no path, bad argument). */
+int32_t mitnc_branch_exchange(mitnc_network* net, int32_t window_bits, int32_t merge_bits, int32_t max_log2_elems,
+                              int32_t passes, double* flops_before, double* flops_after);
 
 /* Plan options.  precision: MITNC_C64 (complex64 storage, FP32 arithmetic on
  * MFMA) or MITNC_CF16 / MITNC_CBF16 (each tensor stored as complex FP16 or
@@ -188,6 +207,25 @@ typedef struct mitnc_plan_opts {
                                  over, K split until the grid reaches it
                                  (0 = 12 register-only, 11 LDS-tiled, 8 for
                                  large tiles; at most 16) */
+  int32_t merge_bits;         /* post-lifetime merge (Sec. III-B, with the
+                                 pre-lifetime reuse: the spindle): 0 = off;
+                                 k = the k innermost slice-id bits (0..12) may
+                                 be merged.  Bit b is merged when the node
+                                 where its index's lifetime ends (lowest
+                                 non-hoisted node holding both tensors that
+                                 carry it) depends on no lower bit that is not
+                                 merged at or below that node (nested
+                                 lifetimes).  That node then sums its values
+                                 for b = 0 and 1 in a kept accumulator, and
+                                 the steps above it run once per pair.  Slice
+                                 ranges of mitnc_execute must then be
+                                 multiples of 2^merge_align_bits (stats).
+                                 Requires reuse; not with differentiable or
+                                 fuse_sections (UNSUPPORTED) */
+  int32_t no_hoist;           /* 1: small subtrees that depend on sliced
+                                 indices are not hoisted (contracted once for
+                                 all slices); they then run per slice under
+                                 the reuse rule like every other node */
 } mitnc_plan_opts;
 
 /* Execution plan of the sliced contraction tree for the network's current
@@ -221,6 +259,9 @@ typedef struct mitnc_plan_stats {
   int32_t n_grad_gates;       /* differentiable plans: single-qubit gates (gradient entries / 4) */
   int32_t n_reverse_ops;      /* adjoint contractions per slice */
   double flops_reverse_slice; /* real flops of the reverse pass of one slice */
+  int32_t n_merged;           /* slice-id bits merged below the root (merge_bits) */
+  int32_t merge_align_bits;   /* execute ranges must be multiples of 2^this (0: any) */
+  uint64_t merged_mask;       /* the merged bits */
 } mitnc_plan_stats;
 int32_t mitnc_plan_query(const mitnc_plan* plan, mitnc_plan_stats* stats);
 
@@ -298,8 +339,30 @@ typedef struct mitnc_node_info {
   int32_t slice_bit[64];
   int32_t slice_pos[64];
   uint64_t ws_offset;
+  /* Launch rule (Sec. III-B pre- and post-lifetime reuse), slices of a range
+   * in increasing order: the node runs only in slices whose elig_mask bits
+   * are all 1; then when the bits recompute_mask & ~merge_mask differ from
+   * its last run (a new value: stored) or, for a merge accumulator
+   * (merge_mask != 0), when the merge_mask bits differ (the next term:
+   * computed into the buffer at merge_tmp_offset, then added). */
+  uint64_t elig_mask;
+  uint64_t recompute_mask;
+  uint64_t merge_mask;
+  uint64_t merge_tmp_offset;       /* workspace byte offset (accumulators) */
 } mitnc_node_info;
 int32_t mitnc_plan_node_info(const mitnc_plan* plan, int32_t node, mitnc_node_info* info);
+
+/* The launches mitnc_execute makes for slices [slice_begin, slice_end), in
+ * order, as (slice, step, mode) triples of int64: mode 1 = the step runs
+ * and stores its output (the root step adds into the result), mode 2 = the
+ * step runs into its node's merge buffer and the buffer is added into the
+ * node's accumulator (post-lifetime merge, Sec. III-B).  Steps of a fused
+ * section are listed at their own positions.  Writes at most `capacity`
+ * triples to ops_out (may be NULL with capacity 0); *n_ops receives the
+ * total count.  Host only.  Errors: INVALID_ARG (null n_ops, bad range,
+ * range not aligned to 2^merge_align_bits). */
+int32_t mitnc_plan_schedule(const mitnc_plan* plan, uint64_t slice_begin, uint64_t slice_end, int64_t capacity,
+                            int64_t* ops_out, int64_t* n_ops);
 
 /* The complex64 entries (re, im interleaved) a plan uploads for leaf
  * `leaf` (a gate tensor of Sec. II-A in its address layout; sliced leaves
@@ -331,10 +394,11 @@ int32_t mitnc_plan_upload(mitnc_plan* plan, void* ws, size_t ws_bytes, void* str
  * overflow or exponent miss.  On a miss the exponents are re-derived from
  * complex64 maxima over this slice range (as mitnc_calibrate) and the range
  * runs once more; only a clean run is added to result_accum.  Errors:
- * INVALID_ARG for an empty or out-of-range slice range or an uncalibrated
- * FP16/BF16 plan, WORKSPACE_TOO_SMALL, HIP_ERROR, NUMERIC when the re-run
- * misses again or the plan was created with no_rerun (result_accum is then
- * unchanged). */
+ * INVALID_ARG for an empty or out-of-range slice range (with merged bits:
+ * also one whose ends are not multiples of 2^merge_align_bits) or an
+ * uncalibrated FP16/BF16 plan, WORKSPACE_TOO_SMALL, HIP_ERROR, NUMERIC when
+ * the re-run misses again or the plan was created with no_rerun
+ * (result_accum is then unchanged). */
 int32_t mitnc_execute(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t slice_begin,
                       uint64_t slice_end, double* result_accum, void* stream);
 

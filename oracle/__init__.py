@@ -17,7 +17,9 @@ Data Reuse Strategy, Sec. III-A):
   * the gradient of sum_b log|a_b|^2 with respect to every single-qubit gate
     tensor by reverse-mode contraction (not in the paper; problem definition of
     the differentiation form), plus the state-vector environment formula;
-  * error metrics (relative L2, overlap fidelity, linear XEB ratio).
+  * error metrics (relative L2, overlap fidelity, linear XEB ratio);
+  * the lifetimes of sliced indices over a path (Sec. III-B), which fix how
+    often the spindle (pre- plus post-lifetime reuse) needs each step.
 
 Every function states the passage it follows.  Parity status of each part is
 recorded in the module headers; all parts are pinned by ``tests/test_oracle_*``.
@@ -28,7 +30,7 @@ from .contract import (  # noqa: F401
     count_contraction_flops,
 )
 from .planning import (  # noqa: F401
-    greedy_path, random_greedy_path, path_stats, choose_slices, index_overhead,
+    greedy_path, random_greedy_path, path_stats, choose_slices, index_overhead, sliced_lifetimes,
 )
 from .statevector import sv_state, sv_amplitudes, sv_gate_gradients  # noqa: F401
 from .grad import tn_gate_gradients, loss_log_abs2, torch_convention_grad  # noqa: F401

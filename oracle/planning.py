@@ -14,6 +14,9 @@ library's own planner.
   * ``choose_slices``: greedily slice the index that minimises the largest
     intermediate, then the per-subtask flops.
   * ``index_overhead``: Eq. (1), O(a) = 2 C_a / C_ori.
+  * ``sliced_lifetimes``: per step, the sliced indices its subtree carries and
+    those alive at it (Sec. III-B: an index's lifetime runs from the first
+    step that holds one of its tensors to the step that joins both).
 """
 from __future__ import annotations
 
@@ -555,3 +558,43 @@ def choose_slices_eval(net: Network, path: Sequence[Tuple[int, int]], cap_log2: 
         chosen.append(best[2])
         cut |= 1 << bit[best[2]]
     return chosen
+
+
+def sliced_lifetimes(net: Network, path: Sequence[Tuple[int, int]], sliced: Sequence[int]):
+    """For every step t of an SSA path, two sets of sliced labels (Sec. III-B,
+    lifetimes of sliced indices):
+
+      * ``below[t]``: labels carried by some leaf of the step's subtree (its
+        value depends on them);
+      * ``alive[t]``: labels whose lifetime covers the step: carried by a leaf
+        of its subtree and by a leaf outside it (started, not ended), or
+        carried by a leaf under each of its two operands (ended here).
+
+    A step whose alive set holds j of the sliced labels has 2^j distinct
+    values over all slices; executing it exactly that often is the spindle's
+    aim of removing every repeated calculation.  Plain definition: leaves
+    below each node by explicit set union."""
+    sl = set(sliced)
+    n = net.n_leaves
+    holders: Dict[int, Set[int]] = {x: set() for x in sl}
+    for i, lab in enumerate(net.labels):
+        for x in lab:
+            if x in sl:
+                holders[x].add(i)
+    leaves_of: Dict[int, Set[int]] = {i: {i} for i in range(n)}
+    below, alive = [], []
+    for t, (i, j) in enumerate(path):
+        li, lj = leaves_of[i], leaves_of[j]
+        lv = li | lj
+        leaves_of[n + t] = lv
+        b, a = set(), set()
+        for x, hs in holders.items():
+            inside = hs & lv
+            if not inside:
+                continue
+            b.add(x)
+            if inside != hs or (hs & li and hs & lj):
+                a.add(x)
+        below.append(b)
+        alive.append(a)
+    return below, alive

@@ -33,14 +33,16 @@ class mitnc_gate(C.Structure):
 class mitnc_search_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("trials", C.c_int32), ("max_log2_elems", C.c_int32),
                 ("min_sliced", C.c_int32), ("max_sliced", C.c_int32), ("keep_slicing", C.c_int32),
-                ("method", C.c_int32), ("window_bits", C.c_int32)]
+                ("method", C.c_int32), ("window_bits", C.c_int32), ("merge_bits", C.c_int32),
+                ("branch_exchange", C.c_int32)]
 
 
 class mitnc_plan_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("reuse", C.c_int32),
                 ("cache_budget_bytes", C.c_uint64), ("force_kernel", C.c_int32),
                 ("differentiable", C.c_int32), ("fuse_sections", C.c_int32), ("no_rerun", C.c_int32),
-                ("splitk_max_mn_bits", C.c_int32), ("splitk_target_bits", C.c_int32)]
+                ("splitk_max_mn_bits", C.c_int32), ("splitk_target_bits", C.c_int32),
+                ("merge_bits", C.c_int32), ("no_hoist", C.c_int32)]
 
 
 class mitnc_plan_stats(C.Structure):
@@ -51,7 +53,8 @@ class mitnc_plan_stats(C.Structure):
                 ("bytes_full_slice", C.c_double), ("bytes_reused_slice", C.c_double),
                 ("steps_by_class", C.c_int32 * 8), ("flops_by_class", C.c_double * 8),
                 ("n_grad_gates", C.c_int32), ("n_reverse_ops", C.c_int32),
-                ("flops_reverse_slice", C.c_double)]
+                ("flops_reverse_slice", C.c_double), ("n_merged", C.c_int32),
+                ("merge_align_bits", C.c_int32), ("merged_mask", C.c_uint64)]
 
 
 class mitnc_step_info(C.Structure):
@@ -69,7 +72,8 @@ class mitnc_step_info(C.Structure):
 class mitnc_node_info(C.Structure):
     _fields_ = [("is_leaf", C.c_int32), ("rank", C.c_int32), ("full_rank", C.c_int32), ("level", C.c_int32),
                 ("hoisted", C.c_int32), ("n_slice_bits", C.c_int32), ("slice_bit", C.c_int32 * 64),
-                ("slice_pos", C.c_int32 * 64), ("ws_offset", C.c_uint64)]
+                ("slice_pos", C.c_int32 * 64), ("ws_offset", C.c_uint64), ("elig_mask", C.c_uint64),
+                ("recompute_mask", C.c_uint64), ("merge_mask", C.c_uint64), ("merge_tmp_offset", C.c_uint64)]
 
 
 _VP = C.c_void_p
@@ -85,12 +89,14 @@ _SIGS = {
     "mitnc_set_slicing": [_VP, _I32, C.POINTER(C.c_int64)],
     "mitnc_slice_greedy": [_VP, _I32, _I32, _I32, C.POINTER(_I32), C.POINTER(C.c_int64)],
     "mitnc_index_overhead": [_VP, C.c_int64, C.POINTER(C.c_double)],
+    "mitnc_branch_exchange": [_VP, _I32, _I32, _I32, _I32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
     "mitnc_plan_create": [_VP, C.POINTER(mitnc_plan_opts), C.POINTER(_VP)],
     "mitnc_plan_query": [_VP, C.POINTER(mitnc_plan_stats)],
     "mitnc_plan_steps": [_VP, C.POINTER(C.c_double)],
     "mitnc_plan_step_info": [_VP, _I32, C.POINTER(mitnc_step_info)],
     "mitnc_plan_reverse_info": [_VP, _I32, C.POINTER(mitnc_step_info), C.POINTER(_I32)],
     "mitnc_plan_node_info": [_VP, _I32, C.POINTER(mitnc_node_info)],
+    "mitnc_plan_schedule": [_VP, C.c_uint64, C.c_uint64, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     "mitnc_plan_leaf_data": [_VP, _I32, C.POINTER(C.c_float), C.c_uint64, C.POINTER(C.c_uint64)],
     "mitnc_plan_upload": [_VP, _VP, C.c_size_t, _VP],
     "mitnc_execute": [_VP, _VP, C.c_size_t, C.c_uint64, C.c_uint64, _VP, _VP],

@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libmitnc.so")
 OBJ = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "network.cpp", "reconf.cpp", "partition.cpp"]
+SOURCES = ["kernels.hip", "merge.hip", "api.cpp", "plan.cpp", "network.cpp", "merge.cpp", "reconf.cpp", "partition.cpp"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "--offload-arch=gfx950"]
 # Packed FP32 instructions are kept out of every device build.
 DEVICE_ONLY = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -40,6 +40,29 @@ static void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) fail(MITNC_HIP_ERROR, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Slice ranges of plans with merged bits cover whole merge groups.
+static void check_range(const mitnc_plan* P, uint64_t s0, uint64_t s1) {
+  const uint64_t n_slices = 1ull << P->S;
+  if (s0 >= s1 || s1 > n_slices) fail(MITNC_INVALID_ARG, "slice range out of bounds");
+  const uint64_t am = (1ull << P->merge_align_bits) - 1;
+  if ((s0 & am) || (s1 & am))
+    fail(MITNC_INVALID_ARG, "slice range must be a multiple of 2^" + std::to_string(P->merge_align_bits) +
+                                " (merged slice-id bits)");
+}
+
+// Calls f(slice, step, mode) for every launch of slices s0 .. s1-1, in order
+// (mode 1: store / accumulate at the root, 2: merge term).
+template <class F>
+static void for_each_launch(const mitnc_plan* P, uint64_t s0, uint64_t s1, F&& f) {
+  SliceSchedule sched(P->nodes.size());
+  for (uint64_t sl = s0; sl < s1; ++sl)
+    for (size_t i = 0; i < P->steps.size(); ++i) {
+      const PlanNode& O = P->nodes[P->steps[i].out];
+      const int mode = sched.decide(P->steps[i].out, O.elig, O.emask, O.bmask, sl);
+      if (mode) f(sl, i, P->steps[i].root ? 1 : mode);
+    }
+}
+
 extern "C" {
 
 const char* mitnc_last_error(void) { return g_err.c_str(); }
@@ -181,6 +204,7 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
     const int method = o->method;
     if (method < 0 || method > 2) fail(MITNC_INVALID_ARG, "unknown search method");
     if (o->window_bits < 0 || o->window_bits > 62) fail(MITNC_INVALID_ARG, "window_bits out of range");
+    if (o->merge_bits < 0 || o->merge_bits > 12) fail(MITNC_INVALID_ARG, "merge_bits out of range (0..12)");
     const double imbs[] = {0.05, 0.1, 0.2, 0.3, 0.5};
     const int cutoffs[] = {4, 6, 8, 10, 12};
     const double exts[] = {0.0, 0.25, 0.5, 1.0};
@@ -263,7 +287,7 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
         std::vector<int> extra(sl.begin() + fixed_list.size(), sl.end());
         std::vector<int> ord = fixed_list;
         for (int x : order_slices(sn, p, extra)) ord.push_back(x);
-        f = reuse_total_flops(sn, p, ord, o->window_bits);
+        f = reuse_total_flops(sn, p, ord, o->window_bits, o->merge_bits);
       } else {
         f = sym_total_flops(sym_run(sn, p, m)) * std::ldexp(1.0, (int)sl.size());
       }
@@ -308,6 +332,14 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
       for (int x : order_slices(sn, best_path, extra)) net->sliced.push_back(sn.label_id[x]);
     } else {
       for (int x : order_slices(sn, best_path, best_sl)) net->sliced.push_back(sn.label_id[x]);
+    }
+    if (o->branch_exchange) {
+      std::vector<int> ord;
+      for (auto x : net->sliced) ord.push_back(sn.dense.at(x));
+      std::vector<char> m(sn.n_labels, 0);
+      for (int x : ord) m[x] = 1;
+      const int cap = std::max<int>(o->max_log2_elems, sym_max_bits(sn, sym_run(sn, net->path, m), m));
+      net->path = branch_exchange(sn, net->path, ord, o->window_bits, o->merge_bits, cap, 8, nullptr, nullptr);
     }
   });
 }
@@ -377,6 +409,23 @@ int32_t mitnc_slice_greedy(mitnc_network* net, int32_t max_log2_elems, int32_t m
   });
 }
 
+int32_t mitnc_branch_exchange(mitnc_network* net, int32_t window_bits, int32_t merge_bits, int32_t max_log2_elems,
+                              int32_t passes, double* flops_before, double* flops_after) {
+  return guarded([&] {
+    if (!net) fail(MITNC_INVALID_ARG, "null network");
+    if (net->path.empty()) fail(MITNC_INVALID_ARG, "no path");
+    if (window_bits < 0 || window_bits > 62 || merge_bits < 0 || merge_bits > 12 || passes < 0 || max_log2_elems < 0)
+      fail(MITNC_INVALID_ARG, "bad argument");
+    SymNet sn = make_symnet(net->leaves, net->output_lsb);
+    std::vector<int> ord;
+    for (auto x : net->sliced) ord.push_back(sn.dense.at(x));
+    double b = 0, a = 0;
+    net->path = branch_exchange(sn, net->path, ord, window_bits, merge_bits, max_log2_elems, passes, &b, &a);
+    if (flops_before) *flops_before = b;
+    if (flops_after) *flops_after = a;
+  });
+}
+
 int32_t mitnc_index_overhead(const mitnc_network* net, int64_t label, double* overhead) {
   return guarded([&] {
     if (!net || !overhead) fail(MITNC_INVALID_ARG, "null argument");
@@ -416,15 +465,15 @@ int32_t mitnc_plan_query(const mitnc_plan* P, mitnc_plan_stats* st) {
       st->bytes_full_slice += s.bytes_slice;
       st->steps_by_class[s.kclass] += 1;
       st->flops_by_class[s.kclass] += s.flops_slice;
-      // how many of the 2^S slices (run in order from 0) recompute this step
-      int lo = P->nodes[s.out].lo;
-      double runs;
-      if (lo >= kLevelNever) runs = 1;
-      else runs = std::ldexp(1.0, P->S - lo);  // slices whose ctz >= lo, plus slice 0
-      runs = std::min(runs, nsl);
+      // how many of the 2^S slices (run in order from 0) compute this step
+      const PlanNode& O = P->nodes[s.out];
+      double runs = std::min(merge_runs(O.elig, O.emask, O.bmask, P->S, P->S), nsl);
       st->flops_reused_slice += s.flops * runs / nsl;
       st->bytes_reused_slice += s.bytes * runs / nsl;
     }
+    st->n_merged = __builtin_popcountll(P->merged);
+    st->merge_align_bits = P->merge_align_bits;
+    st->merged_mask = P->merged;
     st->n_grad_gates = P->n_grad_gates;
     st->n_reverse_ops = (int32_t)P->rev.size();
     st->flops_reverse_slice = P->rev_flops;
@@ -560,6 +609,10 @@ int32_t mitnc_plan_node_info(const mitnc_plan* P, int32_t node, mitnc_node_info*
       info->slice_bit[j] = nd.slice_bits[j].first;
       info->slice_pos[j] = nd.slice_bits[j].second;
     }
+    info->elig_mask = nd.elig;
+    info->recompute_mask = nd.emask;
+    info->merge_mask = nd.bmask;
+    info->merge_tmp_offset = nd.bmask ? P->off_arena + nd.tmp_offset : 0;
     switch (nd.region) {
       case 0: info->ws_offset = nd.offset; break;
       case 1: info->ws_offset = P->off_persist + nd.offset; break;
@@ -629,7 +682,7 @@ mitnc_plan::~mitnc_plan() {
 // Launches one step.  prec: storage precision of this run (the plan's own,
 // or complex64 for a calibration slice of an FP16/BF16 plan).
 static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t slice, double* acc,
-                             hipStream_t s, int prec, bool stats) {
+                             hipStream_t s, int prec, bool stats, bool merge_term = false) {
   StepDesc d = (prec == MITNC_C64 && P->opts.precision != MITNC_C64) ? st.d64 : st.d;
   const bool half = prec != MITNC_C64;
   // Sliced leaves and hoisted results hold every value of their sliced
@@ -663,7 +716,8 @@ static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t s
     d.acc = acc;
     d.mode = EPI_ACC64;
   } else {
-    d.C = ptr(st.out, false);
+    // A merge term goes to the node's term buffer; it is then added.
+    d.C = merge_term ? base + P->off_arena + P->nodes[st.out].tmp_offset : ptr(st.out, false);
     d.acc = nullptr;
     d.mode = EPI_STORE;
   }
@@ -684,6 +738,22 @@ static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t s
     P->ev_used++;
   }
   hip_check(launch_step(st.kclass, d, s, e0, e1), "kernel launch");
+  if (merge_term) {
+    if (P->timing) {
+      while (P->ev_pool.size() < 2 * (P->ev_used + 1)) {
+        hipEvent_t e;
+        hip_check(hipEventCreate(&e), "event create");
+        P->ev_pool.push_back((void*)e);
+      }
+      e0 = (hipEvent_t)P->ev_pool[2 * P->ev_used];
+      e1 = (hipEvent_t)P->ev_pool[2 * P->ev_used + 1];
+      P->ev_step.push_back(d.step_index);
+      P->ev_used++;
+    }
+    unsigned int* slot = stats ? (unsigned int*)(base + P->off_stats) + d.step_index : nullptr;
+    hip_check(launch_merge_add(prec, ptr(st.out, false), d.C, 1ull << P->nodes[st.out].full_rank, slot, s, e0, e1),
+              "merge add launch");
+  }
 }
 
 // Launches a fused section (at the position of its last step).
@@ -727,16 +797,30 @@ static void launch_plan_section(mitnc_plan* P, PlanSection& sec, char* base, uin
 
 static void run_slices(mitnc_plan* P, char* base, uint64_t s0, uint64_t s1, double* acc, hipStream_t s, int prec,
                        bool stats) {
-  for (uint64_t sl = s0; sl < s1; ++sl) {
-    int level = (sl == s0) ? kLevelFirst : __builtin_ctzll(sl);
-    for (size_t i = 0; i < P->steps.size(); ++i) {
-      PlanStep& st = P->steps[i];
-      if (P->nodes[st.out].lo > level) continue;
-      const int sec = P->step_section.empty() ? -1 : P->step_section[i];
-      if (sec < 0) launch_plan_step(P, st, base, sl, acc, s, prec, stats);
-      else if (P->sections[sec].steps.back() == (int)i) launch_plan_section(P, P->sections[sec], base, sl, s, prec, stats);
-    }
-  }
+  for_each_launch(P, s0, s1, [&](uint64_t sl, size_t i, int mode) {
+    PlanStep& st = P->steps[i];
+    const int sec = P->step_section.empty() ? -1 : P->step_section[i];
+    if (sec < 0) launch_plan_step(P, st, base, sl, acc, s, prec, stats, mode == 2);
+    else if (P->sections[sec].steps.back() == (int)i) launch_plan_section(P, P->sections[sec], base, sl, s, prec, stats);
+  });
+}
+
+int32_t mitnc_plan_schedule(const mitnc_plan* P, uint64_t s0, uint64_t s1, int64_t capacity, int64_t* ops_out,
+                            int64_t* n_ops) {
+  return guarded([&] {
+    if (!P || !n_ops || capacity < 0 || (capacity > 0 && !ops_out)) fail(MITNC_INVALID_ARG, "bad argument");
+    check_range(P, s0, s1);
+    int64_t k = 0;
+    for_each_launch(P, s0, s1, [&](uint64_t sl, size_t i, int mode) {
+      if (k < capacity) {
+        ops_out[3 * k] = (int64_t)sl;
+        ops_out[3 * k + 1] = (int64_t)i;
+        ops_out[3 * k + 2] = mode;
+      }
+      ++k;
+    });
+    *n_ops = k;
+  });
 }
 
 static void check_ws(mitnc_plan* P, void* ws, size_t ws_bytes) {
@@ -805,8 +889,7 @@ int32_t mitnc_execute(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, uin
     check_ws(P, ws, ws_bytes);
     if (!acc) fail(MITNC_INVALID_ARG, "null result");
     if (!P->calibrated) fail(MITNC_INVALID_ARG, "FP16/BF16 plan: call mitnc_calibrate first");
-    uint64_t n_slices = 1ull << P->S;
-    if (s0 >= s1 || s1 > n_slices) fail(MITNC_INVALID_ARG, "slice range out of bounds");
+    check_range(P, s0, s1);
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)ws;
     const int prec = P->opts.precision;
@@ -873,7 +956,9 @@ int32_t mitnc_calibrate(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, u
     if (P->opts.precision == MITNC_C64) return;  // nothing to calibrate
     uint64_t n_slices = 1ull << P->S;
     if (s0 >= s1 || s1 > n_slices) fail(MITNC_INVALID_ARG, "slice range out of bounds");
-    calibrate_range(P, (char*)ws, s0, s1, (hipStream_t)stream);
+    // with merged bits: the whole merge groups that hold the range
+    const uint64_t am = (1ull << P->merge_align_bits) - 1;
+    calibrate_range(P, (char*)ws, s0 & ~am, (s1 + am) & ~am, (hipStream_t)stream);
   });
 }
 

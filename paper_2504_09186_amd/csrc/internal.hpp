@@ -65,7 +65,62 @@ std::vector<int> greedy_slices(const SymNet& sn, const Path& path, int cap, int 
                                int max_sliced, bool* ok);
 std::vector<int> slice_reconf(const SymNet& sn, Path& path, const std::vector<int>& fixed, int cap, int min_sliced,
                               int max_sliced, int every, bool* ok);
-double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered, int window_bits = 0);
+double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered, int window_bits = 0,
+                         int merge_bits = 0);
+// Branch exchange (merge.cpp): local reordering of absorptions on chains,
+// see the definition.  Returns the new path; *before / *after receive the
+// reuse_total_flops of the old and new path.
+Path branch_exchange(const SymNet& sn, const Path& path, const std::vector<int>& ordered, int window_bits,
+                     int merge_bits, int cap_bits, int passes, double* before, double* after);
+
+// Post-lifetime merge (merge.cpp).  Tree nodes 0..n-1 are leaves, then step
+// outputs in path order (children before parents, the root last); kids[u] is
+// {-1, -1} for a leaf.  dmask[u]: slice-id bits of the sliced indices carried
+// by the leaves below u.  Bits below `candidate_bits` may be merged.
+struct MergeSets {
+  uint64_t merged = 0;            // merged bits summed below the root
+  int align_bits = 0;             // slice ranges must be multiples of 2^align_bits
+  std::vector<int> at;            // per slice-id bit: node whose parent takes the sum (-1: not merged)
+  std::vector<uint64_t> elig;     // per node: bits that must all be 1 in a slice that computes it
+  std::vector<uint64_t> emask;    // per node: bits its value (as its parent reads it) depends on
+  std::vector<uint64_t> bmask;    // per node: bits summed in its accumulator (merged at this node)
+};
+MergeSets merge_sets(const std::vector<std::pair<int, int>>& kids, const std::vector<uint64_t>& dmask,
+                     const std::vector<char>& hoisted, int candidate_bits);
+// Computations of a node per 2^S slices run in aligned ranges of 2^W slices
+// (W <= S) under the rule of SliceSchedule.
+double merge_runs(uint64_t elig, uint64_t emask, uint64_t bmask, int S, int W);
+
+// The per-slice launch rule shared by execution, the host replay check and
+// the schedule query.  For slice s (slices of a range in increasing order):
+// a node runs only if every bit of elig is 1 in s; it then runs if the bits
+// emask & ~bmask differ from its last run (a new value: stored, or for an
+// accumulator the first term of a new sum) or, for an accumulator, if the
+// bits bmask of s form a pattern above the last term added to the current
+// sum (the next term: added).  Slices in between that repeat an added
+// pattern (a lower bit the node does not depend on changed) run nothing.
+struct SliceSchedule {
+  std::vector<uint64_t> key, pat;
+  std::vector<char> seen;
+  explicit SliceSchedule(size_t n_nodes) : key(n_nodes), pat(n_nodes), seen(n_nodes, 0) {}
+  // 0: skip, 1: compute (store, or accumulate at the root), 2: compute and add into the accumulator.
+  int decide(int node, uint64_t elig, uint64_t emask, uint64_t bmask, uint64_t s) {
+    if ((s & elig) != elig) return 0;
+    const uint64_t k = s & emask & ~bmask, p = s & bmask;
+    if (!seen[node] || k != key[node]) {
+      seen[node] = 1;
+      key[node] = k;
+      pat[node] = p;
+      if (p != 0) fail(MITNC_INVALID_ARG, "internal: merge group starts at a nonzero pattern");
+      return 1;
+    }
+    if (p > pat[node]) {
+      pat[node] = p;
+      return 2;
+    }
+    return 0;
+  }
+};
 std::vector<int> order_slices(const SymNet& sn, const Path& path, const std::vector<int>& sl);
 // Subtree reconfiguration (reconf.cpp): locally optimal re-ordering of the
 // tree, flops measured with `removed` labels (sliced) absent, intermediates

@@ -27,6 +27,11 @@ hipError_t launch_small_multi(const SmallRevOp* ops, const uint32_t* block_op, u
                               char* ws, uint64_t slice, hipStream_t s);
 // acc += src over n complex128 entries (device pointers).
 hipError_t launch_accumulate(double* acc, const double* src, uint64_t n, hipStream_t s);
+// Post-lifetime merge: acc += term over n complex entries stored in
+// precision prec (16-byte aligned device pointers for n >= 2 / 4 entries);
+// raises *stats_slot (may be null) to the largest stored |Re|, |Im|.
+hipError_t launch_merge_add(int prec, void* acc, const void* term, uint64_t n, unsigned int* stats_slot,
+                            hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_grad(const GradEntry* tab, int n_entries, const char* ws, uint64_t slice, double* grad,
                        hipStream_t s);
 

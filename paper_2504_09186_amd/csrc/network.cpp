@@ -330,7 +330,11 @@ std::vector<int> slice_reconf(const SymNet& sn, Path& path, const std::vector<in
 // (Sec. III-B): a step whose subtree holds sliced indices with lowest
 // slice-id bit b is recomputed 2^(S - b) times, a step with none once.
 // `ordered` lists the sliced indices outer -> inner (the last is bit 0).
-double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered, int window_bits) {
+// With merge_bits > 0 the innermost merge_bits bits (within the window) may
+// also be merged after their lifetime ends (post-lifetime reuse; the rule of
+// merge_sets), which the counts then include.
+double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered, int window_bits,
+                         int merge_bits) {
   const int S = (int)ordered.size();
   std::vector<char> sl(sn.n_labels, 0);
   std::vector<int> bit(sn.n_labels, -1);
@@ -344,19 +348,33 @@ double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<i
   for (size_t i = 0; i < n; ++i)
     for (int x : sn.leaf[i])
       if (bit[x] >= 0) dep[i] |= 1ull << bit[x];
+  for (size_t s = 0; s < path.size(); ++s) dep[n + s] = dep[path[s].first] | dep[path[s].second];
+  // Runs of the step over all 2^S slices: in one sequence (the step reruns
+  // whenever slice-id bit ctz(d) or a lower one changes), or dealt in
+  // aligned windows of 2^w slices, each starting with everything computed
+  // (2^(S-w) windows; a step independent of the window's bits runs once
+  // per window).
+  const int W = (window_bits > 0 && window_bits < S) ? window_bits : S;
+  const int mb = std::min(merge_bits, W);
+  if (mb > 0) {
+    std::vector<std::pair<int, int>> kids(n + path.size(), {-1, -1});
+    for (size_t s = 0; s < path.size(); ++s) kids[n + s] = {path[s].first, path[s].second};
+    const MergeSets m = merge_sets(kids, dep, std::vector<char>(kids.size(), 0), mb);
+    double f = 0;
+    for (size_t s = 0; s + 1 < path.size(); ++s)
+      f += st[s].flops * merge_runs(m.elig[n + s], m.emask[n + s], m.bmask[n + s], S, W);
+    // the root adds every slice's value into the result: no accumulator of its own
+    const size_t r = path.size() - 1;
+    f += st[r].flops * merge_runs(m.elig[n + r], m.emask[n + r], 0, S, W);
+    return f;
+  }
   double f = 0;
   for (size_t s = 0; s < path.size(); ++s) {
-    const uint64_t d = dep[path[s].first] | dep[path[s].second];
-    dep[n + s] = d;
-    // Runs of the step over all 2^S slices: in one sequence (the step reruns
-    // whenever slice-id bit ctz(d) or a lower one changes), or dealt in
-    // aligned windows of 2^w slices, each starting with everything computed
-    // (2^(S-w) windows; a step independent of the window's bits runs once
-    // per window).
+    const uint64_t d = dep[n + s];
     const int lo = d ? __builtin_ctzll(d) : 64;
     double runs;
-    if (window_bits > 0 && window_bits < S)
-      runs = std::ldexp(lo >= window_bits ? 1.0 : std::ldexp(1.0, window_bits - lo), S - window_bits);
+    if (W < S)
+      runs = std::ldexp(lo >= W ? 1.0 : std::ldexp(1.0, W - lo), S - W);
     else
       runs = d ? std::ldexp(1.0, S - lo) : 1.0;
     f += st[s].flops * runs;

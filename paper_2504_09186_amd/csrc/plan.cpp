@@ -815,7 +815,10 @@ static bool launch_operands(const mitnc_plan* P, int s, std::vector<int>& ops) {
 // Replays the launch schedule of slices 0 .. n_slices-1 on the host with a
 // map of which node value every workspace byte range holds, and fails if a
 // step reads an operand whose bytes were overwritten since it was produced,
-// or writes its output over one of its own operands.
+// or writes its output over one of its own operands.  It also checks that
+// the value read is the one the reading slice needs: produced in a slice
+// with the same bits of the operand's emask, and for a merge accumulator,
+// summed over every pattern of its merged bits.
 static void verify_memory_plan(const mitnc_plan* P, uint64_t n_slices) {
   struct Buf {
     uint64_t lo, hi;
@@ -828,17 +831,30 @@ static void verify_memory_plan(const mitnc_plan* P, uint64_t n_slices) {
     lo = base + nd.offset;
     hi = lo + (nd.region == 0 ? P->leaf_data[nd.leaf_id].size() * 4 : (8ull << nd.full_rank));
   };
+  auto overlaps = [](uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1) { return a0 < b1 && b0 < a1; };
   for (int i = 0; i < P->n_leaves; ++i) {
     uint64_t lo, hi;
     range(i, lo, hi);
     held.push_back({lo, hi, i});
   }
+  const size_t nn = P->nodes.size();
+  std::vector<uint64_t> vkey(nn, 0);     // emask bits (minus bmask) of the slice that produced the value
+  std::vector<uint64_t> terms(nn, 0);    // accumulators: terms summed so far
+  std::vector<uint64_t> last_pat(nn, 0); // accumulators: compressed merged bits of the last term
+  SliceSchedule sched(nn);
+  auto pattern_index = [](uint64_t s, uint64_t bm) {  // bits of s under bm, compressed
+    uint64_t r = 0;
+    int j = 0;
+    for (; bm; bm &= bm - 1, ++j) r |= ((s >> __builtin_ctzll(bm)) & 1ull) << j;
+    return r;
+  };
   std::vector<int> ops;
   for (uint64_t s = 0; s < n_slices; ++s) {
-    int level = s == 0 ? kLevelFirst : __builtin_ctzll(s);
     for (size_t si = 0; si < P->steps.size(); ++si) {
       const PlanStep& st = P->steps[si];
-      if (P->nodes[st.out].lo > level) continue;
+      const PlanNode& O = P->nodes[st.out];
+      const int mode = sched.decide(st.out, O.elig, O.emask, O.bmask, s);
+      if (mode == 0) continue;
       if (!launch_operands(P, (int)si, ops)) continue;  // runs with its section
       for (int node : ops) {
         uint64_t lo, hi;
@@ -847,19 +863,47 @@ static void verify_memory_plan(const mitnc_plan* P, uint64_t n_slices) {
         for (auto& b : held)
           if (b.node == node && b.lo == lo && b.hi == hi) ok = true;
         if (!ok) fail(MITNC_INVALID_ARG, "internal: operand " + std::to_string(node) + " clobbered before use");
+        const PlanNode& X = P->nodes[node];
+        if (!X.leaf) {
+          if (vkey[node] != (s & X.emask & ~X.bmask))
+            fail(MITNC_INVALID_ARG, "internal: operand " + std::to_string(node) + " holds another slice's value");
+          if (X.bmask && terms[node] != (1ull << __builtin_popcountll(X.bmask)))
+            fail(MITNC_INVALID_ARG, "internal: merge accumulator " + std::to_string(node) + " read before complete");
+        }
       }
       if (st.root) continue;
       uint64_t olo, ohi;
       range(st.out, olo, ohi);
+      uint64_t wlo = olo, whi = ohi;  // bytes the step's kernel writes
+      if (mode == 2) {
+        wlo = P->off_arena + O.tmp_offset;
+        whi = wlo + (8ull << O.full_rank);
+        if (overlaps(wlo, whi, olo, ohi)) fail(MITNC_INVALID_ARG, "internal: merge term overlaps its accumulator");
+      }
       for (int node : ops) {
         uint64_t lo, hi;
         range(node, lo, hi);
-        if (olo < hi && lo < ohi) fail(MITNC_INVALID_ARG, "internal: step output overlaps an operand");
+        if (overlaps(wlo, whi, lo, hi)) fail(MITNC_INVALID_ARG, "internal: step output overlaps an operand");
+      }
+      if (mode == 2) {
+        bool ok = false;
+        for (auto& b : held)
+          if (b.node == (int)st.out && b.lo == olo && b.hi == ohi) ok = true;
+        if (!ok) fail(MITNC_INVALID_ARG, "internal: merge accumulator " + std::to_string(st.out) + " clobbered");
+        const uint64_t t = pattern_index(s, O.bmask);
+        if (t <= last_pat[st.out] || vkey[st.out] != (s & O.emask & ~O.bmask))
+          fail(MITNC_INVALID_ARG, "internal: merge term out of order");
+        last_pat[st.out] = t;
+        terms[st.out]++;
+      } else {
+        vkey[st.out] = s & O.emask & ~O.bmask;
+        terms[st.out] = 1;  // pattern 0
+        last_pat[st.out] = 0;
       }
       std::vector<Buf> keep;
       for (auto& b : held)
-        if (!(b.lo < ohi && olo < b.hi) && b.node != st.out) keep.push_back(b);
-      keep.push_back({olo, ohi, st.out});
+        if (!overlaps(b.lo, b.hi, wlo, whi) && !(mode == 1 && b.node == (int)st.out)) keep.push_back(b);
+      if (mode == 1) keep.push_back({olo, ohi, (int)st.out});
       held.swap(keep);
     }
   }
@@ -1022,6 +1066,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   validate_path(n, net->path);
   if (opts.precision != MITNC_C64 && opts.precision != MITNC_CF16 && opts.precision != MITNC_CBF16)
     fail(MITNC_INVALID_ARG, "unknown precision");
+  if (opts.merge_bits < 0 || opts.merge_bits > 12) fail(MITNC_INVALID_ARG, "merge_bits out of range (0..12)");
   auto P = std::make_unique<mitnc_plan>();
   P->opts = opts;
   P->n_leaves = n;
@@ -1065,7 +1110,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   }
   std::vector<char> in_hoist(n + nsteps, 0);
   std::vector<int> hoist_root(n + nsteps, 0);
-  if (opts.reuse && !opts.differentiable) {
+  if (opts.reuse && !opts.differentiable && !opts.no_hoist) {
     std::vector<int> parent(n + nsteps, -1);
     for (int s = 0; s < nsteps; ++s) parent[net->path[s].first] = parent[net->path[s].second] = n + s;
     for (int s = 0; s < nsteps - 1; ++s) {
@@ -1182,16 +1227,38 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
       O.rank = (int)lab.size();
     }
   }
-  // Recompute levels.
-  for (auto& nd : P->nodes) {
-    if (nd.dmask == 0 || !opts.reuse) nd.lo = nd.dmask == 0 ? kLevelNever : 0;
-    else nd.lo = __builtin_ctzll(nd.dmask);
+  // Recompute rule (SliceSchedule): without merges a node runs when one of
+  // its slice-id bits changes (pre-lifetime reuse); every node runs in
+  // every slice without reuse; hoisted nodes run once per range.  With
+  // merge_bits, the post-lifetime merge of merge_sets on top.
+  const int nn = (int)P->nodes.size();
+  for (int u = 0; u < nn; ++u) {
+    PlanNode& nd = P->nodes[u];
+    nd.emask = !opts.reuse ? ~0ull : (nd.hoisted ? 0 : nd.dmask);
+    nd.elig = nd.bmask = 0;
   }
-  if (!opts.reuse)
-    for (auto& nd : P->nodes) nd.lo = 0;
-  for (auto& nd : P->nodes)
-    if (nd.hoisted) nd.lo = kLevelNever;
-  // Region choice: a node recomputed less often than its parent is kept.
+  if (opts.merge_bits > 0 && opts.reuse) {
+    std::vector<std::pair<int, int>> kids(nn, {-1, -1});
+    std::vector<uint64_t> dm(nn);
+    std::vector<char> hz(nn);
+    for (int u = 0; u < nn; ++u) {
+      dm[u] = P->nodes[u].dmask;
+      hz[u] = P->nodes[u].hoisted;
+    }
+    for (auto& st : P->steps) kids[st.out] = {st.a, st.b};
+    const MergeSets m = merge_sets(kids, dm, hz, std::min(opts.merge_bits, S));
+    for (int u = n; u < nn; ++u) {
+      P->nodes[u].elig = m.elig[u];
+      P->nodes[u].emask = m.emask[u];
+      P->nodes[u].bmask = P->steps[u - n].root ? 0 : m.bmask[u];
+    }
+    P->merged = m.merged;
+    P->merge_align_bits = m.align_bits;
+  }
+  auto set_lo = [&](PlanNode& nd) { nd.lo = nd.emask ? __builtin_ctzll(nd.emask) : kLevelNever; };
+  for (auto& nd : P->nodes) set_lo(nd);
+  // Region choice: a node recomputed less often than its parent (both run
+  // in the same slices otherwise) is kept, and so is a merge accumulator.
   auto assign_regions = [&]() {
     uint64_t pb = 0;
     for (size_t s = 0; s < P->steps.size(); ++s) {
@@ -1201,24 +1268,30 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
         continue;
       }
       int lp = P->nodes[O.parent].lo;
-      O.region = (O.lo > lp) ? 1 : 2;
+      O.region = (O.lo > lp || O.bmask) ? 1 : 2;
       if (O.region == 1) pb += std::ldexp(8.0, O.full_rank);
     }
     return pb;
   };
   uint64_t pbytes = assign_regions();
   if (opts.cache_budget_bytes > 0) {
+    // Demotion: the largest kept node runs whenever its parent does.
     while (pbytes > opts.cache_budget_bytes) {
       int best = -1;
       for (size_t s = 0; s < P->steps.size(); ++s) {
         PlanNode& O = P->nodes[P->steps[s].out];
-        if (O.region == 1 && !O.hoisted && (best < 0 || O.rank > P->nodes[best].rank)) best = P->steps[s].out;
+        if (O.region == 1 && !O.hoisted && !O.bmask && O.lo > P->nodes[O.parent].lo &&
+            (best < 0 || O.rank > P->nodes[best].rank))
+          best = P->steps[s].out;
       }
       if (best < 0) break;
-      P->nodes[best].lo = P->nodes[P->nodes[best].parent].lo;
+      P->nodes[best].emask |= P->nodes[P->nodes[best].parent].emask;
+      set_lo(P->nodes[best]);
       pbytes = assign_regions();
     }
   }
+  if (P->merged && (opts.differentiable || opts.fuse_sections))
+    fail(MITNC_UNSUPPORTED, "post-lifetime merge is not combined with differentiable plans or fused sections");
   // Differentiable plans keep every node (the reverse pass reads them all).
   if (opts.differentiable) {
     if (opts.precision != MITNC_C64) fail(MITNC_UNSUPPORTED, "differentiable plans are complex64 only");
@@ -1251,8 +1324,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
     // The output is placed while the operands are still live (a kernel must
     // never write over its own inputs); the operands are released afterwards.
     PlanNode& O = P->nodes[st.out];
-    if (O.region == 2) {
-      uint64_t sz = align_up(8ull << O.full_rank, 256);
+    auto place = [&](uint64_t sz) {
       std::vector<std::pair<uint64_t, uint64_t>> sorted = live;
       std::sort(sorted.begin(), sorted.end());
       uint64_t cand = 0;
@@ -1260,11 +1332,18 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
         if (cand + sz <= o) break;
         cand = std::max(cand, o + z);
       }
-      O.offset = cand;
-      live.push_back({cand, sz});
-      live_node.push_back(st.out);
       arena = std::max(arena, cand + sz);
+      return cand;
+    };
+    if (O.region == 2) {
+      uint64_t sz = align_up(8ull << O.full_rank, 256);
+      O.offset = place(sz);
+      live.push_back({O.offset, sz});
+      live_node.push_back(st.out);
     }
+    // A merge accumulator's later terms are computed into a transient buffer
+    // and then added; the buffer is free again after the step.
+    if (O.bmask) O.tmp_offset = place(align_up(8ull << O.full_rank, 256));
     for (int op : ops) {
       for (size_t i = 0; i < live_node.size(); ++i)
         if (live_node[i] == op) {
@@ -1299,7 +1378,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   P->off_rblock = align_up(P->off_rtab + sizeof(SmallRevOp) * P->rtab.size(), 256);
   P->ws_bytes = align_up(P->off_rblock + sizeof(uint32_t) * P->rblock.size(), 256);
   P->calibrated = !half;
-  verify_memory_plan(P.get(), std::min<uint64_t>(1ull << P->S, 64));
+  verify_memory_plan(P.get(), std::min<uint64_t>(1ull << std::min(P->S, 62), 1ull << std::max(6, P->merge_align_bits + 1)));
   return P.release();
 }
 

@@ -22,7 +22,12 @@ struct PlanNode {
   int full_rank = 0;            // address bits of the stored tensor (rank plus sliced bits kept, see hoisted)
   bool hoisted = false;         // computed once for all slices, sliced indices kept as ordinary ones
   uint64_t dmask = 0;           // slice-id bits this node depends on
-  int lo = kLevelNever;         // recompute when a slice-id bit <= lo changes
+  int lo = kLevelNever;         // recompute when a slice-id bit <= lo changes (lowest bit of emask)
+  // Launch rule of SliceSchedule (internal.hpp): runs in slices with every
+  // elig bit 1, when the emask bits change; bmask: merged slice-id bits
+  // summed in this node's accumulator (post-lifetime merge).
+  uint64_t elig = 0, emask = 0, bmask = 0;
+  uint64_t tmp_offset = 0;      // accumulators: arena offset of the term being added
   int parent = -1;
   int region = 0;               // 0 leaf, 1 persistent, 2 transient, 3 result accumulator
   uint64_t offset = 0;          // byte offset inside the region (complex64 sizing)
@@ -84,6 +89,10 @@ struct mitnc_plan {
   uint64_t ws_bytes = 0;
   bool calibrated = false;
   int32_t reruns = 0;  // FP16/BF16 executes that re-ran after an exponent miss
+  // Post-lifetime merge: bits summed below the root; slice ranges must be
+  // multiples of 2^merge_align_bits.
+  uint64_t merged = 0;
+  int merge_align_bits = 0;
   // Differentiation form (opts.differentiable): every node keeps its own
   // buffer, adjoints live in [off_adj, off_adj + adj_bytes).
   std::vector<char> has_grad;          // per node: a single-qubit gate leaf below

@@ -62,14 +62,25 @@ class Network:
 
     def path_search(self, seed: int = 0, trials: int = 32, max_log2: int = 30, min_sliced: int = 0,
                     max_sliced: int = 40, keep_slicing: bool = False, method: int = 0,
-                    window_bits: int = 0) -> None:
+                    window_bits: int = 0, merge_bits: int = 0, branch_exchange: bool = False) -> None:
         """Path and slicing search (method 0 greedy, 1 recursive bisection, 2
         both).  Methods 1 and 2 rank trials by the reuse-aware flops of all
         slices, run in one sequence (window_bits 0) or dealt in aligned
-        ranges of 2^window_bits slices that each start cold."""
+        ranges of 2^window_bits slices that each start cold, counting the
+        post-lifetime merge of the merge_bits innermost bits; branch_exchange
+        then reorders absorptions with the same ranking."""
         o = mitnc_search_opts(seed, trials, max_log2, min_sliced, max_sliced, 1 if keep_slicing else 0, method,
-                              window_bits)
+                              window_bits, merge_bits, 1 if branch_exchange else 0)
         call("mitnc_path_search", self.h, C.byref(o))
+
+    def branch_exchange(self, window_bits: int = 0, merge_bits: int = 0, max_log2: int = 30,
+                        passes: int = 8) -> Tuple[float, float]:
+        """Swaps consecutive absorptions of the current path where that lowers
+        the reuse- and merge-aware flops (mitnc_branch_exchange); returns the
+        flops before and after."""
+        b, a = C.c_double(), C.c_double()
+        call("mitnc_branch_exchange", self.h, window_bits, merge_bits, max_log2, passes, C.byref(b), C.byref(a))
+        return b.value, a.value
 
     def path(self) -> List[Tuple[int, int]]:
         buf = (C.c_int32 * (2 * (self.n_leaves - 1)))()
@@ -109,10 +120,10 @@ class Plan:
     def __init__(self, net: Network, precision: int = _lib.MITNC_C64, reuse: bool = True,
                  cache_budget_bytes: int = 0, force_kernel: int = -1, differentiable: bool = False,
                  fuse_sections: bool = False, no_rerun: bool = False, splitk_max_mn_bits: int = 0,
-                 splitk_target_bits: int = 0):
+                 splitk_target_bits: int = 0, merge_bits: int = 0, no_hoist: bool = False):
         o = mitnc_plan_opts(precision, 1 if reuse else 0, cache_budget_bytes, force_kernel,
                             1 if differentiable else 0, 1 if fuse_sections else 0, 1 if no_rerun else 0,
-                            splitk_max_mn_bits, splitk_target_bits)
+                            splitk_max_mn_bits, splitk_target_bits, merge_bits, 1 if no_hoist else 0)
         h = C.c_void_p()
         call("mitnc_plan_create", net.h, C.byref(o), C.byref(h))
         self.h = h
@@ -173,7 +184,21 @@ class Plan:
         k = ni.n_slice_bits
         return {"is_leaf": bool(ni.is_leaf), "rank": ni.rank, "full_rank": ni.full_rank, "level": ni.level,
                 "hoisted": bool(ni.hoisted), "slice_bits": list(zip(list(ni.slice_bit)[:k], list(ni.slice_pos)[:k])),
-                "ws_offset": None if ni.ws_offset == 2 ** 64 - 1 else int(ni.ws_offset)}
+                "ws_offset": None if ni.ws_offset == 2 ** 64 - 1 else int(ni.ws_offset),
+                "elig_mask": int(ni.elig_mask), "recompute_mask": int(ni.recompute_mask),
+                "merge_mask": int(ni.merge_mask), "merge_tmp_offset": int(ni.merge_tmp_offset)}
+
+    def schedule(self, slice_begin: int = 0, slice_end: Optional[int] = None) -> np.ndarray:
+        """The launches mitnc_execute makes for a slice range: rows (slice,
+        step, mode), mode 1 = store (root: accumulate), 2 = merge term."""
+        if slice_end is None:
+            slice_end = self.n_slices
+        n = C.c_int64()
+        call("mitnc_plan_schedule", self.h, slice_begin, slice_end, 0, None, C.byref(n))
+        buf = np.zeros(3 * max(1, n.value), dtype=np.int64)
+        call("mitnc_plan_schedule", self.h, slice_begin, slice_end, n.value,
+             buf.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(n))
+        return buf[:3 * n.value].reshape(-1, 3)
 
     def leaf_data(self, leaf: int) -> np.ndarray:
         """The complex64 entries the plan uploads for one leaf."""

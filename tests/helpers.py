@@ -51,3 +51,23 @@ def ref_contract(a_flat, la, b_flat, lb, lc, absval=False):
 
 def gamma(n: int, u: float = 2.0 ** -24) -> float:
     return n * u / (1 - n * u)
+
+
+def nested_chain(onet, path, k):
+    """k closed labels whose lifetimes (oracle.sliced_lifetimes) are strictly
+    nested, the innermost ending before the root; innermost first (None if
+    the path has no such family)."""
+    closed = onet.closed_labels()
+    below, alive = oracle.sliced_lifetimes(onet, path, closed)
+    life = {x: frozenset(t for t in range(len(path)) if x in alive[t]) for x in closed}
+    labs = sorted(closed, key=lambda x: (len(life[x]), x))
+    for x in labs:
+        if len(path) - 1 in life[x]:
+            continue
+        ch = [x]
+        for y in labs:
+            if len(ch) < k and life[ch[-1]] < life[y]:
+                ch.append(y)
+        if len(ch) == k:
+            return ch
+    return None

@@ -61,33 +61,40 @@ class PlanReplay:
         return self.ws[o:o + (1 << nd["full_rank"])]  # a view; only the slice's address bits are used
 
     def run(self, s0, s1):
-        """Slices s0 .. s1-1 in order, as the library runs them; returns the
-        complex128 sum of their results.  A fused section runs where its last
-        step is; its intermediates live outside the workspace, as on the GPU."""
+        """Slices s0 .. s1-1 in order, as the library runs them (its launch
+        list, mitnc_plan_schedule); returns the complex128 sum of their
+        results.  A fused section runs where its last step is; its
+        intermediates live outside the workspace, as on the GPU.  A merge
+        term (mode 2) is written to the node's term buffer and then added
+        into the node's accumulator."""
         acc = np.zeros(self.result_elems, dtype=np.complex128)
         sections = {}
         for i, st in enumerate(self.steps):
             if st["section"] >= 0:
                 sections.setdefault(st["section"], []).append(i)
-        for s in range(s0, s1):
-            for i, st in enumerate(self.steps):
-                lv = self.nodes[st["out"]]["level"]
-                if s != s0 and (lv < 0 or (s & -s).bit_length() - 1 < lv):
-                    continue  # unchanged since the previous slice
-                if st["section"] >= 0 and st["section_pos"] != st["section_len"] - 1:
-                    continue  # runs with its section
-                chain = sections[st["section"]] if st["section"] >= 0 else [i]
-                a = self._operand(self.steps[chain[0]]["a"], s)
-                for j in chain:
-                    sj = self.steps[j]
-                    self.executed += 1
-                    idx, val = self._contract(sj, a, self._operand(sj["b"], s))
-                    out = np.zeros(1 << self.nodes[sj["out"]]["full_rank"], dtype=np.complex128)
-                    out[idx] = val
-                    a = out
-                if st["root"]:
-                    np.add.at(acc, idx, val)
-                else:
-                    o = self._ptr(st["out"], s, False)
-                    self.ws[o + idx] = val
+        for s, i, mode in self.plan.schedule(s0, s1):
+            st = self.steps[i]
+            if st["section"] >= 0 and st["section_pos"] != st["section_len"] - 1:
+                continue  # runs with its section
+            chain = sections[st["section"]] if st["section"] >= 0 else [i]
+            a = self._operand(self.steps[chain[0]]["a"], s)
+            for j in chain:
+                sj = self.steps[j]
+                self.executed += 1
+                idx, val = self._contract(sj, a, self._operand(sj["b"], s))
+                out = np.zeros(1 << self.nodes[sj["out"]]["full_rank"], dtype=np.complex128)
+                out[idx] = val
+                a = out
+            if st["root"]:
+                np.add.at(acc, idx, val)
+            elif mode == 2:
+                nd = self.nodes[st["out"]]
+                size = 1 << nd["full_rank"]
+                t = nd["merge_tmp_offset"] // 8
+                o = self._ptr(st["out"], s, False)
+                self.ws[t + idx] = val
+                self.ws[o:o + size] += self.ws[t:t + size]
+            else:
+                o = self._ptr(st["out"], s, False)
+                self.ws[o + idx] = val
         return acc

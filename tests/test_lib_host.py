@@ -312,3 +312,160 @@ def test_reverse_schedule_levels(lib, rows, cols, cycles, nbits, nsl, seed):
     assert sum(1 for x in written if x < net.n_leaves) == n_1q
     with pytest.raises(Exception):
         plan.reverse_info(n_ops)
+
+
+# ------------------------------------------- post-lifetime merge (Sec. III-B)
+def _counts(plan, s0, s1):
+    sch = plan.schedule(s0, s1)
+    return np.bincount(sch[:, 1], minlength=plan.stats.n_steps), sch
+
+
+def test_schedule_matches_level_rule(lib):
+    """Without merges the launch list is the pre-lifetime rule: step t runs in
+    slice s iff s is the first of the range or ctz(s) >= its node's level
+    (level -1: first slice only); without reuse every step runs in every
+    slice."""
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(4, 4, 10, seed=7)
+    spec = synth.output_spec(16, [13, 14, 15], seed=8)
+    net = tnc.Network(c, spec)
+    net.path_search(seed=9, trials=8, max_log2=11, min_sliced=5)
+    for reuse in (True, False):
+        plan = tnc.Plan(net, reuse=reuse)
+        levels = [plan.node_info(plan.step_info(t)["out"])["level"] for t in range(plan.stats.n_steps)]
+        for s0, s1 in ((0, plan.n_slices), (5, 19)):
+            want = []
+            for s in range(s0, s1):
+                for t, lv in enumerate(levels):
+                    if s == s0 or (lv >= 0 and (s & -s).bit_length() - 1 >= lv):
+                        want.append((s, t, 1))
+            got = [tuple(int(v) for v in r) for r in plan.schedule(s0, s1)]
+            assert got == want, (reuse, s0, s1)
+
+
+@pytest.mark.parametrize("rows,cols,cycles,seed", [(4, 4, 10, 5), (3, 4, 10, 6), (4, 4, 8, 7)])
+def test_merge_nested_counts_equal_lifetimes(lib, rows, cols, cycles, seed):
+    """Strictly nested lifetimes (the spindle's condition): with every sliced
+    bit merged, each step runs exactly 2^(sliced indices alive at it) times
+    over all slices, the count of distinct values it has (the oracle's
+    lifetimes), so no calculation is repeated; without merges it runs
+    2^(S - lowest bit below it) times (pre-lifetime reuse).  The replayed
+    sums equal the state vector both ways."""
+    from plan_replay import PlanReplay
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(rows, cols, cycles, seed=seed)
+    n = c.n_qubits
+    spec = synth.output_spec(n, [n - 1], seed=seed + 1)
+    onet = oracle.build_network(c, spec)
+    path = oracle.greedy_path(onet)
+    from helpers import nested_chain
+    chain = nested_chain(onet, path, 4)
+    assert chain is not None
+    net = tnc.Network(c, spec)
+    net.set_path(path)
+    net.set_slicing(chain[::-1])  # outer -> inner: the innermost is bit 0
+    below, alive = oracle.sliced_lifetimes(onet, path, chain)
+    bit = {x: i for i, x in enumerate(chain)}
+    S = len(chain)
+    merged = tnc.Plan(net, merge_bits=S, no_hoist=True)
+    plain = tnc.Plan(net, no_hoist=True)
+    assert merged.stats.n_merged == S and merged.stats.merge_align_bits == S
+    cm, sch = _counts(merged, 0, 1 << S)
+    cp, _ = _counts(plain, 0, 1 << S)
+    for t in range(len(path)):
+        assert cm[t] == 2 ** len(alive[t]), t
+        lo = min((bit[x] for x in below[t]), default=None)
+        assert cp[t] == (1 if lo is None else 2 ** (S - lo)), t
+    assert cm.sum() < cp.sum() and (sch[:, 2] == 2).any()
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    for p in (merged, plain):
+        got = PlanReplay(p).run(0, 1 << S)
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+    # flops of the launch list = the plan's analytic count
+    fl = merged.steps()[:, 6]
+    assert (fl * cm).sum() / (1 << S) == pytest.approx(merged.stats.flops_reused_slice, rel=1e-12)
+
+
+@pytest.mark.parametrize("rows,cols,cycles,nsl,seed", [(3, 4, 8, 4, 3), (4, 4, 10, 5, 9), (3, 5, 9, 6, 11)])
+def test_merge_random_slicing_replay(lib, rows, cols, cycles, nsl, seed):
+    """Random slicings (lifetimes not nested in general; hoisting on): only
+    the bits the nesting rule allows are merged.  The replayed launch list
+    sums to the state vector over the whole range and over aligned
+    sub-ranges; no step runs more often than without merges; the plan's
+    analytic flops equal the launch list's; unaligned ranges are refused."""
+    from plan_replay import PlanReplay
+    from paper_2504_09186_amd import tnc
+    from paper_2504_09186_amd._lib import MitncError
+    c = synth.lattice_circuit(rows, cols, cycles, seed=seed)
+    n = c.n_qubits
+    spec = synth.output_spec(n, [n - 2, n - 1], seed=seed + 1)
+    onet = oracle.build_network(c, spec)
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    rng = np.random.default_rng(seed)
+    net = tnc.Network(c, spec)
+    net.set_path(oracle.greedy_path(onet))
+    seen_merge = False
+    for trial in range(6):
+        net.set_slicing([int(x) for x in rng.choice(onet.closed_labels(), size=nsl, replace=False)])
+        merged = tnc.Plan(net, merge_bits=nsl)
+        plain = tnc.Plan(net)
+        N = merged.n_slices
+        cm, sch = _counts(merged, 0, N)
+        cp, _ = _counts(plain, 0, N)
+        assert (cm <= cp).all()
+        fl = merged.steps()[:, 6]
+        assert (fl * cm).sum() / N == pytest.approx(merged.stats.flops_reused_slice, rel=1e-12)
+        got = PlanReplay(merged).run(0, N)
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+        al = merged.stats.merge_align_bits
+        if al:
+            seen_merge = True
+            step = 1 << al
+            if step < N:
+                parts = sum(PlanReplay(merged).run(s, s + step) for s in range(0, N, step))
+                assert np.linalg.norm(parts - ref) <= 1e-5 * np.linalg.norm(ref)
+            with pytest.raises(MitncError, match="multiple"):
+                merged.schedule(1, N)
+    assert seen_merge
+
+
+def test_merge_options_validated(lib):
+    from paper_2504_09186_amd import tnc
+    from paper_2504_09186_amd._lib import MitncError
+    c, spec, onet, net = _nets(3, 4, 8, seed=3, nopen=2)
+    net.set_path(oracle.greedy_path(onet))
+    net.set_slicing([2, 589831, 131074, 458759])
+    with pytest.raises(MitncError, match="merge_bits"):
+        tnc.Plan(net, merge_bits=13)
+    assert tnc.Plan(net, merge_bits=4).stats.n_merged > 0
+    with pytest.raises(MitncError, match="post-lifetime merge"):
+        tnc.Plan(net, merge_bits=4, differentiable=True)
+
+
+def test_branch_exchange_keeps_result_and_lowers_flops(lib):
+    """Branch exchange (Sec. III-B) on a greedy path with sliced indices:
+    the reported flops never rise, the path stays a valid SSA path with the
+    same amplitudes, and the plan's executed flops (merge-aware, no
+    hoisting) after the exchange equal the reported count."""
+    from plan_replay import PlanReplay
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(4, 4, 10, seed=5)
+    spec = synth.output_spec(16, [15], seed=6)
+    onet = oracle.build_network(c, spec)
+    path = oracle.greedy_path(onet)
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    rng = np.random.default_rng(12)
+    improved = 0
+    for trial in range(4):
+        net = tnc.Network(c, spec)
+        net.set_path(path)
+        sl = [int(x) for x in rng.choice(onet.closed_labels(), size=5, replace=False)]
+        net.set_slicing(sl)
+        before, after = net.branch_exchange(window_bits=0, merge_bits=5, max_log2=30)
+        assert after <= before
+        improved += after < before
+        plan = tnc.Plan(net, merge_bits=5, no_hoist=True)
+        assert plan.stats.flops_reused_slice * plan.n_slices == pytest.approx(after, rel=1e-12)
+        got = PlanReplay(plan).run(0, plan.n_slices)
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+    assert improved > 0

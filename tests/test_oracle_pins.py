@@ -415,3 +415,55 @@ def test_choose_slices_eval_follows_the_rule():
         best = min(keys)
         mine = [k for k in keys if k[2] == x][0]
         assert mine[:2] == best[:2]
+
+
+# ------------------------------------------------------- lifetimes (Sec. III-B)
+def _chain_net():
+    """T0(a,b) T1(b,c) T2(c,d) T3(d,e), labels a..e = 1..5, open a and e."""
+    rng = np.random.default_rng(77)
+    arrs = [rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2)) for _ in range(4)]
+    labels = [(1, 2), (2, 3), (3, 4), (4, 5)]
+    net = oracle.Network(n_qubits=0, arrays=arrs, labels=labels, output=(1, 5), dims={x: 2 for x in range(1, 6)})
+    return net, [(0, 1), (4, 2), (5, 3)]
+
+
+def test_sliced_lifetimes_hand_chain():
+    """Worked by hand: b ends at step 0; c starts at step 0 and ends at step
+    1; d starts at step 1 and ends at step 2; b is below steps 1 and 2 but no
+    longer alive there, and d is not below step 0."""
+    net, path = _chain_net()
+    below, alive = oracle.sliced_lifetimes(net, path, [2, 3, 4])
+    assert below == [{2, 3}, {2, 3, 4}, {2, 3, 4}]
+    assert alive == [{2, 3}, {3, 4}, {4}]
+
+
+def test_sliced_lifetimes_count_distinct_partial_sums():
+    """Brute force over the 8 slices of the chain: a step's output summed over
+    the sliced labels that ended strictly below it takes exactly 2^|alive|
+    distinct values (generic random tensors), which is the number of times
+    the spindle must compute it."""
+    net, path = _chain_net()
+    t0, t1, t2, t3 = net.arrays
+    below, alive = oracle.sliced_lifetimes(net, path, [2, 3, 4])
+    vals = {}  # step -> {(b, c, d): vector over the open labels}
+    for b in (0, 1):
+        for c in (0, 1):
+            for d in (0, 1):
+                x = t0[:, b] * t1[b, c]           # step 0: open a
+                y = x * t2[c, d]                  # step 1: open a
+                z = np.outer(y * 1.0, t3[d, :])   # step 2: open a, e
+                for t, v in enumerate((x, y, z)):
+                    vals.setdefault(t, {})[(b, c, d)] = np.asarray(v).reshape(-1)
+    name = {2: 0, 3: 1, 4: 2}
+    for t in range(3):
+        ended = below[t] - alive[t]
+        groups = {}
+        for key, v in vals[t].items():
+            keep = tuple(key[name[x]] for x in sorted(alive[t]))
+            groups[keep] = groups.get(keep, 0) + v
+        # the partial sums differ between groups and the group count is 2^|alive|
+        distinct = {tuple(np.round(g, 9)) for g in groups.values()}
+        assert len(groups) == len(distinct) == 2 ** len(alive[t]), (t, ended)
+        # summing over fewer labels than `ended` would leave more distinct values
+        if ended:
+            assert len({tuple(np.round(v, 9)) for v in vals[t].values()}) > 2 ** len(alive[t])
