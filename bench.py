@@ -33,7 +33,7 @@ METRIC = "slices/s + % MFMA peak, complex64 vs scaled complex-FP16 at stated amp
 PEAK_FP32 = 157.3   # dense MFMA (and vector) TFLOP/s, FP32
 PEAK_FP16 = 2500.0  # dense MFMA TFLOP/s, FP16
 PEAK_HBM_GBS = 8000.0
-CLASS_NAMES = ["small", "stem", "tile", "tall", "splitk", "stream", "section"]
+CLASS_NAMES = ["small", "stem", "tile", "tall", "splitk", "stream", "section", "merge"]
 
 
 def class_peak(label, cls):
@@ -52,7 +52,8 @@ GOLDEN2 = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.json")
 GOLDEN4 = os.path.join(ROOT, "tests", "golden", "config4_subslices.json")
 # Stored path and slicing of the headline network (written by
 # paper_2504_09186_amd/paths/make_paths.py: recursive-bisection search, 256
-# trials, ranked by the flops of all slices dealt in 256-slice shares).
+# trials, ranked by the flops of all slices dealt in 256-slice shares, then
+# branch exchange; its plans merge the 8 inner slice-id bits where nested).
 PATH4 = os.path.join(ROOT, "paper_2504_09186_amd", "paths", "rqc_7x8_20.json")
 WORKLOAD4 = "rqc-7x8-20cyc-4096amp-256slice-share"
 WORKLOAD2 = "rqc-5x6-14cyc-64amp-256slices"
@@ -167,7 +168,9 @@ def run_form(plan, steps, warmup, label, workload, s0=0, s1=None):
     roof["traffic"] = measured_traffic(workload, label, CLASS_NAMES[dom])
     roof["launches"] = int(launches[dom])
     roof["avg_launch_ms"] = ms[dom] / max(1.0, launches[dom])
-    step_flops = float(sum(flops[:nc])) / steps  # algorithmic flops of one step's launches
+    # algorithmic contraction flops of one step's launches (the merge
+    # additions are not contractions)
+    step_flops = float(sum(flops[k] for k in range(nc) if CLASS_NAMES[k] != "merge")) / steps
     total_bytes = sum(nbytes[:nc])
     overflow = None
     if plan.stats is not None and label != "c64":
@@ -330,20 +333,61 @@ def _host_info():
     return {"nproc": os.cpu_count(), "cpu": model, "ram_gib": mem}
 
 
+def share_flops(plan, s0, s1):
+    """Flops the plan's launch list executes for slices s0 .. s1-1."""
+    import numpy as np
+    sch = plan.schedule(s0, s1)
+    runs = np.bincount(sch[:, 1], minlength=plan.stats.n_steps)
+    return float((plan.steps()[:, 6] * runs).sum()), int(len(sch))
+
+
+def spindle_report(net, merge_bits, s0, s1, before=None):
+    """Flops of one share with pre-lifetime reuse only (same path) and with
+    the post-lifetime merge on top (Sec. III-B), host-side from the launch
+    lists; before = (what, flops of the share on the earlier plan) adds the
+    total cut against that plan."""
+    from paper_2504_09186_amd import tnc
+    pre, n_pre = share_flops(tnc.Plan(net, precision=0), s0, s1)
+    p = tnc.Plan(net, precision=0, merge_bits=merge_bits)
+    spin, n_spin = share_flops(p, s0, s1)
+    r = {"merge_bits": merge_bits, "n_merged": int(p.stats.n_merged), "share_flops_prelifetime": pre,
+         "share_flops_spindle": spin, "merge_skipped_frac": 1.0 - spin / pre, "launches_prelifetime": n_pre,
+         "launches_spindle": n_spin}
+    if before is not None and before[1]:
+        r["earlier_plan"] = before[0]
+        r["share_flops_earlier_plan"] = before[1]
+        r["total_skipped_frac"] = 1.0 - spin / before[1]
+    return r
+
+
+def config2_net(trials):
+    """The 5x6-qubit network and its plan search: recursive-bisection and
+    greedy trials ranked by the flops of one 256-slice share with the
+    merge of the 8 sliced bits, then branch exchange (Sec. III-B)."""
+    from paper_2504_09186_amd import tnc
+    c, spec = workload2()
+    net = tnc.Network(c, spec)
+    net.path_search(seed=3001, trials=trials, max_log2=26, min_sliced=8, max_sliced=8, method=2, window_bits=8,
+                    merge_bits=8, branch_exchange=True)
+    return c, spec, net
+
+
 def run_config2(steps, warmup, trials):
     """The 5x6-qubit workload: both forms on the greedy-search plan, errors
     against all 64 oracle amplitudes."""
     import torch
 
     from paper_2504_09186_amd import tnc
-    c, spec = workload2()
-    net = tnc.Network(c, spec)
-    net.path_search(seed=3001, trials=trials, max_log2=26, min_sliced=8, max_sliced=8)
+    c, spec, net = config2_net(trials)
     g = load_json(GOLDEN2)
     ref = to_complex(g["amplitudes"]) if g else None
-    out = {"workload": WORKLOAD2}
+    # the plan of a greedy search ranked by plain flops, for comparison
+    net0 = tnc.Network(c, spec)
+    net0.path_search(seed=3001, trials=trials, max_log2=26, min_sliced=8, max_sliced=8)
+    before = ("greedy search ranked by plain flops, pre-lifetime reuse", share_flops(tnc.Plan(net0), 0, 256)[0])
+    out = {"workload": WORKLOAD2, "spindle": spindle_report(net, 8, 0, 256, before)}
     for prec, label in ((0, "c64"), (1, "cf16")):
-        plan = tnc.Plan(net, precision=prec)
+        plan = tnc.Plan(net, precision=prec, merge_bits=8)
         plan.upload()
         if prec:
             plan.calibrate(0, 2)
@@ -476,18 +520,22 @@ def main():
     c, spec = workload4()
     net = tnc.Network(c, spec)
     stored = load_json(PATH4) if not args.search else None
+    before_exchange = None
     if stored is not None and stored["n_leaves"] == net.n_leaves:
         net.set_path([tuple(x) for x in stored["path"]])
         net.set_slicing(stored["slicing"])
-        search_s = stored["search"]["seconds"]
+        search_s = stored["search"]["seconds"] + stored.get("branch_exchange", {}).get("seconds", 0.0)
+        merge_bits = stored.get("merge_bits", 0)
+        before_exchange = stored["search"].get("share_flops")
         path_source = (f"stored: recursive bisection, {stored['search']['trials']} trials, ranked by job flops "
-                       f"in 256-slice shares")
+                       f"in 256-slice shares, then branch exchange")
     else:
         t0 = time.perf_counter()
         net.path_search(seed=3004, trials=args.trials, max_log2=30, min_sliced=8, max_sliced=62, method=1,
-                        window_bits=8)
+                        window_bits=8, merge_bits=8, branch_exchange=True)
         search_s = time.perf_counter() - t0
-        path_source = f"searched here: recursive bisection, {args.trials} trials"
+        merge_bits = 8
+        path_source = f"searched here: recursive bisection, {args.trials} trials, then branch exchange"
     print(f"path {path_source} ({search_s:.1f} s), {len(net.slicing())} sliced indices", file=sys.stderr,
           flush=True)
     g4 = load_json(GOLDEN4)
@@ -497,7 +545,7 @@ def main():
         # A profiling run: one form's share passes and nothing else, so that
         # kernel statistics of the run are those of the timed passes.
         prec = 0 if args.only == "c64" else 1
-        plan = tnc.Plan(net, precision=prec)
+        plan = tnc.Plan(net, precision=prec, merge_bits=merge_bits)
         plan.upload()
         if prec:
             plan.calibrate(0, 2)
@@ -505,14 +553,14 @@ def main():
         print(json.dumps({"only": args.only, "value": r["value"], "ms_per_step": r["ms_per_step"],
                           "roofline": r["roofline"], "kernel_ms_by_class": r["kernel_ms_by_class"]}), flush=True)
         return
-    plan = tnc.Plan(net, precision=0)
+    plan = tnc.Plan(net, precision=0, merge_bits=merge_bits)
     st = plan.stats
     plan.upload()
     r64, res64 = run_form(plan, args.steps, args.warmup, "c64", WORKLOAD4, *share)
     del plan
     torch.cuda.empty_cache()
     print(f"complex64: {r64['value']:.1f} slices/s", file=sys.stderr, flush=True)
-    plan = tnc.Plan(net, precision=1)
+    plan = tnc.Plan(net, precision=1, merge_bits=merge_bits)
     plan.upload()
     plan.calibrate(0, 2)
     r16, res16 = run_form(plan, args.steps, args.warmup, "cf16", WORKLOAD4, *share)
@@ -531,13 +579,16 @@ def main():
         "config": {"workload": WORKLOAD4, "qubits": 56, "cycles": 20, "open_qubits": 12,
                    "slices_per_step": 256, "n_sliced": st.n_sliced, "max_log2_elems": st.max_log2_elems,
                    "steps_per_slice": st.n_steps, "flops_full_slice": st.flops_full_slice,
-                   "path_search_s": search_s, "path": path_source,
+                   "path_search_s": search_s, "path": path_source, "merge_bits": merge_bits,
+                   "n_merged": st.n_merged,
                    "job_flops": r64["flops_per_step"] * 2.0 ** (st.n_sliced - 8),
                    "precision": "complex64, FP32 MFMA (3M), FP64 cross-slice sum"},
         "tflops": r64["tflops"],
         "hbm_gbs": r64["hbm_gbs"], "amp_error": r64.get("amp_error"),
         "kernel_ms_by_class": r64["kernel_ms_by_class"], "kernel_tflops_by_class": r64["kernel_tflops_by_class"],
         "roofline": r64["roofline"],
+        "spindle": spindle_report(net, merge_bits, *share,
+                                  ("same search before branch exchange, pre-lifetime reuse", before_exchange)),
         "cf16": dict(r16, precision="complex FP16 storage, FP16 MFMA (4M) with FP32 accumulate, per-tensor 2^e "
                                     "scaling, FP64 cross-slice sum"),
     }

@@ -511,9 +511,11 @@ int32_t mitnc_contract_noalloc(const void* A, int32_t ra, const int64_t* la, con
  * mitnc_execute (events are created on first use and reused after a reset);
  * calling it again (enable 0 or 1) discards the recorded pairs.
  * mitnc_plan_timing_read waits for the recorded events and fills, per kernel
- * class (8 entries each; entry 6 = fused sections): summed kernel
- * milliseconds, launch count, and the algorithmic real flops and HBM bytes
- * of those launches (for a section: its input, small tensors and output). */
+ * class (8 entries each; entry 6 = fused sections, entry 7 = the additions
+ * of the post-lifetime merge): summed kernel milliseconds, launch count, and
+ * the algorithmic real flops and HBM bytes of those launches (for a section:
+ * its input, small tensors and output; for a merge addition: the
+ * accumulator read and written and the term read). */
 int32_t mitnc_plan_timing(mitnc_plan* plan, int32_t enable);
 int32_t mitnc_plan_timing_read(mitnc_plan* plan, double* ms, double* launches, double* flops,
                                double* bytes);

@@ -747,7 +747,7 @@ static void launch_plan_step(mitnc_plan* P, PlanStep& st, char* base, uint64_t s
       }
       e0 = (hipEvent_t)P->ev_pool[2 * P->ev_used];
       e1 = (hipEvent_t)P->ev_pool[2 * P->ev_used + 1];
-      P->ev_step.push_back(d.step_index);
+      P->ev_step.push_back(kMergeEvent - (4 * d.step_index + prec));
       P->ev_used++;
     }
     unsigned int* slot = stats ? (unsigned int*)(base + P->off_stats) + d.step_index : nullptr;
@@ -1196,6 +1196,15 @@ int32_t mitnc_plan_timing_read(mitnc_plan* P, double* ms, double* launches, doub
       float t = 0;
       hip_check(hipEventElapsedTime(&t, e0, e1), "event time");
       const int id = P->ev_step[i];
+      if (id <= kMergeEvent) {  // merge addition: acc += term, 2 real flops and 3 accesses per entry
+        const int v = kMergeEvent - id;
+        const double n = std::ldexp(1.0, P->nodes[P->steps[v / 4].out].full_rank);
+        ms[kMergeClass] += t;
+        launches[kMergeClass] += 1;
+        flops[kMergeClass] += 2 * n;
+        bytes[kMergeClass] += 3 * n * (v % 4 == MITNC_C64 ? 8 : 4);
+        continue;
+      }
       if (id < 0) {  // fused section: its own class
         const PlanSection& sec = P->sections[-1 - id];
         ms[kSectionClass] += t;

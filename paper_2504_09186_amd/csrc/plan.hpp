@@ -11,6 +11,9 @@ namespace mitnc {
 
 constexpr int kLevelNever = 1000;   // node does not depend on any sliced index
 constexpr int kLevelFirst = 1001;   // first slice of a range: everything runs
+constexpr int kMergeClass = 7;      // timing slot of the post-lifetime merge additions
+// Timing record of a merge addition: kMergeEvent - (4 * step + precision).
+constexpr int kMergeEvent = -(1 << 30);
 
 struct PlanNode {
   bool leaf = false;

@@ -21,21 +21,23 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 
 # 7x8 lattice, 20 cycles, last 12 qubits open: the headline workload.
 RQC_7X8_20 = dict(rows=7, cols=8, cycles=20, circuit_seed=1004, open_qubits=list(range(44, 56)), spec_seed=2004,
-                  max_log2=30, min_sliced=8, max_sliced=62, window_bits=8)
+                  max_log2=30, min_sliced=8, max_sliced=62, window_bits=8, merge_bits=8)
 
 
 def share_flops(plan, window_bits):
-    """Flops of the first 2^window_bits slices with shared-prefix reuse."""
-    n = 1 << window_bits
-    tot = 0.0
-    for r in plan.steps():
-        lvl = int(r[5])
-        runs = 1 if lvl < 0 else 1 + (n - 1) // (1 << lvl)
-        tot += r[6] * runs
-    return tot
+    """Flops the plan's launch list executes for the first 2^window_bits
+    slices (shared-prefix reuse, and the post-lifetime merge if the plan
+    merges)."""
+    import numpy as np
+    sch = plan.schedule(0, 1 << window_bits)
+    runs = np.bincount(sch[:, 1], minlength=plan.stats.n_steps)
+    return float((plan.steps()[:, 6] * runs).sum())
 
 
 def make_rqc_7x8_20(trials: int, seed: int) -> dict:
+    """Recursive-bisection search ranked by the flops of 256-slice shares,
+    then branch exchange ranked the same way with the merge of the 8 inner
+    slice-id bits."""
     sys.path.insert(0, ROOT)
     import synth
     from paper_2504_09186_amd import tnc
@@ -47,13 +49,22 @@ def make_rqc_7x8_20(trials: int, seed: int) -> dict:
     net.path_search(seed=seed, trials=trials, max_log2=w["max_log2"], min_sliced=w["min_sliced"],
                     max_sliced=w["max_sliced"], method=1, window_bits=w["window_bits"])
     search_s = time.perf_counter() - t0
-    plan = tnc.Plan(net, precision=0)
+    sf_search = share_flops(tnc.Plan(net, precision=0), w["window_bits"])
+    t0 = time.perf_counter()
+    before, after = net.branch_exchange(window_bits=w["window_bits"], merge_bits=w["merge_bits"],
+                                        max_log2=w["max_log2"], passes=8)
+    exchange_s = time.perf_counter() - t0
+    plan = tnc.Plan(net, precision=0, merge_bits=w["merge_bits"])
     sl = [int(x) for x in net.slicing()]
     sf = share_flops(plan, w["window_bits"])
-    return dict(workload=w, n_leaves=net.n_leaves, search=dict(method=1, trials=trials, seed=seed,
-                                                               seconds=round(search_s, 1)),
+    return dict(workload=w, n_leaves=net.n_leaves,
+                search=dict(method=1, trials=trials, seed=seed, seconds=round(search_s, 1),
+                            share_flops=sf_search),
+                branch_exchange=dict(passes=8, seconds=round(exchange_s, 1), job_flops_before=before,
+                                     job_flops_after=after),
                 path=[[int(a), int(b)] for a, b in net.path()], slicing=sl, n_sliced=len(sl),
-                max_log2_elems=int(plan.stats.max_log2_elems), share_flops=sf,
+                max_log2_elems=int(plan.stats.max_log2_elems), merge_bits=w["merge_bits"],
+                n_merged=int(plan.stats.n_merged), share_flops=sf,
                 job_flops=sf * 2.0 ** (len(sl) - w["window_bits"]))
 
 
@@ -66,8 +77,9 @@ def main():
     path = os.path.join(HERE, "rqc_7x8_20.json")
     with open(path, "w") as f:
         json.dump(out, f, separators=(",", ":"))
-    print(f"wrote {path}: {out['n_sliced']} sliced, share flops {out['share_flops']:.3e}, "
-          f"job flops {out['job_flops']:.3e} ({out['search']['seconds']} s search)")
+    print(f"wrote {path}: {out['n_sliced']} sliced, share flops {out['search']['share_flops']:.3e} after the "
+          f"search, {out['share_flops']:.3e} after branch exchange and merge, job flops {out['job_flops']:.3e} "
+          f"({out['search']['seconds']} s search, {out['branch_exchange']['seconds']} s exchange)")
 
 
 if __name__ == "__main__":

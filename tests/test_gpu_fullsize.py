@@ -37,21 +37,38 @@ def _workload():
     return c, spec
 
 
+def _bench_net():
+    """The benchmark's plan search for this network: bisection and greedy
+    trials ranked with the merge of the 8 sliced bits, then branch exchange
+    (its plans merge the 8 bits)."""
+    from paper_2504_09186_amd import tnc
+    c, spec = _workload()
+    net = tnc.Network(c, spec)
+    net.path_search(seed=3001, trials=64, max_log2=26, min_sliced=8, max_sliced=8, method=2, window_bits=8,
+                    merge_bits=8, branch_exchange=True)
+    return net
+
+
 @pytest.mark.parametrize("fuse", [False, True])
 def test_config2_all_slices_bench_plan(fuse):
-    """All 256 slices of the benchmark plan, one launch per step or with the
-    stem chains as fused sections, against the oracle's stored amplitudes."""
+    """All 256 slices, against the oracle's stored amplitudes: the benchmark
+    plan (post-lifetime merge of all 8 sliced bits), and the plain greedy
+    plan with the stem chains as fused sections (fused sections and merges
+    are not combined)."""
     require_gpu()
     import torch
     from paper_2504_09186_amd import tnc
     g, to_c = _golden()
-    c, spec = _workload()
-    net = tnc.Network(c, spec)
-    net.path_search(seed=3001, trials=64, max_log2=26, min_sliced=8, max_sliced=8)
-    plan = tnc.Plan(net, fuse_sections=fuse)
-    assert plan.n_slices == 256
     if fuse:
+        c, spec = _workload()
+        net = tnc.Network(c, spec)
+        net.path_search(seed=3001, trials=64, max_log2=26, min_sliced=8, max_sliced=8)
+        plan = tnc.Plan(net, fuse_sections=True)
         assert any(plan.step_info(i)["section"] >= 0 for i in range(plan.stats.n_steps))
+    else:
+        plan = tnc.Plan(_bench_net(), merge_bits=8)
+        assert plan.stats.n_merged >= 1
+    assert plan.n_slices == 256
     plan.upload()
     acc = plan.new_result()
     print(f"config 2: all 256 slices, bench plan, fused sections {fuse}", flush=True)
@@ -88,8 +105,8 @@ def test_config2_oracle_slicing_first_16_slices():
 
 @pytest.mark.parametrize("prec,xeb_bound,rel_bound", [(1, 1e-3, 2e-2), (2, 1e-2, 1.5e-1)])
 def test_config2_all_slices_half_precision(prec, xeb_bound, rel_bound):
-    """Precision form at full size: all 256 slices of the benchmark plan with
-    complex FP16 (prec 1) or BF16 (prec 2) storage, FP32 accumulation and
+    """Precision form at full size: all 256 slices of the benchmark plan (with
+    merges) with complex FP16 (prec 1) or BF16 (prec 2) storage, FP32 accumulation and
     per-tensor exponents calibrated on slices 0-1, FP64 cross-slice sum.  The
     result is an approximation, pinned only by the error metrics against the
     FP64 oracle's amplitudes: linear-XEB fidelity loss <= 1e-3 (FP16) or
@@ -101,10 +118,8 @@ def test_config2_all_slices_half_precision(prec, xeb_bound, rel_bound):
     import oracle
     from paper_2504_09186_amd import tnc
     g, to_c = _golden()
-    c, spec = _workload()
-    net = tnc.Network(c, spec)
-    net.path_search(seed=3001, trials=64, max_log2=26, min_sliced=8, max_sliced=8)
-    plan = tnc.Plan(net, precision=prec)
+    plan = tnc.Plan(_bench_net(), precision=prec, merge_bits=8)
+    assert plan.stats.n_merged >= 1
     plan.upload()
     plan.calibrate(0, 2)
     acc = plan.new_result()
@@ -126,7 +141,7 @@ def test_config2_all_slices_half_precision(prec, xeb_bound, rel_bound):
 GOLDEN4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config4_subslices.json")
 
 
-def _config4_subslice_plan(prec):
+def _config4_subslice_plan(prec, exchange=False):
     """The 7x8-qubit, 20-cycle network (qubits 44-55 open) with the oracle's
     sliced indices kept (outermost, in its order) and the library's own
     path; extra inner indices only if its path needs them for 2^30."""
@@ -144,23 +159,28 @@ def _config4_subslice_plan(prec):
                     method=1)
     assert net.slicing()[:len(lab)] == lab
     extra = len(net.slicing()) - len(lab)
-    plan = tnc.Plan(net, precision=prec)
+    if exchange:
+        before, after = net.branch_exchange(window_bits=extra, merge_bits=extra, max_log2=30)
+        assert after < before
+    plan = tnc.Plan(net, precision=prec, merge_bits=extra)
     return g, plan, extra
 
 
+@pytest.mark.parametrize("exchange", [False, True])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_config4_oracle_subslices(prec):
+def test_config4_oracle_subslices(prec, exchange):
     """Full-size 56-qubit network, sub-slices of the oracle's 60-index slicing
     (each a partial sum over the sliced indices' other values, about 4e12
     flops for the oracle): complex64 within 1e-5 relative L2 of the FP64
     oracle; complex FP16 (exponents calibrated on the first checked
     sub-slice) within 2e-2 relative L2 and an XEB fidelity loss <= 1e-3 over
-    the 2^12 open amplitudes of each sub-slice."""
+    the 2^12 open amplitudes of each sub-slice.  Also on the path after
+    branch exchange (Sec. III-B), which must not change the values."""
     require_gpu()
     import torch
 
     import oracle
-    g, plan, extra = _config4_subslice_plan(prec)
+    g, plan, extra = _config4_subslice_plan(prec, exchange)
     to_c = lambda v: np.array([a + 1j * b for a, b in v])  # noqa: E731
     plan.upload()
     for sid in g["sub_slice_ids"]:
@@ -168,7 +188,8 @@ def test_config4_oracle_subslices(prec):
         if prec:
             plan.calibrate(s0, min(s1, s0 + 2))
         acc = plan.new_result()
-        print(f"config 4: sub-slice {sid} (library slices {s0}..{s1 - 1}), precision {prec}", flush=True)
+        print(f"config 4: sub-slice {sid} (library slices {s0}..{s1 - 1}), precision {prec}, exchange {exchange}",
+              flush=True)
         plan.execute(acc, s0, s1)
         torch.cuda.synchronize()
         got = acc.cpu().numpy()
