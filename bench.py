@@ -188,6 +188,59 @@ def run_form(plan, steps, warmup, label, workload, s0=0, s1=None):
     return rec, result
 
 
+def grad_config3(steps, n_slices=32):
+    """Differentiation form on the gradient configuration itself: 6x6
+    lattice, 16 cycles, 256 random bitstrings as a batch index (seeds 1003 /
+    2003 / 3003), intermediates <= 2^30 entries with the batch bits
+    (bisection search, 16 trials: 13 sliced indices, 8192 slices; the
+    differentiable plan keeps every node, about 70 GiB).  A sub-batch of the
+    slices is timed: slices 0 .. n_slices-1, forward over the range (with
+    shared-prefix reuse) and backward over the same range, seeded with
+    w = 1 / (the range's partial amplitudes); the full gradient sums every
+    range."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(6, 6, 16, seed=1003)
+    bits = synth.random_bitstrings(36, 256, seed=2003)
+    spec = np.full(36, -2, dtype=np.int8)
+    net = tnc.Network(c, spec, bits)
+    net.path_search(seed=3003, trials=16, max_log2=30, method=1, max_sliced=30)
+    plan = tnc.Plan(net, differentiable=True)
+    plan.upload()
+    acc = plan.new_result()
+    n = min(n_slices, plan.n_slices)
+    plan.execute(acc, 0, n)
+    w = (1.0 / acc).contiguous()
+    grad = torch.zeros(4 * plan.stats.n_grad_gates, dtype=torch.complex128, device=acc.device)
+    plan.backward(w, grad, 0, n)  # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        acc.zero_()
+        plan.execute(acc, 0, n)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        grad.zero_()
+        plan.backward(w, grad, 0, n)
+    torch.cuda.synchronize()
+    bwd = (time.perf_counter() - t0) / steps
+    st = plan.stats
+    out = {"workload": "rqc-6x6-16cyc-256bitstrings-grad-cap30", "slices_total": plan.n_slices,
+           "slices_timed": n, "n_sliced": st.n_sliced, "max_log2_elems": st.max_log2_elems,
+           "workspace_gib": st.workspace_bytes / 2 ** 30,
+           "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "backward_over_forward": bwd / fwd,
+           "reverse_flops_per_slice": st.flops_reverse_slice, "forward_flops_per_slice_reused": st.flops_reused_slice,
+           "n_grad_gates": st.n_grad_gates, "finite": bool(torch.isfinite(torch.view_as_real(grad)).all())}
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def subslice_check(c, spec, g, precision):
     """The oracle's stored sub-slices (its own slicing of the same network),
     recomputed with the library's path for that slicing."""
@@ -501,8 +554,8 @@ def main():
     from paper_2504_09186_amd import tnc
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.grad:
-        print(json.dumps({"grad": grad_timing(args.steps), "grad_sliced": grad_timing(args.steps, cap=22)}),
-              flush=True)
+        print(json.dumps({"grad": grad_timing(args.steps), "grad_sliced": grad_timing(args.steps, cap=22),
+                          "grad_config3": grad_config3(args.steps)}), flush=True)
         return
     if args.micro:
         print(json.dumps(micro(args.micro, args.micro_precision, max(1, args.steps))), flush=True)
@@ -598,6 +651,7 @@ def main():
         # the same with intermediates capped at 2^22 entries: 16 slices, each
         # recomputed per slice by the backward
         out["grad_sliced"] = grad_timing(args.steps, cap=22)
+        out["grad_config3"] = grad_config3(args.steps)
     if not args.no_cpu_baseline and g4 is not None:
         out["cpu_baseline"] = cpu_baseline_subslice(c, spec, g4, r64["flops_per_step"] / 256)
     print(json.dumps(out), flush=True)
