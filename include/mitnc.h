@@ -226,6 +226,16 @@ typedef struct mitnc_plan_opts {
                                  indices are not hoisted (contracted once for
                                  all slices); they then run per slice under
                                  the reuse rule like every other node */
+  int32_t reverse_defer;      /* differentiable plans, grouped reverse pass:
+                                 the reverse below a kept node d depends on
+                                 the slice only through d's sliced bits (all
+                                 at or above its lowest, lo), so adj(d) is
+                                 summed over each run of 2^lo slices and the
+                                 adjoint ops below d run once per run.
+                                 0: at the kept nodes where a cost model
+                                 (flops saved against the added accumulation
+                                 traffic) expects a gain; 1: at every kept
+                                 node; -1: never */
 } mitnc_plan_opts;
 
 /* Execution plan of the sliced contraction tree for the network's current
@@ -262,6 +272,7 @@ typedef struct mitnc_plan_stats {
   int32_t n_merged;           /* slice-id bits merged below the root (merge_bits) */
   int32_t merge_align_bits;   /* execute ranges must be multiples of 2^this (0: any) */
   uint64_t merged_mask;       /* the merged bits */
+  int32_t n_reverse_groups;   /* differentiable plans: deferral roots of the grouped reverse pass */
 } mitnc_plan_stats;
 int32_t mitnc_plan_query(const mitnc_plan* plan, mitnc_plan_stats* stats);
 

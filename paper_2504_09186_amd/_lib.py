@@ -42,7 +42,7 @@ class mitnc_plan_opts(C.Structure):
                 ("cache_budget_bytes", C.c_uint64), ("force_kernel", C.c_int32),
                 ("differentiable", C.c_int32), ("fuse_sections", C.c_int32), ("no_rerun", C.c_int32),
                 ("splitk_max_mn_bits", C.c_int32), ("splitk_target_bits", C.c_int32),
-                ("merge_bits", C.c_int32), ("no_hoist", C.c_int32)]
+                ("merge_bits", C.c_int32), ("no_hoist", C.c_int32), ("reverse_defer", C.c_int32)]
 
 
 class mitnc_plan_stats(C.Structure):
@@ -54,7 +54,7 @@ class mitnc_plan_stats(C.Structure):
                 ("steps_by_class", C.c_int32 * 8), ("flops_by_class", C.c_double * 8),
                 ("n_grad_gates", C.c_int32), ("n_reverse_ops", C.c_int32),
                 ("flops_reverse_slice", C.c_double), ("n_merged", C.c_int32),
-                ("merge_align_bits", C.c_int32), ("merged_mask", C.c_uint64)]
+                ("merge_align_bits", C.c_int32), ("merged_mask", C.c_uint64), ("n_reverse_groups", C.c_int32)]
 
 
 class mitnc_step_info(C.Structure):

@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -474,6 +475,7 @@ int32_t mitnc_plan_query(const mitnc_plan* P, mitnc_plan_stats* st) {
     st->n_merged = __builtin_popcountll(P->merged);
     st->merge_align_bits = P->merge_align_bits;
     st->merged_mask = P->merged;
+    st->n_reverse_groups = P->rev_groups.empty() ? 0 : (int32_t)P->rev_groups.size() - 1;
     st->n_grad_gates = P->n_grad_gates;
     st->n_reverse_ops = (int32_t)P->rev.size();
     st->flops_reverse_slice = P->rev_flops;
@@ -996,12 +998,63 @@ int32_t mitnc_backward(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, ui
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)ws;
     const int root = P->steps.back().out;
+    uint64_t sl = s1;
+    // Accumulators of the deferral roots start each run of slices at zero.
+    auto clear_acc = [&](int node) {
+      hip_check(hipMemsetAsync(base + P->off_adj + P->adj_offset[node], 0, 8ull << P->nodes[node].rank, s),
+                "adjoint accumulator reset");
+    };
+    for (size_t g = 1; g < P->rev_groups.size(); ++g) clear_acc(P->rev_groups[g].root);
+    std::function<void(int)> run_group = [&](int gi) {
+      const mitnc_plan::RevGroup& G = P->rev_groups[gi];
+      for (const mitnc_plan::RevLevel& L : G.levels) {
+        for (int ri : L.big) {
+          const RevOp& r = P->rev[ri];
+          StepDesc d = r.d;
+          char* adj_c = base + P->off_adj + P->adj_offset[P->steps[r.step].out];
+          char* other = node_value_ptr(P, base, r.other, sl);
+          d.A = r.adj_is_a ? adj_c : other;
+          d.B = r.adj_is_a ? other : adj_c;
+          d.C = base + P->off_adj +
+                (P->defer_group[r.target] >= 0 ? P->adj_term_offset[r.target] : P->adj_offset[r.target]);
+          d.acc = nullptr;
+          d.part = (float*)(base + P->off_part);
+          d.stats = nullptr;
+          d.mode = EPI_STORE;
+          d.prec = MITNC_C64;
+          d.out_scale = 1.f;
+          d.acc_scale = 1.0;
+          hip_check(launch_step(r.kclass, d, s), "reverse kernel launch");
+        }
+        if (L.small_blocks)
+          hip_check(launch_small_multi((const SmallRevOp*)(base + P->off_rtab), (const uint32_t*)(base + P->off_rblock),
+                                       L.small_first, L.small_blocks, base, sl, s),
+                    "reverse small-step launch");
+      }
+      for (int c : G.children) {  // this slice's term of each child's adjoint
+        const int v = P->rev_groups[c].root;
+        hip_check(launch_merge_add(MITNC_C64, base + P->off_adj + P->adj_offset[v],
+                                   base + P->off_adj + P->adj_term_offset[v], 1ull << P->nodes[v].rank, nullptr, s),
+                  "adjoint accumulation");
+      }
+      if (G.grad_count)
+        hip_check(launch_grad((const GradEntry*)(base + P->off_gtab) + G.grad_first, (int)G.grad_count, base, sl,
+                              grad, s),
+                  "gradient accumulation");
+      for (int c : G.children) {
+        const mitnc_plan::RevGroup& C = P->rev_groups[c];
+        if (sl == s0 || (sl & ((1ull << C.lo) - 1)) == 0) {
+          run_group(c);
+          clear_acc(C.root);
+        }
+      }
+    };
     // Slices run from the last to the first: when the workspace still holds
     // the values of the last slice (the forward pass that produced the
     // amplitudes ended there), its recomputation is skipped.  Going from
     // slice s + 1 down to s changes the slice-id bits 0 .. ctz(s + 1), so a
     // node is recomputed when its lowest sliced bit is at most that.
-    for (uint64_t sl = s1; sl-- > s0;) {
+    while (sl-- > s0) {
       // forward: recompute the nodes whose sliced indices changed (the root's
       // value itself is not needed)
       int level;
@@ -1012,32 +1065,11 @@ int32_t mitnc_backward(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, ui
         launch_plan_step(P, st, base, sl, nullptr, s, MITNC_C64, false);
       }
       P->valid_slice = (int64_t)sl;
-      // reverse
+      // reverse: group 0 for every slice; a deferral root's group once its
+      // run of slices is complete (the slice id a multiple of 2^lo, or the
+      // range's first slice; slices go downwards)
       hip_check(launch_seed(w, (float*)(base + P->off_adj + P->adj_offset[root]), P->result_elems, s), "seed");
-      for (const mitnc_plan::RevLevel& L : P->rev_levels) {
-        for (int ri : L.big) {
-          const RevOp& r = P->rev[ri];
-          StepDesc d = r.d;
-          char* adj_c = base + P->off_adj + P->adj_offset[P->steps[r.step].out];
-          char* other = node_value_ptr(P, base, r.other, sl);
-          d.A = r.adj_is_a ? adj_c : other;
-          d.B = r.adj_is_a ? other : adj_c;
-          d.C = base + P->off_adj + P->adj_offset[r.target];
-          d.acc = nullptr;
-          d.part = (float*)(base + P->off_part);
-          d.stats = nullptr;
-          d.mode = EPI_STORE;
-          d.prec = MITNC_C64;
-          d.out_scale = 1.f;
-          d.acc_scale = 1.0;
-          hip_check(launch_step(r.kclass, d, s), "reverse kernel launch");
-        }
-        hip_check(launch_small_multi((const SmallRevOp*)(base + P->off_rtab), (const uint32_t*)(base + P->off_rblock),
-                                     L.small_first, L.small_blocks, base, sl, s),
-                  "reverse small-step launch");
-      }
-      hip_check(launch_grad((const GradEntry*)(base + P->off_gtab), (int)P->gtab.size(), base, sl, grad, s),
-                "gradient accumulation");
+      run_group(0);
     }
   });
 }

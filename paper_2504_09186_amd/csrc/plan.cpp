@@ -939,7 +939,6 @@ static void build_reverse(mitnc_plan* P, const mitnc_network* net, const mitnc_p
     P->adj_offset[v] = off;
     off = align_up(off + (8ull << P->nodes[v].rank), 256);
   }
-  P->adj_bytes = off;
   for (int si = (int)P->steps.size() - 1; si >= 0; --si) {
     const PlanStep& st = P->steps[si];
     if (!P->has_grad[st.out]) continue;
@@ -975,6 +974,51 @@ static void build_reverse(mitnc_plan* P, const mitnc_network* net, const mitnc_p
       P->rev.push_back(r);
     }
   }
+  // Grouped reverse pass: deferral roots, chosen top-down (a node's parent
+  // step comes later in the path), each with a term buffer after the
+  // adjoints.  below[v]: reverse flops of the ops that read an adjoint in
+  // v's subtree (the work a deferral at v would run once per run of slices).
+  const int nn = (int)P->nodes.size();
+  const int root = P->steps.back().out;
+  std::vector<int> parent(nn, -1);
+  for (auto& st : P->steps) parent[st.a] = parent[st.b] = st.out;
+  std::vector<double> below(nn, 0.0);
+  for (const RevOp& r : P->rev)
+    for (int v = P->steps[r.step].out; v >= 0; v = parent[v]) below[v] += r.flops;
+  P->defer_group.assign(nn, -1);
+  P->adj_term_offset.assign(nn, 0);
+  P->rev_groups.assign(1, mitnc_plan::RevGroup{});
+  std::vector<int> group_of(nn, 0);  // innermost deferral root's group at or above each node
+  auto lo_of = [&](int v) { return P->nodes[v].lo >= kLevelNever ? 64 : P->nodes[v].lo; };
+  for (int si = (int)P->steps.size() - 1; si >= 0; --si) {
+    const int v = P->steps[si].out;
+    if (v == root) continue;
+    group_of[v] = group_of[parent[v]];
+    const int lo = lo_of(v), lp = lo_of(parent[v]);
+    if (opts.reverse_defer < 0 || !P->has_grad[v] || lo <= lp) continue;
+    // Saved: the subtree's reverse flops in all but one slice of each run
+    // of 2^span; paid: the accumulation, 3 accesses of 8 bytes per adjoint
+    // entry and slice.  The weight of 24 flops per entry follows measurement:
+    // the reverse kernels of these subtrees are themselves HBM-bound (about
+    // one flop per byte), so an accumulation costs about its bytes.
+    const int span = std::min(lo, P->S);
+    const double saved = below[v] * (1.0 - std::ldexp(1.0, -span));
+    const double cost = 24.0 * std::ldexp(1.0, P->nodes[v].rank);
+    if (opts.reverse_defer == 0 && (span == 0 || saved <= cost)) continue;
+    const int g = (int)P->rev_groups.size();
+    mitnc_plan::RevGroup G;
+    G.root = v;
+    G.lo = std::min(lo, 63);
+    P->rev_groups.push_back(G);
+    P->rev_groups[group_of[parent[v]]].children.push_back(g);
+    group_of[v] = g;
+    P->defer_group[v] = g;
+    P->adj_term_offset[v] = off;
+    off = align_up(off + (8ull << P->nodes[v].rank), 256);
+  }
+  P->adj_bytes = off;
+  for (const RevOp& r : P->rev) P->rev_group_of.push_back(group_of[P->steps[r.step].out]);
+  std::vector<std::pair<int, GradEntry>> tagged;  // (group of the op writing the leaf's adjoint, entry)
   for (int i = 0; i < n; ++i) {
     if (gate_of_leaf[i] < 0) continue;
     const PlanNode& nd = P->nodes[i];
@@ -989,6 +1033,14 @@ static void build_reverse(mitnc_plan* P, const mitnc_network* net, const mitnc_p
       e.slice_bit[j] = (int8_t)nd.slice_bits[j].first;
       e.slice_pos[j] = (int8_t)nd.slice_bits[j].second;
     }
+    tagged.push_back({group_of[parent[i]], e});
+  }
+  std::stable_sort(tagged.begin(), tagged.end(),
+                   [](const std::pair<int, GradEntry>& x, const std::pair<int, GradEntry>& y) { return x.first < y.first; });
+  for (auto& [g, e] : tagged) {
+    mitnc_plan::RevGroup& G = P->rev_groups[g];
+    if (G.grad_count == 0) G.grad_first = (uint32_t)P->gtab.size();
+    G.grad_count++;
     P->gtab.push_back(e);
   }
 }
@@ -1019,43 +1071,51 @@ static void build_reverse_levels(mitnc_plan* P) {
     if ((int)P->rev_levels.size() <= lv) P->rev_levels.resize(lv + 1);
     if (!batched_small(r)) P->rev_levels[lv].big.push_back((int)i);
   }
-  for (size_t lv = 0; lv < P->rev_levels.size(); ++lv) {
-    mitnc_plan::RevLevel& L = P->rev_levels[lv];
-    L.small_first = (uint32_t)P->rblock.size();
-    for (size_t i = 0; i < P->rev.size(); ++i) {
-      const RevOp& r = P->rev[i];
-      if (!batched_small(r) || P->rev_level_of[i] != (int)lv) continue;
-      SmallRevOp e;
-      std::memset(&e, 0, sizeof(e));
-      e.d = r.d;
-      e.d.A = e.d.B = nullptr;
-      e.d.C = nullptr;
-      const uint64_t adj_in = P->off_adj + P->adj_offset[P->steps[r.step].out];
-      const PlanNode& o = P->nodes[r.other];
-      uint64_t other = o.offset;
-      if (o.region == 1) other += P->off_persist;
-      else if (o.region == 2) other += P->off_arena;
-      else if (o.region != 0) fail(MITNC_INVALID_ARG, "reverse operand outside the workspace");
-      e.a_off = r.adj_is_a ? adj_in : other;
-      e.b_off = r.adj_is_a ? other : adj_in;
-      e.c_off = P->off_adj + P->adj_offset[r.target];
-      if (o.region == 0 && !o.slice_bits.empty()) {
-        if (o.slice_bits.size() > 8) fail(MITNC_UNSUPPORTED, "leaf with more than 8 sliced indices");
-        e.sl_which = r.adj_is_a ? 2 : 1;
-        e.sl_n = (int8_t)o.slice_bits.size();
-        for (size_t j = 0; j < o.slice_bits.size(); ++j) {
-          e.sl_bit[j] = (int8_t)o.slice_bits[j].first;
-          e.sl_pos[j] = (int8_t)o.slice_bits[j].second;
+  // Where an op writes: a deferral root's adjoint goes to its term buffer.
+  auto write_off = [&](int target) {
+    return P->off_adj + (P->defer_group[target] >= 0 ? P->adj_term_offset[target] : P->adj_offset[target]);
+  };
+  for (mitnc_plan::RevGroup& G : P->rev_groups) G.levels.assign(P->rev_levels.size(), mitnc_plan::RevLevel{});
+  for (size_t gi = 0; gi < P->rev_groups.size(); ++gi)
+    for (size_t lv = 0; lv < P->rev_levels.size(); ++lv) {
+      mitnc_plan::RevLevel& L = P->rev_groups[gi].levels[lv];
+      for (int i : P->rev_levels[lv].big)
+        if (P->rev_group_of[i] == (int)gi) L.big.push_back(i);
+      L.small_first = (uint32_t)P->rblock.size();
+      for (size_t i = 0; i < P->rev.size(); ++i) {
+        const RevOp& r = P->rev[i];
+        if (!batched_small(r) || P->rev_level_of[i] != (int)lv || P->rev_group_of[i] != (int)gi) continue;
+        SmallRevOp e;
+        std::memset(&e, 0, sizeof(e));
+        e.d = r.d;
+        e.d.A = e.d.B = nullptr;
+        e.d.C = nullptr;
+        const uint64_t adj_in = P->off_adj + P->adj_offset[P->steps[r.step].out];
+        const PlanNode& o = P->nodes[r.other];
+        uint64_t other = o.offset;
+        if (o.region == 1) other += P->off_persist;
+        else if (o.region == 2) other += P->off_arena;
+        else if (o.region != 0) fail(MITNC_INVALID_ARG, "reverse operand outside the workspace");
+        e.a_off = r.adj_is_a ? adj_in : other;
+        e.b_off = r.adj_is_a ? other : adj_in;
+        e.c_off = write_off(r.target);
+        if (o.region == 0 && !o.slice_bits.empty()) {
+          if (o.slice_bits.size() > 8) fail(MITNC_UNSUPPORTED, "leaf with more than 8 sliced indices");
+          e.sl_which = r.adj_is_a ? 2 : 1;
+          e.sl_n = (int8_t)o.slice_bits.size();
+          for (size_t j = 0; j < o.slice_bits.size(); ++j) {
+            e.sl_bit[j] = (int8_t)o.slice_bits[j].first;
+            e.sl_pos[j] = (int8_t)o.slice_bits[j].second;
+          }
         }
+        const uint64_t c_elems = 1ull << (r.d.mb + r.d.nb + r.d.bb);
+        e.block0 = (uint32_t)P->rblock.size();
+        const uint32_t idx = (uint32_t)P->rtab.size();
+        for (uint64_t b = 0; b < (c_elems + 255) / 256; ++b) P->rblock.push_back(idx);
+        P->rtab.push_back(e);
       }
-      const uint64_t c_elems = 1ull << (r.d.mb + r.d.nb + r.d.bb);
-      e.block0 = (uint32_t)P->rblock.size();
-      const uint32_t idx = (uint32_t)P->rtab.size();
-      for (uint64_t b = 0; b < (c_elems + 255) / 256; ++b) P->rblock.push_back(idx);
-      P->rtab.push_back(e);
+      L.small_blocks = (uint32_t)P->rblock.size() - L.small_first;
     }
-    L.small_blocks = (uint32_t)P->rblock.size() - L.small_first;
-  }
 }
 
 mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {

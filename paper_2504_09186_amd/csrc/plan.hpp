@@ -112,6 +112,24 @@ struct mitnc_plan {
   };
   std::vector<RevLevel> rev_levels;
   std::vector<int> rev_level_of;        // level of each rev entry
+  // Grouped reverse pass: the reverse ops below a deferral root d (a kept
+  // node whose sliced bits are all at or above lo(d)) are linear in adj(d)
+  // and depend on the slice only through those bits, so adj(d) is summed
+  // over each run of 2^lo(d) consecutive slices (the op writing it writes a
+  // term buffer, added into the accumulator at adj_offset[d]) and the ops of
+  // d's group run once per run.  Group 0 holds the ops above every deferral
+  // root and runs for every slice.
+  struct RevGroup {
+    int root = -1;                 // deferral root node (-1: group 0)
+    int lo = 0;                    // runs when the slice id is a multiple of 2^lo, or the range's first
+    std::vector<RevLevel> levels;  // big ops and SMALL block-table ranges per reverse level
+    std::vector<int> children;     // groups whose root's adjoint term this group writes
+    uint32_t grad_first = 0, grad_count = 0;  // entries of gtab
+  };
+  std::vector<RevGroup> rev_groups;
+  std::vector<uint64_t> adj_term_offset;  // per deferral root: its term buffer (offset in the adjoint region)
+  std::vector<int> defer_group;           // per node: its group if it is a deferral root, else -1
+  std::vector<int> rev_group_of;          // per rev entry: its group
   std::vector<mitnc::SmallRevOp> rtab;  // SMALL ops, uploaded at off_rtab
   std::vector<uint32_t> rblock;         // workgroup -> rtab entry, uploaded at off_rblock
   uint64_t off_rtab = 0, off_rblock = 0;

@@ -36,10 +36,10 @@ def _setup(rows, cols, cycles, nbits, nsl, seed, batched=True, open_q=()):
     return c, spec, bits, net, onet, sliced
 
 
-def _gpu_grad(net, c):
+def _gpu_grad(net, c, defer=0):
     import torch
     from paper_2504_09186_amd import tnc
-    plan = tnc.Plan(net, differentiable=True)
+    plan = tnc.Plan(net, differentiable=True, reverse_defer=defer)
     plan.upload()
     mats = np.stack([g.matrix for g in c.gates if g.arity == 1])
     gates = torch.tensor(mats, dtype=torch.complex128, requires_grad=True)
@@ -50,13 +50,19 @@ def _gpu_grad(net, c):
     return amps.detach().cpu().numpy(), gates.grad.numpy(), plan, float(loss)
 
 
+@pytest.mark.parametrize("defer", [0, 1, -1])
 @pytest.mark.parametrize("rows,cols,cycles,nbits,nsl,seed", [
     (2, 3, 5, 8, 0, 1), (3, 3, 6, 16, 2, 2), (3, 4, 8, 4, 3, 3), (2, 4, 6, 32, 1, 4)])
-def test_gradient_matches_oracle(rows, cols, cycles, nbits, nsl, seed):
+def test_gradient_matches_oracle(rows, cols, cycles, nbits, nsl, seed, defer):
+    """defer: grouped reverse pass at the kept nodes the cost model picks
+    (0), at every kept node (1: adjoints summed over runs of slices, nested
+    groups), or not at all (-1)."""
     require_gpu()
     c, spec, bits, net, onet, sliced = _setup(rows, cols, cycles, nbits, nsl, seed)
-    print(f"gradient case {rows}x{cols}x{cycles}, {nbits} bitstrings, sliced {sliced}", flush=True)
-    amps, grad, plan, _ = _gpu_grad(net, c)
+    print(f"gradient case {rows}x{cols}x{cycles}, {nbits} bitstrings, sliced {sliced}, defer {defer}", flush=True)
+    amps, grad, plan, _ = _gpu_grad(net, c, defer)
+    if defer == 1 and nsl >= 2:
+        assert plan.stats.n_reverse_groups > 0
     ref_amps = oracle.sv_amplitudes(c, spec, bits).reshape(-1)
     assert oracle.rel_l2(amps, ref_amps) < 1e-5
     opath = oracle.greedy_path(onet)
@@ -125,15 +131,19 @@ def test_gradient_finite_differences_gpu():
     assert np.linalg.norm(fd - gv) <= 1e-3 * np.linalg.norm(gv)
 
 
-def test_gradient_20_qubits_sliced():
+@pytest.mark.parametrize("defer", [0, 1])
+def test_gradient_20_qubits_sliced(defer):
     """A 4x5 lattice (20 qubits), 10 cycles, 16 random bitstrings as a batch
     index, 4 sliced indices (16 slices, each recomputed by the backward):
     GPU gradient of L = sum log|a|^2 against the oracle's reverse-mode
-    gradient on the same slicing, relative L2 <= 1e-4."""
+    gradient on the same slicing, relative L2 <= 1e-4; with the grouped
+    reverse pass where the cost model picks it and at every kept node."""
     require_gpu()
     c, spec, bits, net, onet, sliced = _setup(4, 5, 10, 16, 4, 31)
-    print(f"gradient case 4x5x10, 16 bitstrings, sliced {sliced}", flush=True)
-    amps, grad, plan, _ = _gpu_grad(net, c)
+    print(f"gradient case 4x5x10, 16 bitstrings, sliced {sliced}, defer {defer}", flush=True)
+    amps, grad, plan, _ = _gpu_grad(net, c, defer)
+    if defer == 1:
+        assert plan.stats.n_reverse_groups > 0
     assert plan.n_slices == 16
     opath = oracle.greedy_path(onet)
     ref_amps = oracle.contract_sliced(onet, opath, sliced).reshape(-1)
