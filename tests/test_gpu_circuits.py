@@ -214,3 +214,54 @@ def _run_opts(net, **kw):
     plan.execute(acc)
     torch.cuda.synchronize()
     return acc.cpu().numpy(), plan
+
+
+@pytest.mark.parametrize("case", ["demote", "merge"])
+def test_cache_budget_demotion(case):
+    """Shared-prefix reuse under a byte budget for kept tensors (Sec. III-B
+    dynamic tuning).  "demote": with a budget of 4 KiB the largest kept nodes
+    are demoted (recomputed as often as their parent: more flops per slice);
+    "merge": a plan whose four sliced bits are all merged keeps its merge
+    accumulators under the same budget.  The sums over all slices and over
+    two ranges (one, when a merge group spans all slices) equal the state
+    vector."""
+    require_gpu()
+    import torch
+    from helpers import nested_chain
+    from paper_2504_09186_amd import tnc
+    if case == "demote":
+        c = synth.lattice_circuit(4, 4, 10, seed=7)
+        spec = synth.output_spec(16, [13, 14, 15], seed=8)
+        net = _lib_net(c, spec)
+        net.path_search(seed=9, trials=8, max_log2=11, min_sliced=5, max_sliced=5)
+        kw = {}
+    else:
+        c = synth.lattice_circuit(4, 4, 10, seed=5)
+        spec = synth.output_spec(16, [15], seed=6)
+        onet = oracle.build_network(c, spec)
+        path = oracle.greedy_path(onet)
+        net = _lib_net(c, spec)
+        net.set_path(path)
+        net.set_slicing(nested_chain(onet, path, 4)[::-1])
+        kw = {"merge_bits": 4, "no_hoist": True}
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    full = tnc.Plan(net, **kw)
+    plan = tnc.Plan(net, cache_budget_bytes=4096, **kw)
+    if case == "demote":
+        assert plan.stats.flops_reused_slice > full.stats.flops_reused_slice
+    else:
+        assert plan.stats.n_merged == 4
+    print(f"cache budget, {case}: flops/slice {full.stats.flops_reused_slice:.3e} -> "
+          f"{plan.stats.flops_reused_slice:.3e}", flush=True)
+    plan.upload()
+    acc = plan.new_result()
+    plan.execute(acc)
+    # two ranges, each a whole number of merge groups when there are merges
+    half = max(1 << plan.stats.merge_align_bits, plan.n_slices // 2)
+    acc2 = plan.new_result()
+    for s0, s1 in ((0, half), (half, plan.n_slices)):
+        if s0 < s1:
+            plan.execute(acc2, s0, s1)
+    torch.cuda.synchronize()
+    for got in (acc.cpu().numpy(), acc2.cpu().numpy()):
+        assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)
