@@ -55,6 +55,8 @@ GOLDEN4 = os.path.join(ROOT, "tests", "golden", "config4_subslices.json")
 # trials, ranked by the flops of all slices dealt in 256-slice shares, then
 # branch exchange; its plans merge the 8 inner slice-id bits where nested).
 PATH4 = os.path.join(ROOT, "paper_2504_09186_amd", "paths", "rqc_7x8_20.json")
+# The same network with fewer, larger slices (1024 trials; 44 sliced indices).
+PATH4_S44 = os.path.join(ROOT, "paper_2504_09186_amd", "paths", "rqc_7x8_20_s44.json")
 WORKLOAD4 = "rqc-7x8-20cyc-4096amp-256slice-share"
 WORKLOAD2 = "rqc-5x6-14cyc-64amp-256slices"
 
@@ -241,6 +243,34 @@ def grad_config3(steps, n_slices=32):
     return out
 
 
+def alt_path_timing(c, spec, steps, warmup):
+    """Complex64 share of the 56-qubit network on the stored 44-index path:
+    slices/s and the projected time of all its slices on one GPU, against
+    which the headline path's projection compares (slices/s alone does not:
+    slice sizes differ between paths)."""
+    import torch
+
+    from paper_2504_09186_amd import tnc
+    stored = load_json(PATH4_S44)
+    if stored is None:
+        return None
+    net = tnc.Network(c, spec)
+    net.set_path([tuple(x) for x in stored["path"]])
+    net.set_slicing(stored["slicing"])
+    plan = tnc.Plan(net, precision=0, merge_bits=stored.get("merge_bits", 0))
+    plan.upload()
+    r, _ = run_form(plan, steps, warmup, "c64", WORKLOAD4, 0, 256)
+    S = plan.stats.n_sliced
+    out = {"path": "stored: recursive bisection, 1024 trials, then branch exchange", "n_sliced": S,
+           "value": r["value"], "unit": "slices/s", "ms_per_step": r["ms_per_step"],
+           "job_seconds_projected": r["ms_per_step"] * 1e-3 * 2.0 ** (S - 8),
+           "job_flops": r["flops_per_step"] * 2.0 ** (S - 8), "roofline": r["roofline"],
+           "kernel_ms_by_class": r["kernel_ms_by_class"]}
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def subslice_check(c, spec, g, precision):
     """The oracle's stored sub-slices (its own slicing of the same network),
     recomputed with the library's path for that slicing."""
@@ -416,12 +446,13 @@ def spindle_report(net, merge_bits, s0, s1, before=None):
 def config2_net(trials):
     """The 5x6-qubit network and its plan search: recursive-bisection and
     greedy trials ranked by the flops of one 256-slice share with the
-    merge of the 8 sliced bits, then branch exchange (Sec. III-B)."""
+    merge of the 8 sliced bits plus 2e8 flops per step launch (the
+    workload is bound by launches), then branch exchange (Sec. III-B)."""
     from paper_2504_09186_amd import tnc
     c, spec = workload2()
     net = tnc.Network(c, spec)
     net.path_search(seed=3001, trials=trials, max_log2=26, min_sliced=8, max_sliced=8, method=2, window_bits=8,
-                    merge_bits=8, branch_exchange=True)
+                    merge_bits=8, branch_exchange=True, launch_cost_flops=2e8)
     return c, spec, net
 
 
@@ -635,6 +666,7 @@ def main():
                    "path_search_s": search_s, "path": path_source, "merge_bits": merge_bits,
                    "n_merged": st.n_merged,
                    "job_flops": r64["flops_per_step"] * 2.0 ** (st.n_sliced - 8),
+                   "job_seconds_projected": r64["ms_per_step"] * 1e-3 * 2.0 ** (st.n_sliced - 8),
                    "precision": "complex64, FP32 MFMA (3M), FP64 cross-slice sum"},
         "tflops": r64["tflops"],
         "hbm_gbs": r64["hbm_gbs"], "amp_error": r64.get("amp_error"),
@@ -646,6 +678,7 @@ def main():
                                     "scaling, FP64 cross-slice sum"),
     }
     if not args.no_extras:
+        out["alt_path"] = alt_path_timing(c, spec, args.steps, args.warmup)
         out["config2"] = run_config2(args.steps, args.warmup, 64)
         out["grad"] = grad_timing(args.steps)
         # the same with intermediates capped at 2^22 entries: 16 slices, each

@@ -118,6 +118,11 @@ typedef struct mitnc_search_opts {
                            slice-id bits (mitnc_plan_opts.merge_bits; 0..12) */
   int32_t branch_exchange; /* 1: after the search, reorder absorptions
                               (mitnc_branch_exchange) with the same ranking */
+  double launch_cost_flops; /* methods 1 and 2 (and branch exchange): added to
+                               the ranking for every step computation, in
+                               flops (0: flops only); a stand-in for the
+                               fixed cost of a kernel launch, which decides
+                               workloads of many small steps */
 } mitnc_search_opts;
 int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* opts);
 
@@ -161,13 +166,14 @@ int32_t mitnc_index_overhead(const mitnc_network* net, int64_t label, double* ov
  * end.  Local search over such adjacent pairs of the current path (up to
  * `passes` sweeps), keeping each swap that lowers the flops of all slices
  * with pre-lifetime reuse and the post-lifetime merge of the innermost
- * merge_bits bits (ranges of 2^window_bits slices as in mitnc_search_opts)
+ * merge_bits bits (ranges of 2^window_bits slices as in mitnc_search_opts),
+ * plus launch_cost_flops per step computation (as in mitnc_search_opts),
  * and keeps every intermediate within 2^max_log2_elems entries; replaces
  * the path, keeps the slicing.  flops_before / flops_after (either may be
  * NULL) receive that count for the old and new path.  Host only.  Errors:
  * INVALID_ARG (no path, bad argument). */
 int32_t mitnc_branch_exchange(mitnc_network* net, int32_t window_bits, int32_t merge_bits, int32_t max_log2_elems,
-                              int32_t passes, double* flops_before, double* flops_after);
+                              int32_t passes, double launch_cost_flops, double* flops_before, double* flops_after);
 
 /* Plan options.  precision: MITNC_C64 (complex64 storage, FP32 arithmetic on
  * MFMA) or MITNC_CF16 / MITNC_CBF16 (each tensor stored as complex FP16 or

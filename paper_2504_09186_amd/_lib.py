@@ -34,7 +34,7 @@ class mitnc_search_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("trials", C.c_int32), ("max_log2_elems", C.c_int32),
                 ("min_sliced", C.c_int32), ("max_sliced", C.c_int32), ("keep_slicing", C.c_int32),
                 ("method", C.c_int32), ("window_bits", C.c_int32), ("merge_bits", C.c_int32),
-                ("branch_exchange", C.c_int32)]
+                ("branch_exchange", C.c_int32), ("launch_cost_flops", C.c_double)]
 
 
 class mitnc_plan_opts(C.Structure):
@@ -89,7 +89,7 @@ _SIGS = {
     "mitnc_set_slicing": [_VP, _I32, C.POINTER(C.c_int64)],
     "mitnc_slice_greedy": [_VP, _I32, _I32, _I32, C.POINTER(_I32), C.POINTER(C.c_int64)],
     "mitnc_index_overhead": [_VP, C.c_int64, C.POINTER(C.c_double)],
-    "mitnc_branch_exchange": [_VP, _I32, _I32, _I32, _I32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+    "mitnc_branch_exchange": [_VP, _I32, _I32, _I32, _I32, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)],
     "mitnc_plan_create": [_VP, C.POINTER(mitnc_plan_opts), C.POINTER(_VP)],
     "mitnc_plan_query": [_VP, C.POINTER(mitnc_plan_stats)],
     "mitnc_plan_steps": [_VP, C.POINTER(C.c_double)],

@@ -206,6 +206,7 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
     if (method < 0 || method > 2) fail(MITNC_INVALID_ARG, "unknown search method");
     if (o->window_bits < 0 || o->window_bits > 62) fail(MITNC_INVALID_ARG, "window_bits out of range");
     if (o->merge_bits < 0 || o->merge_bits > 12) fail(MITNC_INVALID_ARG, "merge_bits out of range (0..12)");
+    if (!(o->launch_cost_flops >= 0)) fail(MITNC_INVALID_ARG, "launch_cost_flops must be >= 0");
     const double imbs[] = {0.05, 0.1, 0.2, 0.3, 0.5};
     const int cutoffs[] = {4, 6, 8, 10, 12};
     const double exts[] = {0.0, 0.25, 0.5, 1.0};
@@ -288,7 +289,7 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
         std::vector<int> extra(sl.begin() + fixed_list.size(), sl.end());
         std::vector<int> ord = fixed_list;
         for (int x : order_slices(sn, p, extra)) ord.push_back(x);
-        f = reuse_total_flops(sn, p, ord, o->window_bits, o->merge_bits);
+        f = reuse_total_flops(sn, p, ord, o->window_bits, o->merge_bits, o->launch_cost_flops);
       } else {
         f = sym_total_flops(sym_run(sn, p, m)) * std::ldexp(1.0, (int)sl.size());
       }
@@ -340,7 +341,8 @@ int32_t mitnc_path_search(mitnc_network* net, const mitnc_search_opts* o) {
       std::vector<char> m(sn.n_labels, 0);
       for (int x : ord) m[x] = 1;
       const int cap = std::max<int>(o->max_log2_elems, sym_max_bits(sn, sym_run(sn, net->path, m), m));
-      net->path = branch_exchange(sn, net->path, ord, o->window_bits, o->merge_bits, cap, 8, nullptr, nullptr);
+      net->path = branch_exchange(sn, net->path, ord, o->window_bits, o->merge_bits, cap, 8, nullptr, nullptr,
+                                  o->launch_cost_flops);
     }
   });
 }
@@ -411,17 +413,19 @@ int32_t mitnc_slice_greedy(mitnc_network* net, int32_t max_log2_elems, int32_t m
 }
 
 int32_t mitnc_branch_exchange(mitnc_network* net, int32_t window_bits, int32_t merge_bits, int32_t max_log2_elems,
-                              int32_t passes, double* flops_before, double* flops_after) {
+                              int32_t passes, double launch_cost_flops, double* flops_before, double* flops_after) {
   return guarded([&] {
     if (!net) fail(MITNC_INVALID_ARG, "null network");
     if (net->path.empty()) fail(MITNC_INVALID_ARG, "no path");
-    if (window_bits < 0 || window_bits > 62 || merge_bits < 0 || merge_bits > 12 || passes < 0 || max_log2_elems < 0)
+    if (window_bits < 0 || window_bits > 62 || merge_bits < 0 || merge_bits > 12 || passes < 0 || max_log2_elems < 0 ||
+        !(launch_cost_flops >= 0))
       fail(MITNC_INVALID_ARG, "bad argument");
     SymNet sn = make_symnet(net->leaves, net->output_lsb);
     std::vector<int> ord;
     for (auto x : net->sliced) ord.push_back(sn.dense.at(x));
     double b = 0, a = 0;
-    net->path = branch_exchange(sn, net->path, ord, window_bits, merge_bits, max_log2_elems, passes, &b, &a);
+    net->path = branch_exchange(sn, net->path, ord, window_bits, merge_bits, max_log2_elems, passes, &b, &a,
+                                launch_cost_flops);
     if (flops_before) *flops_before = b;
     if (flops_after) *flops_after = a;
   });

@@ -66,12 +66,12 @@ std::vector<int> greedy_slices(const SymNet& sn, const Path& path, int cap, int 
 std::vector<int> slice_reconf(const SymNet& sn, Path& path, const std::vector<int>& fixed, int cap, int min_sliced,
                               int max_sliced, int every, bool* ok);
 double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered, int window_bits = 0,
-                         int merge_bits = 0);
+                         int merge_bits = 0, double launch_cost = 0);
 // Branch exchange (merge.cpp): local reordering of absorptions on chains,
 // see the definition.  Returns the new path; *before / *after receive the
 // reuse_total_flops of the old and new path.
 Path branch_exchange(const SymNet& sn, const Path& path, const std::vector<int>& ordered, int window_bits,
-                     int merge_bits, int cap_bits, int passes, double* before, double* after);
+                     int merge_bits, int cap_bits, int passes, double* before, double* after, double launch_cost = 0);
 
 // Post-lifetime merge (merge.cpp).  Tree nodes 0..n-1 are leaves, then step
 // outputs in path order (children before parents, the root last); kids[u] is

@@ -126,12 +126,12 @@ double merge_runs(uint64_t elig, uint64_t emask, uint64_t bmask, int S, int W) {
 }
 
 Path branch_exchange(const SymNet& sn, const Path& path0, const std::vector<int>& ordered, int window_bits,
-                     int merge_bits, int cap_bits, int passes, double* before, double* after) {
+                     int merge_bits, int cap_bits, int passes, double* before, double* after, double launch_cost) {
   Path path = path0;
   const int n = (int)sn.leaf.size();
   std::vector<char> sl(sn.n_labels, 0);
   for (int x : ordered) sl[x] = 1;
-  double best = reuse_total_flops(sn, path, ordered, window_bits, merge_bits);
+  double best = reuse_total_flops(sn, path, ordered, window_bits, merge_bits, launch_cost);
   if (before) *before = best;
   for (int pass = 0; pass < passes; ++pass) {
     bool improved = false;
@@ -153,7 +153,7 @@ Path branch_exchange(const SymNet& sn, const Path& path0, const std::vector<int>
         else t2.first = old_b1;
         const auto st = sym_run(sn, trial, sl);
         if (sym_max_bits(sn, st, sl) > cap_bits) continue;
-        const double f = reuse_total_flops(sn, trial, ordered, window_bits, merge_bits);
+        const double f = reuse_total_flops(sn, trial, ordered, window_bits, merge_bits, launch_cost);
         if (f < best * (1 - 1e-12)) {
           best = f;
           path = std::move(trial);

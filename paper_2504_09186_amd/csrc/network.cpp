@@ -332,9 +332,11 @@ std::vector<int> slice_reconf(const SymNet& sn, Path& path, const std::vector<in
 // `ordered` lists the sliced indices outer -> inner (the last is bit 0).
 // With merge_bits > 0 the innermost merge_bits bits (within the window) may
 // also be merged after their lifetime ends (post-lifetime reuse; the rule of
-// merge_sets), which the counts then include.
+// merge_sets), which the counts then include.  launch_cost (flops) is added
+// for every step computation, a stand-in for the fixed cost of a kernel
+// launch.
 double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<int>& ordered, int window_bits,
-                         int merge_bits) {
+                         int merge_bits, double launch_cost) {
   const int S = (int)ordered.size();
   std::vector<char> sl(sn.n_labels, 0);
   std::vector<int> bit(sn.n_labels, -1);
@@ -362,10 +364,10 @@ double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<i
     const MergeSets m = merge_sets(kids, dep, std::vector<char>(kids.size(), 0), mb);
     double f = 0;
     for (size_t s = 0; s + 1 < path.size(); ++s)
-      f += st[s].flops * merge_runs(m.elig[n + s], m.emask[n + s], m.bmask[n + s], S, W);
+      f += (st[s].flops + launch_cost) * merge_runs(m.elig[n + s], m.emask[n + s], m.bmask[n + s], S, W);
     // the root adds every slice's value into the result: no accumulator of its own
     const size_t r = path.size() - 1;
-    f += st[r].flops * merge_runs(m.elig[n + r], m.emask[n + r], 0, S, W);
+    f += (st[r].flops + launch_cost) * merge_runs(m.elig[n + r], m.emask[n + r], 0, S, W);
     return f;
   }
   double f = 0;
@@ -377,7 +379,7 @@ double reuse_total_flops(const SymNet& sn, const Path& path, const std::vector<i
       runs = std::ldexp(lo >= W ? 1.0 : std::ldexp(1.0, W - lo), S - W);
     else
       runs = d ? std::ldexp(1.0, S - lo) : 1.0;
-    f += st[s].flops * runs;
+    f += (st[s].flops + launch_cost) * runs;
   }
   return f;
 }

@@ -6,7 +6,12 @@ its run does not repeat a minutes-long search.  Each file holds the SSA path
 pairs and the sliced labels (outer to inner) of one network, with the search
 parameters and the resulting costs.
 
-Usage: python -m paper_2504_09186_amd.paths.make_paths [--trials N]
+Usage: python -m paper_2504_09186_amd.paths.make_paths [--trials N] [--out FILE]
+
+rqc_7x8_20.json: 256 trials, launch cost 5e8 (48 sliced indices: more,
+cheaper slices); rqc_7x8_20_s44.json: --trials 1024 --launch-cost 0 (44
+sliced indices: the whole job takes about a tenth of the flops, each slice
+more).
 """
 from __future__ import annotations
 
@@ -22,6 +27,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 # 7x8 lattice, 20 cycles, last 12 qubits open: the headline workload.
 RQC_7X8_20 = dict(rows=7, cols=8, cycles=20, circuit_seed=1004, open_qubits=list(range(44, 56)), spec_seed=2004,
                   max_log2=30, min_sliced=8, max_sliced=62, window_bits=8, merge_bits=8)
+# flops charged per step launch in the ranking (about 5 us at 100 TFLOP/s)
+LAUNCH_COST = 5e8
 
 
 def share_flops(plan, window_bits):
@@ -34,10 +41,10 @@ def share_flops(plan, window_bits):
     return float((plan.steps()[:, 6] * runs).sum())
 
 
-def make_rqc_7x8_20(trials: int, seed: int) -> dict:
-    """Recursive-bisection search ranked by the flops of 256-slice shares,
-    then branch exchange ranked the same way with the merge of the 8 inner
-    slice-id bits."""
+def make_rqc_7x8_20(trials: int, seed: int, launch_cost: float = LAUNCH_COST) -> dict:
+    """Recursive-bisection search ranked by the flops of 256-slice shares
+    with the merge of the 8 inner slice-id bits and launch_cost flops per
+    step launch, then branch exchange ranked the same way."""
     sys.path.insert(0, ROOT)
     import synth
     from paper_2504_09186_amd import tnc
@@ -47,19 +54,20 @@ def make_rqc_7x8_20(trials: int, seed: int) -> dict:
     net = tnc.Network(c, spec)
     t0 = time.perf_counter()
     net.path_search(seed=seed, trials=trials, max_log2=w["max_log2"], min_sliced=w["min_sliced"],
-                    max_sliced=w["max_sliced"], method=1, window_bits=w["window_bits"])
+                    max_sliced=w["max_sliced"], method=1, window_bits=w["window_bits"],
+                    merge_bits=w["merge_bits"] if launch_cost else 0, launch_cost_flops=launch_cost)
     search_s = time.perf_counter() - t0
     sf_search = share_flops(tnc.Plan(net, precision=0), w["window_bits"])
     t0 = time.perf_counter()
     before, after = net.branch_exchange(window_bits=w["window_bits"], merge_bits=w["merge_bits"],
-                                        max_log2=w["max_log2"], passes=8)
+                                        max_log2=w["max_log2"], passes=8, launch_cost_flops=launch_cost)
     exchange_s = time.perf_counter() - t0
     plan = tnc.Plan(net, precision=0, merge_bits=w["merge_bits"])
     sl = [int(x) for x in net.slicing()]
     sf = share_flops(plan, w["window_bits"])
     return dict(workload=w, n_leaves=net.n_leaves,
                 search=dict(method=1, trials=trials, seed=seed, seconds=round(search_s, 1),
-                            share_flops=sf_search),
+                            share_flops=sf_search, launch_cost_flops=launch_cost),
                 branch_exchange=dict(passes=8, seconds=round(exchange_s, 1), job_flops_before=before,
                                      job_flops_after=after),
                 path=[[int(a), int(b)] for a, b in net.path()], slicing=sl, n_sliced=len(sl),
@@ -72,9 +80,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trials", type=int, default=256)
     ap.add_argument("--seed", type=int, default=3004)
+    ap.add_argument("--out", default="rqc_7x8_20.json")
+    ap.add_argument("--launch-cost", type=float, default=LAUNCH_COST)
     args = ap.parse_args()
-    out = make_rqc_7x8_20(args.trials, args.seed)
-    path = os.path.join(HERE, "rqc_7x8_20.json")
+    out = make_rqc_7x8_20(args.trials, args.seed, args.launch_cost)
+    path = os.path.join(HERE, os.path.basename(args.out))
     with open(path, "w") as f:
         json.dump(out, f, separators=(",", ":"))
     print(f"wrote {path}: {out['n_sliced']} sliced, share flops {out['search']['share_flops']:.3e} after the "

@@ -62,24 +62,27 @@ class Network:
 
     def path_search(self, seed: int = 0, trials: int = 32, max_log2: int = 30, min_sliced: int = 0,
                     max_sliced: int = 40, keep_slicing: bool = False, method: int = 0,
-                    window_bits: int = 0, merge_bits: int = 0, branch_exchange: bool = False) -> None:
+                    window_bits: int = 0, merge_bits: int = 0, branch_exchange: bool = False,
+                    launch_cost_flops: float = 0.0) -> None:
         """Path and slicing search (method 0 greedy, 1 recursive bisection, 2
         both).  Methods 1 and 2 rank trials by the reuse-aware flops of all
         slices, run in one sequence (window_bits 0) or dealt in aligned
         ranges of 2^window_bits slices that each start cold, counting the
         post-lifetime merge of the merge_bits innermost bits; branch_exchange
-        then reorders absorptions with the same ranking."""
+        then reorders absorptions with the same ranking; launch_cost_flops
+        adds a per-launch cost to it."""
         o = mitnc_search_opts(seed, trials, max_log2, min_sliced, max_sliced, 1 if keep_slicing else 0, method,
-                              window_bits, merge_bits, 1 if branch_exchange else 0)
+                              window_bits, merge_bits, 1 if branch_exchange else 0, float(launch_cost_flops))
         call("mitnc_path_search", self.h, C.byref(o))
 
     def branch_exchange(self, window_bits: int = 0, merge_bits: int = 0, max_log2: int = 30,
-                        passes: int = 8) -> Tuple[float, float]:
+                        passes: int = 8, launch_cost_flops: float = 0.0) -> Tuple[float, float]:
         """Swaps consecutive absorptions of the current path where that lowers
         the reuse- and merge-aware flops (mitnc_branch_exchange); returns the
         flops before and after."""
         b, a = C.c_double(), C.c_double()
-        call("mitnc_branch_exchange", self.h, window_bits, merge_bits, max_log2, passes, C.byref(b), C.byref(a))
+        call("mitnc_branch_exchange", self.h, window_bits, merge_bits, max_log2, passes, C.c_double(launch_cost_flops),
+             C.byref(b), C.byref(a))
         return b.value, a.value
 
     def path(self) -> List[Tuple[int, int]]:

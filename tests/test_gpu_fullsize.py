@@ -39,13 +39,13 @@ def _workload():
 
 def _bench_net():
     """The benchmark's plan search for this network: bisection and greedy
-    trials ranked with the merge of the 8 sliced bits, then branch exchange
-    (its plans merge the 8 bits)."""
+    trials ranked with the merge of the 8 sliced bits and a cost per launch,
+    then branch exchange (its plans merge where lifetimes nest)."""
     from paper_2504_09186_amd import tnc
     c, spec = _workload()
     net = tnc.Network(c, spec)
     net.path_search(seed=3001, trials=64, max_log2=26, min_sliced=8, max_sliced=8, method=2, window_bits=8,
-                    merge_bits=8, branch_exchange=True)
+                    merge_bits=8, branch_exchange=True, launch_cost_flops=2e8)
     return net
 
 
