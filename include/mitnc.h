@@ -341,8 +341,10 @@ int32_t mitnc_plan_reverse_info(const mitnc_plan* plan, int32_t op, mitnc_step_i
 /* Storage and schedule of one node (host only; Sec. III-B reuse levels).
  * ws_offset: byte offset of the node's tensor in the workspace of a
  * complex64 run (UINT64_MAX for the root, which is the caller's result);
- * level: -1 = computed once per slice range, else recomputed for slice s
- * when ctz(s) >= level (Sec. III-B); a slice reads the sub-tensor at
+ * level: the lowest bit of recompute_mask, -1 if it is empty; without
+ * merged bits a node is recomputed for slice s when ctz(s) >= level and
+ * once per slice range for -1 (Sec. III-B; the masks below give the
+ * general rule); a slice reads the sub-tensor at
  * element offset sum_j ((s >> slice_bit[j]) & 1) << slice_pos[j] (sliced
  * leaves and hoisted results; the step that writes a hoisted result writes
  * all 2^full_rank entries). */

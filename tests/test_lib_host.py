@@ -469,3 +469,38 @@ def test_branch_exchange_keeps_result_and_lowers_flops(lib):
         got = PlanReplay(plan).run(0, plan.n_slices)
         assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
     assert improved > 0
+
+
+def test_reverse_groups_structure(lib):
+    """Grouped reverse pass (every kept node deferred): each deferral root is
+    a kept node (its sliced bits all at or above a level its parent's are
+    not), so a nested root has a strictly larger level than the one above
+    it; the plan's workspace grows by one term buffer per root; with
+    deferral off there are no groups."""
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(4, 5, 10, seed=31)
+    bits = synth.random_bitstrings(20, 16, seed=32)
+    spec = np.full(20, -2, dtype=np.int8)
+    net = tnc.Network(c, spec, bits)
+    net.path_search(seed=31, trials=8, max_log2=30)
+    rng = np.random.default_rng(33)
+    onet = oracle.build_network(c, spec, bits)
+    net.set_slicing([int(x) for x in rng.choice(onet.closed_labels(), size=4, replace=False)])
+    off = tnc.Plan(net, differentiable=True, reverse_defer=-1)
+    allg = tnc.Plan(net, differentiable=True, reverse_defer=1)
+    model = tnc.Plan(net, differentiable=True, reverse_defer=0)
+    assert off.stats.n_reverse_groups == 0
+    assert allg.stats.n_reverse_groups > 0
+    assert 0 <= model.stats.n_reverse_groups <= allg.stats.n_reverse_groups
+    assert allg.stats.workspace_bytes > off.stats.workspace_bytes
+    # kept nodes: level strictly above the parent's (level -1 = never recomputed)
+    steps = [allg.step_info(i) for i in range(allg.stats.n_steps)]
+    parent = {}
+    for st in steps:
+        parent[st["a"]] = st["out"]
+        parent[st["b"]] = st["out"]
+    lv = lambda v: 10 ** 6 if allg.node_info(v)["level"] < 0 else allg.node_info(v)["level"]  # noqa: E731
+    kept = [st["out"] for st in steps if not st["root"] and lv(st["out"]) > lv(parent[st["out"]])]
+    assert len(kept) >= allg.stats.n_reverse_groups
+    # the reverse schedule itself (levels, each adjoint written once) is unchanged by grouping
+    assert off.reverse_info() == allg.reverse_info()
