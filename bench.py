@@ -51,9 +51,10 @@ def executed_fraction(label, cls):
 GOLDEN2 = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.json")
 GOLDEN4 = os.path.join(ROOT, "tests", "golden", "config4_subslices.json")
 # Stored path and slicing of the headline network (written by
-# paper_2504_09186_amd/paths/make_paths.py: recursive-bisection search, 256
-# trials, ranked by the flops of all slices dealt in 256-slice shares, then
-# branch exchange; its plans merge the 8 inner slice-id bits where nested).
+# paper_2504_09186_amd/paths/make_paths.py: recursive-bisection search, 1024
+# trials, 48 sliced indices, ranked by the flops of all slices dealt in
+# 256-slice shares, then branch exchange; its plans merge the 8 inner
+# slice-id bits where nested).
 PATH4 = os.path.join(ROOT, "paper_2504_09186_amd", "paths", "rqc_7x8_20.json")
 # The same network with fewer, larger slices (1024 trials; 44 sliced indices).
 PATH4_S44 = os.path.join(ROOT, "paper_2504_09186_amd", "paths", "rqc_7x8_20_s44.json")
@@ -261,7 +262,8 @@ def alt_path_timing(c, spec, steps, warmup):
     plan.upload()
     r, _ = run_form(plan, steps, warmup, "c64", WORKLOAD4, 0, 256)
     S = plan.stats.n_sliced
-    out = {"path": "stored: recursive bisection, 1024 trials, then branch exchange", "n_sliced": S,
+    out = {"path": "stored: recursive bisection, 1024 trials, sliced indices as the 2^30 cap needs, then branch "
+                   "exchange", "n_sliced": S,
            "value": r["value"], "unit": "slices/s", "ms_per_step": r["ms_per_step"],
            "job_seconds_projected": r["ms_per_step"] * 1e-3 * 2.0 ** (S - 8),
            "job_flops": r["flops_per_step"] * 2.0 ** (S - 8), "roofline": r["roofline"],
@@ -611,8 +613,9 @@ def main():
         search_s = stored["search"]["seconds"] + stored.get("branch_exchange", {}).get("seconds", 0.0)
         merge_bits = stored.get("merge_bits", 0)
         before_exchange = stored["search"].get("share_flops")
-        path_source = (f"stored: recursive bisection, {stored['search']['trials']} trials, ranked by job flops "
-                       f"in 256-slice shares, then branch exchange")
+        path_source = (f"stored: recursive bisection, {stored['search']['trials']} trials, "
+                       f"{stored['workload']['min_sliced']}-{stored['workload']['max_sliced']} sliced indices, "
+                       f"ranked by job flops in 256-slice shares (merge, launch cost), then branch exchange")
     else:
         t0 = time.perf_counter()
         net.path_search(seed=3004, trials=args.trials, max_log2=30, min_sliced=8, max_sliced=62, method=1,

@@ -8,10 +8,9 @@ parameters and the resulting costs.
 
 Usage: python -m paper_2504_09186_amd.paths.make_paths [--trials N] [--out FILE]
 
-rqc_7x8_20.json: 256 trials, launch cost 5e8 (48 sliced indices: more,
-cheaper slices); rqc_7x8_20_s44.json: --trials 1024 --launch-cost 0 (44
-sliced indices: the whole job takes about a tenth of the flops, each slice
-more).
+rqc_7x8_20.json: the defaults (1024 trials, exactly 48 sliced indices, launch
+cost 5e8); rqc_7x8_20_s44.json: --trials 1024 --launch-cost 0 --min-sliced 8
+--max-sliced 62 (the size cap decides the count: 44 sliced indices).
 """
 from __future__ import annotations
 
@@ -41,14 +40,18 @@ def share_flops(plan, window_bits):
     return float((plan.steps()[:, 6] * runs).sum())
 
 
-def make_rqc_7x8_20(trials: int, seed: int, launch_cost: float = LAUNCH_COST) -> dict:
-    """Recursive-bisection search ranked by the flops of 256-slice shares
-    with the merge of the 8 inner slice-id bits and launch_cost flops per
-    step launch, then branch exchange ranked the same way."""
+def make_rqc_7x8_20(trials: int, seed: int, launch_cost: float = LAUNCH_COST, min_sliced: int = 48,
+                    max_sliced: int = 48) -> dict:
+    """Recursive-bisection search ranked by the flops of all slices dealt in
+    256-slice shares with the merge of the 8 inner slice-id bits and
+    launch_cost flops per step launch, then branch exchange ranked the same
+    way.  With min_sliced = max_sliced the slicing goes on past the size cap
+    to that many indices (smaller slices: each 256-slice share is a fixed
+    2^-(S-8) of the job)."""
     sys.path.insert(0, ROOT)
     import synth
     from paper_2504_09186_amd import tnc
-    w = RQC_7X8_20
+    w = dict(RQC_7X8_20, min_sliced=min_sliced, max_sliced=max_sliced)
     c = synth.lattice_circuit(w["rows"], w["cols"], w["cycles"], seed=w["circuit_seed"])
     spec = synth.output_spec(w["rows"] * w["cols"], w["open_qubits"], seed=w["spec_seed"])
     net = tnc.Network(c, spec)
@@ -78,12 +81,14 @@ def make_rqc_7x8_20(trials: int, seed: int, launch_cost: float = LAUNCH_COST) ->
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trials", type=int, default=256)
+    ap.add_argument("--trials", type=int, default=1024)
     ap.add_argument("--seed", type=int, default=3004)
     ap.add_argument("--out", default="rqc_7x8_20.json")
     ap.add_argument("--launch-cost", type=float, default=LAUNCH_COST)
+    ap.add_argument("--min-sliced", type=int, default=48)
+    ap.add_argument("--max-sliced", type=int, default=48)
     args = ap.parse_args()
-    out = make_rqc_7x8_20(args.trials, args.seed, args.launch_cost)
+    out = make_rqc_7x8_20(args.trials, args.seed, args.launch_cost, args.min_sliced, args.max_sliced)
     path = os.path.join(HERE, os.path.basename(args.out))
     with open(path, "w") as f:
         json.dump(out, f, separators=(",", ":"))
