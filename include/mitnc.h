@@ -279,6 +279,9 @@ typedef struct mitnc_plan_stats {
   int32_t merge_align_bits;   /* execute ranges must be multiples of 2^this (0: any) */
   uint64_t merged_mask;       /* the merged bits */
   int32_t n_reverse_groups;   /* differentiable plans: deferral roots of the grouped reverse pass */
+  int32_t n_batched_small;    /* forward SMALL steps computed once per slice range that run batched
+                                 (runs of consecutive such steps, one launch per dependency level) */
+  int32_t n_batched_launches; /* the launches those batches take per slice range */
 } mitnc_plan_stats;
 int32_t mitnc_plan_query(const mitnc_plan* plan, mitnc_plan_stats* stats);
 

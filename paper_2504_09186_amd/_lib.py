@@ -54,7 +54,8 @@ class mitnc_plan_stats(C.Structure):
                 ("steps_by_class", C.c_int32 * 8), ("flops_by_class", C.c_double * 8),
                 ("n_grad_gates", C.c_int32), ("n_reverse_ops", C.c_int32),
                 ("flops_reverse_slice", C.c_double), ("n_merged", C.c_int32),
-                ("merge_align_bits", C.c_int32), ("merged_mask", C.c_uint64), ("n_reverse_groups", C.c_int32)]
+                ("merge_align_bits", C.c_int32), ("merged_mask", C.c_uint64), ("n_reverse_groups", C.c_int32),
+                ("n_batched_small", C.c_int32), ("n_batched_launches", C.c_int32)]
 
 
 class mitnc_step_info(C.Structure):

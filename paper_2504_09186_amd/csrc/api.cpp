@@ -52,15 +52,19 @@ static void check_range(const mitnc_plan* P, uint64_t s0, uint64_t s1) {
 }
 
 // Calls f(slice, step, mode) for every launch of slices s0 .. s1-1, in order
-// (mode 1: store / accumulate at the root, 2: merge term).
+// (mode 1: store / accumulate at the root, 2: merge term).  The steps of the
+// range prologue come first (level by level, at slice s0), or not at all
+// with list_prologue false (the caller launches them batched).
 template <class F>
-static void for_each_launch(const mitnc_plan* P, uint64_t s0, uint64_t s1, F&& f) {
+static void for_each_launch(const mitnc_plan* P, uint64_t s0, uint64_t s1, F&& f, bool list_prologue = true) {
   SliceSchedule sched(P->nodes.size());
+  if (list_prologue)
+    for (int i : P->prologue_order) f(s0, (size_t)i, 1);
   for (uint64_t sl = s0; sl < s1; ++sl)
     for (size_t i = 0; i < P->steps.size(); ++i) {
       const PlanNode& O = P->nodes[P->steps[i].out];
       const int mode = sched.decide(P->steps[i].out, O.elig, O.emask, O.bmask, sl);
-      if (mode) f(sl, i, P->steps[i].root ? 1 : mode);
+      if (mode && P->fwd_run_of[i] < 0) f(sl, i, P->steps[i].root ? 1 : mode);
     }
 }
 
@@ -480,6 +484,8 @@ int32_t mitnc_plan_query(const mitnc_plan* P, mitnc_plan_stats* st) {
     st->merge_align_bits = P->merge_align_bits;
     st->merged_mask = P->merged;
     st->n_reverse_groups = P->rev_groups.empty() ? 0 : (int32_t)P->rev_groups.size() - 1;
+    st->n_batched_small = (int32_t)P->prologue_order.size();
+    for (const mitnc_plan::FwdRun& R : P->fwd_runs) st->n_batched_launches += (int32_t)R.levels.size();
     st->n_grad_gates = P->n_grad_gates;
     st->n_reverse_ops = (int32_t)P->rev.size();
     st->flops_reverse_slice = P->rev_flops;
@@ -674,7 +680,15 @@ int32_t mitnc_plan_upload(mitnc_plan* P, void* ws, size_t ws_bytes, void* stream
                                hipMemcpyHostToDevice, s),
                 "reverse block table upload");
     }
+    auto put = [&](uint64_t off, const void* src, size_t bytes) {
+      if (bytes) hip_check(hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, s), "batch table upload");
+    };
+    put(P->off_ftab, P->ftab.data(), sizeof(SmallRevOp) * P->ftab.size());
+    put(P->off_fblock, P->fblock.data(), sizeof(uint32_t) * P->fblock.size());
+    put(P->off_ftab64, P->ftab64.data(), sizeof(SmallRevOp) * P->ftab64.size());
+    put(P->off_fblock64, P->fblock64.data(), sizeof(uint32_t) * P->fblock64.size());
     hip_check(hipStreamSynchronize(s), "leaf upload sync");
+    P->ftab_uploaded = P->ftab_version;
     P->uploaded = true;
     P->valid_slice = -1;
     P->uploaded_ws = ws;
@@ -801,14 +815,55 @@ static void launch_plan_section(mitnc_plan* P, PlanSection& sec, char* base, uin
   hip_check(launch_section(sd, s, e0, e1), "section launch");
 }
 
+// One batched run of forward SMALL steps, level by level.  The table of the
+// plan's precision carries each step's out_scale: it is copied again after
+// the exponents change.
+static void launch_fwd_run(mitnc_plan* P, int run, char* base, hipStream_t s, int prec, bool stats) {
+  const bool c64_of_half = prec == MITNC_C64 && P->opts.precision != MITNC_C64;
+  if (!c64_of_half && P->ftab_uploaded != P->ftab_version) {
+    for (size_t e = 0; e < P->ftab.size(); ++e) P->ftab[e].d.out_scale = P->steps[P->ftab_step[e]].d.out_scale;
+    if (P->opts.precision == MITNC_C64)
+      for (auto& e : P->ftab) e.d.out_scale = 1.f;
+    hip_check(hipMemcpyAsync(base + P->off_ftab, P->ftab.data(), sizeof(SmallRevOp) * P->ftab.size(),
+                             hipMemcpyHostToDevice, s),
+              "batch table refresh");
+    hip_check(hipStreamSynchronize(s), "batch table refresh sync");
+    P->ftab_uploaded = P->ftab_version;
+  }
+  const mitnc_plan::FwdRun& R = P->fwd_runs[run];
+  const auto& levels = c64_of_half ? R.levels64 : R.levels;
+  const SmallRevOp* tab = (const SmallRevOp*)(base + (c64_of_half ? P->off_ftab64 : P->off_ftab));
+  const uint32_t* blk = (const uint32_t*)(base + (c64_of_half ? P->off_fblock64 : P->off_fblock));
+  for (size_t l = 0; l < levels.size(); ++l) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (P->timing) {
+      while (P->ev_pool.size() < 2 * (P->ev_used + 1)) {
+        hipEvent_t e;
+        hip_check(hipEventCreate(&e), "event create");
+        P->ev_pool.push_back((void*)e);
+      }
+      e0 = (hipEvent_t)P->ev_pool[2 * P->ev_used];
+      e1 = (hipEvent_t)P->ev_pool[2 * P->ev_used + 1];
+      P->ev_step.push_back(kFwdEvent - (int)l);
+      P->ev_used++;
+      hip_check(hipEventRecord(e0, s), "event record");
+    }
+    hip_check(launch_small_fwd(prec, tab, blk, levels[l].first, levels[l].blocks, base,
+                               stats ? (float*)(base + P->off_stats) : nullptr, s),
+              "batched small launch");
+    if (P->timing) hip_check(hipEventRecord(e1, s), "event record");
+  }
+}
+
 static void run_slices(mitnc_plan* P, char* base, uint64_t s0, uint64_t s1, double* acc, hipStream_t s, int prec,
                        bool stats) {
+  if (!P->fwd_runs.empty()) launch_fwd_run(P, 0, base, s, prec, stats);  // the range prologue
   for_each_launch(P, s0, s1, [&](uint64_t sl, size_t i, int mode) {
     PlanStep& st = P->steps[i];
     const int sec = P->step_section.empty() ? -1 : P->step_section[i];
     if (sec < 0) launch_plan_step(P, st, base, sl, acc, s, prec, stats, mode == 2);
     else if (P->sections[sec].steps.back() == (int)i) launch_plan_section(P, P->sections[sec], base, sl, s, prec, stats);
-  });
+  }, false);
 }
 
 int32_t mitnc_plan_schedule(const mitnc_plan* P, uint64_t s0, uint64_t s1, int64_t capacity, int64_t* ops_out,
@@ -865,6 +920,7 @@ static void calibrate_range(mitnc_plan* P, char* base, uint64_t s0, uint64_t s1,
     st.d.out_scale = (float)std::ldexp(1.0, ea + eb - ec);
     st.d.acc_scale = 1.0;
   }
+  P->ftab_version++;
   hip_check(hipMemsetAsync(base + P->off_stats, 0, 4 * nst, s), "stats reset");
   P->calibrated = true;
 }
@@ -953,6 +1009,7 @@ int32_t mitnc_plan_exponents(mitnc_plan* P, int32_t* exps_out, const int32_t* ex
         st.d.acc_scale = 1.0;
       }
     }
+    P->ftab_version++;
   });
 }
 
@@ -1232,6 +1289,14 @@ int32_t mitnc_plan_timing_read(mitnc_plan* P, double* ms, double* launches, doub
       float t = 0;
       hip_check(hipEventElapsedTime(&t, e0, e1), "event time");
       const int id = P->ev_step[i];
+      if (id > kMergeEvent && id <= kFwdEvent) {  // batched forward SMALL steps of one level
+        const mitnc_plan::FwdBatch& b = P->fwd_runs[0].levels[kFwdEvent - id];
+        ms[MITNC_K_SMALL] += t;
+        launches[MITNC_K_SMALL] += 1;
+        flops[MITNC_K_SMALL] += b.flops;
+        bytes[MITNC_K_SMALL] += b.bytes;
+        continue;
+      }
       if (id <= kMergeEvent) {  // merge addition: acc += term, 2 real flops and 3 accesses per entry
         const int v = kMergeEvent - id;
         const double n = std::ldexp(1.0, P->nodes[P->steps[v / 4].out].full_rank);

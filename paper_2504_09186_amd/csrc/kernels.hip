@@ -312,6 +312,47 @@ __global__ __launch_bounds__(256) void k_small_multi(const SmallRevOp* ops, cons
   if (c < c_elems) C[c] = small_entry<0, true>(A, B, tab, mb, nb, kb, bb, c);
 }
 
+// Many independent SMALL steps of the forward pass in one launch (the steps
+// a slice range computes once, grouped by dependency level): workgroup first
+// + blockIdx.x of the block table names its step; operands and output are
+// workspace offsets; the output goes through the step's epilogue (16-bit
+// storage scaled by its out_scale) and its stored maximum into stats.
+template <int P>
+__global__ __launch_bounds__(256) void k_small_fwd(const SmallRevOp* ops, const uint32_t* block_op, uint32_t first,
+                                                   char* ws, float* stats) {
+  __shared__ __align__(4) uint8_t tab[TAB_BYTES];
+  const uint32_t gb = first + blockIdx.x;
+  const SmallRevOp& op = ops[block_op[gb]];
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(op.d.am);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(tab);
+    for (int i = threadIdx.x; i < TAB_BYTES / 4; i += blockDim.x) dst[i] = src[i];
+  }
+  StepDesc d = op.d;
+  d.C = ws + op.c_off;
+  d.stats = stats;
+  const void* A = ws + op.a_off;
+  const void* B = ws + op.b_off;
+  __syncthreads();
+  const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
+  const uint64_t c = (uint64_t)(gb - op.block0) * 256 + threadIdx.x;
+  float mx = 0.f;
+  if (c < c_elems) mx = epilogue_store<P>(d, c, small_entry<P, true>(A, B, tab, d.mb, d.nb, d.kb, d.bb, c), 0, c_elems);
+  record_max(d, mx);
+}
+
+hipError_t launch_small_fwd(int prec, const SmallRevOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,
+                            char* ws, float* stats, hipStream_t s) {
+  if (!blocks) return hipSuccess;
+  switch (prec) {
+    case MITNC_C64: hipLaunchKernelGGL(k_small_fwd<0>, dim3(blocks), dim3(256), 0, s, ops, block_op, first, ws, stats); break;
+    case MITNC_CF16: hipLaunchKernelGGL(k_small_fwd<1>, dim3(blocks), dim3(256), 0, s, ops, block_op, first, ws, stats); break;
+    case MITNC_CBF16: hipLaunchKernelGGL(k_small_fwd<2>, dim3(blocks), dim3(256), 0, s, ops, block_op, first, ws, stats); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // Every op of the table satisfies small_bounded (the planner puts the others
 // on single launches).
 hipError_t launch_small_multi(const SmallRevOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,

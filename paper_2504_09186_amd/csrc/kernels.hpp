@@ -25,6 +25,10 @@ hipError_t launch_seed(const double* w, float* adj, uint64_t n, hipStream_t s);
 // table block_op (entries index ops), operands relative to the workspace ws.
 hipError_t launch_small_multi(const SmallRevOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,
                               char* ws, uint64_t slice, hipStream_t s);
+// Batched forward SMALL steps (any precision): workgroups [first, first +
+// blocks) of the block table; stats: the per-step maxima (may be null).
+hipError_t launch_small_fwd(int prec, const SmallRevOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,
+                            char* ws, float* stats, hipStream_t s);
 // acc += src over n complex128 entries (device pointers).
 hipError_t launch_accumulate(double* acc, const double* src, uint64_t n, hipStream_t s);
 // Post-lifetime merge: acc += term over n complex entries stored in

@@ -849,12 +849,36 @@ static void verify_memory_plan(const mitnc_plan* P, uint64_t n_slices) {
     return r;
   };
   std::vector<int> ops;
+  // A batched run executes level by level: every buffer its steps read or
+  // write must be distinct from every other one of the run.
+  for (size_t r = 0; r < P->fwd_runs.size(); ++r) {
+    const mitnc_plan::FwdRun& R = P->fwd_runs[r];
+    std::vector<int> nodes;
+    for (int i = R.first_step; i <= R.last_step; ++i)
+      if (P->fwd_run_of[i] == (int)r)
+        for (int v : {P->steps[i].a, P->steps[i].b, P->steps[i].out})
+          if (std::find(nodes.begin(), nodes.end(), v) == nodes.end()) nodes.push_back(v);
+    for (size_t x = 0; x < nodes.size(); ++x)
+      for (size_t y = x + 1; y < nodes.size(); ++y) {
+        uint64_t a0, a1, b0, b1;
+        range(nodes[x], a0, a1);
+        range(nodes[y], b0, b1);
+        if (overlaps(a0, a1, b0, b1)) fail(MITNC_INVALID_ARG, "internal: buffers of a batched run overlap");
+      }
+  }
   for (uint64_t s = 0; s < n_slices; ++s) {
+    // the range prologue runs before the first slice, then its steps are skipped
+    std::vector<std::pair<size_t, int>> seq;  // (step, mode) in launch order
+    if (s == 0)
+      for (int i : P->prologue_order) seq.push_back({(size_t)i, 1});
     for (size_t si = 0; si < P->steps.size(); ++si) {
+      const PlanNode& O = P->nodes[P->steps[si].out];
+      const int mode = sched.decide(P->steps[si].out, O.elig, O.emask, O.bmask, s);
+      if (mode && P->fwd_run_of[si] < 0) seq.push_back({si, mode});
+    }
+    for (auto [si, mode] : seq) {
       const PlanStep& st = P->steps[si];
       const PlanNode& O = P->nodes[st.out];
-      const int mode = sched.decide(st.out, O.elig, O.emask, O.bmask, s);
-      if (mode == 0) continue;
       if (!launch_operands(P, (int)si, ops)) continue;  // runs with its section
       for (int node : ops) {
         uint64_t lo, hi;
@@ -1118,6 +1142,69 @@ static void build_reverse_levels(mitnc_plan* P) {
     }
 }
 
+// Tables of the batched forward SMALL runs (workspace offsets are known):
+// per run and level, one table entry per step and one block-table entry per
+// workgroup of 256 outputs; the FP16/BF16 plan's own geometry in ftab, the
+// complex64 geometry of its calibration slices in ftab64.
+static void build_forward_batches(mitnc_plan* P) {
+  const bool half = P->opts.precision != MITNC_C64;
+  auto node_off = [&](int node, bool h) -> uint64_t {
+    const PlanNode& nd = P->nodes[node];
+    if (nd.region == 0) return h ? P->off_leaf_half + nd.offset / 2 : nd.offset;
+    if (nd.region == 1) return P->off_persist + nd.offset;
+    if (nd.region == 2) return P->off_arena + nd.offset;
+    fail(MITNC_INVALID_ARG, "internal: batched step output outside the workspace");
+  };
+  const std::vector<int>& level = P->fwd_levels_tmp;
+  for (size_t r = 0; r < P->fwd_runs.size(); ++r) {
+    mitnc_plan::FwdRun& R = P->fwd_runs[r];
+    int nlev = 0;
+    for (int i = R.first_step; i <= R.last_step; ++i)
+      if (P->fwd_run_of[i] == (int)r) nlev = std::max(nlev, level[P->steps[i].out] + 1);
+    for (int l = 0; l < nlev; ++l)
+      for (int i = R.first_step; i <= R.last_step; ++i)
+        if (P->fwd_run_of[i] == (int)r && level[P->steps[i].out] == l) P->prologue_order.push_back(i);
+    for (int pass = 0; pass < (half ? 2 : 1); ++pass) {
+      const bool h = half && pass == 0;  // pass 0: the plan's precision; pass 1: complex64 calibration
+      std::vector<SmallRevOp>& tab = pass == 0 ? P->ftab : P->ftab64;
+      std::vector<uint32_t>& blk = pass == 0 ? P->fblock : P->fblock64;
+      std::vector<mitnc_plan::FwdBatch>& lv = pass == 0 ? R.levels : R.levels64;
+      lv.assign(nlev, mitnc_plan::FwdBatch{});
+      for (int l = 0; l < nlev; ++l) {
+        lv[l].first = (uint32_t)blk.size();
+        for (int i = R.first_step; i <= R.last_step; ++i) {
+          const PlanStep& st = P->steps[i];
+          if (P->fwd_run_of[i] != (int)r || level[st.out] != l) continue;
+          SmallRevOp e;
+          std::memset(&e, 0, sizeof(e));
+          e.d = pass == 0 ? st.d : st.d64;
+          e.d.A = e.d.B = nullptr;
+          e.d.C = nullptr;
+          e.d.acc = nullptr;
+          e.d.part = nullptr;
+          e.d.stats = nullptr;
+          e.d.step_index = i;
+          e.d.mode = EPI_STORE;
+          if (!h) e.d.out_scale = 1.f;
+          e.a_off = node_off(st.a, h);
+          e.b_off = node_off(st.b, h);
+          e.c_off = node_off(st.out, h);
+          const uint64_t c_elems = 1ull << (e.d.mb + e.d.nb + e.d.bb);
+          e.block0 = (uint32_t)blk.size();
+          const uint32_t idx = (uint32_t)tab.size();
+          for (uint64_t b = 0; b < (c_elems + 255) / 256; ++b) blk.push_back(idx);
+          tab.push_back(e);
+          if (pass == 0) P->ftab_step.push_back(i);
+          lv[l].flops += st.flops;
+          lv[l].bytes += st.bytes;
+        }
+        lv[l].blocks = (uint32_t)blk.size() - lv[l].first;
+      }
+    }
+  }
+  std::vector<int>().swap(P->fwd_levels_tmp);
+}
+
 mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   if (!net->output_set) fail(MITNC_INVALID_ARG, "output not set");
   int n = (int)net->leaves.size();
@@ -1362,6 +1449,39 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   // intermediate inside a section must be transient).
   P->step_section.assign(P->steps.size(), -1);
   if (opts.fuse_sections && opts.force_kernel < 0 && !opts.differentiable) form_sections(P.get(), opts.precision);
+  // The range prologue: forward SMALL steps computed once per slice range
+  // (no sliced operand index, or hoisted), run before the range's first
+  // slice level by level (a level's steps read leaves, kept nodes or outputs
+  // of earlier levels), one batched launch per level.
+  P->fwd_run_of.assign(P->steps.size(), -1);
+  if (!opts.differentiable) {
+    std::vector<int> level(P->nodes.size(), -1);
+    std::vector<int> chosen;
+    for (size_t i = 0; i < P->steps.size(); ++i) {
+      const PlanStep& st = P->steps[i];
+      const PlanNode& O = P->nodes[st.out];
+      if (st.root || st.kclass != MITNC_K_SMALL || P->step_section[i] >= 0) continue;
+      if (!small_bounded(st.d.mb, st.d.nb, st.d.kb, st.d.bb)) continue;
+      if (O.emask || O.elig || O.bmask) continue;
+      if (!P->nodes[st.a].slice_bits.empty() || !P->nodes[st.b].slice_bits.empty()) continue;
+      // operands: leaves, or outputs of prologue steps (anything else is
+      // computed after the prologue)
+      if ((st.a >= n && level[st.a] < 0) || (st.b >= n && level[st.b] < 0)) continue;
+      int lv = 0;
+      for (int o : {st.a, st.b})
+        if (level[o] >= 0) lv = std::max(lv, level[o] + 1);
+      level[st.out] = lv;
+      chosen.push_back((int)i);
+    }
+    if (chosen.size() >= 2) {
+      for (int i : chosen) P->fwd_run_of[i] = 0;
+      mitnc_plan::FwdRun R;
+      R.first_step = chosen.front();
+      R.last_step = chosen.back();
+      P->fwd_runs.push_back(R);
+    }
+    P->fwd_levels_tmp.swap(level);
+  }
   // Memory: persistent slots, then a transient arena with first-fit reuse.
   uint64_t poff = 0;
   for (auto& st : P->steps) {
@@ -1374,9 +1494,19 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   P->persist_bytes = poff;
   std::vector<std::pair<uint64_t, uint64_t>> live;  // (offset, size) of live transient buffers
   std::vector<int> live_node;
+  std::vector<int> pending;  // operands to release once the prologue has run
   uint64_t arena = 0;
   std::vector<int> ops;
-  for (size_t s = 0; s < P->steps.size(); ++s) {
+  // The prologue's steps come first (their outputs live until their
+  // consumers, operands until the prologue ends); then the others in order.
+  std::vector<size_t> order;
+  for (size_t s = 0; s < P->steps.size(); ++s)
+    if (P->fwd_run_of[s] >= 0) order.push_back(s);
+  const size_t n_pro = order.size();
+  for (size_t s = 0; s < P->steps.size(); ++s)
+    if (P->fwd_run_of[s] < 0) order.push_back(s);
+  for (size_t oi = 0; oi < order.size(); ++oi) {
+    const size_t s = order[oi];
     PlanStep& st = P->steps[s];
     // A section's steps run at its last step: earlier ones store nothing and
     // release nothing (the section's input and small tensors stay live).
@@ -1404,7 +1534,11 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
     // A merge accumulator's later terms are computed into a transient buffer
     // and then added; the buffer is free again after the step.
     if (O.bmask) O.tmp_offset = place(align_up(8ull << O.full_rank, 256));
-    for (int op : ops) {
+    // Operands of the prologue's steps stay allocated until it ends (its
+    // steps run level by level, not in step order).
+    for (int op : ops) pending.push_back(op);
+    if (oi + 1 < n_pro) continue;
+    for (int op : pending) {
       for (size_t i = 0; i < live_node.size(); ++i)
         if (live_node[i] == op) {
           live.erase(live.begin() + i);
@@ -1412,6 +1546,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
           break;
         }
     }
+    pending.clear();
   }
   P->arena_bytes = arena;
   uint64_t part = 0;
@@ -1436,7 +1571,12 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   if (opts.differentiable) build_reverse_levels(P.get());
   P->off_rtab = align_up(P->off_gtab + sizeof(GradEntry) * P->gtab.size(), 256);
   P->off_rblock = align_up(P->off_rtab + sizeof(SmallRevOp) * P->rtab.size(), 256);
-  P->ws_bytes = align_up(P->off_rblock + sizeof(uint32_t) * P->rblock.size(), 256);
+  build_forward_batches(P.get());
+  P->off_ftab = align_up(P->off_rblock + sizeof(uint32_t) * P->rblock.size(), 256);
+  P->off_fblock = align_up(P->off_ftab + sizeof(SmallRevOp) * P->ftab.size(), 256);
+  P->off_ftab64 = align_up(P->off_fblock + sizeof(uint32_t) * P->fblock.size(), 256);
+  P->off_fblock64 = align_up(P->off_ftab64 + sizeof(SmallRevOp) * P->ftab64.size(), 256);
+  P->ws_bytes = align_up(P->off_fblock64 + sizeof(uint32_t) * P->fblock64.size(), 256);
   P->calibrated = !half;
   verify_memory_plan(P.get(), std::min<uint64_t>(1ull << std::min(P->S, 62), 1ull << std::max(6, P->merge_align_bits + 1)));
   return P.release();

@@ -14,6 +14,8 @@ constexpr int kLevelFirst = 1001;   // first slice of a range: everything runs
 constexpr int kMergeClass = 7;      // timing slot of the post-lifetime merge additions
 // Timing record of a merge addition: kMergeEvent - (4 * step + precision).
 constexpr int kMergeEvent = -(1 << 30);
+// Timing record of a batched forward SMALL launch of the range prologue: kFwdEvent - level.
+constexpr int kFwdEvent = -(1 << 29);
 
 struct PlanNode {
   bool leaf = false;
@@ -92,6 +94,29 @@ struct mitnc_plan {
   uint64_t ws_bytes = 0;
   bool calibrated = false;
   int32_t reruns = 0;  // FP16/BF16 executes that re-ran after an exponent miss
+  // Batched forward SMALL steps: runs of consecutive steps that a slice range
+  // computes once (no sliced index, or hoisted), each run launched level by
+  // level (a level's steps read only outputs of earlier levels) through a
+  // table of workspace offsets; the arena keeps every buffer of a run
+  // distinct until the run ends.  ftab64 holds the complex64 geometry for
+  // the calibration slices of FP16/BF16 plans.
+  struct FwdBatch {
+    uint32_t first = 0, blocks = 0;  // block-table range
+    double flops = 0, bytes = 0;
+  };
+  struct FwdRun {
+    int first_step = -1, last_step = -1;
+    std::vector<FwdBatch> levels, levels64;
+  };
+  std::vector<FwdRun> fwd_runs;
+  std::vector<int> fwd_run_of;                // per step: its run or -1
+  std::vector<mitnc::SmallRevOp> ftab, ftab64;
+  std::vector<int> ftab_step;                 // step of each ftab entry
+  std::vector<uint32_t> fblock, fblock64;
+  uint64_t off_ftab = 0, off_fblock = 0, off_ftab64 = 0, off_fblock64 = 0;
+  int ftab_version = 0, ftab_uploaded = -1;   // out_scale changes since the table was copied
+  std::vector<int> fwd_levels_tmp;            // plan construction: level of each run step's output
+  std::vector<int> prologue_order;            // the prologue's steps, level by level
   // Post-lifetime merge: bits summed below the root; slice ranges must be
   // multiples of 2^merge_align_bits.
   uint64_t merged = 0;
