@@ -232,6 +232,14 @@ typedef struct mitnc_plan_opts {
                                  indices are not hoisted (contracted once for
                                  all slices); they then run per slice under
                                  the reuse rule like every other node */
+  int32_t prologue_bits;      /* forward steps computed once per slice range
+                                 run first, level by level, SMALL ones
+                                 batched into one launch per level (the range
+                                 prologue).  0: steps with no sliced index
+                                 (or hoisted); w > 0: also steps whose sliced
+                                 indices are all at slice-id bits >= w, and
+                                 ranges must then lie in one aligned block of
+                                 2^w slices (at most 62) */
   int32_t reverse_defer;      /* differentiable plans, grouped reverse pass:
                                  the reverse below a kept node d depends on
                                  the slice only through d's sliced bits (all
@@ -279,9 +287,9 @@ typedef struct mitnc_plan_stats {
   int32_t merge_align_bits;   /* execute ranges must be multiples of 2^this (0: any) */
   uint64_t merged_mask;       /* the merged bits */
   int32_t n_reverse_groups;   /* differentiable plans: deferral roots of the grouped reverse pass */
-  int32_t n_batched_small;    /* forward SMALL steps computed once per slice range that run batched
-                                 (runs of consecutive such steps, one launch per dependency level) */
-  int32_t n_batched_launches; /* the launches those batches take per slice range */
+  int32_t n_batched_small;    /* forward steps of the range prologue (computed once per slice
+                                 range, run first level by level; see prologue_bits) */
+  int32_t n_batched_launches; /* the batched launches of its SMALL steps (one per level) */
 } mitnc_plan_stats;
 int32_t mitnc_plan_query(const mitnc_plan* plan, mitnc_plan_stats* stats);
 
@@ -417,7 +425,9 @@ int32_t mitnc_plan_upload(mitnc_plan* plan, void* ws, size_t ws_bytes, void* str
  * complex64 maxima over this slice range (as mitnc_calibrate) and the range
  * runs once more; only a clean run is added to result_accum.  Errors:
  * INVALID_ARG for an empty or out-of-range slice range (with merged bits:
- * also one whose ends are not multiples of 2^merge_align_bits) or an
+ * also one whose ends are not multiples of 2^merge_align_bits; with
+ * prologue_bits > 0, one that leaves an aligned block of 2^prologue_bits
+ * slices) or an
  * uncalibrated FP16/BF16 plan, WORKSPACE_TOO_SMALL, HIP_ERROR, NUMERIC when
  * the re-run misses again or the plan was created with no_rerun
  * (result_accum is then unchanged). */
@@ -431,9 +441,11 @@ int32_t mitnc_execute(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t slic
  * [2^13, 2^14) (two bits of headroom below the FP16 maximum); a step that
  * was all zero gets the worst-case exponent e_A + e_B + 14 + (contracted
  * bits).  Slices are statistically alike, so one or a few slices suffice;
- * mitnc_execute corrects a miss.  Synchronises the stream.  No effect on
- * complex64 plans.  Errors: INVALID_ARG (range), WORKSPACE_TOO_SMALL,
- * HIP_ERROR. */
+ * mitnc_execute corrects a miss.  With merged bits the range is widened to
+ * whole merge groups; it must then lie in one aligned block of
+ * 2^prologue_bits slices if prologue_bits > 0.  Synchronises the stream.
+ * No effect on complex64 plans.  Errors: INVALID_ARG (range),
+ * WORKSPACE_TOO_SMALL, HIP_ERROR. */
 int32_t mitnc_calibrate(mitnc_plan* plan, void* ws, size_t ws_bytes, uint64_t slice_begin,
                         uint64_t slice_end, void* stream);
 

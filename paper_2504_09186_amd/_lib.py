@@ -42,7 +42,8 @@ class mitnc_plan_opts(C.Structure):
                 ("cache_budget_bytes", C.c_uint64), ("force_kernel", C.c_int32),
                 ("differentiable", C.c_int32), ("fuse_sections", C.c_int32), ("no_rerun", C.c_int32),
                 ("splitk_max_mn_bits", C.c_int32), ("splitk_target_bits", C.c_int32),
-                ("merge_bits", C.c_int32), ("no_hoist", C.c_int32), ("reverse_defer", C.c_int32)]
+                ("merge_bits", C.c_int32), ("no_hoist", C.c_int32), ("prologue_bits", C.c_int32),
+                ("reverse_defer", C.c_int32)]
 
 
 class mitnc_plan_stats(C.Structure):

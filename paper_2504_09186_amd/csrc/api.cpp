@@ -49,6 +49,10 @@ static void check_range(const mitnc_plan* P, uint64_t s0, uint64_t s1) {
   if ((s0 & am) || (s1 & am))
     fail(MITNC_INVALID_ARG, "slice range must be a multiple of 2^" + std::to_string(P->merge_align_bits) +
                                 " (merged slice-id bits)");
+  const int pw = P->opts.prologue_bits;
+  if (pw > 0 && (s0 >> pw) != ((s1 - 1) >> pw))
+    fail(MITNC_INVALID_ARG, "slice range must lie in one aligned block of 2^" + std::to_string(pw) +
+                                " slices (prologue_bits)");
 }
 
 // Calls f(slice, step, mode) for every launch of slices s0 .. s1-1, in order
@@ -683,9 +687,9 @@ int32_t mitnc_plan_upload(mitnc_plan* P, void* ws, size_t ws_bytes, void* stream
     auto put = [&](uint64_t off, const void* src, size_t bytes) {
       if (bytes) hip_check(hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, s), "batch table upload");
     };
-    put(P->off_ftab, P->ftab.data(), sizeof(SmallRevOp) * P->ftab.size());
+    put(P->off_ftab, P->ftab.data(), sizeof(SmallFwdOp) * P->ftab.size());
     put(P->off_fblock, P->fblock.data(), sizeof(uint32_t) * P->fblock.size());
-    put(P->off_ftab64, P->ftab64.data(), sizeof(SmallRevOp) * P->ftab64.size());
+    put(P->off_ftab64, P->ftab64.data(), sizeof(SmallFwdOp) * P->ftab64.size());
     put(P->off_fblock64, P->fblock64.data(), sizeof(uint32_t) * P->fblock64.size());
     hip_check(hipStreamSynchronize(s), "leaf upload sync");
     P->ftab_uploaded = P->ftab_version;
@@ -818,13 +822,13 @@ static void launch_plan_section(mitnc_plan* P, PlanSection& sec, char* base, uin
 // One batched run of forward SMALL steps, level by level.  The table of the
 // plan's precision carries each step's out_scale: it is copied again after
 // the exponents change.
-static void launch_fwd_run(mitnc_plan* P, int run, char* base, hipStream_t s, int prec, bool stats) {
+static void launch_fwd_run(mitnc_plan* P, int run, char* base, uint64_t slice, hipStream_t s, int prec, bool stats) {
   const bool c64_of_half = prec == MITNC_C64 && P->opts.precision != MITNC_C64;
   if (!c64_of_half && P->ftab_uploaded != P->ftab_version) {
     for (size_t e = 0; e < P->ftab.size(); ++e) P->ftab[e].d.out_scale = P->steps[P->ftab_step[e]].d.out_scale;
     if (P->opts.precision == MITNC_C64)
       for (auto& e : P->ftab) e.d.out_scale = 1.f;
-    hip_check(hipMemcpyAsync(base + P->off_ftab, P->ftab.data(), sizeof(SmallRevOp) * P->ftab.size(),
+    hip_check(hipMemcpyAsync(base + P->off_ftab, P->ftab.data(), sizeof(SmallFwdOp) * P->ftab.size(),
                              hipMemcpyHostToDevice, s),
               "batch table refresh");
     hip_check(hipStreamSynchronize(s), "batch table refresh sync");
@@ -832,7 +836,7 @@ static void launch_fwd_run(mitnc_plan* P, int run, char* base, hipStream_t s, in
   }
   const mitnc_plan::FwdRun& R = P->fwd_runs[run];
   const auto& levels = c64_of_half ? R.levels64 : R.levels;
-  const SmallRevOp* tab = (const SmallRevOp*)(base + (c64_of_half ? P->off_ftab64 : P->off_ftab));
+  const SmallFwdOp* tab = (const SmallFwdOp*)(base + (c64_of_half ? P->off_ftab64 : P->off_ftab));
   const uint32_t* blk = (const uint32_t*)(base + (c64_of_half ? P->off_fblock64 : P->off_fblock));
   for (size_t l = 0; l < levels.size(); ++l) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -849,15 +853,17 @@ static void launch_fwd_run(mitnc_plan* P, int run, char* base, hipStream_t s, in
       hip_check(hipEventRecord(e0, s), "event record");
     }
     hip_check(launch_small_fwd(prec, tab, blk, levels[l].first, levels[l].blocks, base,
-                               stats ? (float*)(base + P->off_stats) : nullptr, s),
+                               stats ? (float*)(base + P->off_stats) : nullptr, slice, s),
               "batched small launch");
     if (P->timing) hip_check(hipEventRecord(e1, s), "event record");
+    // the level's other steps, one launch each
+    for (int i : R.levels[l].big) launch_plan_step(P, P->steps[i], base, slice, nullptr, s, prec, stats);
   }
 }
 
 static void run_slices(mitnc_plan* P, char* base, uint64_t s0, uint64_t s1, double* acc, hipStream_t s, int prec,
                        bool stats) {
-  if (!P->fwd_runs.empty()) launch_fwd_run(P, 0, base, s, prec, stats);  // the range prologue
+  if (!P->fwd_runs.empty()) launch_fwd_run(P, 0, base, s0, s, prec, stats);  // the range prologue
   for_each_launch(P, s0, s1, [&](uint64_t sl, size_t i, int mode) {
     PlanStep& st = P->steps[i];
     const int sec = P->step_section.empty() ? -1 : P->step_section[i];
@@ -1021,6 +1027,7 @@ int32_t mitnc_calibrate(mitnc_plan* P, void* ws, size_t ws_bytes, uint64_t s0, u
     if (s0 >= s1 || s1 > n_slices) fail(MITNC_INVALID_ARG, "slice range out of bounds");
     // with merged bits: the whole merge groups that hold the range
     const uint64_t am = (1ull << P->merge_align_bits) - 1;
+    check_range(P, s0 & ~am, (s1 + am) & ~am);
     calibrate_range(P, (char*)ws, s0 & ~am, (s1 + am) & ~am, (hipStream_t)stream);
   });
 }

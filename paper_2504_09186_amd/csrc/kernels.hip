@@ -315,14 +315,15 @@ __global__ __launch_bounds__(256) void k_small_multi(const SmallRevOp* ops, cons
 // Many independent SMALL steps of the forward pass in one launch (the steps
 // a slice range computes once, grouped by dependency level): workgroup first
 // + blockIdx.x of the block table names its step; operands and output are
-// workspace offsets; the output goes through the step's epilogue (16-bit
+// workspace offsets, a sliced operand read at the slice's values of its
+// sliced indices; the output goes through the step's epilogue (16-bit
 // storage scaled by its out_scale) and its stored maximum into stats.
 template <int P>
-__global__ __launch_bounds__(256) void k_small_fwd(const SmallRevOp* ops, const uint32_t* block_op, uint32_t first,
-                                                   char* ws, float* stats) {
+__global__ __launch_bounds__(256) void k_small_fwd(const SmallFwdOp* ops, const uint32_t* block_op, uint32_t first,
+                                                   char* ws, float* stats, uint64_t slice) {
   __shared__ __align__(4) uint8_t tab[TAB_BYTES];
   const uint32_t gb = first + blockIdx.x;
-  const SmallRevOp& op = ops[block_op[gb]];
+  const SmallFwdOp& op = ops[block_op[gb]];
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(op.d.am);
     uint32_t* dst = reinterpret_cast<uint32_t*>(tab);
@@ -331,8 +332,12 @@ __global__ __launch_bounds__(256) void k_small_fwd(const SmallRevOp* ops, const 
   StepDesc d = op.d;
   d.C = ws + op.c_off;
   d.stats = stats;
-  const void* A = ws + op.a_off;
-  const void* B = ws + op.b_off;
+  constexpr uint64_t ES = P == 0 ? 8 : 4;
+  uint64_t sa = 0, sb = 0;
+  for (int j = 0; j < op.na; ++j) sa |= ((slice >> op.a_bit[j]) & 1ull) << op.a_pos[j];
+  for (int j = 0; j < op.nb; ++j) sb |= ((slice >> op.b_bit[j]) & 1ull) << op.b_pos[j];
+  const void* A = ws + op.a_off + sa * ES;
+  const void* B = ws + op.b_off + sb * ES;
   __syncthreads();
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
   const uint64_t c = (uint64_t)(gb - op.block0) * 256 + threadIdx.x;
@@ -341,13 +346,19 @@ __global__ __launch_bounds__(256) void k_small_fwd(const SmallRevOp* ops, const 
   record_max(d, mx);
 }
 
-hipError_t launch_small_fwd(int prec, const SmallRevOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,
-                            char* ws, float* stats, hipStream_t s) {
+hipError_t launch_small_fwd(int prec, const SmallFwdOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,
+                            char* ws, float* stats, uint64_t slice, hipStream_t s) {
   if (!blocks) return hipSuccess;
   switch (prec) {
-    case MITNC_C64: hipLaunchKernelGGL(k_small_fwd<0>, dim3(blocks), dim3(256), 0, s, ops, block_op, first, ws, stats); break;
-    case MITNC_CF16: hipLaunchKernelGGL(k_small_fwd<1>, dim3(blocks), dim3(256), 0, s, ops, block_op, first, ws, stats); break;
-    case MITNC_CBF16: hipLaunchKernelGGL(k_small_fwd<2>, dim3(blocks), dim3(256), 0, s, ops, block_op, first, ws, stats); break;
+    case MITNC_C64:
+      hipLaunchKernelGGL(k_small_fwd<0>, dim3(blocks), dim3(256), 0, s, ops, block_op, first, ws, stats, slice);
+      break;
+    case MITNC_CF16:
+      hipLaunchKernelGGL(k_small_fwd<1>, dim3(blocks), dim3(256), 0, s, ops, block_op, first, ws, stats, slice);
+      break;
+    case MITNC_CBF16:
+      hipLaunchKernelGGL(k_small_fwd<2>, dim3(blocks), dim3(256), 0, s, ops, block_op, first, ws, stats, slice);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -27,8 +27,8 @@ hipError_t launch_small_multi(const SmallRevOp* ops, const uint32_t* block_op, u
                               char* ws, uint64_t slice, hipStream_t s);
 // Batched forward SMALL steps (any precision): workgroups [first, first +
 // blocks) of the block table; stats: the per-step maxima (may be null).
-hipError_t launch_small_fwd(int prec, const SmallRevOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,
-                            char* ws, float* stats, hipStream_t s);
+hipError_t launch_small_fwd(int prec, const SmallFwdOp* ops, const uint32_t* block_op, uint32_t first, uint32_t blocks,
+                            char* ws, float* stats, uint64_t slice, hipStream_t s);
 // acc += src over n complex128 entries (device pointers).
 hipError_t launch_accumulate(double* acc, const double* src, uint64_t n, hipStream_t s);
 // Post-lifetime merge: acc += term over n complex entries stored in

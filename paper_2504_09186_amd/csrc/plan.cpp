@@ -1166,7 +1166,7 @@ static void build_forward_batches(mitnc_plan* P) {
         if (P->fwd_run_of[i] == (int)r && level[P->steps[i].out] == l) P->prologue_order.push_back(i);
     for (int pass = 0; pass < (half ? 2 : 1); ++pass) {
       const bool h = half && pass == 0;  // pass 0: the plan's precision; pass 1: complex64 calibration
-      std::vector<SmallRevOp>& tab = pass == 0 ? P->ftab : P->ftab64;
+      std::vector<SmallFwdOp>& tab = pass == 0 ? P->ftab : P->ftab64;
       std::vector<uint32_t>& blk = pass == 0 ? P->fblock : P->fblock64;
       std::vector<mitnc_plan::FwdBatch>& lv = pass == 0 ? R.levels : R.levels64;
       lv.assign(nlev, mitnc_plan::FwdBatch{});
@@ -1175,9 +1175,21 @@ static void build_forward_batches(mitnc_plan* P) {
         for (int i = R.first_step; i <= R.last_step; ++i) {
           const PlanStep& st = P->steps[i];
           if (P->fwd_run_of[i] != (int)r || level[st.out] != l) continue;
-          SmallRevOp e;
+          if (st.kclass != MITNC_K_SMALL || !small_bounded(st.d.mb, st.d.nb, st.d.kb, st.d.bb)) {
+            if (pass == 0) lv[l].big.push_back(i);  // launched on its own, in its level
+            continue;
+          }
+          SmallFwdOp e;
           std::memset(&e, 0, sizeof(e));
           e.d = pass == 0 ? st.d : st.d64;
+          for (auto& [b, pos] : P->nodes[st.a].slice_bits) {
+            e.a_bit[e.na] = (int8_t)b;
+            e.a_pos[e.na++] = (int8_t)pos;
+          }
+          for (auto& [b, pos] : P->nodes[st.b].slice_bits) {
+            e.b_bit[e.nb] = (int8_t)b;
+            e.b_pos[e.nb++] = (int8_t)pos;
+          }
           e.d.A = e.d.B = nullptr;
           e.d.C = nullptr;
           e.d.acc = nullptr;
@@ -1214,6 +1226,7 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   if (opts.precision != MITNC_C64 && opts.precision != MITNC_CF16 && opts.precision != MITNC_CBF16)
     fail(MITNC_INVALID_ARG, "unknown precision");
   if (opts.merge_bits < 0 || opts.merge_bits > 12) fail(MITNC_INVALID_ARG, "merge_bits out of range (0..12)");
+  if (opts.prologue_bits < 0 || opts.prologue_bits > 62) fail(MITNC_INVALID_ARG, "prologue_bits out of range (0..62)");
   auto P = std::make_unique<mitnc_plan>();
   P->opts = opts;
   P->n_leaves = n;
@@ -1449,21 +1462,30 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   // intermediate inside a section must be transient).
   P->step_section.assign(P->steps.size(), -1);
   if (opts.fuse_sections && opts.force_kernel < 0 && !opts.differentiable) form_sections(P.get(), opts.precision);
-  // The range prologue: forward SMALL steps computed once per slice range
-  // (no sliced operand index, or hoisted), run before the range's first
-  // slice level by level (a level's steps read leaves, kept nodes or outputs
-  // of earlier levels), one batched launch per level.
+  // The range prologue: forward steps a slice range computes once (their
+  // sliced indices, if any, all at slice-id bits >= prologue_bits, which a
+  // range inside one aligned block of 2^prologue_bits slices keeps fixed;
+  // hoisted ones; also those the merge schedule would only run at a later
+  // slice of the range), run before the range's first slice level by level
+  // (a level's steps read leaves and outputs of earlier levels); a level's
+  // SMALL steps go out in one batched launch.
   P->fwd_run_of.assign(P->steps.size(), -1);
+  const int pw = opts.prologue_bits;
+  const uint64_t low = pw > 0 ? (1ull << pw) - 1 : ~0ull;  // bits that may vary inside a range
+  auto fixed_bits = [&](const PlanNode& nd) {
+    for (auto& [b, pos] : nd.slice_bits)
+      if (pw == 0 || b < pw || (int)nd.slice_bits.size() > 16) return false;
+    return true;
+  };
   if (!opts.differentiable) {
     std::vector<int> level(P->nodes.size(), -1);
     std::vector<int> chosen;
     for (size_t i = 0; i < P->steps.size(); ++i) {
       const PlanStep& st = P->steps[i];
       const PlanNode& O = P->nodes[st.out];
-      if (st.root || st.kclass != MITNC_K_SMALL || P->step_section[i] >= 0) continue;
-      if (!small_bounded(st.d.mb, st.d.nb, st.d.kb, st.d.bb)) continue;
-      if (O.emask || O.elig || O.bmask) continue;
-      if (!P->nodes[st.a].slice_bits.empty() || !P->nodes[st.b].slice_bits.empty()) continue;
+      if (st.root || P->step_section[i] >= 0) continue;
+      if ((O.emask & low) || O.bmask) continue;
+      if (!fixed_bits(P->nodes[st.a]) || !fixed_bits(P->nodes[st.b])) continue;
       // operands: leaves, or outputs of prologue steps (anything else is
       // computed after the prologue)
       if ((st.a >= n && level[st.a] < 0) || (st.b >= n && level[st.b] < 0)) continue;
@@ -1474,7 +1496,12 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
       chosen.push_back((int)i);
     }
     if (chosen.size() >= 2) {
-      for (int i : chosen) P->fwd_run_of[i] = 0;
+      for (int i : chosen) {
+        P->fwd_run_of[i] = 0;
+        // A step the schedule would run later (waiting for merged bits) is
+        // read at that later slice: its output is kept.
+        if (P->nodes[P->steps[i].out].elig) P->nodes[P->steps[i].out].region = 1;
+      }
       mitnc_plan::FwdRun R;
       R.first_step = chosen.front();
       R.last_step = chosen.back();
@@ -1573,12 +1600,14 @@ mitnc_plan* build_plan(const mitnc_network* net, const mitnc_plan_opts& opts) {
   P->off_rblock = align_up(P->off_rtab + sizeof(SmallRevOp) * P->rtab.size(), 256);
   build_forward_batches(P.get());
   P->off_ftab = align_up(P->off_rblock + sizeof(uint32_t) * P->rblock.size(), 256);
-  P->off_fblock = align_up(P->off_ftab + sizeof(SmallRevOp) * P->ftab.size(), 256);
+  P->off_fblock = align_up(P->off_ftab + sizeof(SmallFwdOp) * P->ftab.size(), 256);
   P->off_ftab64 = align_up(P->off_fblock + sizeof(uint32_t) * P->fblock.size(), 256);
-  P->off_fblock64 = align_up(P->off_ftab64 + sizeof(SmallRevOp) * P->ftab64.size(), 256);
+  P->off_fblock64 = align_up(P->off_ftab64 + sizeof(SmallFwdOp) * P->ftab64.size(), 256);
   P->ws_bytes = align_up(P->off_fblock64 + sizeof(uint32_t) * P->fblock64.size(), 256);
   P->calibrated = !half;
-  verify_memory_plan(P.get(), std::min<uint64_t>(1ull << std::min(P->S, 62), 1ull << std::max(6, P->merge_align_bits + 1)));
+  uint64_t n_check = std::min<uint64_t>(1ull << std::min(P->S, 62), 1ull << std::max(6, P->merge_align_bits + 1));
+  if (opts.prologue_bits > 0) n_check = std::min<uint64_t>(n_check, 1ull << opts.prologue_bits);
+  verify_memory_plan(P.get(), n_check);
   return P.release();
 }
 

@@ -94,15 +94,17 @@ struct mitnc_plan {
   uint64_t ws_bytes = 0;
   bool calibrated = false;
   int32_t reruns = 0;  // FP16/BF16 executes that re-ran after an exponent miss
-  // Batched forward SMALL steps: runs of consecutive steps that a slice range
-  // computes once (no sliced index, or hoisted), each run launched level by
-  // level (a level's steps read only outputs of earlier levels) through a
-  // table of workspace offsets; the arena keeps every buffer of a run
-  // distinct until the run ends.  ftab64 holds the complex64 geometry for
-  // the calibration slices of FP16/BF16 plans.
+  // The range prologue: the steps a slice range computes once (no sliced
+  // operand index, or hoisted), run level by level before the range's first
+  // slice (a level's steps read only leaves and outputs of earlier levels);
+  // a level's SMALL steps go out in one launch through a table of workspace
+  // offsets.  The arena keeps every prologue buffer distinct until the
+  // prologue ends.  ftab64 holds the complex64 geometry for the calibration
+  // slices of FP16/BF16 plans.
   struct FwdBatch {
-    uint32_t first = 0, blocks = 0;  // block-table range
+    uint32_t first = 0, blocks = 0;  // block-table range of the level's batched SMALL steps
     double flops = 0, bytes = 0;
+    std::vector<int> big;            // the level's other steps (launched one by one)
   };
   struct FwdRun {
     int first_step = -1, last_step = -1;
@@ -110,7 +112,7 @@ struct mitnc_plan {
   };
   std::vector<FwdRun> fwd_runs;
   std::vector<int> fwd_run_of;                // per step: its run or -1
-  std::vector<mitnc::SmallRevOp> ftab, ftab64;
+  std::vector<mitnc::SmallFwdOp> ftab, ftab64;
   std::vector<int> ftab_step;                 // step of each ftab entry
   std::vector<uint32_t> fblock, fblock64;
   uint64_t off_ftab = 0, off_fblock = 0, off_ftab64 = 0, off_fblock64 = 0;

@@ -111,6 +111,19 @@ struct SmallRevOp {
   int8_t pad_[6];
 };
 
+// One step of the batched range prologue (forward steps a slice range
+// computes once): operands and output are workspace byte offsets; an operand
+// with sliced indices (all constant over the range) is read at entry offset
+// sum_j ((slice >> bit[j]) & 1) << pos[j].
+struct SmallFwdOp {
+  StepDesc d;                    // A, B, C, stats unused
+  uint64_t a_off, b_off, c_off;
+  uint32_t block0;               // index of the op's first workgroup in the block table
+  int8_t na, nb;                 // sliced indices of A and B (at most 16 each)
+  int8_t a_bit[16], a_pos[16], b_bit[16], b_pos[16];
+  int8_t pad_[2];
+};
+
 // Tile geometry of the MFMA kernel classes (bits of the m, n, k tile).
 struct TileGeom {
   int tm_bits, tn_bits, tk_bits;

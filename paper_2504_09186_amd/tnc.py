@@ -124,11 +124,11 @@ class Plan:
                  cache_budget_bytes: int = 0, force_kernel: int = -1, differentiable: bool = False,
                  fuse_sections: bool = False, no_rerun: bool = False, splitk_max_mn_bits: int = 0,
                  splitk_target_bits: int = 0, merge_bits: int = 0, no_hoist: bool = False,
-                 reverse_defer: int = 0):
+                 reverse_defer: int = 0, prologue_bits: int = 0):
         o = mitnc_plan_opts(precision, 1 if reuse else 0, cache_budget_bytes, force_kernel,
                             1 if differentiable else 0, 1 if fuse_sections else 0, 1 if no_rerun else 0,
                             splitk_max_mn_bits, splitk_target_bits, merge_bits, 1 if no_hoist else 0,
-                            reverse_defer)
+                            prologue_bits, reverse_defer)
         h = C.c_void_p()
         call("mitnc_plan_create", net.h, C.byref(o), C.byref(h))
         self.h = h

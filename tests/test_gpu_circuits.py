@@ -265,3 +265,35 @@ def test_cache_budget_demotion(case):
     torch.cuda.synchronize()
     for got in (acc.cpu().numpy(), acc2.cpu().numpy()):
         assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("pb", [0, 3])
+def test_range_prologue(prec, pb):
+    """The range prologue on the GPU: steps computed once per slice range run
+    first, SMALL ones batched per dependency level (prologue_bits 0: no
+    sliced index; 3: sliced indices at bits >= 3, ranges within aligned
+    blocks of 8 slices).  Sums over the blocks equal the state vector
+    (complex64 1e-5; FP16 5e-3 relative L2)."""
+    require_gpu()
+    import torch
+    from paper_2504_09186_amd import tnc
+    c = synth.lattice_circuit(4, 4, 10, seed=7)
+    spec = synth.output_spec(16, [13, 14, 15], seed=8)
+    net = _lib_net(c, spec)
+    net.path_search(seed=9, trials=8, max_log2=11, min_sliced=5, max_sliced=5)
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    plan = tnc.Plan(net, precision=prec, prologue_bits=pb)
+    assert plan.stats.n_batched_small >= 2
+    print(f"range prologue, precision {prec}, prologue_bits {pb}: {plan.stats.n_batched_small} steps in "
+          f"{plan.stats.n_batched_launches} batched launches", flush=True)
+    plan.upload()
+    step = 8 if pb else plan.n_slices
+    if prec:
+        plan.calibrate(0, 2)
+    acc = plan.new_result()
+    for s0 in range(0, plan.n_slices, step):
+        plan.execute(acc, s0, s0 + step)
+    torch.cuda.synchronize()
+    got = acc.cpu().numpy()
+    assert np.linalg.norm(got - ref) <= (TOL if prec == 0 else 5e-3) * np.linalg.norm(ref)

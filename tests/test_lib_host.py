@@ -514,3 +514,29 @@ def test_reverse_groups_structure(lib):
     assert len(kept) >= allg.stats.n_reverse_groups
     # the reverse schedule itself (levels, each adjoint written once) is unchanged by grouping
     assert off.reverse_info() == allg.reverse_info()
+
+
+@pytest.mark.parametrize("merge", [0, 4])
+def test_range_prologue_replay(lib, merge):
+    """The range prologue (steps a slice range computes once, batched by
+    dependency level): with prologue_bits 0 and 3 the host replay of the
+    library's launch list (prologue first) sums to the state vector over
+    whole ranges and aligned blocks, with and without merges; a range that
+    crosses a 2^3 block is refused when prologue_bits is 3."""
+    from plan_replay import PlanReplay
+    from paper_2504_09186_amd import tnc
+    from paper_2504_09186_amd._lib import MitncError
+    c = synth.lattice_circuit(4, 4, 10, seed=7)
+    spec = synth.output_spec(16, [13, 14, 15], seed=8)
+    net = tnc.Network(c, spec)
+    net.path_search(seed=9, trials=8, max_log2=11, min_sliced=5, max_sliced=5)
+    ref = oracle.sv_amplitudes(c, spec).reshape(-1)
+    for pb in (0, 3):
+        plan = tnc.Plan(net, merge_bits=merge, prologue_bits=pb)
+        assert plan.stats.n_batched_small >= 2
+        step = 1 << max(pb, plan.stats.merge_align_bits, 0) if pb else plan.n_slices
+        got = sum(PlanReplay(plan).run(s0, s0 + step) for s0 in range(0, plan.n_slices, step))
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), (pb, merge)
+        if pb:
+            with pytest.raises(MitncError, match="aligned block"):
+                plan.schedule(0, 16)
