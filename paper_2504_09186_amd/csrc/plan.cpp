@@ -37,6 +37,12 @@ namespace mitnc {
 
 static uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// Split-K: every split keeps more than 2^kSplitMinStageBits k tiles.
+#ifndef MITNC_SPLIT_MIN_STAGE_BITS
+#define MITNC_SPLIT_MIN_STAGE_BITS 2
+#endif
+static constexpr int kSplitMinStageBits = MITNC_SPLIT_MIN_STAGE_BITS;
+
 static void fill_positions(uint8_t* dst, const std::vector<int>& src) {
   for (size_t i = 0; i < src.size(); ++i) dst[i] = (uint8_t)src[i];
 }
@@ -567,7 +573,7 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
                       : skinny                                    ? 12
                                                                   : 11;
     int ks = 0;
-    while (tiles_bits + ks < target_bits && ks + 2 < khigh) ++ks;
+    while (tiles_bits + ks < target_bits && ks + kSplitMinStageBits < khigh) ++ks;
     uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
     while (ks > 0 && (c_elems << ks) * 8 > (256ull << 20)) --ks;
     d.ks_bits = ks;
