@@ -1261,9 +1261,14 @@ struct TileSlot {
   int lo, hi;  // (m, k) for A tiles, (k, n) for B tiles, (m, n) for C tiles
 };
 
-// Unrolled over the at most 16 tile bits so that the LDS reads of one decode
-// are independent of each other (two round trips instead of two per bit).
-__device__ __forceinline__ TileSlot decode_slot(int e, int nbits, const uint8_t* codes, const uint8_t* tab,
+// Tile bits [B0, B1) of element number e (the others are ignored); the
+// decode of e is the OR of the decodes of disjoint bit ranges, so a thread
+// decodes the bits its thread index gives once and adds the bits of each
+// load slot (uniform across the workgroup) separately.  Unrolled so that the
+// LDS reads of one decode are independent of each other (two round trips
+// instead of two per bit).
+template <int B0, int B1>
+__device__ __forceinline__ TileSlot decode_bits(uint32_t e, int nbits, const uint8_t* codes, const uint8_t* tab,
                                                 int first_cls, int off_first, int off_second) {
   // Branch-free (index clamped, contribution masked): the LDS reads of all
   // bits issue together instead of one dependent pair per bit.  Both
@@ -1271,7 +1276,7 @@ __device__ __forceinline__ TileSlot decode_slot(int e, int nbits, const uint8_t*
   // so no control flow or scalar select depends on the class.
   TileSlot r{0, 0, 0};
 #pragma unroll
-  for (int b = 0; b < 16; ++b) {
+  for (int b = B0; b < B1; ++b) {
     const int on = b < nbits ? 1 : 0;
     const int code = codes[on ? b : 0];
     const int idx = code & 31;
@@ -1284,6 +1289,12 @@ __device__ __forceinline__ TileSlot decode_slot(int e, int nbits, const uint8_t*
   }
   return r;
 }
+
+__device__ __forceinline__ TileSlot or_slots(TileSlot a, TileSlot b) {
+  return TileSlot{a.off | b.off, a.lo | b.lo, a.hi | b.hi};
+}
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
 // Stores the staged C tile (LDS, complex float, row stride SC) to the output,
 // enumerating the tile in C's address order; WK partial tiles are summed.
@@ -1299,11 +1310,12 @@ __device__ __forceinline__ void store_c_tile(const StepDesc& d, const uint8_t* t
   // per thread), the others from j (uniform across the workgroup).
   const int nlo = nc < 8 ? nc : 8;
   const bool active = tid < (1 << nlo);
-  const TileSlot lo = decode_slot(tid & ((1 << nlo) - 1), nlo, tab + T_CTILE, tab, TB_M, T_CM, T_CN);
+  const TileSlot lo = decode_bits<0, 8>(tid & ((1 << nlo) - 1), nlo, tab + T_CTILE, tab, TB_M, T_CM, T_CN);
   const int n_hi = 1 << (nc - nlo);
   // The high parts (uniform per j) are decoded once, one per thread, into LDS.
   __shared__ TileSlot hi_tab[C_ITEMS];
-  if (tid < n_hi && tid < C_ITEMS) hi_tab[tid] = decode_slot(tid << nlo, nc, tab + T_CTILE, tab, TB_M, T_CM, T_CN);
+  // (nc <= 8: only tid 0, whose high part is empty)
+  if (tid < n_hi && tid < C_ITEMS) hi_tab[tid] = decode_bits<8, 16>(tid << nlo, nc, tab + T_CTILE, tab, TB_M, T_CM, T_CN);
   __syncthreads();
   float mx = 0.f;
 #pragma unroll
@@ -1412,21 +1424,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // Decoding ignores bits at or above the operand's tile bits, so a slot
   // past a tile smaller than the template repeats a valid one (same load,
   // same value to the same LDS slot): loads and stores need no branches.
+  // Slot tid + 256 j: the low 8 tile bits come from tid, the others from j.
+  static_assert((A_LOADS & (A_LOADS - 1)) == 0 && (B_LOADS & (B_LOADS - 1)) == 0, "load counts are powers of two");
   uint32_t a_off[A_LOADS];
   int a_lds[A_LOADS];
   const int na = d.tm + d.tk;
+  const TileSlot a_base = decode_bits<0, 8>(tid, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK);
 #pragma unroll
   for (int j = 0; j < A_LOADS; ++j) {
-    const TileSlot s = decode_slot(tid + 256 * j, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK);
+    const TileSlot s =
+        or_slots(a_base, decode_bits<8, 8 + ilog2(A_LOADS)>(256u * j, na, tab + T_ATILE, tab, TB_M, T_AM, T_AK));
     a_off[j] = s.off;
     a_lds[j] = s.hi * SA + (s.lo ^ row_xor(d.a_swz, s.hi, TM - 1));
   }
   uint32_t b_off[B_LOADS];
   int b_lds[B_LOADS];
   const int nbt = d.tk + d.tn;
+  const TileSlot b_base = decode_bits<0, 8>(tid, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN);
 #pragma unroll
   for (int j = 0; j < B_LOADS; ++j) {
-    const TileSlot s = decode_slot(tid + 256 * j, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN);
+    const TileSlot s =
+        or_slots(b_base, decode_bits<8, 8 + ilog2(B_LOADS)>(256u * j, nbt, tab + T_BTILE, tab, TB_K, T_BK, T_BN));
     b_off[j] = s.off;
     b_lds[j] = TK * SA + s.lo * SB + (s.hi ^ row_xor(d.b_swz, s.lo, TN - 1));
   }
