@@ -211,8 +211,8 @@ typedef struct mitnc_plan_opts {
   int32_t splitk_target_bits; /* log2 of the workgroups (waves for the
                                  register-only form) a split-K step is spread
                                  over, K split until the grid reaches it
-                                 (0 = 12 register-only, 11 LDS-tiled, 8 for
-                                 large tiles; at most 16) */
+                                 (0 = 12 register-only, 11 LDS-tiled, 9 for
+                                 the large TILE and TALL tiles; at most 16) */
   int32_t merge_bits;         /* post-lifetime merge (Sec. III-B, with the
                                  pre-lifetime reuse: the spindle): 0 = off;
                                  k = the k innermost slice-id bits (0..12) may

@@ -2192,6 +2192,10 @@ static void launch_tile_h(const StepDesc& d, dim3 grid, hipStream_t s, Timing t)
   else launch_k(k_tile_h<P, WM, WN, WK, BM, BN, TK, 1, 1>, grid, dim3(256), 0, s, t, d);
 }
 
+#ifndef MITNC_TALL_SLOTS_PER_CU
+#define MITNC_TALL_SLOTS_PER_CU 2ull
+#endif
+
 template <int P>
 static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
   const uint64_t c_elems = 1ull << (d.mb + d.nb + d.bb);
@@ -2233,7 +2237,7 @@ static hipError_t launch_p(int kclass, StepDesc d, hipStream_t s, Timing t) {
       // fewer.
       const uint64_t n_tiles = 1ull << ((d.mb - d.tm) + (d.nb - d.tn));
       const uint64_t yz = (1ull << d.ks_bits) << d.bb;
-      const uint64_t slots = 2ull * 256;
+      const uint64_t slots = (kclass == MITNC_K_TALL ? MITNC_TALL_SLOTS_PER_CU : 2ull) * 256;
       const uint64_t cap = yz * 8 >= slots ? 8 : (slots / yz) & ~7ull;
       dim3 grid((unsigned)(n_tiles < cap ? n_tiles : cap), (unsigned)(1ull << d.ks_bits), (unsigned)(1ull << d.bb));
       if constexpr (P == 0) {

@@ -42,6 +42,13 @@ static uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 #define MITNC_SPLIT_MIN_STAGE_BITS 2
 #endif
 static constexpr int kSplitMinStageBits = MITNC_SPLIT_MIN_STAGE_BITS;
+// Split-K workgroup targets (log2) of the TILE and TALL classes.
+#ifndef MITNC_TILE_SPLIT_TARGET
+#define MITNC_TILE_SPLIT_TARGET 9
+#endif
+#ifndef MITNC_TALL_SPLIT_TARGET
+#define MITNC_TALL_SPLIT_TARGET 9
+#endif
 
 static void fill_positions(uint8_t* dst, const std::vector<int>& src) {
   for (size_t i = 0; i < src.size(); ++i) dst[i] = (uint8_t)src[i];
@@ -569,7 +576,8 @@ static void build_step(mitnc_plan* P, PlanStep& st, const std::vector<int64_t>& 
     const bool skinny = st.kclass == MITNC_K_SPLITK && precision == MITNC_C64 && d.mb + d.nb <= 4 &&
                         d.kb >= kSkinnyLaneBits + 2 && d.bb <= 16;
     int target_bits = P->opts.splitk_target_bits > 0 ? std::min(P->opts.splitk_target_bits, 16)
-                      : st.kclass == MITNC_K_TILE || st.kclass == MITNC_K_TALL ? 9
+                      : st.kclass == MITNC_K_TILE                 ? MITNC_TILE_SPLIT_TARGET
+                      : st.kclass == MITNC_K_TALL                 ? MITNC_TALL_SPLIT_TARGET
                       : skinny                                    ? 12
                                                                   : 11;
     int ks = 0;
