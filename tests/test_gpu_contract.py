@@ -187,6 +187,55 @@ def test_splitk_k27_elementwise():
     print(f"max err / bound {np.max(err / bound):.3e}, max err / sum|a||b| {np.max(err / absab):.3e}")
     assert np.all(err <= bound)
 
+@pytest.mark.parametrize("prec", [1, 2])
+def test_half_splitk_rank30_exact(prec):
+    """The split-K GEPDOT on FP16 / BF16 storage at the narrow-factor shape of
+    the split-common evaluation with a rank-30 operand: A[m][k] (M = 4, K =
+    2^28, 4 GiB of 16-bit pairs) times B[n][k] (N = 2, 2 GiB).  Entries are
+    Gaussian integers (A sparse with parts in {-1, 0, 1}, B = +-1 +-i), so
+    every product and every partial sum, in the FP32 MFMA chains and the FP64
+    reduction alike, is an exact small integer: the stored result must equal
+    C 2^-s_C bit for bit (|C| < 2^8 is exact in both 16-bit formats).  Any k
+    range read twice, skipped or read from the wrong address changes C."""
+    require_gpu()
+    import torch
+    from paper_2504_09186_amd import tnc
+    kb, mb, nb = 28, 2, 1
+    K = [3000 + i for i in range(kb)]
+    la = K + [1000, 1001]        # A index = k + 2^28 m
+    lb = K + [2000]              # B index = k + 2^28 n
+    lc = [1000, 1001, 2000]      # C index = m + 4 n
+    one, neg = (0x3C00, 0xBC00) if prec == 1 else (0x3F80, 0xBF80)
+    rng = np.random.default_rng(4300 + prec)
+    idx = np.unique(rng.integers(0, 1 << (kb + mb), size=1 << 12, dtype=np.int64))
+    parts = rng.integers(-1, 2, size=(idx.size, 2))
+    enc = lambda v: np.where(v > 0, one, np.where(v < 0, neg, 0)).astype(np.uint32)
+    wa = np.zeros(1 << (kb + mb), dtype=np.uint32)
+    wa[idx] = enc(parts[:, 0]) | (enc(parts[:, 1]) << 16)
+    br = rng.integers(0, 2, size=1 << (kb + nb), dtype=np.uint8)
+    bi = rng.integers(0, 2, size=1 << (kb + nb), dtype=np.uint8)
+    wb = np.where(br == 1, np.uint32(neg), np.uint32(one)) | (np.where(bi == 1, np.uint32(neg), np.uint32(one)) << 16)
+    # exact reference: only the nonzero entries of A contribute
+    ref = np.zeros(1 << (mb + nb), dtype=np.complex128)
+    k, m = idx & ((1 << kb) - 1), idx >> kb
+    a = parts[:, 0] + 1j * parts[:, 1]
+    for n in range(1 << nb):
+        bv = (1 - 2.0 * br[k + (n << kb)]) + 1j * (1 - 2.0 * bi[k + (n << kb)])
+        np.add.at(ref, m + (n << mb), a * bv)
+    mx = max(np.max(np.abs(ref.real)), np.max(np.abs(ref.imag)))
+    assert 0 < mx < 256
+    s_c = int(np.frexp(mx)[1] - 1) - 13       # max |C| 2^-s_C in [2^13, 2^14)
+    print(f"half split-K rank 30: m{mb} n{nb} k{kb} prec {prec} (seed {4300 + prec}) s_C {s_c}", flush=True)
+    ta = torch.from_numpy(wa.view(np.int32)).cuda()
+    tb = torch.from_numpy(wb.view(np.int32)).cuda()
+    del wa, wb
+    c = tnc.contract(ta, la, tb, lb, lc, kernel=SPLITK, precision=prec, out_scale=2.0 ** -s_c)
+    torch.cuda.synchronize()
+    del ta, tb
+    got = _from_half_words(c, prec) * 2.0 ** s_c
+    assert np.array_equal(got, ref), f"got {got} want {ref}"
+
+
 # ---------------------------------------------------------------- FP16 / BF16 storage
 def _to_half_words(x, prec):
     """complex entries -> int32 words of two 16-bit halves (re low)."""
