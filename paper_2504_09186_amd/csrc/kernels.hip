@@ -728,6 +728,8 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
   if (((uint64_t)blockIdx.x * 4 + w) * iters * R >= (1ull << (d.mb - 4 + d.bb)))
     iters = 0;  // a wave past the last row block (grids of one workgroup)
   const uint64_t b_b = L.wv[WV_BB + w];
+  // Column group blockIdx.y: this launch's waves cover columns [n0, n0 + 16 NBLK).
+  const int n0 = (int)blockIdx.y * 16 * NBLK;
   // MFMA row r of a column block is column n = (r >> 2) + 4 (r & 3) of it, so
   // that output register i of lane group lq is column lq + 4 i: the lowest
   // two n bits sit on lanes and a store instruction covers them.
@@ -737,7 +739,7 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
   for (int cb = 0; cb < NBLK; ++cb)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + lq, n = 16 * cb + (lr >> 2) + 4 * (lr & 3);
+      const int k = 4 * ks + lq, n = n0 + 16 * cb + (lr >> 2) + 4 * (lr & 3);
       float2 v = make_float2(0.f, 0.f);
       if (k < K && n < N) v = load_c<P>(d.B, b_b + L.bk[k] + L.bn[n]);
       br[cb][ks] = v.x;
@@ -759,7 +761,7 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
   for (int ks = 0; ks < KS; ++ks) a_hi[ks] = __builtin_amdgcn_readfirstlane(L.ak[(4 * ks) & 63]);
   uint32_t c_hb[NBLK], c_hi[4];  // n bits 4-5 (column block) and 2-3
 #pragma unroll
-  for (int cb = 0; cb < NBLK; ++cb) c_hb[cb] = __builtin_amdgcn_readfirstlane(L.cn[(16 * cb) & 63]);
+  for (int cb = 0; cb < NBLK; ++cb) c_hb[cb] = __builtin_amdgcn_readfirstlane(L.cn[(n0 + 16 * cb) & 63]);
 #pragma unroll
   for (int i = 0; i < 4; ++i) c_hi[i] = __builtin_amdgcn_readfirstlane(L.cn[4 * i]);
   // Row-block addresses are wave-uniform: keep them in scalar registers.
@@ -812,7 +814,7 @@ __device__ __forceinline__ float stream_body(const StepDesc& d, const uint8_t* t
       for (int cb = 0; cb < NBLK; ++cb)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (16 * cb + lq + 4 * i < N) {
+          if (n0 + 16 * cb + lq + 4 * i < N) {
             const float t1 = acc[0][cb][i], t2 = acc[1][cb][i], t3 = acc[2][cb][i];
             mx = fmaxf(mx, stream_store<P, EPI>(out + ((xrc | xjc) + (uint64_t)(c_hb[cb] + c_hi[i])) * ESC, d,
                                                 lane_offset(c_lo),
@@ -861,6 +863,8 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
   if (((uint64_t)blockIdx.x * 4 + w) * iters * R >= (1ull << (d.mb - 4 + d.bb)))
     iters = 0;  // a wave past the last row block (grids of one workgroup)
   const uint64_t b_b = L.wv[WV_BB + w];
+  // Column group blockIdx.y: this launch's waves cover columns [n0, n0 + 8 NB8).
+  const int n0 = (int)blockIdx.y * 8 * NB8;
   // B''^T fragments: row lr of each 16-row block, k' = 4 lq + t
   v4h bf[NB8][KS8];
   {
@@ -869,7 +873,7 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
     for (int nb = 0; nb < NB8; ++nb)
 #pragma unroll
       for (int ks = 0; ks < KS8; ++ks) {
-        const int n = 8 * nb + nl;
+        const int n = n0 + 8 * nb + nl;
         float2 b0 = make_float2(0.f, 0.f), b1 = make_float2(0.f, 0.f);
         const int k0 = 8 * ks + 2 * lq;
         if (n < N && k0 < K) b0 = load_c<P>(d.B, b_b + L.bk[k0] + L.bn[n]);
@@ -902,7 +906,7 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
   const uint32_t c_lo = (L.cm[lr] + L.cn[lq]) * ESC;
   uint32_t c_hb[NB8];  // n bits 3-5 (column block); bit 2 is h
 #pragma unroll
-  for (int nb = 0; nb < NB8; ++nb) c_hb[nb] = __builtin_amdgcn_readfirstlane(L.cn[(8 * nb) & 63]);
+  for (int nb = 0; nb < NB8; ++nb) c_hb[nb] = __builtin_amdgcn_readfirstlane(L.cn[(n0 + 8 * nb) & 63]);
   const uint32_t c_h4 = __builtin_amdgcn_readfirstlane(L.cn[4]);
   const uint64_t mra = uniform64(L.wv[WV_MRA]), mja = uniform64(L.wv[WV_MJA]), mrc = uniform64(L.wv[WV_MRC]),
                  mjc = uniform64(L.wv[WV_MJC]);
@@ -946,7 +950,7 @@ __device__ __forceinline__ float stream_body_h(const StepDesc& d, const uint8_t*
       for (int nb = 0; nb < NB8; ++nb)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-          if (8 * nb + lq + 4 * h < N)
+          if (n0 + 8 * nb + lq + 4 * h < N)
             mx = fmaxf(mx, stream_store<P, EPI>(out + ((xrc | xjc) + (uint64_t)(c_hb[nb] + (h ? c_h4 : 0u))) * ESC, d,
                                                 lane_offset(c_lo),
                                                 make_float2(acc[nb][2 * h], acc[nb][2 * h + 1])));
@@ -2095,15 +2099,29 @@ static int stream_wave_cap_log() {
 }
 
 template <auto Kern, int MaxLog>
-static hipError_t launch_stream_k(const StepDesc& d, int rl, hipStream_t s, Timing t) {
+static hipError_t launch_stream_k(const StepDesc& d, int rl, int cs, hipStream_t s, Timing t) {
   const int ngl = d.mb - 4 + d.bb - rl;  // log2 of row-block groups of all batch indices
   const int cap = stream_wave_cap_log<Kern, MaxLog>();
   const int wl = ngl < cap ? ngl : cap;        // log2 waves (>= 0 since mb >= 8)
   if (wl < d.bb) return hipErrorInvalidValue;  // a wave must stay inside one batch index
   const uint32_t iters = 1u << (ngl - wl);
-  const dim3 grid(wl >= 2 ? 1u << (wl - 2) : 1u);  // fewer than 4 waves: one workgroup, idle waves exit
+  // fewer than 4 waves: one workgroup, idle waves exit; 2^cs column groups
+  const dim3 grid(wl >= 2 ? 1u << (wl - 2) : 1u, 1u << cs);
   launch_k(Kern, grid, dim3(256), 0, s, t, d, iters);
   return hipGetLastError();
+}
+
+// Column groups of a stream launch with few waves: a step with few rows
+// would leave most of the chip idle while each wave stores all N columns,
+// so up to 2^10 waves the column blocks are dealt to 2^cs launch columns
+// (each re-reads its rows of A; kept to K 2^cs <= N so that the extra reads
+// stay below the output's bytes).
+static int stream_column_split(const StepDesc& d, int rl, int nbl, int cap) {
+  const int ngl = d.mb - 4 + d.bb - rl;
+  const int wl = ngl < cap ? ngl : cap;
+  int cs = wl < 10 ? (10 - wl < nbl ? 10 - wl : nbl) : 0;
+  while (cs > 0 && d.kb + cs > d.nb) --cs;
+  return cs;
 }
 
 // 16-bit storage: KS8 = 2^ksl k steps of 8, NB8 = 2^nbl column blocks of 8.
@@ -2113,8 +2131,10 @@ static hipError_t launch_stream_h(const StepDesc& d, hipStream_t s, Timing t) {
   if (!stream_fits(d.mb, d.nb, d.kb, d.bb) || ksl + nbl > 4) return hipErrorInvalidValue;
   if (!stream_rows_sorted(d) || !stream_offsets_fit(d, 4, d.mode == EPI_ACC64 ? 16 : 4)) return hipErrorInvalidValue;
   const int rl = kStreamRowsH > ksl ? kStreamRowsH - ksl : 0;  // log2 R, as in the kernel
+  const int cs = stream_column_split(d, rl, nbl, 12);
+  const int nbg = nbl - cs;  // column blocks per launch column
 #define MITNC_STREAMH(KSL, NBL) \
-  if (ksl == KSL && nbl == NBL) return launch_stream_k<k_stream_h<P, 1 << KSL, 1 << NBL>, 12>(d, rl, s, t);
+  if (ksl == KSL && nbg == NBL) return launch_stream_k<k_stream_h<P, 1 << KSL, 1 << NBL>, 12>(d, rl, cs, s, t);
   MITNC_STREAMH(0, 0) MITNC_STREAMH(0, 1) MITNC_STREAMH(0, 2) MITNC_STREAMH(0, 3)
   MITNC_STREAMH(1, 0) MITNC_STREAMH(1, 1) MITNC_STREAMH(1, 2) MITNC_STREAMH(1, 3)
   MITNC_STREAMH(2, 0) MITNC_STREAMH(2, 1) MITNC_STREAMH(2, 2)
@@ -2130,8 +2150,10 @@ static hipError_t launch_stream_f(const StepDesc& d, hipStream_t s, Timing t) {
   if (!stream_fits(d.mb, d.nb, d.kb, d.bb)) return hipErrorInvalidValue;
   if (!stream_rows_sorted(d) || !stream_offsets_fit(d, 8, d.mode == EPI_ACC64 ? 16 : 8)) return hipErrorInvalidValue;
   const int rl = kStreamRowsF > ksl ? kStreamRowsF - ksl : 0;  // log2 R, as in the kernel
+  const int cs = stream_column_split(d, rl, nbl, 13);
+  const int nbg = nbl - cs;  // column blocks per launch column
 #define MITNC_STREAM(KSL, NBL) \
-  if (ksl == KSL && nbl == NBL) return launch_stream_k<k_stream<P, 1 << KSL, 1 << NBL>, 13>(d, rl, s, t);
+  if (ksl == KSL && nbg == NBL) return launch_stream_k<k_stream<P, 1 << KSL, 1 << NBL>, 13>(d, rl, cs, s, t);
   MITNC_STREAM(0, 0) MITNC_STREAM(1, 0) MITNC_STREAM(2, 0) MITNC_STREAM(3, 0) MITNC_STREAM(4, 0)
   MITNC_STREAM(0, 1) MITNC_STREAM(1, 1) MITNC_STREAM(2, 1) MITNC_STREAM(3, 1)
   MITNC_STREAM(0, 2) MITNC_STREAM(1, 2) MITNC_STREAM(2, 2)
