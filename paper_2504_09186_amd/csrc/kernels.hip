@@ -1316,25 +1316,44 @@ __device__ __forceinline__ void store_c_tile(const StepDesc& d, const uint8_t* t
   const bool active = tid < (1 << nlo);
   const TileSlot lo = decode_bits<0, 8>(tid & ((1 << nlo) - 1), nlo, tab + T_CTILE, tab, TB_M, T_CM, T_CN);
   const int n_hi = 1 << (nc - nlo);
-  // The high parts (uniform per j) are decoded once, one per thread, into LDS.
-  __shared__ TileSlot hi_tab[C_ITEMS];
-  // (nc <= 8: only tid 0, whose high part is empty)
-  if (tid < n_hi && tid < C_ITEMS) hi_tab[tid] = decode_bits<8, 16>(tid << nlo, nc, tab + T_CTILE, tab, TB_M, T_CM, T_CN);
-  __syncthreads();
-  float mx = 0.f;
+  // The high parts are uniform: item j is the OR of the decodes of its set
+  // bits (tile bits 8 + t, t < log2 C_ITEMS), each decoded once into
+  // wave-uniform registers, so an item's LDS address is the thread's part
+  // plus a uniform offset and all items' LDS reads issue back to back.
+  constexpr int HB = ilog2(C_ITEMS);
+  uint32_t h_off[HB > 0 ? HB : 1];
+  int h_lds[HB > 0 ? HB : 1];
+#pragma unroll
+  for (int t = 0; t < HB; ++t) {
+    const TileSlot h = decode_bits<8, 16>(1u << (8 + t), nc, tab + T_CTILE, tab, TB_M, T_CM, T_CN);
+    h_off[t] = __builtin_amdgcn_readfirstlane(h.off);
+    h_lds[t] = __builtin_amdgcn_readfirstlane(h.lo * SC + h.hi);  // disjoint bits: OR = sum
+  }
+  const int lds_lo = lo.lo * SC + lo.hi;
+  float2 vals[C_ITEMS];
 #pragma unroll
   for (int j = 0; j < C_ITEMS; ++j) {
-    if (j >= n_hi) break;
-    const TileSlot hi = hi_tab[j];
-    const int mi = lo.lo | hi.lo, ni = lo.hi | hi.hi;
+    int hl = 0;
+#pragma unroll
+    for (int t = 0; t < HB; ++t)
+      if ((j >> t) & 1) hl += h_lds[t];
     float2 v = make_float2(0.f, 0.f);
 #pragma unroll
     for (int w = 0; w < WK; ++w) {
-      const float2 c = Cs[(w * TM + mi) * SC + ni];
+      const float2 c = Cs[w * TM * SC + lds_lo + hl];
       v.x += c.x;
       v.y += c.y;
     }
-    if (active) mx = fmaxf(mx, epilogue_store<P>(d, baseC + (lo.off | hi.off), v, blockIdx.y, c_elems));
+    vals[j] = v;
+  }
+  float mx = 0.f;
+#pragma unroll
+  for (int j = 0; j < C_ITEMS; ++j) {
+    uint32_t ho = 0;
+#pragma unroll
+    for (int t = 0; t < HB; ++t)
+      if ((j >> t) & 1) ho |= h_off[t];
+    if (active && j < n_hi) mx = fmaxf(mx, epilogue_store<P>(d, baseC + (lo.off | ho), vals[j], blockIdx.y, c_elems));
   }
   record_max(d, mx);
 }
